@@ -1,0 +1,206 @@
+"""ctypes binding of the FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+The oracle (``fftnk_oracle.cpp``) is a plain single-threaded implementation of
+the finite-strain FFT Newton-Krylov method of de Geus et al. (CMAME 2017).  It is
+the parity reference for the HIP library and shares no code with it.  Only the
+tests, the smoke check and the benchmark's CPU-baseline leg may import this
+module; the library itself never does.
+
+Arrays are numpy float64, tensor fields shaped ``(9, n0, n1, n2)`` (component
+``c = 3*i + j``, axis a2 fastest).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fftnk_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MAX_SOLVES = 64
+
+STATUS = {0: "ok", 1: "cg_maxit", 2: "cg_breakdown", 3: "newton_maxit", 4: "nonfinite", 5: "einval",
+          6: "return_map_fail"}
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("n_solves", ctypes.c_int),
+        ("cg_iters", ctypes.c_int * MAX_SOLVES),
+        ("newton_res", ctypes.c_double * MAX_SOLVES),
+        ("cg_relres", ctypes.c_double * MAX_SOLVES),
+    ]
+
+    def as_dict(self):
+        k = self.n_solves
+        return {
+            "status": self.status,
+            "n_solves": k,
+            "cg_iters": list(self.cg_iters[:k]),
+            "newton_res": list(self.newton_res[:k]),
+            "cg_relres": list(self.cg_relres[:k]),
+        }
+
+
+def build(force=False):
+    """Compile the oracle with g++ (no GPU code, no shared sources)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["g++", "-O2", "-fcx-limited-range", "-std=c++17", "-fPIC", "-shared", "-o", tmp, _SRC])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        i = ctypes.c_int
+        L.orc_fft1d.argtypes = [dp, i, i]
+        L.orc_dft1d_naive.argtypes = [dp, dp, i, i]
+        L.orc_fft3d.argtypes = [dp, i, i, i, i]
+        L.orc_dft3d_naive.argtypes = [dp, dp, i, i, i, i]
+        L.orc_project.argtypes = [i, i, i, dp, dp]
+        L.orc_svk_stress.argtypes = [ctypes.c_long, dp, dp, dp, dp]
+        L.orc_svk_tangent.argtypes = [ctypes.c_long, dp, dp, dp, dp, dp]
+        L.orc_apply_operator.argtypes = [i, i, i, dp, dp, dp, dp, dp]
+        L.orc_cg.argtypes = [i, i, i, dp, dp, dp, dp, dp, ctypes.c_double, i,
+                             ctypes.POINTER(i), dp]
+        L.orc_cg.restype = i
+        L.orc_solve_increment.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                          i, i, dp, dp, ctypes.POINTER(Stats)]
+        L.orc_solve_increment.restype = i
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------- transforms
+def fft1d(x, sign=-1):
+    x = np.array(x, dtype=np.complex128, copy=True)
+    buf = x.view(np.float64)
+    lib().orc_fft1d(_p(buf), x.size, sign)
+    return x
+
+
+def dft1d_naive(x, sign=-1):
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    out = np.empty_like(x)
+    lib().orc_dft1d_naive(_p(x.view(np.float64)), _p(out.view(np.float64)), x.size, sign)
+    return out
+
+
+def fft3d(x, sign=-1):
+    x = np.array(x, dtype=np.complex128, copy=True)
+    n0, n1, n2 = x.shape
+    lib().orc_fft3d(_p(x.view(np.float64).reshape(-1)), n0, n1, n2, sign)
+    return x
+
+
+def dft3d_naive(x, sign=-1):
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    out = np.empty_like(x)
+    n0, n1, n2 = x.shape
+    lib().orc_dft3d_naive(_p(x.view(np.float64).reshape(-1)), _p(out.view(np.float64).reshape(-1)),
+                          n0, n1, n2, sign)
+    return out
+
+
+# ---------------------------------------------------------------- projection
+def project(A):
+    """G(A) for a tensor field A of shape (9, n0, n1, n2) (or (3, 3, n0, n1, n2))."""
+    shp = A.shape
+    A = _c(A).reshape(9, *shp[-3:])
+    out = np.empty_like(A)
+    n0, n1, n2 = A.shape[1:]
+    lib().orc_project(n0, n1, n2, _p(A), _p(out))
+    return out.reshape(shp)
+
+
+# ---------------------------------------------------------------- material
+def _fields(F, K, mu):
+    F = _c(F)
+    grid = F.shape[-3:] if F.ndim >= 4 else F.shape[1:]
+    n = int(np.prod(F.shape)) // 9
+    K = _c(np.broadcast_to(K, grid) if np.ndim(K) else np.full(grid, float(K)))
+    mu = _c(np.broadcast_to(mu, grid) if np.ndim(mu) else np.full(grid, float(mu)))
+    return F, K, mu, n
+
+
+def svk_stress(F, K, mu):
+    """First Piola-Kirchhoff stress of St. Venant-Kirchhoff, per voxel."""
+    F, K, mu, n = _fields(F, K, mu)
+    P = np.empty_like(F)
+    lib().orc_svk_stress(n, _p(F), _p(K), _p(mu), _p(P))
+    return P
+
+
+def svk_tangent(F, K, mu, dF):
+    """Consistent tangent of St. Venant-Kirchhoff applied to dF."""
+    F, K, mu, n = _fields(F, K, mu)
+    dF = _c(np.broadcast_to(dF, F.shape))
+    out = np.empty_like(F)
+    lib().orc_svk_tangent(n, _p(F), _p(K), _p(mu), _p(dF), _p(out))
+    return out
+
+
+def apply_operator(F, K, mu, p):
+    """A p = G(K(F) : p), the projected-tangent operator."""
+    F, K, mu, n = _fields(F, K, mu)
+    p = _c(p).reshape(F.shape)
+    out = np.empty_like(F)
+    n0, n1, n2 = F.shape[-3:]
+    lib().orc_apply_operator(n0, n1, n2, _p(K), _p(mu), _p(F), _p(p), _p(out))
+    return out
+
+
+def cg(F, K, mu, b, eta=1e-8, max_cg=10000):
+    F, K, mu, n = _fields(F, K, mu)
+    b = _c(b).reshape(F.shape)
+    x = np.empty_like(F)
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    n0, n1, n2 = F.shape[-3:]
+    st = lib().orc_cg(n0, n1, n2, _p(K), _p(mu), _p(F), _p(b), _p(x), eta, max_cg, ctypes.byref(it),
+                      ctypes.byref(rel))
+    return x, st, it.value, rel.value
+
+
+def identity_field(shape):
+    F = np.zeros((9,) + tuple(shape))
+    F[0] = F[4] = F[8] = 1.0
+    return F
+
+
+def solve_increment(K, mu, F, Fbar, eta_nw=1e-5, eta_cg=1e-8, max_newton=50, max_cg=10000):
+    """One increment of Algorithm 1.  Returns (status, F_new, P, Pbar, stats)."""
+    F = np.array(F, dtype=np.float64, copy=True, order="C")
+    grid = F.shape[1:]
+    K = _c(np.broadcast_to(K, grid))
+    mu = _c(np.broadcast_to(mu, grid))
+    Fbar = _c(np.asarray(Fbar, dtype=np.float64).reshape(9))
+    P = np.zeros_like(F)
+    Pbar = np.zeros(9)
+    st = Stats()
+    status = lib().orc_solve_increment(grid[0], grid[1], grid[2], _p(K), _p(mu), _p(F), _p(Fbar),
+                                       eta_nw, eta_cg, max_newton, max_cg, _p(P), _p(Pbar),
+                                       ctypes.byref(st))
+    return status, F, P, Pbar, st.as_dict()

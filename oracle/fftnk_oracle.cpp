@@ -1,0 +1,537 @@
+// fftnk oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, single-threaded FP64 implementation of what the finite-strain
+// FFT Newton-Krylov homogenisation method of de Geus, Vondrejc, Zeman, Peerlings
+// and Geers ("Finite strain FFT-based non-linear solvers made simple", CMAME 318,
+// 2017) computes.  It is the parity reference for the HIP library and shares no
+// code, header, table or helper with it.  Only the test suite, the smoke check
+// and the benchmark's CPU-baseline leg may load it.
+//
+// Every routine names the passage of the paper it follows.  Conventions:
+//   * a second-order tensor field is stored component-major, [9][n0][n1][n2],
+//     component c = 3*i + j holds A_ij, grid axis a2 is the fastest;
+//   * grid axis d is the reference direction X_{d+1};
+//   * F_ij = dx_i / dX_j (nomenclature appendix).
+//
+// Parity pins (tests/test_oracle_*.py) check every routine against something
+// other than itself: naive DFTs, numpy's FFT, projector invariants, a
+// brute-force orthogonal projector built from spectral gradients, closed-form
+// hyperelastic states, central finite differences, the paper's fourth-order
+// tangent written in its own notation, a 1-D laminate solved by a 3-unknown
+// Newton iteration, linear-elastic laminate bounds, and the iteration count the
+// paper reports for its cubic-inclusion example.
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+typedef std::complex<double> cplx;
+
+extern "C" {
+
+// ---------------------------------------------------------------------------
+// Status codes and statistics of one increment.
+// ---------------------------------------------------------------------------
+enum {
+  ORC_OK = 0,
+  ORC_ECG_MAXIT = 1,
+  ORC_ECG_BREAKDOWN = 2,
+  ORC_ENEWTON_MAXIT = 3,
+  ORC_ENONFINITE = 4,
+  ORC_EINVAL = 5,
+};
+
+#define ORC_MAX_SOLVES 64
+
+typedef struct {
+  int status;
+  int n_solves;                       // linear solves in the increment (BC solve included)
+  int cg_iters[ORC_MAX_SOLVES];       // CG iterations (operator applications) per solve
+  double newton_res[ORC_MAX_SOLVES];  // ||dF|| / Fn after each solve
+  double cg_relres[ORC_MAX_SOLVES];   // final recursive ||r|| / ||b|| per solve
+} orc_stats;
+
+// ---------------------------------------------------------------------------
+// 1-D discrete Fourier transforms.
+//
+// Forward: X[k] = sum_j x[j] exp(-2 pi i j k / n); backward uses +i and is not
+// normalised (the 1/n of the inverse is applied by the 3-D driver).
+// ---------------------------------------------------------------------------
+
+static int smallest_prime_factor(int n) {
+  for (int p = 2; p * p <= n; ++p)
+    if (n % p == 0) return p;
+  return n;
+}
+
+// Recursive decimation-in-time Cooley-Tukey for any n.  The sub-sequences
+// x[r], x[r+p], x[r+2p], ... (r = 0..p-1, p the smallest prime factor of n)
+// are transformed recursively (length m = n/p), then combined:
+//   X[k + m q] = sum_r W_n^{r (k + m q)} Y_r[k],   W_n = exp(sign 2 pi i / n).
+// A prime length is done by the naive O(n^2) sum.  The table w[e] holds
+// W_N^e for the top-level length N; W_n^e = w[e * N / n].
+static void fft_rec(const cplx* in, long stride, cplx* out, int n, int sign,
+                    const cplx* w, int N) {
+  if (n == 1) {
+    out[0] = in[0];
+    return;
+  }
+  const int p = smallest_prime_factor(n);
+  const int step = N / n;
+  if (p == n) {
+    for (int k = 0; k < n; ++k) {
+      cplx s = 0.0;
+      int e = 0;  // e = j * k mod n, advanced incrementally
+      for (int j = 0; j < n; ++j) {
+        s += in[j * stride] * w[(long)e * step];
+        e += k;
+        if (e >= n) e -= n;
+      }
+      out[k] = s;
+    }
+    return;
+  }
+  const int m = n / p;
+  for (int r = 0; r < p; ++r) fft_rec(in + r * stride, stride * p, out + (long)r * m, m, sign, w, N);
+  std::vector<cplx> tmp(n);
+  for (int k = 0; k < m; ++k)
+    for (int q = 0; q < p; ++q) {
+      const int kk = k + m * q;
+      cplx s = 0.0;
+      int e = 0;  // e = r * kk mod n
+      for (int r = 0; r < p; ++r) {
+        s += out[(long)r * m + k] * w[(long)e * step];
+        e += kk;
+        if (e >= n) e -= n;
+      }
+      tmp[kk] = s;
+    }
+  for (int k = 0; k < n; ++k) out[k] = tmp[k];
+}
+
+static std::vector<cplx> twiddle_table(int n, int sign) {
+  std::vector<cplx> w(n);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int e = 0; e < n; ++e) {
+    const double a = sign * two_pi * (double)e / (double)n;
+    w[e] = cplx(std::cos(a), std::sin(a));
+  }
+  return w;
+}
+
+// In-place 1-D transform of n interleaved complex values (re, im, re, im, ...).
+void orc_fft1d(double* data, int n, int sign) {
+  cplx* x = reinterpret_cast<cplx*>(data);
+  std::vector<cplx> w = twiddle_table(n, sign);
+  std::vector<cplx> in(x, x + n), out(n);
+  fft_rec(in.data(), 1, out.data(), n, sign, w.data(), n);
+  for (int k = 0; k < n; ++k) x[k] = out[k];
+}
+
+// Naive 1-D DFT, the pin of orc_fft1d.
+void orc_dft1d_naive(const double* in_, double* out_, int n, int sign) {
+  const cplx* in = reinterpret_cast<const cplx*>(in_);
+  cplx* out = reinterpret_cast<cplx*>(out_);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int k = 0; k < n; ++k) {
+    cplx s = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double a = sign * two_pi * (double)((long)j * k % n) / (double)n;
+      s += in[j] * cplx(std::cos(a), std::sin(a));
+    }
+    out[k] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3-D transforms: one 1-D transform per grid line along each axis in turn
+// (the separable form the paper notes: 3 x 3 x 3 one-dimensional transforms per
+// second-order tensor, Implementation aspects, Sec. 3.3).
+// ---------------------------------------------------------------------------
+
+static void fft3d_inplace(cplx* x, int n0, int n1, int n2, int sign) {
+  const int dims[3] = {n0, n1, n2};
+  const long strides[3] = {(long)n1 * n2, (long)n2, 1};
+  for (int ax = 0; ax < 3; ++ax) {
+    const int n = dims[ax];
+    if (n == 1) continue;
+    std::vector<cplx> w = twiddle_table(n, sign);
+    std::vector<cplx> line(n), res(n);
+    const long s = strides[ax];
+    // iterate over all lines along this axis
+    const int oa = (ax == 0) ? 1 : 0, ob = (ax == 2) ? 1 : 2;
+    for (int ia = 0; ia < dims[oa]; ++ia)
+      for (int ib = 0; ib < dims[ob]; ++ib) {
+        const long base = (long)ia * strides[oa] + (long)ib * strides[ob];
+        for (int t = 0; t < n; ++t) line[t] = x[base + t * s];
+        fft_rec(line.data(), 1, res.data(), n, sign, w.data(), n);
+        for (int t = 0; t < n; ++t) x[base + t * s] = res[t];
+      }
+  }
+}
+
+void orc_fft3d(double* data, int n0, int n1, int n2, int sign) {
+  fft3d_inplace(reinterpret_cast<cplx*>(data), n0, n1, n2, sign);
+}
+
+// Naive O(n^2) 3-D DFT: the definition, used to pin orc_fft3d on tiny grids.
+void orc_dft3d_naive(const double* in_, double* out_, int n0, int n1, int n2, int sign) {
+  const cplx* in = reinterpret_cast<const cplx*>(in_);
+  cplx* out = reinterpret_cast<cplx*>(out_);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int k0 = 0; k0 < n0; ++k0)
+    for (int k1 = 0; k1 < n1; ++k1)
+      for (int k2 = 0; k2 < n2; ++k2) {
+        cplx s = 0.0;
+        for (int j0 = 0; j0 < n0; ++j0)
+          for (int j1 = 0; j1 < n1; ++j1)
+            for (int j2 = 0; j2 < n2; ++j2) {
+              const double ph = (double)((long)j0 * k0 % n0) / n0 + (double)((long)j1 * k1 % n1) / n1 +
+                                (double)((long)j2 * k2 % n2) / n2;
+              const double a = sign * two_pi * ph;
+              s += in[((long)j0 * n1 + j1) * n2 + j2] * cplx(std::cos(a), std::sin(a));
+            }
+        out[((long)k0 * n1 + k1) * n2 + k2] = s;
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Compatibility projection (Sec. 2.5, equation for G-hat; even grids: App. C;
+// properties: App. D).
+//
+//   G(A) = Re F^{-1}[ G-hat : F(A) ],  (G-hat : A-hat)_ij = xi_j (sum_l xi_l A-hat_il) / |xi|^2
+//
+// using the double contraction A:B = A_ijkl B_lk of the nomenclature and
+// G-hat_ijlm = delta_im xi_j xi_l / |xi|^2.  xi_d = k_d / N_d with k_d the signed
+// integer frequency of axis d (for cubic grids the common factor 1/N cancels).
+// G-hat is zero at k = 0 (zero-mean property) and, on an even axis, whenever that
+// axis sits at its Nyquist index N_d/2 (App. C, the "compatible F" choice).
+// Full complex transforms are used (no real-to-complex shortcut).
+// ---------------------------------------------------------------------------
+
+static int signed_freq(int idx, int n) { return (2 * idx > n) ? idx - n : idx; }
+
+void orc_project(int n0, int n1, int n2, const double* A, double* GA) {
+  const long n = (long)n0 * n1 * n2;
+  std::vector<cplx> Ah(9 * n);
+  for (int c = 0; c < 9; ++c) {
+    for (long v = 0; v < n; ++v) Ah[c * n + v] = cplx(A[c * n + v], 0.0);
+    fft3d_inplace(&Ah[c * n], n0, n1, n2, -1);
+  }
+  for (int i0 = 0; i0 < n0; ++i0)
+    for (int i1 = 0; i1 < n1; ++i1)
+      for (int i2 = 0; i2 < n2; ++i2) {
+        const long v = ((long)i0 * n1 + i1) * n2 + i2;
+        const bool nyq = (n0 % 2 == 0 && 2 * i0 == n0) || (n1 % 2 == 0 && 2 * i1 == n1) ||
+                         (n2 % 2 == 0 && 2 * i2 == n2);
+        const double xi[3] = {(double)signed_freq(i0, n0) / n0, (double)signed_freq(i1, n1) / n1,
+                              (double)signed_freq(i2, n2) / n2};
+        const double xx = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
+        cplx out[9];
+        if (xx == 0.0 || nyq) {
+          for (int c = 0; c < 9; ++c) out[c] = 0.0;
+        } else {
+          for (int i = 0; i < 3; ++i) {
+            // row i of A-hat projected on xi
+            cplx s = 0.0;
+            for (int l = 0; l < 3; ++l) s += Ah[(3 * i + l) * n + v] * xi[l];
+            for (int j = 0; j < 3; ++j) out[3 * i + j] = s * xi[j] / xx;
+          }
+        }
+        for (int c = 0; c < 9; ++c) Ah[c * n + v] = out[c];
+      }
+  for (int c = 0; c < 9; ++c) {
+    fft3d_inplace(&Ah[c * n], n0, n1, n2, +1);
+    for (long v = 0; v < n; ++v) GA[c * n + v] = Ah[c * n + v].real() / (double)n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// St. Venant-Kirchhoff hyperelasticity (Sec. 4.2):
+//   E = (F^T F - I)/2,  S = C : E = lambda tr(E) I + 2 mu E,  P = F . S,
+// with the isotropic stiffness parameterised by bulk modulus K and shear
+// modulus mu, lambda = K - 2 mu / 3 (the deviatoric split of the example).
+// ---------------------------------------------------------------------------
+
+static inline void mat_get(const double* X, long n, long v, double a[9]) {
+  for (int c = 0; c < 9; ++c) a[c] = X[c * n + v];
+}
+static inline void mat_put(double* X, long n, long v, const double a[9]) {
+  for (int c = 0; c < 9; ++c) X[c * n + v] = a[c];
+}
+
+// Second Piola-Kirchhoff stress of one material point.
+static void svk_S(const double F[9], double K, double mu, double S[9]) {
+  const double lam = K - 2.0 * mu / 3.0;
+  double E[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += F[3 * k + i] * F[3 * k + j];  // (F^T F)_ij
+      E[3 * i + j] = 0.5 * (s - (i == j ? 1.0 : 0.0));
+    }
+  const double trE = E[0] + E[4] + E[8];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) S[3 * i + j] = lam * trE * (i == j ? 1.0 : 0.0) + 2.0 * mu * E[3 * i + j];
+}
+
+static void matmul(const double A[9], const double B[9], double C[9]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[3 * i + k] * B[3 * k + j];
+      C[3 * i + j] = s;
+    }
+}
+
+void orc_svk_stress(long n, const double* F, const double* K, const double* mu, double* P) {
+  for (long v = 0; v < n; ++v) {
+    double f[9], S[9], p[9];
+    mat_get(F, n, v, f);
+    svk_S(f, K[v], mu[v], S);
+    matmul(f, S, p);
+    mat_put(P, n, v, p);
+  }
+}
+
+// Consistent tangent applied to a direction (Sec. 4.3): the linearisation
+//   dP = dF . S + F . dS,  dS = C : dE,  dE = (dF^T F + F^T dF)/2,
+// which is the action of the paper's fourth-order K = S.I + I^RT:(F.C.F^T):I^RT
+// on dF (checked against that form and against finite differences by tests).
+void orc_svk_tangent(long n, const double* F, const double* K, const double* mu, const double* dF,
+                     double* dP) {
+  for (long v = 0; v < n; ++v) {
+    double f[9], d[9], S[9];
+    mat_get(F, n, v, f);
+    mat_get(dF, n, v, d);
+    svk_S(f, K[v], mu[v], S);
+    const double lam = K[v] - 2.0 * mu[v] / 3.0;
+    double dE[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += d[3 * k + i] * f[3 * k + j] + f[3 * k + i] * d[3 * k + j];
+        dE[3 * i + j] = 0.5 * s;
+      }
+    const double trdE = dE[0] + dE[4] + dE[8];
+    double dS[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) dS[3 * i + j] = lam * trdE * (i == j ? 1.0 : 0.0) + 2.0 * mu[v] * dE[3 * i + j];
+    double t1[9], t2[9], out[9];
+    matmul(d, S, t1);
+    matmul(f, dS, t2);
+    for (int c = 0; c < 9; ++c) out[c] = t1[c] + t2[c];
+    mat_put(dP, n, v, out);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Linear algebra helpers over whole fields.
+// ---------------------------------------------------------------------------
+
+// Compensated (Kahan) sum of a[i] * b[i].
+static double dot(const double* a, const double* b, long m) {
+  double s = 0.0, c = 0.0;
+  for (long i = 0; i < m; ++i) {
+    const double y = a[i] * b[i] - c;
+    const double t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  return s;
+}
+
+static bool all_finite(const double* a, long m) {
+  for (long i = 0; i < m; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Material description shared by the routines below.  model 0 = St. Venant-
+// Kirchhoff with per-voxel (K, mu).
+// ---------------------------------------------------------------------------
+typedef struct {
+  int n0, n1, n2;
+  const double* K;
+  const double* mu;
+} orc_problem;
+
+// The projected-tangent operator of the linearised system (eq. iter:system):
+// A p = G( K_(i) applied to p ) with the tangent taken at F_lin.
+void orc_apply_operator(int n0, int n1, int n2, const double* K, const double* mu, const double* Flin,
+                        const double* p, double* Ap) {
+  const long n = (long)n0 * n1 * n2;
+  std::vector<double> t(9 * n);
+  orc_svk_tangent(n, Flin, K, mu, p, t.data());
+  orc_project(n0, n1, n2, t.data(), Ap);
+}
+
+// ---------------------------------------------------------------------------
+// Conjugate gradients on the projected-tangent operator (Sec. 2.6: a projection
+// based Krylov solver that stays compatible; Sec. 3: solved to accuracy eta_CG).
+// x0 = 0, r = b, p = r; stop when ||r|| <= eta ||b|| (recursive residual).
+// Returns the number of operator applications in *iters.
+// ---------------------------------------------------------------------------
+static int cg_solve(const orc_problem& pb, const double* Flin, const double* b, double* x, double eta,
+                    int max_cg, int* iters, double* relres) {
+  const long n = (long)pb.n0 * pb.n1 * pb.n2, m = 9 * n;
+  std::vector<double> r(b, b + m), p(b, b + m), w(m);
+  for (long i = 0; i < m; ++i) x[i] = 0.0;
+  const double bb = dot(b, b, m);
+  double rr = bb;
+  *iters = 0;
+  *relres = 1.0;
+  const double stop = eta * std::sqrt(bb);
+  if (std::sqrt(rr) <= stop) {
+    *relres = 0.0;
+    return ORC_OK;
+  }
+  while (true) {
+    if (*iters >= max_cg) return ORC_ECG_MAXIT;
+    orc_apply_operator(pb.n0, pb.n1, pb.n2, pb.K, pb.mu, Flin, p.data(), w.data());
+    ++*iters;
+    const double pw = dot(p.data(), w.data(), m);
+    if (!(pw > 0.0) || !std::isfinite(pw)) return ORC_ECG_BREAKDOWN;
+    const double alpha = rr / pw;
+    for (long i = 0; i < m; ++i) {
+      x[i] += alpha * p[i];
+      r[i] -= alpha * w[i];
+    }
+    const double rr_new = dot(r.data(), r.data(), m);
+    *relres = std::sqrt(rr_new / bb);
+    if (!std::isfinite(rr_new)) return ORC_ENONFINITE;
+    if (std::sqrt(rr_new) <= stop) return ORC_OK;
+    const double beta = rr_new / rr;
+    rr = rr_new;
+    for (long i = 0; i < m; ++i) p[i] = r[i] + beta * p[i];
+  }
+}
+
+// Solve A dF = b unless b is at the round-off floor ||b|| <= 1e-14 ||Y|| of the
+// field Y that G was applied to; then dF = 0 with zero iterations.
+static int cg_or_zero(const orc_problem& pb, const double* Flin, const double* b, const double* Y,
+                      double* x, double eta, int max_cg, int* iters, double* relres) {
+  const long m = 9L * pb.n0 * pb.n1 * pb.n2;
+  const double nb = std::sqrt(dot(b, b, m)), ny = std::sqrt(dot(Y, Y, m));
+  if (nb <= 1e-14 * ny || nb == 0.0) {
+    for (long i = 0; i < m; ++i) x[i] = 0.0;
+    *iters = 0;
+    *relres = 0.0;
+    return ORC_OK;
+  }
+  return cg_solve(pb, Flin, b, x, eta, max_cg, iters, relres);
+}
+
+// ---------------------------------------------------------------------------
+// One load increment of Algorithm 1 with a prescribed macroscopic deformation
+// gradient (Sec. 3.1 boundary conditions, Sec. 3.2 program structure).
+//
+//   dFbar = Fbar - mean(F_t)
+//   i = 0:  solve G:K(F_t):dF = -G:K(F_t):dFbar (tangent about the start state),
+//           F = F_t + dFbar + dF
+//   i > 0:  solve G:K(F_i):dF = -G:P(F_i),  F = F_i + dF
+//   stop when ||dF|| / ||F_t + dFbar|| < eta_NW and i > 0.
+//
+// F holds F_t on entry and the converged field on exit (unchanged on failure).
+// P receives the stress of the converged field and Pbar its voxel mean.
+// ---------------------------------------------------------------------------
+int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* mu, double* F,
+                        const double* Fbar, double eta_nw, double eta_cg, int max_newton, int max_cg,
+                        double* P, double* Pbar, orc_stats* st) {
+  const long n = (long)n0 * n1 * n2, m = 9 * n;
+  orc_problem pb{n0, n1, n2, K, mu};
+  orc_stats local;
+  if (!st) st = &local;
+  std::memset(st, 0, sizeof(*st));
+  if (n0 < 1 || n1 < 1 || n2 < 1 || max_newton < 1 || max_newton > ORC_MAX_SOLVES) {
+    st->status = ORC_EINVAL;
+    return ORC_EINVAL;
+  }
+  if (!all_finite(Fbar, 9)) {
+    st->status = ORC_ENONFINITE;
+    return ORC_ENONFINITE;
+  }
+  std::vector<double> Ft(F, F + m), Fc(F, F + m), Flin(F, F + m), b(m), Y(m), dF(m), Pc(m);
+
+  // macroscopic increment relative to the mean of the start state
+  double dFbar[9];
+  for (int c = 0; c < 9; ++c) {
+    double s = 0.0, comp = 0.0;
+    for (long v = 0; v < n; ++v) {
+      const double y = Ft[c * n + v] - comp;
+      const double t = s + y;
+      comp = (t - s) - y;
+      s = t;
+    }
+    dFbar[c] = Fbar[c] - s / (double)n;
+  }
+  // BC right-hand side: Y = K(F_t) : dFbar (uniform dFbar field), b = -G(Y)
+  {
+    std::vector<double> U(m);
+    for (int c = 0; c < 9; ++c)
+      for (long v = 0; v < n; ++v) U[c * n + v] = dFbar[c];
+    orc_svk_tangent(n, Ft.data(), K, mu, U.data(), Y.data());
+    orc_project(n0, n1, n2, Y.data(), b.data());
+    for (long i = 0; i < m; ++i) b[i] = -b[i];
+  }
+  for (int c = 0; c < 9; ++c)
+    for (long v = 0; v < n; ++v) Fc[c * n + v] += dFbar[c];
+  const double Fn = std::sqrt(dot(Fc.data(), Fc.data(), m));
+
+  int status = ORC_OK;
+  for (int it = 0;; ++it) {
+    if (it >= max_newton) {
+      status = ORC_ENEWTON_MAXIT;
+      break;
+    }
+    int cgit = 0;
+    double relres = 0.0;
+    status = cg_or_zero(pb, Flin.data(), b.data(), Y.data(), dF.data(), eta_cg, max_cg, &cgit, &relres);
+    st->cg_iters[it] = cgit;
+    st->cg_relres[it] = relres;
+    st->n_solves = it + 1;
+    if (status != ORC_OK) break;
+    for (long i = 0; i < m; ++i) Fc[i] += dF[i];
+    if (!all_finite(Fc.data(), m)) {
+      status = ORC_ENONFINITE;
+      break;
+    }
+    orc_svk_stress(n, Fc.data(), K, mu, Pc.data());
+    for (long i = 0; i < m; ++i) Y[i] = Pc[i];
+    orc_project(n0, n1, n2, Pc.data(), b.data());
+    for (long i = 0; i < m; ++i) b[i] = -b[i];
+    const double res = std::sqrt(dot(dF.data(), dF.data(), m)) / Fn;
+    st->newton_res[it] = res;
+    if (res < eta_nw && it > 0) break;
+    Flin = Fc;  // next linearisation point
+  }
+  st->status = status;
+  if (status != ORC_OK) return status;
+  for (long i = 0; i < m; ++i) {
+    F[i] = Fc[i];
+    P[i] = Pc[i];
+  }
+  for (int c = 0; c < 9; ++c) {
+    double s = 0.0, comp = 0.0;
+    for (long v = 0; v < n; ++v) {
+      const double y = Pc[c * n + v] - comp;
+      const double t = s + y;
+      comp = (t - s) - y;
+      s = t;
+    }
+    Pbar[c] = s / (double)n;
+  }
+  return ORC_OK;
+}
+
+// Exposed for tests: plain CG on the operator at a given linearisation point.
+int orc_cg(int n0, int n1, int n2, const double* K, const double* mu, const double* Flin, const double* b,
+           double* x, double eta, int max_cg, int* iters, double* relres) {
+  orc_problem pb{n0, n1, n2, K, mu};
+  return cg_solve(pb, Flin, b, x, eta, max_cg, iters, relres);
+}
+
+}  // extern "C"
