@@ -1,0 +1,245 @@
+"""Benchmark of the finite-strain FFT Newton-Krylov hot path on one MI355X.
+
+Workload (the paper's method on a 128^3 periodic cell): two phases from a
+seeded Gaussian random field (correlation length 8 voxels) thresholded at 30 %
+inclusion volume fraction, St. Venant-Kirchhoff with 10x modulus contrast
+(K, mu = 0.833, 0.386 and 8.33, 3.86), isochoric stretch Fbar =
+diag(l, l^-1/2, l^-1/2) with l = 1.01 ... 1.05 in 5 increments, Newton
+tolerance 1e-5, CG tolerance 1e-8, FP64.
+
+A step is one load increment: constitutive update, right-hand sides, every CG
+iteration (projected-tangent operator: tangent action, 3-D FFT, projection,
+inverse FFT; fused vector updates) and the Newton update.  The timed steps run
+the 5-increment schedule from the stress-free state (repeating it if --steps
+exceeds 5).  `value` is projected-tangent operator applications per second over
+the timed steps.  Besides that line's fields the JSON carries the operator
+alone (back-to-back applications), every pass's measured bandwidth, the
+FP32-mixed solve of the same increments, and the CPU oracle's rate.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N = 128
+TABLE = [(0.833, 0.386), (8.33, 3.86)]
+
+
+def pass_bytes_per_voxel(prec_bytes, n2):
+    """Algorithmic HBM bytes per voxel of each operator pass (no re-reads).
+
+    Real fields: 9 components; spectra: 9 complex half-lines of h entries per
+    n2 voxels (h = n2/2 for even n2).  Pass 1 reads the direction p and F
+    (and one phase byte) and writes the spectrum; passes 2-4 read and write
+    the spectrum; pass 5 reads the spectrum and writes the result.
+    """
+    h = n2 // 2 if n2 % 2 == 0 else (n2 + 1) // 2
+    spec = 9 * 2 * prec_bytes * h / n2
+    field = 9 * prec_bytes
+    return {1: 2 * field + 1 + spec, 2: 2 * spec, 3: 2 * spec, 4: 2 * spec, 5: spec + field}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--matvec-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the per-GPU work is one periodic cell; see DESIGN.md for how it would shard).", flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_1603_08893_amd import microstructure as ms
+    from paper_1603_08893_amd.fftnk import Solver
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    phase = ms.grf_threshold(N, ell=8.0, frac=0.3, seed=1603)
+    sched = ms.c2_schedule(5)
+    print("# inputs ready (%.1fs), inclusion fraction %.4f" % (time.time() - t0, phase.mean()), file=sys.stderr,
+          flush=True)
+
+    def make(prec):
+        s = Solver((N, N, N), precision=prec)
+        s.set_phases(phase)
+        s.set_material(TABLE)
+        return s
+
+    def run_steps(s, k0, count):
+        cg, solves, pbars, stats = 0, 0, [], []
+        for k in range(k0, k0 + count):
+            if k % len(sched) == 0:
+                s.reset_state()
+            _, _, _, Pbar, st = s.solve_increment(sched[k % len(sched)], 1e-5, 1e-8, fields=False)
+            cg += sum(st[0]["cg_iters"])
+            solves += st[0]["n_solves"]
+            pbars.append(Pbar[0].copy())
+            stats.append(st[0])
+        return cg, solves, pbars, stats
+
+    # ------------------------------------------------------------ FP64 solve (the timed steps)
+    s64 = make("fp64")
+    for k in range(args.warmup):
+        run_steps(s64, k, 1)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    ev0.record()
+    cg64, solves64, pbars64, stats64 = run_steps(s64, 0, args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_total = ev0.elapsed_time(ev1)
+    sec = ms_total / 1e3
+    print("# fp64 steps: %.1f ms, %d CG iterations, %d solves, wall %.2fs" % (ms_total, cg64, solves64, wall),
+          file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------ operator alone + per-pass timing
+    F_lin = s64.get_state()  # converged state of the last timed increment
+    res = {}
+
+    def operator_bench(s, reps):
+        s.set_linearization(F_lin)
+        p = s.project(torch.from_numpy(ms.random_field((N, N, N), seed=42).reshape(-1)).to(dev))
+        out = s.field()
+        for _ in range(3):
+            s.apply_operator(p, out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            s.apply_operator(p, out)
+        e1.record()
+        torch.cuda.synchronize()
+        t_mv = e0.elapsed_time(e1) / reps
+        # pass by pass, each timed alone over the same number of launches
+        # (the internal buffers of the context: pass 1 reads its direction field)
+        passes = {}
+        for k in range(1, 6):
+            for _ in range(2):
+                s.launch_pass(k)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                s.launch_pass(k)
+            e1.record()
+            torch.cuda.synchronize()
+            passes[k] = e0.elapsed_time(e1) / reps
+        return t_mv, passes
+
+    n = N ** 3
+    t_mv64, passes64 = operator_bench(s64, args.matvec_reps)
+    bpv64 = pass_bytes_per_voxel(8, N)
+    mv_bytes64 = sum(bpv64.values()) * n
+    pass_rows = {}
+    for k in range(1, 6):
+        gbs = bpv64[k] * n / (passes64[k] * 1e-3) / 1e9
+        pass_rows["pass%d" % k] = {"ms": round(passes64[k], 5), "bytes_per_voxel": round(bpv64[k], 3),
+                                   "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    dom = max(range(1, 6), key=lambda k: passes64[k])
+    dom_names = {1: "k_fwd_a2<double,FWD_TANGENT>", 2: "k_col_a1<double,fwd>", 3: "k_col_a0_project<double>",
+                 4: "k_col_a1<double,inv>", 5: "k_inv_a2<double,INV_OUT>"}
+    achieved = bpv64[dom] * n / (passes64[dom] * 1e-3) / 1e9
+    print("# fp64 operator %.3f ms (%.0f GB/s over the 5-pass bytes); passes %s" %
+          (t_mv64, mv_bytes64 / (t_mv64 * 1e-3) / 1e9, {k: round(v, 4) for k, v in passes64.items()}),
+          file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------ FP32-mixed solve of the same increments
+    fp32 = None
+    if not args.no_fp32:
+        s32 = make("fp32")
+        run_steps(s32, 0, 1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cg32, solves32, pbars32, stats32 = run_steps(s32, 0, min(args.steps, 5))
+        e1.record()
+        torch.cuda.synchronize()
+        sec32 = e0.elapsed_time(e1) / 1e3
+        err = max(float(np.max(np.abs(a - b)) / np.max(np.abs(b))) for a, b in zip(pbars32, pbars64))
+        t_mv32, passes32 = operator_bench(s32, args.matvec_reps)
+        bpv32 = pass_bytes_per_voxel(4, N)
+        fp32 = {
+            "increments_per_s": round(min(args.steps, 5) / sec32, 3),
+            "cg_matvecs_per_s": round(cg32 / sec32, 1),
+            "cg_iterations": cg32,
+            "operator_ms": round(t_mv32, 4),
+            "operator_matvecs_per_s": round(1e3 / t_mv32, 1),
+            "operator_GB_s": round(sum(bpv32.values()) * n / (t_mv32 * 1e-3) / 1e9, 1),
+            "passes_ms": {k: round(v, 5) for k, v in passes32.items()},
+            "pbar_rel_diff_vs_fp64_gpu": err,
+            "speedup_vs_fp64": round((min(args.steps, 5) / sec32) / (args.steps / sec), 3),
+        }
+        del s32
+
+    # ------------------------------------------------------------ CPU oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        K, mu = ms.phase_moduli(phase, TABLE)
+        F_np = F_lin.view(9, N, N, N).cpu().numpy()
+        p_np = ms.random_field((N, N, N), seed=42)
+        reps, t_cpu = 0, 0.0
+        while reps < 3 and t_cpu < 20.0:
+            c0 = time.perf_counter()
+            oracle.apply_operator(F_np, K, mu, p_np)
+            t_cpu += time.perf_counter() - c0
+            reps += 1
+        cpu = {"value": round(reps / t_cpu, 4), "unit": "matvec/s", "cores": 1, "kind": "oracle",
+               "sample": "%d projected-tangent operator applications at 128^3 (FP64, C2 linearisation point) on one "
+                         "host core, %.1f s" % (reps, t_cpu)}
+
+    line = {
+        "metric": "projected-tangent matvecs/s at 128^3 (FP64 Newton-Krylov solve)",
+        "value": round(cg64 / sec, 2),
+        "unit": "matvec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_total / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "C2: 128^3 two-phase GRF cell (30%, 10x contrast), St.V-K, isochoric stretch "
+                               "1.01..1.05 in 5 increments, eta_NW 1e-5, eta_CG 1e-8", "grid": [N, N, N],
+                   "precision": "fp64"},
+        "newton_increments_per_s": round(args.steps / sec, 3),
+        "linear_solves": solves64,
+        "cg_iterations": cg64,
+        "cg_per_increment": [s["cg_iters"] for s in stats64],
+        "pbar_last": [float(v) for v in pbars64[-1]],
+        "operator": {"ms": round(t_mv64, 4), "matvecs_per_s": round(1e3 / t_mv64, 1),
+                     "bytes_5pass_per_voxel": round(sum(bpv64.values()), 2),
+                     "GB_s": round(mv_bytes64 / (t_mv64 * 1e-3) / 1e9, 1),
+                     "frac_of_hbm_peak": round(mv_bytes64 / (t_mv64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "passes": pass_rows,
+        "roofline": {"bound": "hbm", "kernel": dom_names[dom], "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "fp32_mixed": fp32,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

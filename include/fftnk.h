@@ -1,0 +1,190 @@
+/*
+ * fftnk.h -- C-ABI of libfftnk, an MI355X (gfx950) implementation of the hot
+ * path of the finite-strain FFT-based Newton-Krylov homogenisation solver of
+ * T.W.J. de Geus, J. Vondrejc, J. Zeman, R.H.J. Peerlings, M.G.D. Geers,
+ * "Finite strain FFT-based non-linear solvers made simple", CMAME 318 (2017).
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ *  - Grid: a periodic cell of n0 x n1 x n2 voxels; grid axis d is the reference
+ *    direction X_{d+1}.  n = n0*n1*n2.
+ *  - Tensor fields are device arrays, component-major [9][n0][n1][n2] (axis a2
+ *    fastest), component c = 3*i + j holds A_ij, F_ij = dx_i/dX_j (paper's
+ *    nomenclature appendix).  A batched context concatenates the RVE blocks in
+ *    RVE order: RVE r starts at element 9*(n_0 + ... + n_{r-1}).
+ *  - F, P and the homogenised stresses are always FP64.  Fields passed to
+ *    fftnk_project / fftnk_apply_operator use the context precision
+ *    (FFTNK_FP64: double, FFTNK_FP32_MIXED: float).
+ *  - Device memory is owned by the caller.  The context never allocates device
+ *    memory: all of its state lives in one caller-provided workspace (see
+ *    fftnk_workspace_bytes / fftnk_bind_workspace) and is never freed by it.
+ *    Host arrays are read (or written) during the call only.
+ *  - All work is enqueued on the HIP stream given at creation; calls that
+ *    return host results synchronise that stream before returning.
+ *  - Every call returns an int status (FFTNK_OK = 0) and never throws.
+ *  - A context is not thread safe; calls on one context must not overlap.
+ */
+#ifndef FFTNK_H
+#define FFTNK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+  FFTNK_OK = 0,
+  FFTNK_EINVAL = 1,          /* bad argument (size, pointer, tolerance, parameters)          */
+  FFTNK_ESTATE = 2,          /* call order: workspace / phases / material not set            */
+  FFTNK_ENOMEM = 3,          /* workspace smaller than fftnk_workspace_bytes                 */
+  FFTNK_EHIP = 4,            /* a HIP runtime call failed                                     */
+  FFTNK_ECG_MAXIT = 5,       /* CG reached max_cg iterations without convergence            */
+  FFTNK_ECG_BREAKDOWN = 6,   /* CG found <p, A p> <= 0 or non-finite (indefinite tangent)    */
+  FFTNK_ENEWTON_MAXIT = 7,   /* Newton reached max_newton solves without convergence        */
+  FFTNK_ENONFINITE = 8,      /* NaN / Inf in the load, the iterate or a residual             */
+  FFTNK_EMATERIAL = 9,       /* constitutive update failed (e.g. return mapping)             */
+  FFTNK_EUNSUPPORTED = 10    /* grid length or configuration not supported by the kernels   */
+};
+
+/* precision of the Krylov solve (the Newton residual, F, P are always FP64) */
+enum { FFTNK_FP64 = 0, FFTNK_FP32_MIXED = 1 };
+
+/* material models */
+enum { FFTNK_SVK = 0, FFTNK_J2 = 1 };
+
+#define FFTNK_MAX_SOLVES 64
+
+/* statistics of one load increment of one RVE */
+typedef struct {
+  int status;                              /* FFTNK_* of this RVE                          */
+  int n_solves;                            /* linear solves (the boundary-condition solve included) */
+  int cg_iters[FFTNK_MAX_SOLVES];          /* CG iterations (operator applications) per solve */
+  double newton_res[FFTNK_MAX_SOLVES];     /* ||dF|| / ||F_t + dFbar|| after each solve    */
+  double cg_relres[FFTNK_MAX_SOLVES];      /* final recursive ||r|| / ||b|| of each solve   */
+  double t_ms;                             /* wall time of the call                          */
+} fftnk_stats;
+
+typedef struct fftnk_ctx fftnk_ctx;
+
+/*
+ * Create a context for one periodic cell of n0 x n1 x n2 voxels (each length
+ * 2..256; any factorisation: radices 2, 3, 4, 5, 7, 8 run as register
+ * butterflies, other primes as direct sums).  precision: FFTNK_FP64 or
+ * FFTNK_FP32_MIXED.  hip_stream: a hipStream_t (NULL = default stream).
+ * Returns FFTNK_EINVAL for bad sizes.  The context owns host memory only.
+ */
+int fftnk_create(fftnk_ctx** out, int n0, int n1, int n2, int precision, void* hip_stream);
+
+/*
+ * Create a context for nrve independent cells solved together (batching
+ * pattern); dims is a host array [nrve][3].  Each RVE has its own load,
+ * Newton and CG state; every kernel launch covers all RVEs.
+ */
+int fftnk_create_batched(fftnk_ctx** out, int nrve, const int* dims, int precision, void* hip_stream);
+
+/* Bytes of device workspace the context needs (256-byte aligned start). */
+size_t fftnk_workspace_bytes(const fftnk_ctx* ctx);
+
+/*
+ * Hand the context its workspace: dev must stay valid until the context is
+ * destroyed or rebound.  Resets the state to F_t = I (stress-free start,
+ * Algorithm 1's initialisation).  FFTNK_ENOMEM if bytes is too small.
+ */
+int fftnk_bind_workspace(fftnk_ctx* ctx, void* dev, size_t bytes);
+
+/* Phase index per voxel (device uint8 [n]; batched: concatenated).  Copied. */
+int fftnk_set_phases(fftnk_ctx* ctx, const uint8_t* phase_dev);
+
+/*
+ * Material (paper Sec. 4.2 for FFTNK_SVK: S = C:E, E = (F^T F - I)/2,
+ * P = F S with isotropic C from bulk modulus K and shear modulus mu,
+ * lambda = K - 2 mu/3; Sec. 5.2 for FFTNK_J2).  params_host holds, per phase,
+ * {K, mu} for SVK and {K, mu, tau_y0, H} for J2.  nphase <= 16.
+ */
+int fftnk_set_material(fftnk_ctx* ctx, int model, int nphase, const double* params_host);
+
+/*
+ * Optional per-voxel shear modulus mu(x) (device double [n]; copied) that
+ * replaces the phase value of mu; K stays per phase.  NULL switches it off.
+ */
+int fftnk_set_modulus_field(fftnk_ctx* ctx, const double* mu_dev);
+
+/* F_t := I (and virgin history): the start state of Algorithm 1. */
+int fftnk_reset_state(fftnk_ctx* ctx);
+
+/*
+ * One load increment of Algorithm 1 (Sec. 3.1-3.2) with the macroscopic
+ * deformation gradient prescribed: dFbar = Fbar - mean(F_t); the first solve
+ * G:K(F_t):dF = -G:K(F_t):dFbar distributes the load with the tangent of the
+ * start state, then Newton iterations G:K(F_i):dF = -G:P(F_i) until
+ * ||dF|| / ||F_t + dFbar|| < eta_nw (and at least two solves).  Each linear
+ * system is solved by CG to ||r|| <= eta_cg ||b|| (FP32_MIXED: at least 1e-6).
+ *
+ * Fbar_host [nrve][9]; F_dev, P_dev (optional, may be NULL): device double
+ * [9][n] receiving the converged F and P; Pbar_host [nrve][9] receives the
+ * voxel mean of P; stats (optional) [nrve].  On success the converged state is
+ * committed as the new F_t.  On any failure the committed state is unchanged
+ * and the outputs are undefined.
+ */
+int fftnk_solve_increment(fftnk_ctx* ctx, const double* Fbar_host, double eta_nw, double eta_cg, int max_newton,
+                          int max_cg, double* F_dev, double* P_dev, double* Pbar_host, fftnk_stats* stats);
+
+/*
+ * Linearisation point of fftnk_apply_operator: F (device double [9][n]) is
+ * copied into the context (and rounded to float in FP32_MIXED mode).
+ */
+int fftnk_set_linearization(fftnk_ctx* ctx, const double* F_dev);
+
+/*
+ * The projected-tangent operator (Sec. 2.6, eq. iter:system; Sec. 4.3):
+ * Ap = G( K(F) : p ), with the St. Venant-Kirchhoff tangent action
+ * dP = p S + F [lambda tr(F^T p) I + mu (F^T p + p^T F)] recomputed per voxel
+ * from the linearisation point F.  p, Ap: device [9][n] in context precision;
+ * they must not alias.
+ */
+int fftnk_apply_operator(fftnk_ctx* ctx, const void* p_dev, void* Ap_dev);
+
+/*
+ * The compatibility projection alone (Sec. 2.5; App. C for even axes):
+ * Ga = Re F^-1[ G-hat : F(a) ], (G-hat : A-hat)_ij = xi_j (sum_l xi_l A-hat_il)/|xi|^2,
+ * zero at k = 0 and on every even axis' Nyquist index.  a, Ga: device
+ * [9][n] in context precision; may alias.
+ */
+int fftnk_project(fftnk_ctx* ctx, const void* a_dev, void* Ga_dev);
+
+/*
+ * Constitutive update alone: P = P(F) per voxel (device double [9][n]) and
+ * the voxel mean Pbar_host [nrve][9].  For J2 the history of the last
+ * committed state is used and not modified.
+ */
+int fftnk_constitutive(fftnk_ctx* ctx, const double* F_dev, double* P_dev, double* Pbar_host);
+
+/*
+ * Instrumentation: enqueue pass `pass` (1..5) of the projected-tangent
+ * operator alone, on the context's internal buffers (pass 1 reads the internal
+ * direction field and the linearisation point, pass 5 writes the internal
+ * result field), without synchronising.  The passes are: 1 tangent action and
+ * a2 forward transform, 2 a1 forward, 3 a0 forward + projection + a0 inverse,
+ * 4 a1 inverse, 5 a2 inverse.  For timing a single kernel with stream events;
+ * results are meaningful only when the five run in order.
+ */
+int fftnk_launch_pass(fftnk_ctx* ctx, int pass);
+
+/* Checkpoint: copy out / in the committed F_t (device double [9][n]). */
+int fftnk_get_state(fftnk_ctx* ctx, double* F_dev);
+int fftnk_set_state(fftnk_ctx* ctx, const double* F_dev);
+
+/* Human-readable name of a status code (static string). */
+const char* fftnk_status_string(int status);
+
+/* Release the context's host memory (the workspace stays the caller's). */
+void fftnk_destroy(fftnk_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTNK_H */

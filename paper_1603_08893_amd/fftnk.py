@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libfftnk (include/fftnk.h).
+
+Argument marshalling only: every step of the solver runs in the HIP kernels of
+the library.  PyTorch supplies device memory (the workspace and all fields are
+torch tensors on ``cuda``) and the stream.  Importing works without a GPU; any
+call that needs the library raises ``FftnkError`` if it has not been built
+(``python -m paper_1603_08893_amd.build``) -- there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libfftnk.so")
+
+OK, EINVAL, ESTATE, ENOMEM, EHIP, ECG_MAXIT, ECG_BREAKDOWN, ENEWTON_MAXIT, ENONFINITE, EMATERIAL, EUNSUPPORTED = range(11)
+FP64, FP32_MIXED = 0, 1
+SVK, J2 = 0, 1
+MAX_SOLVES = 64
+
+# every symbol include/fftnk.h declares
+EXPORTS = [
+    "fftnk_create", "fftnk_create_batched", "fftnk_workspace_bytes", "fftnk_bind_workspace", "fftnk_set_phases",
+    "fftnk_set_material", "fftnk_set_modulus_field", "fftnk_reset_state", "fftnk_solve_increment",
+    "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_launch_pass",
+    "fftnk_get_state",
+    "fftnk_set_state", "fftnk_status_string", "fftnk_destroy",
+]
+
+
+class FftnkError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what, status_string(status), status))
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("n_solves", ctypes.c_int),
+        ("cg_iters", ctypes.c_int * MAX_SOLVES),
+        ("newton_res", ctypes.c_double * MAX_SOLVES),
+        ("cg_relres", ctypes.c_double * MAX_SOLVES),
+        ("t_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        k = self.n_solves
+        return {"status": self.status, "n_solves": k, "cg_iters": list(self.cg_iters[:k]),
+                "newton_res": list(self.newton_res[:k]), "cg_relres": list(self.cg_relres[:k]), "t_ms": self.t_ms}
+
+
+_lib = None
+
+
+def lib():
+    """Load libfftnk.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise FftnkError(EHIP, "libfftnk.so not built (run python -m paper_1603_08893_amd.build)")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.fftnk_create.argtypes = [ctypes.POINTER(vp), i, i, i, i, vp]
+    L.fftnk_create_batched.argtypes = [ctypes.POINTER(vp), i, ctypes.POINTER(i), i, vp]
+    L.fftnk_workspace_bytes.argtypes = [vp]
+    L.fftnk_workspace_bytes.restype = sz
+    L.fftnk_bind_workspace.argtypes = [vp, vp, sz]
+    L.fftnk_set_phases.argtypes = [vp, vp]
+    L.fftnk_set_material.argtypes = [vp, i, i, dp]
+    L.fftnk_set_modulus_field.argtypes = [vp, vp]
+    L.fftnk_reset_state.argtypes = [vp]
+    L.fftnk_solve_increment.argtypes = [vp, dp, d, d, i, i, vp, vp, dp, ctypes.POINTER(Stats)]
+    L.fftnk_set_linearization.argtypes = [vp, vp]
+    L.fftnk_apply_operator.argtypes = [vp, vp, vp]
+    L.fftnk_project.argtypes = [vp, vp, vp]
+    L.fftnk_constitutive.argtypes = [vp, vp, vp, dp]
+    L.fftnk_launch_pass.argtypes = [vp, i]
+    L.fftnk_get_state.argtypes = [vp, vp]
+    L.fftnk_set_state.argtypes = [vp, vp]
+    L.fftnk_status_string.argtypes = [i]
+    L.fftnk_status_string.restype = ctypes.c_char_p
+    L.fftnk_destroy.argtypes = [vp]
+    L.fftnk_destroy.restype = None
+    for name in EXPORTS:
+        getattr(L, name)
+    _lib = L
+    return L
+
+
+def status_string(s):
+    try:
+        return lib().fftnk_status_string(int(s)).decode()
+    except FftnkError:
+        return "status %d" % s
+
+
+def _check(status, what):
+    if status != OK:
+        raise FftnkError(status, what)
+
+
+def _dptr(a):
+    return ctypes.cast(ctypes.c_void_p(a.ctypes.data), ctypes.POINTER(ctypes.c_double))
+
+
+class Solver:
+    """One fftnk context: a periodic cell (or a batch of cells) on one GPU.
+
+    dims: (n0, n1, n2) or a list of them (batched).  precision: "fp64" or
+    "fp32" (FP32 Krylov solve, FP64 Newton residual).
+    """
+
+    def __init__(self, dims, precision="fp64", device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        if isinstance(dims[0], (int, np.integer)):
+            dims = [tuple(int(v) for v in dims)]
+        self.dims = [tuple(int(v) for v in d) for d in dims]
+        self.nrve = len(self.dims)
+        self.n = [d[0] * d[1] * d[2] for d in self.dims]
+        self.ntot = sum(self.n)
+        self.precision = precision
+        self.prec = FP64 if precision == "fp64" else FP32_MIXED
+        self.vdtype = torch.float64 if self.prec == FP64 else torch.float32
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L = lib()
+        ctx = ctypes.c_void_p()
+        arr = (ctypes.c_int * (3 * self.nrve))(*[v for d in self.dims for v in d])
+        _check(L.fftnk_create_batched(ctypes.byref(ctx), self.nrve, arr, self.prec,
+                                      ctypes.c_void_p(self.stream.cuda_stream)), "fftnk_create_batched")
+        self.ctx = ctx
+        nbytes = L.fftnk_workspace_bytes(ctx)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        _check(L.fftnk_bind_workspace(ctx, ctypes.c_void_p(aligned), nbytes), "fftnk_bind_workspace")
+        self.workspace_bytes = nbytes
+
+    def __del__(self):
+        if getattr(self, "ctx", None) is not None and _lib is not None:
+            _lib.fftnk_destroy(self.ctx)
+            self.ctx = None
+
+    # ------------------------------------------------------------ set-up
+    def field(self, dtype=None):
+        return self.torch.empty(9 * self.ntot, dtype=dtype or self.vdtype, device=self.device)
+
+    def set_phases(self, phase):
+        ph = np.ascontiguousarray(phase, dtype=np.uint8).reshape(-1)
+        if ph.size != self.ntot:
+            raise FftnkError(EINVAL, "set_phases: %d values for %d voxels" % (ph.size, self.ntot))
+        self._max_phase = int(ph.max())
+        if getattr(self, "_nphase", None) is not None and self._max_phase >= self._nphase:
+            raise FftnkError(EINVAL, "set_phases: phase index beyond the material table")
+        t = self.torch.as_tensor(ph).to(self.device)
+        self._phase = t
+        _check(lib().fftnk_set_phases(self.ctx, ctypes.c_void_p(t.data_ptr())), "fftnk_set_phases")
+
+    def set_material(self, table, model=SVK):
+        tab = np.ascontiguousarray(table, dtype=np.float64)
+        if getattr(self, "_max_phase", None) is not None and self._max_phase >= tab.shape[0]:
+            raise FftnkError(EINVAL, "set_material: fewer phases than the phase map uses")
+        self._nphase = tab.shape[0]
+        _check(lib().fftnk_set_material(self.ctx, model, tab.shape[0], _dptr(tab)), "fftnk_set_material")
+
+    def set_modulus_field(self, mu):
+        if mu is None:
+            _check(lib().fftnk_set_modulus_field(self.ctx, None), "fftnk_set_modulus_field")
+            return
+        t = self.torch.as_tensor(np.ascontiguousarray(mu, dtype=np.float64).reshape(-1)).to(self.device)
+        assert t.numel() == self.ntot
+        _check(lib().fftnk_set_modulus_field(self.ctx, ctypes.c_void_p(t.data_ptr())), "fftnk_set_modulus_field")
+
+    def reset_state(self):
+        _check(lib().fftnk_reset_state(self.ctx), "fftnk_reset_state")
+
+    # ------------------------------------------------------------ solve
+    def solve_increment(self, Fbar, eta_nw=1e-5, eta_cg=1e-8, max_newton=50, max_cg=10000, fields=True,
+                        raise_on_error=True):
+        """One load increment.  Returns (status, F, P, Pbar[nrve, 9], stats list)."""
+        Fb = np.ascontiguousarray(np.asarray(Fbar, dtype=np.float64).reshape(self.nrve, 9))
+        Pbar = np.zeros((self.nrve, 9))
+        stats = (Stats * self.nrve)()
+        F = self.field(self.torch.float64) if fields else None
+        P = self.field(self.torch.float64) if fields else None
+        st = lib().fftnk_solve_increment(self.ctx, _dptr(Fb), eta_nw, eta_cg, max_newton, max_cg,
+                                         ctypes.c_void_p(F.data_ptr()) if fields else None,
+                                         ctypes.c_void_p(P.data_ptr()) if fields else None,
+                                         _dptr(Pbar), stats)
+        if raise_on_error:
+            _check(st, "fftnk_solve_increment")
+        return st, F, P, Pbar, [s.as_dict() for s in stats]
+
+    def set_linearization(self, F):
+        F = F.to(self.device, self.torch.float64).contiguous()
+        _check(lib().fftnk_set_linearization(self.ctx, ctypes.c_void_p(F.data_ptr())), "fftnk_set_linearization")
+
+    def apply_operator(self, p, out=None):
+        p = p.to(self.device, self.vdtype).contiguous()
+        out = self.field() if out is None else out
+        _check(lib().fftnk_apply_operator(self.ctx, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(out.data_ptr())),
+               "fftnk_apply_operator")
+        return out
+
+    def project(self, a, out=None):
+        a = a.to(self.device, self.vdtype).contiguous()
+        out = self.field() if out is None else out
+        _check(lib().fftnk_project(self.ctx, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(out.data_ptr())),
+               "fftnk_project")
+        return out
+
+    def constitutive(self, F):
+        F = F.to(self.device, self.torch.float64).contiguous()
+        P = self.field(self.torch.float64)
+        Pbar = np.zeros((self.nrve, 9))
+        _check(lib().fftnk_constitutive(self.ctx, ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(P.data_ptr()),
+                                        _dptr(Pbar)), "fftnk_constitutive")
+        return P, Pbar
+
+    def launch_pass(self, k):
+        """Enqueue pass k (1..5) of the operator alone (timing instrumentation)."""
+        _check(lib().fftnk_launch_pass(self.ctx, int(k)), "fftnk_launch_pass")
+
+    def get_state(self):
+        F = self.field(self.torch.float64)
+        _check(lib().fftnk_get_state(self.ctx, ctypes.c_void_p(F.data_ptr())), "fftnk_get_state")
+        return F
+
+    def set_state(self, F):
+        F = F.to(self.device, self.torch.float64).contiguous()
+        _check(lib().fftnk_set_state(self.ctx, ctypes.c_void_p(F.data_ptr())), "fftnk_set_state")

@@ -1,0 +1,210 @@
+"""Parity of the HIP library with the FP64 oracle, through the C-ABI.
+
+Kernel level (same inputs to both sides): the projection G, the projected-
+tangent operator A p = G(K(F):p), the constitutive update.  FP64 bar: relative
+L2 error <= 1e-13 (a DFT of this size accumulates a few 1e-16 per stage);
+FP32 bar: <= 5e-6 (float rounding of the data plus ~log2 n stages of FFT).
+Sizes cover odd/prime (31, 5, 7), even (8, 32, 128), mixed radix (24, 48, 96),
+non-cubic grids and several tiles with ragged tails.
+
+Solve level: one increment of the cubic-inclusion cell (31^3) and of a random
+two-phase cell; equal Newton counts, CG counts within +-2 per solve, P-bar within
+1e-10 relative (FP64) and 1e-5 (FP32 Krylov solve with FP64 residual).
+"""
+import numpy as np
+import pytest
+
+from paper_1603_08893_amd import microstructure as ms
+
+pytestmark = pytest.mark.gpu
+
+TABLE = [(ms.K_SOFT, ms.MU_SOFT), (ms.K_HARD, ms.MU_HARD)]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _solver(dims, prec, phase=None, table=TABLE):
+    from paper_1603_08893_amd.fftnk import Solver
+    s = Solver(dims, precision=prec)
+    if phase is None:
+        phase = np.zeros(dims, dtype=np.uint8)
+    s.set_phases(phase)
+    s.set_material(table)
+    return s
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+SHAPES = [(5, 5, 5), (8, 8, 8), (7, 6, 9), (24, 24, 24), (31, 31, 31), (32, 32, 32), (12, 10, 17), (48, 40, 36),
+          (3, 64, 4)]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_project_parity(torch_cuda, orc, shape, prec, tol):
+    torch = torch_cuda
+    print("project", shape, prec, flush=True)
+    A = ms.random_field(shape, seed=sum(shape))
+    ref = orc.project(A)
+    s = _solver(shape, prec)
+    got = s.project(torch.from_numpy(A.reshape(-1))).double().cpu().numpy()
+    torch.cuda.synchronize()
+    assert _rel(got, ref) <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_apply_operator_parity(torch_cuda, orc, shape, prec, tol):
+    torch = torch_cuda
+    print("apply_operator", shape, prec, flush=True)
+    rng = np.random.default_rng(7)
+    ph = rng.integers(0, 2, size=shape).astype(np.uint8)
+    K, mu = ms.phase_moduli(ph, TABLE)
+    F = ms.near_identity_field(shape, seed=3, scale=0.05)
+    p = ms.random_field(shape, seed=4)
+    ref = orc.apply_operator(F, K, mu, p)
+    s = _solver(shape, prec, ph)
+    s.set_linearization(torch.from_numpy(F.reshape(-1)))
+    got = s.apply_operator(torch.from_numpy(p.reshape(-1))).double().cpu().numpy()
+    assert _rel(got, ref) <= tol
+
+
+def test_constitutive_parity(torch_cuda, orc):
+    torch = torch_cuda
+    shape = (9, 10, 11)
+    rng = np.random.default_rng(8)
+    ph = rng.integers(0, 2, size=shape).astype(np.uint8)
+    K, mu = ms.phase_moduli(ph, TABLE)
+    F = ms.near_identity_field(shape, seed=9, scale=0.2)
+    ref = orc.svk_stress(F, K, mu)
+    s = _solver(shape, "fp64", ph)
+    P, Pbar = s.constitutive(torch.from_numpy(F.reshape(-1)))
+    assert _rel(P.cpu().numpy(), ref) <= 1e-14
+    assert np.max(np.abs(Pbar[0] - ref.reshape(9, -1).mean(axis=1))) <= 1e-15
+
+
+def test_gpu_projection_invariants_128(torch_cuda):
+    torch = torch_cuda
+    shape = (128, 128, 128)
+    s = _solver(shape, "fp64")
+    A = torch.from_numpy(ms.random_field(shape, seed=1).reshape(-1)).cuda()
+    GA = s.project(A)
+    GGA = s.project(GA)
+    scale = GA.abs().max().item()
+    assert (GGA - GA).abs().max().item() <= 1e-13 * scale
+    assert GA.view(9, -1).mean(dim=1).abs().max().item() <= 1e-15 * scale
+    # self-adjoint
+    B = torch.from_numpy(ms.random_field(shape, seed=2).reshape(-1)).cuda()
+    GB = s.project(B)
+    assert abs((B * GA).sum().item() - (GB * A).sum().item()) <= 1e-11 * abs((B * GA).sum().item())
+
+
+def test_project_parity_128_sampled(torch_cuda, orc):
+    """Full 128^3 size: the oracle's projection of the same field."""
+    torch = torch_cuda
+    shape = (128, 128, 128)
+    A = ms.random_field(shape, seed=5)
+    ref = orc.project(A)
+    for prec, tol in [("fp64", 1e-13), ("fp32", 5e-6)]:
+        s = _solver(shape, prec)
+        got = s.project(torch.from_numpy(A.reshape(-1))).double().cpu().numpy()
+        assert _rel(got, ref) <= tol, prec
+
+
+def _solve_both(orc, torch, shape, ph, Fbar, prec, eta_nw=1e-5, eta_cg=1e-8):
+    K, mu = ms.phase_moduli(ph, TABLE)
+    st, Fo, Po, Pbar_o, So = orc.solve_increment(K, mu, orc.identity_field(shape), Fbar, eta_nw, eta_cg)
+    assert st == 0
+    s = _solver(shape, prec, ph)
+    stg, F, P, Pbar, S = s.solve_increment(Fbar, eta_nw, eta_cg)
+    return (Fo, Po, Pbar_o, So), (F.cpu().numpy(), P.cpu().numpy(), Pbar[0], S[0]), s
+
+
+def test_solve_cubic_inclusion_fp64(torch_cuda, orc):
+    torch = torch_cuda
+    N = 31
+    ph = ms.cubic_inclusion(N)
+    (Fo, Po, Pbo, So), (F, P, Pb, S), _ = _solve_both(orc, torch, (N, N, N), ph, ms.simple_shear(0.05), "fp64")
+    print("oracle", So["cg_iters"], "gpu", S["cg_iters"], flush=True)
+    assert S["n_solves"] == So["n_solves"]
+    assert all(abs(a - b) <= 2 for a, b in zip(S["cg_iters"], So["cg_iters"]))
+    assert np.max(np.abs(Pb - Pbo)) <= 1e-10 * np.max(np.abs(Pbo))
+    assert _rel(F, Fo) <= 1e-8
+    assert _rel(P, Po) <= 1e-8
+
+
+def test_solve_cubic_inclusion_fp32_mixed(torch_cuda, orc):
+    torch = torch_cuda
+    N = 31
+    ph = ms.cubic_inclusion(N)
+    (Fo, Po, Pbo, So), (F, P, Pb, S), _ = _solve_both(orc, torch, (N, N, N), ph, ms.simple_shear(0.05), "fp32")
+    print("oracle", So["cg_iters"], "gpu fp32", S["cg_iters"], flush=True)
+    assert np.max(np.abs(Pb - Pbo)) <= 1e-5 * np.max(np.abs(Pbo))
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 16), (15, 12, 9)])
+def test_solve_random_two_phase_fp64(torch_cuda, orc, shape):
+    torch = torch_cuda
+    ph = (np.random.default_rng(4).random(shape) < 0.3).astype(np.uint8)
+    Fbar = ms.tensor(np.eye(3) + np.array([[0.02, 0.03, 0.0], [0.0, -0.01, 0.02], [0.01, 0.0, 0.01]]))
+    (Fo, Po, Pbo, So), (F, P, Pb, S), _ = _solve_both(orc, torch, shape, ph, Fbar, "fp64")
+    assert S["n_solves"] == So["n_solves"]
+    assert all(abs(a - b) <= 2 for a, b in zip(S["cg_iters"], So["cg_iters"]))
+    assert np.max(np.abs(Pb - Pbo)) <= 1e-10 * np.max(np.abs(Pbo))
+    assert _rel(F, Fo) <= 1e-8
+
+
+def test_solve_homogeneous_and_errors(torch_cuda):
+    torch = torch_cuda
+    from paper_1603_08893_amd.fftnk import ECG_MAXIT, ENONFINITE
+    shape = (8, 8, 8)
+    s = _solver(shape, "fp64")
+    Fbar = ms.simple_shear(0.1)
+    st, F, P, Pbar, S = s.solve_increment(Fbar)
+    assert S[0]["cg_iters"] == [0, 0]
+    assert (F.view(9, -1) - torch.from_numpy(Fbar).cuda()[:, None]).abs().max().item() < 1e-15
+    # failures leave the committed state untouched
+    ph = ms.cubic_inclusion(8, 3)
+    s2 = _solver(shape, "fp64", ph)
+    F0 = s2.get_state().clone()
+    st, *_ = s2.solve_increment(Fbar, max_cg=1, raise_on_error=False)
+    assert st == ECG_MAXIT
+    assert torch.equal(s2.get_state(), F0)
+    st, *_ = s2.solve_increment(np.full(9, np.nan), raise_on_error=False)
+    assert st == ENONFINITE
+    assert torch.equal(s2.get_state(), F0)
+
+
+def test_two_increments_state_commit(torch_cuda, orc):
+    torch = torch_cuda
+    N = 9
+    shape = (N, N, N)
+    ph = ms.cubic_inclusion(N, 3)
+    K, mu = ms.phase_moduli(ph, TABLE)
+    s = _solver(shape, "fp64", ph)
+    F = orc.identity_field(shape)
+    for g in [0.03, 0.06]:
+        st, F, _, Pbo, So = orc.solve_increment(K, mu, F, ms.simple_shear(g))
+        _, _, _, Pb, S = s.solve_increment(ms.simple_shear(g))
+        assert S[0]["n_solves"] == So["n_solves"]
+        assert np.max(np.abs(Pb[0] - Pbo)) <= 1e-10 * np.max(np.abs(Pbo))
+    assert _rel(s.get_state().cpu().numpy(), F) <= 1e-8
+
+
+def test_bitwise_repeatable(torch_cuda):
+    torch = torch_cuda
+    shape = (32, 32, 32)
+    ph = ms.cubic_inclusion(32, 9)
+    s = _solver(shape, "fp64", ph)
+    _, F1, _, P1, _ = s.solve_increment(ms.simple_shear(0.05))
+    s.reset_state()
+    _, F2, _, P2, _ = s.solve_increment(ms.simple_shear(0.05))
+    assert torch.equal(F1, F2) and np.array_equal(P1, P2)
