@@ -163,6 +163,21 @@ int fftnk_project(fftnk_ctx* ctx, const void* a_dev, void* Ga_dev);
 int fftnk_constitutive(fftnk_ctx* ctx, const double* F_dev, double* P_dev, double* Pbar_host);
 
 /*
+ * Adjoint sensitivity of the homogenised stress at the last committed state
+ * (not in the paper; derived from its boundary-condition system, Sec. 3.1,
+ * and the symmetry of G, Sec. 2.3).  For each RVE r with cotangent
+ * g_r = dL/dPbar_r (gbar_host [nrve][9]) one CG solve with the same operator
+ * at F_t gives the adjoint field w in range(G): A w = G(K(F_t) : g_r); then per
+ * voxel  dL/dmu(x) = (1/n)(g_r - w(x)) : F.2dev(E)  and
+ *        dL/dK(x)  = (1/n)(g_r - w(x)) : tr(E) F.
+ * dLdmu_dev / dLdK_dev (device double [n], batched: concatenated per RVE;
+ * dLdK_dev may be NULL) are overwritten.  Parameters of the CG as in
+ * fftnk_solve_increment; stats (optional) [nrve] gets one solve per RVE.
+ */
+int fftnk_adjoint(fftnk_ctx* ctx, const double* gbar_host, double eta_cg, int max_cg, double* dLdmu_dev,
+                  double* dLdK_dev, fftnk_stats* stats);
+
+/*
  * Instrumentation: enqueue pass `pass` (1..5) of the projected-tangent
  * operator alone, on the context's internal buffers (pass 1 reads the internal
  * direction field and the linearisation point, pass 5 writes the internal

@@ -80,6 +80,8 @@ def lib():
         L.orc_solve_increment.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                           i, i, dp, dp, ctypes.POINTER(Stats)]
         L.orc_solve_increment.restype = i
+        L.orc_adjoint.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, i, dp, dp, ctypes.POINTER(i)]
+        L.orc_adjoint.restype = i
         _lib = L
     return _lib
 
@@ -188,6 +190,23 @@ def identity_field(shape):
     F = np.zeros((9,) + tuple(shape))
     F[0] = F[4] = F[8] = 1.0
     return F
+
+
+def adjoint(K, mu, F, g, eta_cg=1e-8, max_cg=10000):
+    """dL/dmu(x), dL/dK(x) for the cotangent g = dL/dPbar at the converged F.
+
+    Returns (status, dLdmu, dLdK, cg_iterations), fields shaped like the grid."""
+    F = _c(F)
+    grid = F.shape[1:]
+    K = _c(np.broadcast_to(K, grid))
+    mu = _c(np.broadcast_to(mu, grid))
+    g = _c(np.asarray(g, dtype=np.float64).reshape(9))
+    dmu = np.zeros(grid)
+    dK = np.zeros(grid)
+    it = ctypes.c_int(0)
+    st = lib().orc_adjoint(grid[0], grid[1], grid[2], _p(K), _p(mu), _p(F), _p(g), eta_cg, max_cg, _p(dmu),
+                           _p(dK), ctypes.byref(it))
+    return st, dmu, dK, it.value
 
 
 def solve_increment(K, mu, F, Fbar, eta_nw=1e-5, eta_cg=1e-8, max_newton=50, max_cg=10000):

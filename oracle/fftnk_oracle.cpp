@@ -527,6 +527,62 @@ int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* m
   return ORC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint sensitivity of the homogenised stress (not in the paper; derived from
+// the boundary-condition system of Sec. 3.1 and the symmetry of G, Sec. 2.3).
+//
+// At a converged state, G(P(F, mu)) = 0 with F - Fbar in range(G).  A change
+// dmu moves P-bar = mean P by mean(K dF + Q dmu), Q = dP/dmu at fixed F, where
+// dF in range(G) solves A dF = -G(Q dmu), A = G K.  For a cotangent g (a 3x3
+// tensor, dL/dP-bar) the adjoint field w in range(G) solves
+//     A w = G(K : g)        (K : g = tangent action on the uniform field g),
+// and then, because A is symmetric on range(G),
+//     dL/dmu(x) = (1/n) (g - w(x)) : Q_mu(x),   Q_mu = F . 2 dev(E),
+//     dL/dK(x)  = (1/n) (g - w(x)) : Q_K(x),    Q_K  = tr(E) F,
+// (S = (K - 2 mu/3) tr(E) I + 2 mu E, so dS/dmu = 2 dev E, dS/dK = tr(E) I).
+// F is the converged deformation gradient; K, mu the per-voxel moduli.
+// Returns the CG status; *iters the CG iterations.
+// ---------------------------------------------------------------------------
+int orc_adjoint(int n0, int n1, int n2, const double* K, const double* mu, const double* F, const double* g,
+                double eta_cg, int max_cg, double* dLdmu, double* dLdK, int* iters) {
+  const long n = (long)n0 * n1 * n2, m = 9 * n;
+  orc_problem pb{n0, n1, n2, K, mu};
+  std::vector<double> U(m), Y(m), b(m), w(m);
+  for (int c = 0; c < 9; ++c)
+    for (long v = 0; v < n; ++v) U[c * n + v] = g[c];
+  orc_svk_tangent(n, F, K, mu, U.data(), Y.data());
+  orc_project(n0, n1, n2, Y.data(), b.data());
+  double relres = 0.0;
+  const int st = cg_or_zero(pb, F, b.data(), Y.data(), w.data(), eta_cg, max_cg, iters, &relres);
+  if (st != ORC_OK) return st;
+  for (long v = 0; v < n; ++v) {
+    double f[9];
+    mat_get(F, n, v, f);
+    double E[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += f[3 * k + i] * f[3 * k + j];
+        E[3 * i + j] = 0.5 * (s - (i == j ? 1.0 : 0.0));
+      }
+    const double trE = E[0] + E[4] + E[8];
+    double D[9];  // 2 dev(E)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) D[3 * i + j] = 2.0 * (E[3 * i + j] - (i == j ? trE / 3.0 : 0.0));
+    double Qmu[9];
+    matmul(f, D, Qmu);
+    double smu = 0.0, sK = 0.0;
+    for (int c = 0; c < 9; ++c) {
+      const double a = g[c] - w[c * n + v];
+      smu += a * Qmu[c];
+      sK += a * trE * f[c];
+    }
+    dLdmu[v] = smu / (double)n;
+    if (dLdK) dLdK[v] = sK / (double)n;
+  }
+  return ORC_OK;
+}
+
 // Exposed for tests: plain CG on the operator at a given linearisation point.
 int orc_cg(int n0, int n1, int n2, const double* K, const double* mu, const double* Flin, const double* b,
            double* x, double eta, int max_cg, int* iters, double* relres) {

@@ -250,12 +250,13 @@ void middle_passes(fftnk_ctx* c, int prec, const PassArgs& a, const CgState* cg)
 
 // b = -G(Y) in FP64, written to r (context precision) with x = 0;
 // partials: ||Y||^2 in SLOT_YY, ||b||^2 in SLOT_BB.
-void rhs_pipeline(fftnk_ctx* c, int r, int mode, const double* Y, const double* Flin, const double* uni) {
+void rhs_pipeline(fftnk_ctx* c, int r, int mode, const double* Y, const double* Flin, const double* uni,
+                  double sign = -1.0) {
   const PassArgs a = c->args(r);
   const Material m = c->material();
   launch_fwd_a2(PREC_F64, mode, a, m, Y, nullptr, nullptr, Flin, uni, 1.0, c->spec(), nullptr, c->stream);
   middle_passes(c, PREC_F64, a, nullptr);
-  launch_inv_a2(PREC_F64, INV_RHS, a, c->spec(), c->r(), c->prec, nullptr, c->x(), -1.0, nullptr, c->stream);
+  launch_inv_a2(PREC_F64, INV_RHS, a, c->spec(), c->r(), c->prec, nullptr, c->x(), sign, nullptr, c->stream);
 }
 
 // CG on A = G K(Flin) with right-hand side r (x = 0 on entry).
@@ -540,6 +541,55 @@ int fftnk_apply_operator(fftnk_ctx* c, const void* p_dev, void* Ap_dev) {
     launch_inv_a2(c->prec, INV_OUT, a, c->spec(), Ap_dev, c->prec, nullptr, nullptr, 1.0, nullptr, c->stream);
   }
   return check_launch();
+}
+
+int fftnk_adjoint(fftnk_ctx* c, const double* gbar, double eta_cg, int max_cg, double* dLdmu, double* dLdK,
+                  fftnk_stats* stats) {
+  if (!c || !gbar || !dLdmu || !(eta_cg > 0) || max_cg < 1) return FFTNK_EINVAL;
+  if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
+  const size_t bytes = (size_t)c->ntot * sizeof(double);
+  HIP_TRY(hipMemsetAsync(dLdmu, 0, bytes, c->stream));
+  if (dLdK) HIP_TRY(hipMemsetAsync(dLdK, 0, bytes, c->stream));
+  const double eta_eff = c->prec == PREC_F32 ? std::max(eta_cg, 1e-6) : eta_cg;
+  int worst = FFTNK_OK;
+  for (int r = 0; r < c->nrve; ++r) {
+    const PassArgs a = c->args(r);
+    const Grid& g = a.g;
+    fftnk_stats local;
+    fftnk_stats* st = stats ? &stats[r] : &local;
+    std::memset(st, 0, sizeof(*st));
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(gbar[9 * r + k])) return FFTNK_ENONFINITE;
+    // b = +G(K(F_t) : g), adjoint of the boundary-condition system
+    rhs_pipeline(c, r, FWD_TANGENT_UNI, nullptr, c->Ft(), gbar + 9 * r, +1.0);
+    if (c->prec == PREC_F32)
+      launch_convert(PREC_F32, c->Ft() + 9 * g.vox_off, c->F32() + 9 * g.vox_off, 9 * g.n, c->stream);
+    launch_reduce(a, SLOT_YY, 1, fwd_a2_blocks(g), c->red() + 0, c->stream);
+    launch_reduce(a, SLOT_BB, 1, inv_a2_blocks(g), c->red() + 1, c->stream);
+    int e = check_launch();
+    if (!e) e = fetch(c, c->red(), 2 * sizeof(double));
+    if (e) return e;
+    const double yy = c->pinned[0], bb = c->pinned[1];
+    int iters = 0;
+    double relres = 0.0;
+    if (!std::isfinite(bb)) return FFTNK_ENONFINITE;
+    if (!(std::sqrt(bb) <= 1e-14 * std::sqrt(yy) || bb == 0.0)) {
+      const void* Flin = c->prec == PREC_F32 ? static_cast<const void*>(c->F32()) : static_cast<const void*>(c->Ft());
+      e = run_cg(c, r, Flin, eta_eff, max_cg, &iters, &relres);
+    }
+    st->n_solves = 1;
+    st->cg_iters[0] = iters;
+    st->cg_relres[0] = relres;
+    st->status = e;
+    if (e) {
+      if (!worst) worst = e;
+      continue;
+    }
+    launch_adjoint_grad(c->prec, a, c->Ft(), c->x(), gbar + 9 * r, dLdmu, dLdK, g.vox_off, c->stream);
+  }
+  const int e = check_launch();
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return worst ? worst : e;
 }
 
 int fftnk_launch_pass(fftnk_ctx* c, int pass) {

@@ -138,6 +138,8 @@ void launch_reduce(const PassArgs& a, int slot0, int nslots, int nblk, double* o
 void launch_convert(int to_prec, const void* in, void* out, long long count, hipStream_t s);
 void launch_fill_zero(int prec, void* x, long long count, hipStream_t s);
 void launch_set_identity(const PassArgs& a, double* F, hipStream_t s);
+void launch_adjoint_grad(int prec, const PassArgs& a, const double* F, const void* w, const double* g, double* dmu,
+                         double* dK, long long out_off, hipStream_t s);
 
 int fwd_a2_blocks(const Grid& g);
 int elem_blocks_vox(const Grid& g);

@@ -873,6 +873,48 @@ __global__ __launch_bounds__(kThreads) void k_fill_zero(T* __restrict__ x, long 
     x[i] = (T)0;
 }
 
+// Adjoint gradient per voxel at the converged F with adjoint field w:
+//   dL/dmu = (1/n) (g - w) : F . 2 dev(E),  dL/dK = (1/n) (g - w) : tr(E) F
+// (S = (K - 2mu/3) tr(E) I + 2 mu E).  Accumulates (+=) so that several load
+// cases on one modulus field add up.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_adjoint_grad(PassArgs a, const double* __restrict__ F,
+                                                           const T* __restrict__ w, Uni9 g,
+                                                           double* __restrict__ dmu, double* __restrict__ dK,
+                                                           long long out_off) {
+  const long long n = a.g.n, off = 9 * a.g.vox_off;
+  for (long long v = blockIdx.x * (long long)kThreads + threadIdx.x; v < n; v += (long long)gridDim.x * kThreads) {
+    double f[9], d[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      f[c] = F[off + c * n + v];
+      d[c] = g.v[c] - (double)w[off + c * n + v];
+    }
+    double C[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) C[3 * i + j] = f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j];
+    const double trE = 0.5 * (C[0] + C[4] + C[8] - 3.0);
+    double D[9];  // 2 dev E = C - I - (2/3) tr(E) I
+#pragma unroll
+    for (int c = 0; c < 9; ++c) D[c] = C[c];
+    D[0] -= 1.0 + 2.0 * trE / 3.0;
+    D[4] -= 1.0 + 2.0 * trE / 3.0;
+    D[8] -= 1.0 + 2.0 * trE / 3.0;
+    double Q[9];
+    mat33<double>(f, D, Q);
+    double smu = 0.0, sK = 0.0;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      smu += d[c] * Q[c];
+      sK += d[c] * f[c];
+    }
+    dmu[out_off + v] += smu * a.g.inv_n;
+    if (dK) dK[out_off + v] += sK * trE * a.g.inv_n;
+  }
+}
+
 // F = I on every voxel of one RVE (the stress-free start of Algorithm 1).
 __global__ __launch_bounds__(kThreads) void k_set_identity(PassArgs a, double* __restrict__ F) {
   const long long n = a.g.n, off = 9 * a.g.vox_off;
@@ -1052,6 +1094,19 @@ void launch_convert(int to_prec, const void* in, void* out, long long count, hip
   else
     hipLaunchKernelGGL((k_convert<float, double>), dim3(nb), dim3(kThreads), 0, s, static_cast<const float*>(in),
                        static_cast<double*>(out), count);
+}
+
+void launch_adjoint_grad(int prec, const PassArgs& a, const double* F, const void* w, const double* g, double* dmu,
+                         double* dK, long long out_off, hipStream_t s) {
+  Uni9 u{};
+  for (int c = 0; c < 9; ++c) u.v[c] = g[c];
+  const int nb = elem_blocks(a.g.n);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL((k_adjoint_grad<double>), dim3(nb), dim3(kThreads), 0, s, a, F, static_cast<const double*>(w),
+                       u, dmu, dK, out_off);
+  else
+    hipLaunchKernelGGL((k_adjoint_grad<float>), dim3(nb), dim3(kThreads), 0, s, a, F, static_cast<const float*>(w),
+                       u, dmu, dK, out_off);
 }
 
 void launch_set_identity(const PassArgs& a, double* F, hipStream_t s) {

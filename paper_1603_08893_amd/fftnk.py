@@ -22,8 +22,8 @@ MAX_SOLVES = 64
 EXPORTS = [
     "fftnk_create", "fftnk_create_batched", "fftnk_workspace_bytes", "fftnk_bind_workspace", "fftnk_set_phases",
     "fftnk_set_material", "fftnk_set_modulus_field", "fftnk_reset_state", "fftnk_solve_increment",
-    "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_launch_pass",
-    "fftnk_get_state",
+    "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_adjoint",
+    "fftnk_launch_pass", "fftnk_get_state",
     "fftnk_set_state", "fftnk_status_string", "fftnk_destroy",
 ]
 
@@ -77,6 +77,7 @@ def lib():
     L.fftnk_apply_operator.argtypes = [vp, vp, vp]
     L.fftnk_project.argtypes = [vp, vp, vp]
     L.fftnk_constitutive.argtypes = [vp, vp, vp, dp]
+    L.fftnk_adjoint.argtypes = [vp, dp, d, i, vp, vp, ctypes.POINTER(Stats)]
     L.fftnk_launch_pass.argtypes = [vp, i]
     L.fftnk_get_state.argtypes = [vp, vp]
     L.fftnk_set_state.argtypes = [vp, vp]
@@ -171,8 +172,12 @@ class Solver:
         if mu is None:
             _check(lib().fftnk_set_modulus_field(self.ctx, None), "fftnk_set_modulus_field")
             return
-        t = self.torch.as_tensor(np.ascontiguousarray(mu, dtype=np.float64).reshape(-1)).to(self.device)
-        assert t.numel() == self.ntot
+        if isinstance(mu, self.torch.Tensor):
+            t = mu.detach().reshape(-1).to(self.device, self.torch.float64).contiguous()
+        else:
+            t = self.torch.as_tensor(np.ascontiguousarray(mu, dtype=np.float64).reshape(-1)).to(self.device)
+        if t.numel() != self.ntot:
+            raise FftnkError(EINVAL, "set_modulus_field: %d values for %d voxels" % (t.numel(), self.ntot))
         _check(lib().fftnk_set_modulus_field(self.ctx, ctypes.c_void_p(t.data_ptr())), "fftnk_set_modulus_field")
 
     def reset_state(self):
@@ -221,6 +226,16 @@ class Solver:
                                         _dptr(Pbar)), "fftnk_constitutive")
         return P, Pbar
 
+    def adjoint(self, gbar, eta_cg=1e-8, max_cg=10000, want_K=False):
+        """dL/dmu (and dL/dK) per voxel, [ntot] device doubles, for cotangents gbar [nrve, 9]."""
+        g = np.ascontiguousarray(np.asarray(gbar, dtype=np.float64).reshape(self.nrve, 9))
+        dmu = self.torch.empty(self.ntot, dtype=self.torch.float64, device=self.device)
+        dK = self.torch.empty(self.ntot, dtype=self.torch.float64, device=self.device) if want_K else None
+        stats = (Stats * self.nrve)()
+        _check(lib().fftnk_adjoint(self.ctx, _dptr(g), eta_cg, max_cg, ctypes.c_void_p(dmu.data_ptr()),
+                                   ctypes.c_void_p(dK.data_ptr()) if want_K else None, stats), "fftnk_adjoint")
+        return dmu, dK, [s.as_dict() for s in stats]
+
     def launch_pass(self, k):
         """Enqueue pass k (1..5) of the operator alone (timing instrumentation)."""
         _check(lib().fftnk_launch_pass(self.ctx, int(k)), "fftnk_launch_pass")
@@ -233,3 +248,49 @@ class Solver:
     def set_state(self, F):
         F = F.to(self.device, self.torch.float64).contiguous()
         _check(lib().fftnk_set_state(self.ctx, ctypes.c_void_p(F.data_ptr())), "fftnk_set_state")
+
+
+def _autograd_function():
+    import torch
+
+    class HomogenizedStress(torch.autograd.Function):
+        """P-bar of one load increment from the stress-free state, for each load
+        case, as a differentiable function of the per-voxel shear modulus.
+
+        forward(mu [N0, N1, N2] float64 cuda, solver, Fbars [nrve, 9]) -> Pbar [nrve, 9]
+        The solver's RVEs share the modulus field (one load case per RVE, same
+        grid).  backward runs fftnk_adjoint (one CG per load case at the
+        converged states) and sums the per-case gradients.
+        """
+
+        @staticmethod
+        def forward(ctx, mu, solver, Fbars, eta_nw=1e-5, eta_cg=1e-8):
+            m = mu.detach().reshape(-1).to(solver.device, torch.float64)
+            solver.set_modulus_field(m.repeat(solver.nrve))
+            solver.reset_state()
+            _, _, _, Pbar, stats = solver.solve_increment(Fbars, eta_nw, eta_cg, fields=False)
+            ctx.solver = solver
+            ctx.eta_cg = eta_cg
+            ctx.shape = mu.shape
+            ctx.forward_stats = stats
+            return torch.from_numpy(Pbar).to(mu.device)
+
+        @staticmethod
+        def backward(ctx, grad_Pbar):
+            s = ctx.solver
+            dmu, _, _ = s.adjoint(grad_Pbar.detach().cpu().numpy(), eta_cg=ctx.eta_cg)
+            g = dmu.view(s.nrve, -1).sum(dim=0).reshape(ctx.shape)
+            return g, None, None, None, None
+
+    return HomogenizedStress
+
+
+_HS = None
+
+
+def homogenized_stress(mu, solver, Fbars, eta_nw=1e-5, eta_cg=1e-8):
+    """Differentiable P-bar [nrve, 9] (see HomogenizedStress)."""
+    global _HS
+    if _HS is None:
+        _HS = _autograd_function()
+    return _HS.apply(mu, solver, Fbars, eta_nw, eta_cg)
