@@ -112,6 +112,15 @@ int fftnk_set_material(fftnk_ctx* ctx, int model, int nphase, const double* para
  */
 int fftnk_set_modulus_field(fftnk_ctx* ctx, const double* mu_dev);
 
+/*
+ * Options: FFTNK_OPT_GRAPHS (1 = replay CG iterations from captured HIP graphs,
+ * the default; 0 = launch every kernel), FFTNK_OPT_CHECK_EVERY (CG iterations
+ * between two host checks of the convergence flags, 1..64, default 4).  Both
+ * change timing only, never results.
+ */
+enum { FFTNK_OPT_GRAPHS = 1, FFTNK_OPT_CHECK_EVERY = 2 };
+int fftnk_set_option(fftnk_ctx* ctx, int option, int value);
+
 /* F_t := I (and virgin history): the start state of Algorithm 1. */
 int fftnk_reset_state(fftnk_ctx* ctx);
 

@@ -11,8 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libfftnk.so")
-SOURCES = ["fftnk_kernels.hip", "fftnk_api.hip"]
-HEADERS = ["fftnk_internal.h"]
+SOURCES = ["fftnk_fft_kernels.hip", "fftnk_solver_kernels.hip", "fftnk_api.hip"]
+HEADERS = ["fftnk_internal.h", "fftnk_device.h"]
 
 # -packed-fp32-ops: no v_pk_*_f32 instructions anywhere in the device code.
 HIPFLAGS = [

@@ -1,12 +1,14 @@
 // Host driver and C-ABI of libfftnk (declared in include/fftnk.h).
 //
-// The driver runs Algorithm 1 of de Geus et al. (2017) for one load increment:
-// boundary-condition solve with the tangent of the start state (Sec. 3.1),
-// Newton iterations on G:K:dF = -G:P (Sec. 2.6) each solved by CG, the
-// convergence test ||dF|| / ||F_t + dFbar|| < eta_NW after at least two solves,
-// and the transactional commit of the converged state ("store converged
-// state", Alg. 1).  All field work runs in the kernels of fftnk_kernels.hip; the
-// host only sequences launches and reads back a few scalars per Newton
+// The driver runs Algorithm 1 of de Geus et al. (2017) for one load increment
+// on every RVE of a context at once: boundary-condition solve with the tangent
+// of the start state (Sec. 3.1), Newton iterations on G:K:dF = -G:P (Sec. 2.6)
+// each solved by CG, the convergence test ||dF|| / ||F_t + dFbar|| < eta_NW
+// after at least two solves, and the transactional commit of the converged
+// state ("store converged state", Alg. 1).  All field work runs in the kernels
+// (fftnk_fft_kernels.hip, fftnk_solver_kernels.hip); every launch covers all
+// RVEs, finished RVEs are masked on the device.  CG iterations are replayed
+// from captured HIP graphs; the host reads back a few scalars per Newton
 // iteration and per batch of CG iterations.
 #include "fftnk.h"
 #include "fftnk_internal.h"
@@ -15,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -25,8 +28,8 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Radix plan: powers of two in as few stages of 8 / 4 / 2 as possible, then
-// 3, 5, 7 and any remaining prime (direct-sum stage).
+// Radix plan: the power-of-two part in as few stages of 8 / 4 / 2 as possible
+// (bits spread evenly), then 3, 5, 7 and any remaining prime (direct sum).
 bool make_plan(int n, AxisPlan& pl) {
   pl.n = n;
   pl.nstages = 0;
@@ -37,7 +40,6 @@ bool make_plan(int n, AxisPlan& pl) {
   }
   if (e2 > 0) {
     const int ns = (e2 + 2) / 3;
-    // distribute e2 bits over ns stages as evenly as possible (each <= 3)
     std::vector<int> b(ns, e2 / ns);
     for (int s = 0; s < e2 % ns; ++s) b[s] += 1;
     for (int s = 0; s < ns; ++s) {
@@ -52,6 +54,7 @@ bool make_plan(int n, AxisPlan& pl) {
       m /= p;
     }
   }
+  pl.reg = (m == 1 && e2 >= 3 && (1 << e2) == n) ? 1 : 0;
   return true;
 }
 
@@ -61,14 +64,22 @@ int largest_pow2_leq(int x) {
   return p;
 }
 
-// pencils per work-group in the a1 / a0 passes: contiguous rows of at least
-// 128 bytes where possible, within the LDS (60 KiB) and register (8 points per
-// thread in pass 3) budgets.
+// pencils per work-group in the LDS-engine a1 / a0 passes: contiguous rows of
+// at least 128 bytes where possible, within the LDS (60 KiB) and register
+// (8 points per thread in pass 3) budgets.
 int pick_m(int h, int nmax, size_t csz, int pref) {
   int m = std::min(pref, largest_pow2_leq(std::max(1, h)));
   while (m > 1 && ((size_t)nmax * m > (size_t)8 * kThreads || csz * ((size_t)nmax + 2 * (size_t)nmax * m) > 61440))
     m /= 2;
   return m;
+}
+
+size_t row_lds(const Grid& g, size_t csz) { return csz * ((size_t)g.n2 + 2 * 5 * (size_t)g.rt * g.n2); }
+size_t col_lds(const Grid& g, int axis, size_t csz) {
+  const int n = axis == 0 ? g.n0 : g.n1;
+  if (g.ax[axis].reg) return csz * ((size_t)n + (size_t)kThreads * kRegP);
+  const int M = csz == 16 ? g.m64 : g.m32;
+  return csz * ((size_t)n + 2 * (size_t)n * M);
 }
 
 }  // namespace
@@ -77,27 +88,34 @@ struct fftnk_ctx {
   int nrve = 0;
   int prec = PREC_F64;
   hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // capture stream of the CG graphs
   std::vector<Grid> g;
-  long long ntot = 0;   // voxels over all RVEs
-  long long nspec = 0;  // complex spectrum entries over all RVEs (9 components included)
-  long long pstride = 0;
+  long long ntot = 0, nspec = 0, pstride = 0;
   std::vector<int> tw_len, tw_off;
   int tw_total = 0;
+  std::vector<int> starts;  // [NKIND][nrve + 1]
+  int nblk[NKIND] = {};
+  size_t lds[6] = {};
   // workspace layout (byte offsets)
-  size_t o_Ft, o_F, o_P, o_x, o_r, o_p, o_w, o_F32, o_spec, o_phase, o_mu, o_mtab, o_part, o_cg, o_red, o_tw64,
-      o_tw32, total = 0;
+  size_t o_Ft, o_F, o_P, o_x, o_r, o_p, o_w, o_F32, o_d64, o_spec, o_phase, o_mu, o_mtab, o_part, o_cg, o_red,
+      o_tw64, o_tw32, o_grids, o_starts, o_active, o_uni, total = 0;
   char* ws = nullptr;
   bool have_phase = false, have_mat = false, use_mu = false;
   int model = MODEL_SVK, nphase = 0;
   double mtab[kMaxPhase * 4] = {};
-  double* pinned = nullptr;  // host staging for device -> host scalars
-  std::vector<double> Fbar_t;  // committed macroscopic F per RVE (host copy, informative)
+  unsigned char* pinned = nullptr;  // host staging for device -> host scalars
+  size_t pinned_bytes = 0;
+  std::vector<int> active;   // host copy of the Newton mask (uploaded when it changes)
+  std::vector<double> uni;   // host copy of the per-RVE uniform tensors
+  bool use_graphs = true;
+  int check_every = 4;
+  int cg_estimate = 8;
+  std::map<int, hipGraphExec_t> graphs;
 
   template <typename T>
   T* at(size_t off) const {
     return reinterpret_cast<T*>(ws + off);
   }
-  size_t vsz() const { return prec == PREC_F64 ? sizeof(double) : sizeof(float); }
   double* Ft() const { return at<double>(o_Ft); }
   double* F() const { return at<double>(o_F); }
   double* P() const { return at<double>(o_P); }
@@ -106,20 +124,35 @@ struct fftnk_ctx {
   void* p() const { return ws + o_p; }
   void* w() const { return ws + o_w; }
   float* F32() const { return prec == PREC_F32 ? at<float>(o_F32) : nullptr; }
+  double* d64() const { return at<double>(o_d64); }  // FP64 copy of the FP32 solution (FP32 mode)
   void* spec() const { return ws + o_spec; }
-  CgState* cg(int r) const { return at<CgState>(o_cg) + r; }
+  CgState* cg() const { return at<CgState>(o_cg); }
   double* red() const { return at<double>(o_red); }
+  // linearisation point of the CG kernels: F itself (FP64) or its FP32 copy
+  const void* flin() const { return prec == PREC_F32 ? static_cast<const void*>(F32()) : static_cast<const void*>(F()); }
 
-  PassArgs args(int r) const {
-    PassArgs a;
-    a.g = g[r];
-    a.tw64 = ws + o_tw64;
-    a.tw32 = ws + o_tw32;
-    a.partials = at<double>(o_part);
-    a.pstride = pstride;
-    a.slot_base = 0;
-    return a;
+  Launch launch(hipStream_t s) const {
+    Launch L;
+    L.b.grids = at<Grid>(o_grids);
+    L.b.starts = at<int>(o_starts);
+    L.b.active = at<int>(o_active);
+    L.b.uni = at<double>(o_uni);
+    L.b.tw64 = ws + o_tw64;
+    L.b.tw32 = ws + o_tw32;
+    L.b.partials = at<double>(o_part);
+    L.b.pstride = pstride;
+    L.b.nrve = nrve;
+    for (int k = 0; k < NKIND; ++k) L.nblk[k] = nblk[k];
+    L.lds_row64 = lds[0];
+    L.lds_row32 = lds[1];
+    L.lds_col1_64 = lds[2];
+    L.lds_col1_32 = lds[3];
+    L.lds_col0_64 = lds[4];
+    L.lds_col0_32 = lds[5];
+    L.s = s;
+    return L;
   }
+  Launch launch() const { return launch(stream); }
   Material material() const {
     Material m;
     m.phase = at<uint8_t>(o_phase);
@@ -129,20 +162,35 @@ struct fftnk_ctx {
     m.nphase = nphase;
     return m;
   }
+  const CgState* host_cg() const { return reinterpret_cast<const CgState*>(pinned); }
+  const double* host_red() const { return reinterpret_cast<const double*>(pinned); }
 };
 
 namespace {
 
-#define HIP_TRY(expr)                          \
-  do {                                         \
+#define HIP_TRY(expr)                            \
+  do {                                           \
     if ((expr) != hipSuccess) return FFTNK_EHIP; \
   } while (0)
 
 int check_launch() { return hipGetLastError() == hipSuccess ? FFTNK_OK : FFTNK_EHIP; }
 
 int fetch(fftnk_ctx* c, const void* dev, size_t bytes) {
+  if (bytes > c->pinned_bytes) return FFTNK_EINVAL;
   HIP_TRY(hipMemcpyAsync(c->pinned, dev, bytes, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  return FFTNK_OK;
+}
+
+// host arrays uploaded here stay untouched until the next stream synchronisation
+int upload_active(fftnk_ctx* c) {
+  HIP_TRY(hipMemcpyAsync(c->ws + c->o_active, c->active.data(), c->nrve * sizeof(int), hipMemcpyHostToDevice,
+                         c->stream));
+  return FFTNK_OK;
+}
+int upload_uni(fftnk_ctx* c) {
+  HIP_TRY(hipMemcpyAsync(c->ws + c->o_uni, c->uni.data(), 9 * c->nrve * sizeof(double), hipMemcpyHostToDevice,
+                         c->stream));
   return FFTNK_OK;
 }
 
@@ -152,7 +200,7 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
   c->nrve = nrve;
   c->prec = precision == FFTNK_FP64 ? PREC_F64 : PREC_F32;
   c->stream = static_cast<hipStream_t>(stream);
-  long long vox = 0, spec = 0, pmax = kRedBlocks;
+  long long vox = 0, spec = 0;
   for (int r = 0; r < nrve; ++r) {
     Grid g{};
     g.n0 = dims[3 * r];
@@ -163,6 +211,7 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
       if (nd < 2 || nd > kMaxLen) return nd > kMaxLen ? FFTNK_EUNSUPPORTED : FFTNK_EINVAL;
       if (!make_plan(nd, g.ax[d])) return FFTNK_EUNSUPPORTED;
     }
+    g.ax[2].reg = 0;  // the a2 passes always use the LDS engine
     g.h = (g.n2 % 2 == 0) ? g.n2 / 2 : (g.n2 + 1) / 2;
     g.n = (long long)g.n0 * g.n1 * g.n2;
     g.rows = (long long)g.n0 * g.n1;
@@ -175,12 +224,44 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
     g.m32 = pick_m(g.h, nmax, 8, 16);
     vox += g.n;
     spec += 9LL * g.rows * g.h;
-    pmax = std::max(pmax, (long long)fwd_a2_blocks(g));
     c->g.push_back(g);
   }
   c->ntot = vox;
   c->nspec = spec;
-  c->pstride = pmax;
+  // launch geometry: work-group ranges of every RVE per launch kind
+  c->starts.assign((size_t)NKIND * (nrve + 1), 0);
+  for (int k = 0; k < NKIND; ++k) {
+    long long acc = 0;
+    for (int r = 0; r < nrve; ++r) {
+      const Grid& g = c->g[r];
+      c->starts[k * (nrve + 1) + r] = (int)acc;
+      long long b = 0;
+      switch (k) {
+        case K_ROW: b = row_blocks(g); break;
+        case K_COL1_64: b = col1_blocks(g, PREC_F64); break;
+        case K_COL1_32: b = col1_blocks(g, PREC_F32); break;
+        case K_COL0_64: b = col0_blocks(g, PREC_F64); break;
+        case K_COL0_32: b = col0_blocks(g, PREC_F32); break;
+        case K_ELEM9: b = elem_blocks(9 * g.n); break;
+        default: b = elem_blocks(g.n); break;
+      }
+      acc += b;
+    }
+    if (acc > (1LL << 30)) return FFTNK_EUNSUPPORTED;
+    c->starts[k * (nrve + 1) + nrve] = (int)acc;
+    c->nblk[k] = (int)acc;
+    c->pstride = std::max(c->pstride, acc);
+  }
+  for (const Grid& g : c->g) {
+    c->lds[0] = std::max(c->lds[0], row_lds(g, 16));
+    c->lds[1] = std::max(c->lds[1], row_lds(g, 8));
+    c->lds[2] = std::max(c->lds[2], col_lds(g, 1, 16));
+    c->lds[3] = std::max(c->lds[3], col_lds(g, 1, 8));
+    c->lds[4] = std::max(c->lds[4], col_lds(g, 0, 16));
+    c->lds[5] = std::max(c->lds[5], col_lds(g, 0, 8));
+  }
+  for (size_t b : c->lds)
+    if (b > 61440) return FFTNK_EUNSUPPORTED;
   // twiddle tables, one per distinct axis length
   for (auto& g : c->g)
     for (int d = 0; d < 3; ++d) {
@@ -212,26 +293,36 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
   c->o_p = take(fv);
   c->o_w = take(fv);
   c->o_F32 = take(c->prec == PREC_F32 ? 9 * (size_t)vox * 4 : 0);
+  c->o_d64 = take(c->prec == PREC_F32 ? f64 : 0);
   c->o_spec = take((size_t)spec * 16);
   c->o_phase = take((size_t)vox);
   c->o_mu = take((size_t)vox * 8);
   c->o_mtab = take(kMaxPhase * 4 * 8);
-  c->o_part = take((size_t)NSLOT * pmax * 8);
+  c->o_part = take((size_t)NSLOT * c->pstride * 8);
   c->o_cg = take((size_t)nrve * sizeof(CgState));
-  c->o_red = take((size_t)NSLOT * 8);
+  c->o_red = take((size_t)nrve * NSLOT * 8);
   c->o_tw64 = take((size_t)c->tw_total * 16);
   c->o_tw32 = take((size_t)c->tw_total * 8);
+  c->o_grids = take((size_t)nrve * sizeof(Grid));
+  c->o_starts = take(c->starts.size() * sizeof(int));
+  c->o_active = take((size_t)nrve * sizeof(int));
+  c->o_uni = take((size_t)nrve * 9 * sizeof(double));
   c->total = o;
-  c->Fbar_t.assign(9 * (size_t)nrve, 0.0);
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 4096) != hipSuccess) return FFTNK_EHIP;
+  c->active.assign(nrve, 1);
+  c->uni.assign(9 * (size_t)nrve, 0.0);
+  c->pinned_bytes = std::max((size_t)nrve * NSLOT * 8, (size_t)nrve * sizeof(CgState)) + 256;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), c->pinned_bytes) != hipSuccess) return FFTNK_EHIP;
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) return FFTNK_EHIP;
   return FFTNK_OK;
 }
 
+void drop_graphs(fftnk_ctx* c) {
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
+}
+
 int reset_state(fftnk_ctx* c) {
-  for (int r = 0; r < c->nrve; ++r) {
-    launch_set_identity(c->args(r), c->Ft(), c->stream);
-    for (int k = 0; k < 9; ++k) c->Fbar_t[9 * r + k] = (k % 4 == 0) ? 1.0 : 0.0;
-  }
+  launch_set_identity(c->launch(), c->Ft());
   int e = check_launch();
   if (e) return e;
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -239,137 +330,130 @@ int reset_state(fftnk_ctx* c) {
 }
 
 // ---------------------------------------------------------------------------
-// the five passes of one projection G( Y ) where Y is produced by the first
-// pass according to `mode`
+// pipelines
 // ---------------------------------------------------------------------------
-void middle_passes(fftnk_ctx* c, int prec, const PassArgs& a, const CgState* cg) {
-  launch_col_a1(prec, false, a, c->spec(), cg, c->stream);
-  launch_col_a0_project(prec, a, c->spec(), cg, c->stream);
-  launch_col_a1(prec, true, a, c->spec(), cg, c->stream);
+void middle_passes(int prec, const Launch& L, void* spec, const CgState* cg) {
+  launch_col_a1(prec, false, L, spec, cg);
+  launch_col_a0_project(prec, L, spec, cg);
+  launch_col_a1(prec, true, L, spec, cg);
 }
 
-// b = -G(Y) in FP64, written to r (context precision) with x = 0;
-// partials: ||Y||^2 in SLOT_YY, ||b||^2 in SLOT_BB.
-void rhs_pipeline(fftnk_ctx* c, int r, int mode, const double* Y, const double* Flin, const double* uni,
-                  double sign = -1.0) {
-  const PassArgs a = c->args(r);
-  const Material m = c->material();
-  launch_fwd_a2(PREC_F64, mode, a, m, Y, nullptr, nullptr, Flin, uni, 1.0, c->spec(), nullptr, c->stream);
-  middle_passes(c, PREC_F64, a, nullptr);
-  launch_inv_a2(PREC_F64, INV_RHS, a, c->spec(), c->r(), c->prec, nullptr, c->x(), sign, nullptr, c->stream);
+// b = sign * G(Y) in FP64, written to r (context precision) with x = 0;
+// partials: ||Y||^2 in SLOT_YY, ||b||^2 in SLOT_BB.  Y is produced by pass 1
+// in `mode` (the field in, or the tangent at Flin applied to Batch::uni).
+void rhs_pipeline(fftnk_ctx* c, int mode, const double* Y, const double* Flin, double sign) {
+  const Launch L = c->launch();
+  launch_fwd_a2(PREC_F64, mode, L, c->material(), Y, nullptr, nullptr, Flin, 1.0, c->spec(), nullptr);
+  middle_passes(PREC_F64, L, c->spec(), nullptr);
+  launch_inv_a2(PREC_F64, INV_RHS, L, c->spec(), c->r(), c->prec, nullptr, c->x(), sign, nullptr);
 }
 
-// CG on A = G K(Flin) with right-hand side r (x = 0 on entry).
-int run_cg(fftnk_ctx* c, int r, const void* Flin, double eta, int max_cg, int* iters, double* relres) {
-  const PassArgs a = c->args(r);
-  const Material m = c->material();
-  CgState* cg = c->cg(r);
-  const int stall = c->prec == PREC_F32 ? 50 : 0;
-  launch_cg_init(a, inv_a2_blocks(a.g), cg, eta, max_cg, stall, c->stream);
-  int launched = 0, chunk = 4;
-  while (true) {
-    for (int k = 0; k < chunk; ++k) {
-      launch_fwd_a2(c->prec, FWD_CG, a, m, nullptr, c->r(), c->p(), Flin, nullptr, 1.0, c->spec(), cg, c->stream);
-      middle_passes(c, c->prec, a, cg);
-      launch_inv_a2(c->prec, INV_PW, a, c->spec(), c->w(), c->prec, c->p(), nullptr, 1.0, cg, c->stream);
-      launch_cg_alpha(a, inv_a2_blocks(a.g), cg, c->stream);
-      launch_cg_update(c->prec, a, c->x(), c->r(), c->p(), c->w(), cg, c->stream);
-      launch_cg_beta(a, cg, c->stream);
-    }
-    launched += chunk;
-    int st = check_launch();
-    if (st) return st;
-    st = fetch(c, cg, sizeof(CgState));
-    if (st) return st;
-    CgState h;
-    std::memcpy(&h, c->pinned, sizeof(h));
-    if (h.done) {
-      *iters = h.iter;
-      *relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
-      return h.status;  // kernel status values equal the FFTNK_* codes
-    }
-    if (launched > max_cg + 64) return FFTNK_ECG_MAXIT;  // unreachable: k_cg_beta stops at max_cg
-    chunk = std::min(chunk * 2, 32);
+// The CG solution as the Newton update.  FP64: x itself.  FP32: x rounded up to
+// FP64 and projected again with G in FP64.  In FP32 the Krylov vectors pick up
+// rounding noise outside range(G) (incompatible and mean components) that the
+// operator cannot see and the FP64 residual -G(P) can never remove; projecting
+// the update restores compatibility and the prescribed mean exactly.
+const void* newton_update_source(fftnk_ctx* c) {
+  if (c->prec == PREC_F64) return c->x();
+  const Launch L = c->launch();
+  launch_convert(PREC_F64, c->x(), c->d64(), 9 * c->ntot, c->stream);
+  launch_fwd_a2(PREC_F64, FWD_COPY, L, c->material(), c->d64(), nullptr, nullptr, nullptr, 1.0, c->spec(), nullptr);
+  middle_passes(PREC_F64, L, c->spec(), nullptr);
+  launch_inv_a2(PREC_F64, INV_OUT, L, c->spec(), c->d64(), PREC_F64, nullptr, nullptr, 1.0, nullptr);
+  return c->d64();
+}
+
+// one CG iteration on every RVE whose CG is still running
+void cg_iteration(fftnk_ctx* c, const Launch& L) {
+  CgState* cg = c->cg();
+  launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->p(), c->flin(), 1.0, c->spec(), cg);
+  middle_passes(c->prec, L, c->spec(), cg);
+  launch_inv_a2(c->prec, INV_PW, L, c->spec(), c->w(), c->prec, c->p(), nullptr, 1.0, cg);
+  launch_cg_alpha(L, cg);
+  launch_cg_update(c->prec, L, c->x(), c->r(), c->p(), c->w(), cg);
+  launch_cg_beta(L, cg);
+}
+
+// a HIP graph replaying k CG iterations (captured once per context)
+int cg_graph(fftnk_ctx* c, int k, hipGraphExec_t* out) {
+  auto it = c->graphs.find(k);
+  if (it != c->graphs.end()) {
+    *out = it->second;
+    return FFTNK_OK;
   }
-}
-
-int solve_rve(fftnk_ctx* c, int r, const double* Fbar, double eta_nw, double eta_cg, int max_newton, int max_cg,
-              fftnk_stats* st) {
-  const PassArgs a = c->args(r);
-  const Grid& g = a.g;
-  const Material m = c->material();
-  const hipStream_t s = c->stream;
-  double* red = c->red();
-  const int nvox = elem_blocks_vox(g);
-  for (int k = 0; k < 9; ++k)
-    if (!std::isfinite(Fbar[k])) return FFTNK_ENONFINITE;
-
-  // dFbar = Fbar - mean(F_t)  (Sec. 3.1)
-  launch_field_sum(a, c->Ft(), SLOT_FBAR, s);
-  launch_reduce(a, SLOT_FBAR, 9, nvox, red, s);
-  int e = check_launch();
-  if (!e) e = fetch(c, red, 9 * sizeof(double));
-  if (e) return e;
-  double dFbar[9];
-  for (int k = 0; k < 9; ++k) dFbar[k] = Fbar[k] - c->pinned[k] / (double)g.n;
-
-  // boundary-condition right-hand side with the tangent of the start state
-  rhs_pipeline(c, r, FWD_TANGENT_UNI, nullptr, c->Ft(), dFbar);
-  launch_set_F(a, c->Ft(), c->F(), dFbar, c->F32(), s);
-  launch_reduce(a, SLOT_YY, 1, fwd_a2_blocks(g), red + 0, s);
-  launch_reduce(a, SLOT_BB, 1, inv_a2_blocks(g), red + 1, s);
-  launch_reduce(a, SLOT_FF, 1, nvox, red + 2, s);
-  e = check_launch();
-  if (!e) e = fetch(c, red, 3 * sizeof(double));
-  if (e) return e;
-  double yy = c->pinned[0], bb = c->pinned[1];
-  const double Fn = std::sqrt(c->pinned[2]);
-
-  const double eta_eff = c->prec == PREC_F32 ? std::max(eta_cg, 1e-6) : eta_cg;
-  for (int it = 0;; ++it) {
-    if (it >= max_newton) return FFTNK_ENEWTON_MAXIT;
-    int iters = 0;
-    double relres = 0.0;
-    if (!std::isfinite(bb) || !std::isfinite(yy)) return FFTNK_ENONFINITE;
-    if (!(std::sqrt(bb) <= 1e-14 * std::sqrt(yy) || bb == 0.0)) {
-      const void* Flin = c->prec == PREC_F32 ? static_cast<const void*>(c->F32())
-                                             : static_cast<const void*>(it == 0 ? c->Ft() : c->F());
-      e = run_cg(c, r, Flin, eta_eff, max_cg, &iters, &relres);
-      if (st) {
-        st->cg_iters[it] = iters;
-        st->cg_relres[it] = relres;
-        st->n_solves = it + 1;
-      }
-      if (e) return e;
-    } else if (st) {
-      st->cg_iters[it] = 0;
-      st->cg_relres[it] = 0.0;
-      st->n_solves = it + 1;
-    }
-    // F += dF, constitutive update, new right-hand side -G(P)
-    launch_newton_update(c->prec, a, m, c->F(), c->x(), c->P(), c->F32(), s);
-    rhs_pipeline(c, r, FWD_COPY, c->P(), nullptr, nullptr);
-    launch_reduce(a, SLOT_DF, 1, nvox, red + 0, s);
-    launch_reduce(a, SLOT_PBAR, 9, nvox, red + 1, s);
-    launch_reduce(a, SLOT_YY, 1, fwd_a2_blocks(g), red + 10, s);
-    launch_reduce(a, SLOT_BB, 1, inv_a2_blocks(g), red + 11, s);
-    e = check_launch();
-    if (!e) e = fetch(c, red, 12 * sizeof(double));
-    if (e) return e;
-    const double df = c->pinned[0];
-    yy = c->pinned[10];
-    bb = c->pinned[11];
-    const double res = std::sqrt(df) / Fn;
-    if (st) st->newton_res[it] = res;
-    if (!std::isfinite(res)) return FFTNK_ENONFINITE;
-    for (int k = 0; k < 9; ++k)
-      if (!std::isfinite(c->pinned[1 + k])) return FFTNK_ENONFINITE;
-    if (res < eta_nw && it > 0) break;
-  }
-  // converged: P-bar, commit F_t
-  for (int k = 0; k < 9; ++k) c->Fbar_t[9 * r + k] = Fbar[k];
+  HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  const Launch L = c->launch(c->cap);
+  for (int i = 0; i < k; ++i) cg_iteration(c, L);
+  hipGraph_t graph = nullptr;
+  const hipError_t e1 = hipStreamEndCapture(c->cap, &graph);
+  if (e1 != hipSuccess || !graph) return FFTNK_EHIP;
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return FFTNK_EHIP;
+  c->graphs[k] = exec;
+  *out = exec;
   return FFTNK_OK;
 }
+
+int launch_iterations(fftnk_ctx* c, int k) {
+  if (!c->use_graphs) {
+    const Launch L = c->launch();
+    for (int i = 0; i < k; ++i) cg_iteration(c, L);
+    return check_launch();
+  }
+  for (int chunk = 32; chunk >= 1; chunk /= 2) {
+    while (k >= chunk) {
+      hipGraphExec_t g = nullptr;
+      const int e = cg_graph(c, chunk, &g);
+      if (e) return e;
+      HIP_TRY(hipGraphLaunch(g, c->stream));
+      k -= chunk;
+    }
+  }
+  return FFTNK_OK;
+}
+
+// CG on every active RVE: A = G K(linearisation point), right-hand side r,
+// x = 0 on entry.  Per-RVE outcome in the device CgState array.
+int run_cg(fftnk_ctx* c, double eta, int max_cg) {
+  const Launch L = c->launch();
+  const int stall = c->prec == PREC_F32 ? 50 : 0;
+  launch_cg_init(L, c->cg(), eta, max_cg, stall);
+  int e = check_launch();
+  if (e) return e;
+  int launched = std::max(1, std::min(c->cg_estimate - 2, max_cg));
+  e = launch_iterations(c, launched);
+  if (e) return e;
+  while (true) {
+    e = fetch(c, c->cg(), c->nrve * sizeof(CgState));
+    if (e) return e;
+    bool all = true;
+    int most = 0;
+    for (int r = 0; r < c->nrve; ++r) {
+      all = all && c->host_cg()[r].done;
+      most = std::max(most, c->host_cg()[r].iter);
+    }
+    if (all) {
+      if (most > 0) c->cg_estimate = most;
+      return FFTNK_OK;
+    }
+    if (launched > max_cg + 64) return FFTNK_ECG_MAXIT;  // unreachable: k_cg_beta stops at max_cg
+    e = launch_iterations(c, c->check_every);
+    if (e) return e;
+    launched += c->check_every;
+  }
+}
+
+int reduce_fetch(fftnk_ctx* c, std::initializer_list<std::pair<int, std::pair<int, int>>> req) {
+  const Launch L = c->launch();
+  for (const auto& q : req) launch_reduce(L, q.first, q.second.first, q.second.second, c->red());
+  const int e = check_launch();
+  if (e) return e;
+  return fetch(c, c->red(), (size_t)c->nrve * NSLOT * sizeof(double));
+}
+
+double red_at(fftnk_ctx* c, int r, int slot) { return c->host_red()[r * NSLOT + slot]; }
 
 }  // namespace
 
@@ -403,6 +487,7 @@ int fftnk_bind_workspace(fftnk_ctx* c, void* dev, size_t bytes) {
   if (!c || !dev) return FFTNK_EINVAL;
   if ((reinterpret_cast<uintptr_t>(dev) % kAlign) != 0) return FFTNK_EINVAL;
   if (bytes < c->total) return FFTNK_ENOMEM;
+  drop_graphs(c);
   c->ws = static_cast<char*>(dev);
   // twiddle tables W_n^e = exp(-2 pi i e / n), FP64 and FP32
   std::vector<double> t64(2 * (size_t)c->tw_total);
@@ -421,8 +506,18 @@ int fftnk_bind_workspace(fftnk_ctx* c, void* dev, size_t bytes) {
   }
   HIP_TRY(hipMemcpyAsync(c->ws + c->o_tw64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->ws + c->o_tw32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->o_grids, c->g.data(), c->g.size() * sizeof(Grid), hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->o_starts, c->starts.data(), c->starts.size() * sizeof(int),
+                         hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemsetAsync(c->ws + c->o_cg, 0, (size_t)c->nrve * sizeof(CgState), c->stream));
   HIP_TRY(hipMemsetAsync(c->ws + c->o_part, 0, (size_t)NSLOT * c->pstride * 8, c->stream));
+  std::fill(c->active.begin(), c->active.end(), 1);
+  std::fill(c->uni.begin(), c->uni.end(), 0.0);
+  int e = upload_active(c);
+  if (!e) e = upload_uni(c);
+  if (e) return e;
+  HIP_TRY(hipStreamSynchronize(c->stream));  // the host tables above are temporaries
   return reset_state(c);
 }
 
@@ -445,6 +540,7 @@ int fftnk_set_material(fftnk_ctx* c, int model, int nphase, const double* params
   std::memset(c->mtab, 0, sizeof(c->mtab));
   for (int ph = 0; ph < nphase; ++ph)
     for (int k = 0; k < np; ++k) c->mtab[4 * ph + k] = params[np * ph + k];
+  drop_graphs(c);  // captured launches carry the material
   c->model = model;
   c->nphase = nphase;
   HIP_TRY(hipMemcpyAsync(c->ws + c->o_mtab, c->mtab, sizeof(c->mtab), hipMemcpyHostToDevice, c->stream));
@@ -457,13 +553,27 @@ int fftnk_set_modulus_field(fftnk_ctx* c, const double* mu_dev) {
   if (!c) return FFTNK_EINVAL;
   if (!c->ws) return FFTNK_ESTATE;
   if (!mu_dev) {
+    if (c->use_mu) drop_graphs(c);  // captured launches carry the material
     c->use_mu = false;
     return FFTNK_OK;
   }
   HIP_TRY(hipMemcpyAsync(c->ws + c->o_mu, mu_dev, (size_t)c->ntot * 8, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  if (!c->use_mu) drop_graphs(c);
   c->use_mu = true;
   return FFTNK_OK;
+}
+
+int fftnk_set_option(fftnk_ctx* c, int option, int value) {
+  if (!c) return FFTNK_EINVAL;
+  switch (option) {
+    case FFTNK_OPT_GRAPHS: c->use_graphs = value != 0; return FFTNK_OK;
+    case FFTNK_OPT_CHECK_EVERY:
+      if (value < 1 || value > 64) return FFTNK_EINVAL;
+      c->check_every = value;
+      return FFTNK_OK;
+    default: return FFTNK_EINVAL;
+  }
 }
 
 int fftnk_reset_state(fftnk_ctx* c) {
@@ -479,43 +589,158 @@ int fftnk_solve_increment(fftnk_ctx* c, const double* Fbar, double eta_nw, doubl
     return FFTNK_EINVAL;
   if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
   const auto t0 = std::chrono::steady_clock::now();
-  int worst = FFTNK_OK;
-  std::vector<int> ok(c->nrve, 0);
-  for (int r = 0; r < c->nrve; ++r) {
-    fftnk_stats local;
-    fftnk_stats* st = stats ? &stats[r] : &local;
-    std::memset(st, 0, sizeof(*st));
-    const int e = solve_rve(c, r, Fbar + 9 * r, eta_nw, eta_cg, max_newton, max_cg, st);
-    st->status = e;
-    if (e) {
-      if (!worst) worst = e;
-      continue;
+  const int nr = c->nrve;
+  std::vector<fftnk_stats> st(nr);
+  std::memset(st.data(), 0, nr * sizeof(fftnk_stats));
+  std::vector<int> status(nr, FFTNK_OK), done(nr, 0);
+  std::vector<double> Fn(nr, 0.0), pbar(9 * (size_t)nr, 0.0);
+  const Material mat = c->material();
+  int e = FFTNK_OK;
+
+  for (int r = 0; r < nr; ++r)
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(Fbar[9 * r + k])) {
+        status[r] = FFTNK_ENONFINITE;
+        done[r] = 1;
+      }
+  for (int r = 0; r < nr; ++r) c->active[r] = done[r] ? 0 : 1;
+  e = upload_active(c);
+  if (e) return e;
+
+  // dFbar = Fbar - mean(F_t)  (Sec. 3.1)
+  launch_field_sum(c->launch(), c->Ft(), SLOT_FBAR);
+  e = reduce_fetch(c, {{K_VOX, {SLOT_FBAR, 9}}});
+  if (e) return e;
+  for (int r = 0; r < nr; ++r)
+    for (int k = 0; k < 9; ++k) c->uni[9 * r + k] = Fbar[9 * r + k] - red_at(c, r, SLOT_FBAR + k) / (double)c->g[r].n;
+  e = upload_uni(c);
+  if (e) return e;
+
+  // boundary-condition right-hand side with the tangent of the start state;
+  // F = F_t until the first update adds dFbar
+  rhs_pipeline(c, FWD_TANGENT_UNI, nullptr, c->Ft(), -1.0);
+  launch_set_F(c->launch(), c->Ft(), c->F(), c->F32());
+  e = reduce_fetch(c, {{K_VOX, {SLOT_FF, 1}}});
+  if (e) return e;
+  for (int r = 0; r < nr; ++r) Fn[r] = std::sqrt(red_at(c, r, SLOT_FF));
+
+  const double eta_eff = c->prec == PREC_F32 ? std::max(eta_cg, 1e-6) : eta_cg;
+  for (int it = 0; it < max_newton; ++it) {
+    bool any = false;
+    for (int r = 0; r < nr; ++r) any = any || !done[r];
+    if (!any) break;
+    e = run_cg(c, eta_eff, max_cg);
+    if (e) return e;
+    for (int r = 0; r < nr; ++r) {
+      if (done[r]) continue;
+      const CgState& s = c->host_cg()[r];
+      st[r].cg_iters[it] = s.iter;
+      st[r].cg_relres[it] = (s.bb > 0 && !s.zero_rhs) ? std::sqrt(s.rr / s.bb) : 0.0;
+      st[r].n_solves = it + 1;
+      if (s.status != FFTNK_OK) {
+        status[r] = s.status;
+        done[r] = 1;
+        c->active[r] = 0;
+      }
     }
-    ok[r] = 1;
-    const Grid& g = c->g[r];
-    const PassArgs a = c->args(r);
-    launch_reduce(a, SLOT_PBAR, 9, elem_blocks_vox(g), c->red(), c->stream);
-    int e2 = check_launch();
-    if (!e2) e2 = fetch(c, c->red(), 9 * sizeof(double));
-    if (e2) return e2;
-    for (int k = 0; k < 9; ++k) Pbar[9 * r + k] = c->pinned[k] / (double)g.n;
+    e = upload_active(c);
+    if (e) return e;
+    // F += dF (+ dFbar after the boundary-condition solve), constitutive
+    // update, new right-hand side -G(P)
+    const void* dF = newton_update_source(c);  // FP64 in both precisions
+    launch_newton_update(PREC_F64, c->launch(), mat, c->F(), dF, c->P(), c->F32(), it == 0);
+    rhs_pipeline(c, FWD_COPY, c->P(), nullptr, -1.0);
+    e = reduce_fetch(c, {{K_VOX, {SLOT_DF, 1}}, {K_VOX, {SLOT_PBAR, 9}}});
+    if (e) return e;
+    for (int r = 0; r < nr; ++r) {
+      if (done[r]) continue;
+      const double res = std::sqrt(red_at(c, r, SLOT_DF)) / Fn[r];
+      st[r].newton_res[it] = res;
+      bool finite = std::isfinite(res);
+      for (int k = 0; k < 9; ++k) {
+        pbar[9 * r + k] = red_at(c, r, SLOT_PBAR + k) / (double)c->g[r].n;
+        finite = finite && std::isfinite(pbar[9 * r + k]);
+      }
+      if (!finite) {
+        status[r] = FFTNK_ENONFINITE;
+        done[r] = 1;
+      } else if (res < eta_nw && it > 0) {
+        done[r] = 1;  // converged
+      } else if (it + 1 >= max_newton) {
+        status[r] = FFTNK_ENEWTON_MAXIT;
+        done[r] = 1;
+      }
+      if (done[r]) c->active[r] = 0;
+    }
+    e = upload_active(c);
+    if (e) return e;
   }
   // commit the converged RVEs (transactional per RVE), copy out
-  const size_t f64 = 9 * (size_t)c->ntot * sizeof(double);
-  for (int r = 0; r < c->nrve; ++r) {
-    if (!ok[r]) continue;
+  int worst = FFTNK_OK;
+  for (int r = 0; r < nr; ++r) {
+    st[r].status = status[r];
+    if (status[r]) {
+      if (!worst) worst = status[r];
+      continue;
+    }
     const Grid& g = c->g[r];
     const size_t off = 9 * (size_t)g.vox_off, bytes = 9 * (size_t)g.n * sizeof(double);
     HIP_TRY(hipMemcpyAsync(c->Ft() + off, c->F() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
     if (F_dev) HIP_TRY(hipMemcpyAsync(F_dev + off, c->F() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
     if (P_dev) HIP_TRY(hipMemcpyAsync(P_dev + off, c->P() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
+    for (int k = 0; k < 9; ++k) Pbar[9 * r + k] = pbar[9 * r + k];
   }
-  (void)f64;
+  HIP_TRY(hipStreamSynchronize(c->stream));  // the last mask upload has read the host vector
+  std::fill(c->active.begin(), c->active.end(), 1);
+  e = upload_active(c);
+  if (e) return e;
   HIP_TRY(hipStreamSynchronize(c->stream));
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (stats)
-    for (int r = 0; r < c->nrve; ++r) stats[r].t_ms = ms;
+    for (int r = 0; r < nr; ++r) {
+      stats[r] = st[r];
+      stats[r].t_ms = ms;
+    }
   return worst;
+}
+
+int fftnk_adjoint(fftnk_ctx* c, const double* gbar, double eta_cg, int max_cg, double* dLdmu, double* dLdK,
+                  fftnk_stats* stats) {
+  if (!c || !gbar || !dLdmu || !(eta_cg > 0) || max_cg < 1) return FFTNK_EINVAL;
+  if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
+  const int nr = c->nrve;
+  for (int k = 0; k < 9 * nr; ++k)
+    if (!std::isfinite(gbar[k])) return FFTNK_ENONFINITE;
+  for (int k = 0; k < 9 * nr; ++k) c->uni[k] = gbar[k];
+  int e = upload_uni(c);
+  if (e) return e;
+  // linearisation point: the committed state
+  const size_t bytes = 9 * (size_t)c->ntot * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(c->F(), c->Ft(), bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (c->prec == PREC_F32) launch_convert(PREC_F32, c->Ft(), c->F32(), 9 * c->ntot, c->stream);
+  // b = +G(K(F_t) : g), the adjoint of the boundary-condition system
+  rhs_pipeline(c, FWD_TANGENT_UNI, nullptr, c->Ft(), +1.0);
+  const double eta_eff = c->prec == PREC_F32 ? std::max(eta_cg, 1e-6) : eta_cg;
+  e = run_cg(c, eta_eff, max_cg);
+  if (e) return e;
+  int worst = FFTNK_OK;
+  for (int r = 0; r < nr; ++r) {
+    const CgState& s = c->host_cg()[r];
+    if (stats) {
+      std::memset(&stats[r], 0, sizeof(fftnk_stats));
+      stats[r].n_solves = 1;
+      stats[r].cg_iters[0] = s.iter;
+      stats[r].cg_relres[0] = (s.bb > 0 && !s.zero_rhs) ? std::sqrt(s.rr / s.bb) : 0.0;
+      stats[r].status = s.status;
+    }
+    if (s.status && !worst) worst = s.status;
+  }
+  if (worst) return worst;
+  const void* w = newton_update_source(c);
+  launch_adjoint_grad(w == c->x() ? c->prec : PREC_F64, c->launch(), c->Ft(), w, dLdmu, dLdK);
+  e = check_launch();
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return e;
 }
 
 int fftnk_set_linearization(fftnk_ctx* c, const double* F_dev) {
@@ -531,118 +756,49 @@ int fftnk_set_linearization(fftnk_ctx* c, const double* F_dev) {
 int fftnk_apply_operator(fftnk_ctx* c, const void* p_dev, void* Ap_dev) {
   if (!c || !p_dev || !Ap_dev || p_dev == Ap_dev) return FFTNK_EINVAL;
   if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
-  const Material m = c->material();
-  const void* Flin = c->prec == PREC_F32 ? static_cast<const void*>(c->F32()) : static_cast<const void*>(c->F());
-  for (int r = 0; r < c->nrve; ++r) {
-    const PassArgs a = c->args(r);
-    launch_fwd_a2(c->prec, FWD_TANGENT, a, m, p_dev, nullptr, nullptr, Flin, nullptr, 1.0, c->spec(), nullptr,
-                  c->stream);
-    middle_passes(c, c->prec, a, nullptr);
-    launch_inv_a2(c->prec, INV_OUT, a, c->spec(), Ap_dev, c->prec, nullptr, nullptr, 1.0, nullptr, c->stream);
-  }
-  return check_launch();
-}
-
-int fftnk_adjoint(fftnk_ctx* c, const double* gbar, double eta_cg, int max_cg, double* dLdmu, double* dLdK,
-                  fftnk_stats* stats) {
-  if (!c || !gbar || !dLdmu || !(eta_cg > 0) || max_cg < 1) return FFTNK_EINVAL;
-  if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
-  const size_t bytes = (size_t)c->ntot * sizeof(double);
-  HIP_TRY(hipMemsetAsync(dLdmu, 0, bytes, c->stream));
-  if (dLdK) HIP_TRY(hipMemsetAsync(dLdK, 0, bytes, c->stream));
-  const double eta_eff = c->prec == PREC_F32 ? std::max(eta_cg, 1e-6) : eta_cg;
-  int worst = FFTNK_OK;
-  for (int r = 0; r < c->nrve; ++r) {
-    const PassArgs a = c->args(r);
-    const Grid& g = a.g;
-    fftnk_stats local;
-    fftnk_stats* st = stats ? &stats[r] : &local;
-    std::memset(st, 0, sizeof(*st));
-    for (int k = 0; k < 9; ++k)
-      if (!std::isfinite(gbar[9 * r + k])) return FFTNK_ENONFINITE;
-    // b = +G(K(F_t) : g), adjoint of the boundary-condition system
-    rhs_pipeline(c, r, FWD_TANGENT_UNI, nullptr, c->Ft(), gbar + 9 * r, +1.0);
-    if (c->prec == PREC_F32)
-      launch_convert(PREC_F32, c->Ft() + 9 * g.vox_off, c->F32() + 9 * g.vox_off, 9 * g.n, c->stream);
-    launch_reduce(a, SLOT_YY, 1, fwd_a2_blocks(g), c->red() + 0, c->stream);
-    launch_reduce(a, SLOT_BB, 1, inv_a2_blocks(g), c->red() + 1, c->stream);
-    int e = check_launch();
-    if (!e) e = fetch(c, c->red(), 2 * sizeof(double));
-    if (e) return e;
-    const double yy = c->pinned[0], bb = c->pinned[1];
-    int iters = 0;
-    double relres = 0.0;
-    if (!std::isfinite(bb)) return FFTNK_ENONFINITE;
-    if (!(std::sqrt(bb) <= 1e-14 * std::sqrt(yy) || bb == 0.0)) {
-      const void* Flin = c->prec == PREC_F32 ? static_cast<const void*>(c->F32()) : static_cast<const void*>(c->Ft());
-      e = run_cg(c, r, Flin, eta_eff, max_cg, &iters, &relres);
-    }
-    st->n_solves = 1;
-    st->cg_iters[0] = iters;
-    st->cg_relres[0] = relres;
-    st->status = e;
-    if (e) {
-      if (!worst) worst = e;
-      continue;
-    }
-    launch_adjoint_grad(c->prec, a, c->Ft(), c->x(), gbar + 9 * r, dLdmu, dLdK, g.vox_off, c->stream);
-  }
-  const int e = check_launch();
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return worst ? worst : e;
-}
-
-int fftnk_launch_pass(fftnk_ctx* c, int pass) {
-  if (!c || pass < 1 || pass > 5) return FFTNK_EINVAL;
-  if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
-  const Material m = c->material();
-  const void* Flin = c->prec == PREC_F32 ? static_cast<const void*>(c->F32()) : static_cast<const void*>(c->F());
-  for (int r = 0; r < c->nrve; ++r) {
-    const PassArgs a = c->args(r);
-    switch (pass) {
-      case 1:
-        launch_fwd_a2(c->prec, FWD_TANGENT, a, m, c->p(), nullptr, nullptr, Flin, nullptr, 1.0, c->spec(), nullptr,
-                      c->stream);
-        break;
-      case 2: launch_col_a1(c->prec, false, a, c->spec(), nullptr, c->stream); break;
-      case 3: launch_col_a0_project(c->prec, a, c->spec(), nullptr, c->stream); break;
-      case 4: launch_col_a1(c->prec, true, a, c->spec(), nullptr, c->stream); break;
-      default:
-        launch_inv_a2(c->prec, INV_OUT, a, c->spec(), c->w(), c->prec, nullptr, nullptr, 1.0, nullptr, c->stream);
-        break;
-    }
-  }
+  const Launch L = c->launch();
+  launch_fwd_a2(c->prec, FWD_TANGENT, L, c->material(), p_dev, nullptr, nullptr, c->flin(), 1.0, c->spec(), nullptr);
+  middle_passes(c->prec, L, c->spec(), nullptr);
+  launch_inv_a2(c->prec, INV_OUT, L, c->spec(), Ap_dev, c->prec, nullptr, nullptr, 1.0, nullptr);
   return check_launch();
 }
 
 int fftnk_project(fftnk_ctx* c, const void* a_dev, void* Ga_dev) {
   if (!c || !a_dev || !Ga_dev) return FFTNK_EINVAL;
   if (!c->ws) return FFTNK_ESTATE;
-  const Material m = c->material();
-  for (int r = 0; r < c->nrve; ++r) {
-    const PassArgs a = c->args(r);
-    launch_fwd_a2(c->prec, FWD_COPY, a, m, a_dev, nullptr, nullptr, nullptr, nullptr, 1.0, c->spec(), nullptr,
-                  c->stream);
-    middle_passes(c, c->prec, a, nullptr);
-    launch_inv_a2(c->prec, INV_OUT, a, c->spec(), Ga_dev, c->prec, nullptr, nullptr, 1.0, nullptr, c->stream);
-  }
+  const Launch L = c->launch();
+  launch_fwd_a2(c->prec, FWD_COPY, L, c->material(), a_dev, nullptr, nullptr, nullptr, 1.0, c->spec(), nullptr);
+  middle_passes(c->prec, L, c->spec(), nullptr);
+  launch_inv_a2(c->prec, INV_OUT, L, c->spec(), Ga_dev, c->prec, nullptr, nullptr, 1.0, nullptr);
   return check_launch();
 }
 
 int fftnk_constitutive(fftnk_ctx* c, const double* F_dev, double* P_dev, double* Pbar) {
   if (!c || !F_dev || !P_dev || !Pbar) return FFTNK_EINVAL;
   if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
-  const Material m = c->material();
-  for (int r = 0; r < c->nrve; ++r) {
-    const PassArgs a = c->args(r);
-    launch_constitutive(a, m, F_dev, P_dev, c->stream);
-    launch_reduce(a, SLOT_PBAR, 9, elem_blocks_vox(a.g), c->red(), c->stream);
-    int e = check_launch();
-    if (!e) e = fetch(c, c->red(), 9 * sizeof(double));
-    if (e) return e;
-    for (int k = 0; k < 9; ++k) Pbar[9 * r + k] = c->pinned[k] / (double)a.g.n;
-  }
+  launch_constitutive(c->launch(), c->material(), F_dev, P_dev);
+  const int e = reduce_fetch(c, {{K_VOX, {SLOT_PBAR, 9}}});
+  if (e) return e;
+  for (int r = 0; r < c->nrve; ++r)
+    for (int k = 0; k < 9; ++k) Pbar[9 * r + k] = red_at(c, r, SLOT_PBAR + k) / (double)c->g[r].n;
   return FFTNK_OK;
+}
+
+int fftnk_launch_pass(fftnk_ctx* c, int pass) {
+  if (!c || pass < 1 || pass > 5) return FFTNK_EINVAL;
+  if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
+  const Launch L = c->launch();
+  switch (pass) {
+    case 1:
+      launch_fwd_a2(c->prec, FWD_TANGENT, L, c->material(), c->p(), nullptr, nullptr, c->flin(), 1.0, c->spec(),
+                    nullptr);
+      break;
+    case 2: launch_col_a1(c->prec, false, L, c->spec(), nullptr); break;
+    case 3: launch_col_a0_project(c->prec, L, c->spec(), nullptr); break;
+    case 4: launch_col_a1(c->prec, true, L, c->spec(), nullptr); break;
+    default: launch_inv_a2(c->prec, INV_OUT, L, c->spec(), c->w(), c->prec, nullptr, nullptr, 1.0, nullptr); break;
+  }
+  return check_launch();
 }
 
 int fftnk_get_state(fftnk_ctx* c, double* F_dev) {
@@ -680,6 +836,8 @@ const char* fftnk_status_string(int s) {
 
 void fftnk_destroy(fftnk_ctx* c) {
   if (!c) return;
+  drop_graphs(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   if (c->pinned) (void)hipHostFree(c->pinned);
   delete c;
 }

@@ -1,0 +1,423 @@
+// Device helpers of libfftnk (gfx950): complex arithmetic, the two FFT engines,
+// deterministic block reductions, the work-group -> RVE map and the
+// St. Venant-Kirchhoff constitutive law.  Included by the kernel sources only.
+#pragma once
+
+#include "fftnk_internal.h"
+
+namespace fftnk {
+
+// ---------------------------------------------------------------------------
+// complex arithmetic
+// ---------------------------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) {
+  return {a.x * s, a.y * s};
+}
+// a * (+i) for the inverse direction, a * (-i) for the forward one
+template <typename T>
+__device__ __forceinline__ cx<T> rot(cx<T> a, bool inv) {
+  return inv ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
+}
+// W_n^e from the forward table (exp(-2 pi i e / n)); conjugated for the inverse
+template <typename T>
+__device__ __forceinline__ cx<T> twid(const cx<T>* tw, int e, bool inv) {
+  cx<T> w = tw[e];
+  if (inv) w.y = -w.y;
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// small DFTs in registers: v[q] <- sum_r v[r] W_R^{rq}, W_R = exp(-+2 pi i / R)
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+struct SmallDft {
+  // any radix through the length-n twiddle table (W_R^e = W_n^{e n/R})
+  __device__ __forceinline__ static void run(cx<T>* v, const cx<T>* tw, int n, bool inv) {
+    cx<T> o[R];
+    const int st = n / R;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      cx<T> s = v[0];
+#pragma unroll
+      for (int r = 1; r < R; ++r) s = s + cmul(v[r], twid(tw, ((r * q) % R) * st, inv));
+      o[q] = s;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = o[q];
+  }
+};
+
+template <typename T>
+struct SmallDft<T, 2> {
+  __device__ __forceinline__ static void run(cx<T>* v, const cx<T>*, int, bool) {
+    const cx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void dft4(cx<T>& v0, cx<T>& v1, cx<T>& v2, cx<T>& v3, bool inv) {
+  const cx<T> s02 = v0 + v2, d02 = v0 - v2, s13 = v1 + v3, d13 = rot(v1 - v3, inv);
+  v0 = s02 + s13;
+  v1 = d02 + d13;
+  v2 = s02 - s13;
+  v3 = d02 - d13;
+}
+
+template <typename T>
+struct SmallDft<T, 4> {
+  __device__ __forceinline__ static void run(cx<T>* v, const cx<T>*, int, bool inv) {
+    dft4(v[0], v[1], v[2], v[3], inv);
+  }
+};
+
+template <typename T>
+struct SmallDft<T, 8> {
+  __device__ __forceinline__ static void run(cx<T>* v, const cx<T>*, int, bool inv) {
+    cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3, inv);
+    dft4(o0, o1, o2, o3, inv);
+    const T h = (T)0.70710678118654752440;  // 1 / sqrt(2)
+    const T s = inv ? (T)1 : (T)-1;
+    o1 = cmul(o1, cx<T>{h, s * h});   // W_8
+    o2 = rot(o2, inv);                // W_8^2
+    o3 = cmul(o3, cx<T>{-h, s * h});  // W_8^3
+    v[0] = e0 + o0;
+    v[4] = e0 - o0;
+    v[1] = e1 + o1;
+    v[5] = e1 - o1;
+    v[2] = e2 + o2;
+    v[6] = e2 - o2;
+    v[3] = e3 + o3;
+    v[7] = e3 - o3;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// LDS engine (any length): Stockham autosort stages on `npen` pencils of
+// length n held in LDS, element e of pencil m at m*sp + e*se.  Ns is the
+// product of the previous radices.  Butterfly j (0 <= j < n/R) reads
+// e = j + r n/R, applies W_{Ns R}^{k r} (k = j mod Ns), does an R-point DFT and
+// writes e = (j - k) R + k + r Ns.  pen_fast selects which index consecutive
+// threads walk (pencils for column tiles, butterflies for row tiles).
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__device__ __forceinline__ void stage_lds(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n, int Ns, int npen, int sp,
+                          int se, const cx<T>* tw, bool inv, bool pen_fast) {
+  const int nbf = n / R;
+  const int total = nbf * npen;
+  const int tws = n / (Ns * R);
+  for (int b = threadIdx.x; b < total; b += kThreads) {
+    int m, j;
+    if (pen_fast) {
+      j = b / npen;
+      m = b - j * npen;
+    } else {
+      m = b / nbf;
+      j = b - m * nbf;
+    }
+    const cx<T>* s = src + m * sp;
+    cx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = s[(j + r * nbf) * se];
+    const int k = j % Ns;
+    if (k != 0) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twid(tw, k * r * tws, inv));
+    }
+    SmallDft<T, R>::run(v, tw, n, inv);
+    cx<T>* d = dst + m * sp;
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[(base + r * Ns) * se] = v[r];
+  }
+}
+
+// Stage for a prime radix R > 8: one output per thread, direct sum.
+// Output q of butterfly j: sum_r x[j + r n/R] W_n^{r (k n/(Ns R) + q n/R)}.
+template <typename T>
+__device__ __forceinline__ void stage_lds_prime(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n, int Ns, int R,
+                                int npen, int sp, int se, const cx<T>* tw, bool inv, bool pen_fast) {
+  const int nbf = n / R;
+  const int total = n * npen;
+  const int tws = n / (Ns * R);
+  for (int b = threadIdx.x; b < total; b += kThreads) {
+    int m, idx;
+    if (pen_fast) {
+      idx = b / npen;
+      m = b - idx * npen;
+    } else {
+      m = b / n;
+      idx = b - m * n;
+    }
+    const int q = idx / nbf, j = idx - q * nbf;
+    const int k = j % Ns;
+    const int e = k * tws + q * nbf;  // < n
+    const cx<T>* s = src + m * sp;
+    cx<T> acc = s[j * se];
+    int er = e;
+    for (int r = 1; r < R; ++r) {
+      acc = acc + cmul(s[(j + r * nbf) * se], twid(tw, er, inv));
+      er += e;
+      if (er >= n) er -= n;
+    }
+    dst[m * sp + ((j - k) * R + k + q * Ns) * se] = acc;
+  }
+}
+
+// Full 1-D transform of npen pencils; buffers a (input) and b (scratch)
+// ping-pong.  Returns the buffer holding the result.  The caller synchronises
+// before (input written); the routine synchronises after every stage.
+template <typename T>
+__device__ __forceinline__ cx<T>* fft_lds(cx<T>* a, cx<T>* b, const AxisPlan& pl, int npen, int sp, int se, const cx<T>* tw,
+                          bool inv, bool pen_fast) {
+  int Ns = 1;
+  for (int s = 0; s < pl.nstages; ++s) {
+    const int R = pl.radix[s];
+    switch (R) {
+      case 2: stage_lds<T, 2>(a, b, pl.n, Ns, npen, sp, se, tw, inv, pen_fast); break;
+      case 3: stage_lds<T, 3>(a, b, pl.n, Ns, npen, sp, se, tw, inv, pen_fast); break;
+      case 4: stage_lds<T, 4>(a, b, pl.n, Ns, npen, sp, se, tw, inv, pen_fast); break;
+      case 5: stage_lds<T, 5>(a, b, pl.n, Ns, npen, sp, se, tw, inv, pen_fast); break;
+      case 7: stage_lds<T, 7>(a, b, pl.n, Ns, npen, sp, se, tw, inv, pen_fast); break;
+      case 8: stage_lds<T, 8>(a, b, pl.n, Ns, npen, sp, se, tw, inv, pen_fast); break;
+      default: stage_lds_prime<T>(a, b, pl.n, Ns, R, npen, sp, se, tw, inv, pen_fast); break;
+    }
+    __syncthreads();
+    cx<T>* t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident engine (power-of-two lengths n >= 8, radices 8 / 4 / 2).
+// A pencil is split over Tp = n / kRegP threads; thread t holds
+// v[q] = x[t + Tp q], q < kRegP, for the whole transform.  In every Stockham
+// stage the butterflies of thread t are j = t + k Tp (k < kRegP / R) and their
+// inputs are exactly its own registers v[k + r kRegP/R]; only the outputs move,
+// through one LDS exchange per stage (element e of the thread's pencil at
+// xl[e * es]), and the outputs of the last stage land in natural order on the
+// same register slots, so loads from and stores to global memory need no LDS.
+// All threads of the work-group must call it (it contains barriers).
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__device__ __forceinline__ void reg_stage(cx<T> (&v)[kRegP], int t, int Tp, int n, int Ns, const cx<T>* tw, bool inv,
+                                          cx<T>* xl, int es, bool last) {
+  constexpr int B = kRegP / R;
+  const int tws = n / (Ns * R);
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    cx<T> a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = v[k + r * B];
+    const int j = t + k * Tp;
+    const int kk = j & (Ns - 1);  // Ns is a power of two
+    if (kk != 0) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) a[r] = cmul(a[r], twid(tw, kk * r * tws, inv));
+    }
+    SmallDft<T, R>::run(a, tw, n, inv);
+    if (last) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[k + r * B] = a[r];
+    } else {
+      const int base = (j - kk) * R + kk;
+#pragma unroll
+      for (int r = 0; r < R; ++r) xl[(base + r * Ns) * es] = a[r];
+    }
+  }
+  if (!last) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kRegP; ++q) v[q] = xl[(t + Tp * q) * es];
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void reg_fft(cx<T> (&v)[kRegP], const AxisPlan& pl, int t, int Tp, const cx<T>* tw,
+                                        bool inv, cx<T>* xl, int es) {
+  int Ns = 1;
+  for (int s = 0; s < pl.nstages; ++s) {
+    const int R = pl.radix[s];
+    const bool last = s == pl.nstages - 1;
+    if (R == 8)
+      reg_stage<T, 8>(v, t, Tp, pl.n, Ns, tw, inv, xl, es, last);
+    else if (R == 4)
+      reg_stage<T, 4>(v, t, Tp, pl.n, Ns, tw, inv, xl, es, last);
+    else
+      reg_stage<T, 2>(v, t, Tp, pl.n, Ns, tw, inv, xl, es, last);
+    Ns *= R;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ const cx<T>* table_of(const Batch& B) {
+  return reinterpret_cast<const cx<T>*>(sizeof(T) == 8 ? B.tw64 : B.tw32);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_twiddles(cx<T>* dst, const Batch& B, int off, int n) {
+  const cx<T>* src = table_of<T>(B) + off;
+  for (int i = threadIdx.x; i < n; i += kThreads) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// work-group -> RVE (binary search in the launch kind's start table)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_rve(const Batch& B, int kind, int b, int& local) {
+  const int* s = B.starts + kind * (B.nrve + 1);
+  int lo = 0, hi = B.nrve;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (s[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  local = b - s[lo];
+  return lo;
+}
+
+__device__ __forceinline__ int rve_blocks(const Batch& B, int kind, int r) {
+  const int* s = B.starts + kind * (B.nrve + 1);
+  return s[r + 1] - s[r];
+}
+
+// skip rule of a launch: CG launches skip RVEs whose CG is done, Newton-level
+// launches skip RVEs that have finished the increment
+__device__ __forceinline__ bool skip_rve(const Batch& B, const CgState* cg, int r) {
+  if (cg) return cg[r].done != 0;
+  return B.active && B.active[r] == 0;
+}
+
+// ---------------------------------------------------------------------------
+// deterministic block reduction (wave shuffles, then the waves in order)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+template <int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double* out /* K results, thread 0 */) {
+  __shared__ double red[kThreads / 64][K];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) red[wid][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < kThreads / 64; ++w) s += red[w][k];
+      out[k] = s;
+    }
+  }
+}
+
+__device__ __forceinline__ double* pslot(const Batch& B, int slot) { return B.partials + (long long)slot * B.pstride; }
+
+// Fixed-order sum of partials[lo, hi) by one work-group; result in every thread.
+__device__ __forceinline__ double reduce_range(const double* part, int lo, int hi) {
+  double s[1] = {0.0};
+  for (int i = lo + threadIdx.x; i < hi; i += kThreads) s[0] += part[i];
+  double res[1];
+  block_sums<1>(s, res);
+  __shared__ double bc;
+  if (threadIdx.x == 0) bc = res[0];
+  __syncthreads();
+  return bc;
+}
+
+// ---------------------------------------------------------------------------
+// St. Venant-Kirchhoff (Sec. 4.2) and its tangent action (Sec. 4.3), per voxel.
+//   S = lam tr(E) I + 2 mu E, E = (F^T F - I)/2, P = F S
+//   dP = p S + F [lam tr(F^T p) I + mu (F^T p + p^T F)]
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void svk_S(const T* F, T lam, T mu, T* S) {
+  T C[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = F[i] * F[j] + F[3 + i] * F[3 + j] + F[6 + i] * F[6 + j];
+  const T trE = (T)0.5 * (C[0] + C[4] + C[8] - (T)3);
+#pragma unroll
+  for (int c = 0; c < 9; ++c) S[c] = mu * C[c];
+  S[0] += lam * trE - mu;
+  S[4] += lam * trE - mu;
+  S[8] += lam * trE - mu;
+}
+
+template <typename T>
+__device__ __forceinline__ void mat33(const T* A, const T* B, T* C) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+template <typename T>
+__device__ __forceinline__ void svk_tangent(const T* F, const T* p, T lam, T mu, T* out) {
+  T S[9];
+  svk_S(F, lam, mu, S);
+  T A[9];  // F^T p
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) A[3 * i + j] = F[i] * p[j] + F[3 + i] * p[3 + j] + F[6 + i] * p[6 + j];
+  const T trA = A[0] + A[4] + A[8];
+  T B[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) B[3 * i + j] = mu * (A[3 * i + j] + A[3 * j + i]);
+  B[0] += lam * trA;
+  B[4] += lam * trA;
+  B[8] += lam * trA;
+  T t1[9], t2[9];
+  mat33(p, S, t1);
+  mat33(F, B, t2);
+#pragma unroll
+  for (int c = 0; c < 9; ++c) out[c] = t1[c] + t2[c];
+}
+
+// v: global voxel index (over all RVEs)
+__device__ __forceinline__ void material_at(const Material& mat, long long v, double& lam, double& mu) {
+  const int ph = mat.phase[v];
+  const double* row = mat.table + 4 * ph;
+  mu = mat.mu_field ? mat.mu_field[v] : row[1];
+  lam = row[0] - 2.0 * mu / 3.0;
+}
+
+__device__ __forceinline__ int signed_freq(int k, int n) { return 2 * k > n ? k - n : k; }
+
+}  // namespace fftnk

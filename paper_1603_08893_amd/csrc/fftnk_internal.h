@@ -14,14 +14,16 @@ constexpr int kMaxStages = 12;     // radix stages of one 1-D transform
 constexpr int kMaxPhase = 16;      // material phases
 constexpr int kMaxLen = 256;       // longest supported grid axis
 constexpr int kMaxRve = 256;       // RVEs of one batched context
-constexpr int kRedBlocks = 2048;   // grid of the element-wise kernels (partial-sum slots)
+constexpr int kRedBlocks = 2048;   // most work-groups of an element-wise kernel per RVE
+constexpr int kRegP = 8;           // points per thread of the register-resident FFT engine
 
 // Radix plan of one 1-D transform of length n: n = prod radix[s].
 struct AxisPlan {
   int n;
   int nstages;
   int radix[kMaxStages];
-  int tw;  // offset (in complex entries) of the length-n twiddle table W_n^e, e in [0, n)
+  int tw;   // offset (in complex entries) of the length-n twiddle table W_n^e, e in [0, n)
+  int reg;  // 1: power of two >= 8, transformed by the register-resident engine
 };
 
 // One periodic cell (RVE).  Real tensor fields are component-major
@@ -37,8 +39,21 @@ struct Grid {
   long long spec_off;
   double inv_n;
   int rt;           // grid lines per work-group in the a2 passes
-  int m64, m32;     // pencils per work-group in the a1 / a0 passes (FP64 / FP32)
+  int m64, m32;     // pencils per work-group in the LDS-engine a1 / a0 passes (FP64 / FP32)
   AxisPlan ax[3];
+};
+
+// Launch kinds: every kernel launch covers all RVEs of a context; work-group b
+// belongs to RVE r when starts[kind][r] <= b < starts[kind][r + 1].
+enum {
+  K_ROW = 0,     // a2 passes: grid lines
+  K_COL1_64,     // a1 pass, FP64
+  K_COL1_32,     // a1 pass, FP32
+  K_COL0_64,     // a0 + projection pass, FP64
+  K_COL0_32,     // a0 + projection pass, FP32
+  K_ELEM9,       // element-wise over 9 n values
+  K_VOX,         // per voxel
+  NKIND
 };
 
 // Material: St. Venant-Kirchhoff uses K, mu per phase (lambda = K - 2 mu / 3),
@@ -46,22 +61,22 @@ struct Grid {
 // yield stress and the linear hardening modulus.
 enum { MODEL_SVK = 0, MODEL_J2 = 1 };
 struct Material {
-  const uint8_t* phase;    // [n] phase index per voxel
-  const double* mu_field;  // [n] per-voxel mu, or null
+  const uint8_t* phase;    // [ntot] phase index per voxel
+  const double* mu_field;  // [ntot] per-voxel mu, or null
   const double* table;     // [nphase][4] device table: K, mu, tau_y0, H
   int model;
   int nphase;
 };
 
-// Slots of block partial sums (FP64), each kRedBlocks long... the a2 passes may
-// use more blocks, so every slot is sized for the largest grid.
+// Slots of block partial sums (FP64); each slot holds one value per work-group
+// of the launch that fills it.
 enum {
   SLOT_YY = 0,    // ||Y||^2, the field the projection was applied to (RHS)
   SLOT_BB = 1,    // ||b||^2 (RHS)
   SLOT_PW = 2,    // <p, A p>
   SLOT_RR = 3,    // <r, r>
   SLOT_DF = 4,    // ||dF||^2
-  SLOT_FF = 5,    // ||F||^2
+  SLOT_FF = 5,    // ||F_t + dFbar||^2
   SLOT_PBAR = 6,  // 9 slots: sum of P
   SLOT_FBAR = 15, // 9 slots: sum of F
   SLOT_AUX = 24,  // 2 spare slots
@@ -81,24 +96,28 @@ struct CgState {
   int max_cg;
   int stall_limit; // 0: off; else stop when rr_min has not improved for this many iterations
   int since_min;
-  int pad[2];
+  int zero_rhs;    // 1: ||b|| at the round-off floor of the projected field, dF = 0
+  int pad;
 };
 
-// Precision-independent launch arguments of one RVE.
-struct PassArgs {
-  Grid g;
-  const void* tw64;  // double2 twiddle tables
-  const void* tw32;  // float2 twiddle tables
-  double* partials;  // [NSLOT][pstride]
+// Everything a launch needs to find its RVE, tables and partial-sum slots.
+struct Batch {
+  const Grid* grids;    // [nrve] device copy of the grids
+  const int* starts;    // [NKIND][nrve + 1] first work-group of each RVE per launch kind
+  const int* active;    // [nrve] Newton-level mask: 0 = RVE finished for this increment
+  const double* uni;    // [nrve][9] per-RVE uniform tensor (load increment, cotangent, ...)
+  const void* tw64;     // double2 twiddle tables
+  const void* tw32;     // float2 twiddle tables
+  double* partials;     // [NSLOT][pstride]
   long long pstride;
-  int slot_base;     // per-RVE offset added to partial indices (batched: 0)
+  int nrve;
 };
 
 // Modes of the first (a2, forward) pass.
 enum {
   FWD_COPY = 0,        // transform the input field itself (scaled)
   FWD_TANGENT = 1,     // transform K(F) : p
-  FWD_TANGENT_UNI = 2, // transform K(F) : U with a uniform U (9 doubles)
+  FWD_TANGENT_UNI = 2, // transform K(F) : U with the RVE's uniform tensor U (Batch::uni)
   FWD_CG = 3           // p <- r + beta p (or r on the first iteration), then K(F) : p
 };
 // Modes of the last (a2, inverse) pass.
@@ -110,39 +129,44 @@ enum {
 
 enum { PREC_F64 = 0, PREC_F32 = 1 };
 
-// ---- launchers (fftnk_kernels.hip) ----------------------------------------
-// prec selects the storage / arithmetic type of the transforms and of the
-// vectors named "T" below; F, P, material data are always FP64 except Flin32.
-void launch_fwd_a2(int prec, int mode, const PassArgs& a, const Material& mat, const void* in_T,
-                   const void* r_T, void* p_T, const void* Flin, const double* uni, double scale,
-                   void* spec, const CgState* cg, hipStream_t s);
-void launch_col_a1(int prec, bool inverse, const PassArgs& a, void* spec, const CgState* cg, hipStream_t s);
-void launch_col_a0_project(int prec, const PassArgs& a, void* spec, const CgState* cg, hipStream_t s);
-void launch_inv_a2(int prec, int mode, const PassArgs& a, const void* spec, void* out_T, int out_prec,
-                   const void* p_T, void* x_T, double scale, const CgState* cg, hipStream_t s);
+// ---- launch geometry (shared by host and kernels) --------------------------
+int row_blocks(const Grid& g);
+int col1_blocks(const Grid& g, int prec);
+int col0_blocks(const Grid& g, int prec);
+int elem_blocks(long long m);
 
-void launch_cg_update(int prec, const PassArgs& a, void* x_T, void* r_T, const void* p_T, const void* w_T,
-                      CgState* cg, hipStream_t s);
-void launch_cg_alpha(const PassArgs& a, int nblk_pw, CgState* cg, hipStream_t s);
-void launch_cg_beta(const PassArgs& a, CgState* cg, hipStream_t s);
-void launch_cg_init(const PassArgs& a, int nblk_bb, CgState* cg, double eta, int max_cg, int stall,
-                    hipStream_t s);
+// ---- launchers (fftnk_fft_kernels.hip) ------------------------------------
+// nblk_* is the total work-group count of the launch kind (sum over RVEs).
+// cg == nullptr: Newton-level launch (RVEs with active == 0 are skipped);
+// cg != nullptr: CG launch (RVEs whose CG is done are skipped).
+struct Launch {
+  Batch b;
+  int nblk[NKIND];
+  size_t lds_row64, lds_row32, lds_col1_64, lds_col1_32, lds_col0_64, lds_col0_32;
+  hipStream_t s;
+};
+void launch_fwd_a2(int prec, int mode, const Launch& L, const Material& mat, const void* in_T, const void* r_T,
+                   void* p_T, const void* Flin, double scale, void* spec, const CgState* cg);
+void launch_col_a1(int prec, bool inverse, const Launch& L, void* spec, const CgState* cg);
+void launch_col_a0_project(int prec, const Launch& L, void* spec, const CgState* cg);
+void launch_inv_a2(int prec, int mode, const Launch& L, const void* spec, void* out_T, int out_prec,
+                   const void* p_T, void* x_T, double scale, const CgState* cg);
 
-void launch_set_F(const PassArgs& a, const double* Ft, double* F, const double* dFbar, float* Flin32,
-                  hipStream_t s);
-void launch_newton_update(int prec, const PassArgs& a, const Material& mat, double* F, const void* x_T,
-                          double* P, float* Flin32, hipStream_t s);
-void launch_constitutive(const PassArgs& a, const Material& mat, const double* F, double* P, hipStream_t s);
-void launch_field_sum(const PassArgs& a, const double* X, int slot0, hipStream_t s);
-void launch_reduce(const PassArgs& a, int slot0, int nslots, int nblk, double* out, hipStream_t s);
+// ---- launchers (fftnk_solver_kernels.hip) ---------------------------------
+void launch_cg_update(int prec, const Launch& L, void* x_T, void* r_T, const void* p_T, const void* w_T,
+                      CgState* cg);
+void launch_cg_alpha(const Launch& L, CgState* cg);
+void launch_cg_beta(const Launch& L, CgState* cg);
+void launch_cg_init(const Launch& L, CgState* cg, double eta, int max_cg, int stall);
+void launch_set_F(const Launch& L, const double* Ft, double* F, float* Flin32);
+void launch_newton_update(int prec, const Launch& L, const Material& mat, double* F, const void* x_T, double* P,
+                          float* Flin32, bool add_uni);
+void launch_constitutive(const Launch& L, const Material& mat, const double* F, double* P);
+void launch_field_sum(const Launch& L, const double* X, int slot0);
+// out[r * NSLOT + slot0 + s] = sum over RVE r's work-groups of slot slot0 + s, for s < nslots
+void launch_reduce(const Launch& L, int kind, int slot0, int nslots, double* out);
 void launch_convert(int to_prec, const void* in, void* out, long long count, hipStream_t s);
-void launch_fill_zero(int prec, void* x, long long count, hipStream_t s);
-void launch_set_identity(const PassArgs& a, double* F, hipStream_t s);
-void launch_adjoint_grad(int prec, const PassArgs& a, const double* F, const void* w, const double* g, double* dmu,
-                         double* dK, long long out_off, hipStream_t s);
-
-int fwd_a2_blocks(const Grid& g);
-int elem_blocks_vox(const Grid& g);
-int inv_a2_blocks(const Grid& g);
+void launch_set_identity(const Launch& L, double* F);
+void launch_adjoint_grad(int prec, const Launch& L, const double* F, const void* w, double* dmu, double* dK);
 
 }  // namespace fftnk

@@ -1,0 +1,413 @@
+// CG, Newton and reduction kernels of libfftnk (gfx950).
+//
+// CG on the projected-tangent operator (de Geus et al. 2017, Sec. 2.6: a
+// projection-based Krylov solver that keeps every iterate compatible; Sec. 3:
+// solved to accuracy eta_CG), with all scalars resident on the device so that
+// iterations can be replayed without host round trips; the Newton-level
+// element-wise steps of Algorithm 1 (increment of the macroscopic deformation,
+// iterative update F += dF with the constitutive update, homogenised stress);
+// and the adjoint gradient.  Every launch covers all RVEs of a context.
+// Reductions: block partial sums in fixed slots, summed in a fixed order by one
+// work-group per RVE, so results are bitwise reproducible.
+#include "fftnk_device.h"
+
+namespace fftnk {
+
+enum { ST_OK = 0, ST_CG_MAXIT = 5, ST_CG_BREAKDOWN = 6, ST_NONFINITE = 8 };
+
+// loop over this work-group's share of the RVE's index range [0, m)
+#define FOR_RVE_RANGE(i, m, local, nb) \
+  for (long long i = (long long)(local) * kThreads + threadIdx.x; i < (m); i += (long long)(nb) * kThreads)
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_update(Batch B, T* __restrict__ x, T* __restrict__ r,
+                                                        const T* __restrict__ p, const T* __restrict__ w,
+                                                        const CgState* __restrict__ cg) {
+  int local;
+  const int rv = find_rve(B, K_ELEM9, blockIdx.x, local);
+  if (cg[rv].done) return;
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_ELEM9, rv);
+  const long long m = 9 * g.n, off = 9 * g.vox_off;
+  const T alpha = (T)cg[rv].alpha;
+  double acc[1] = {0.0};
+  FOR_RVE_RANGE(i, m, local, nb) {
+    const T xi = x[off + i] + alpha * p[off + i];
+    const T ri = r[off + i] - alpha * w[off + i];
+    x[off + i] = xi;
+    r[off + i] = ri;
+    acc[0] += (double)ri * (double)ri;
+  }
+  double res[1];
+  block_sums<1>(acc, res);
+  if (threadIdx.x == 0) pslot(B, SLOT_RR)[blockIdx.x] = res[0];
+}
+
+__device__ __forceinline__ int kstart(const Batch& B, int kind, int r) { return B.starts[kind * (B.nrve + 1) + r]; }
+
+// One work-group per RVE.  A finished RVE (Newton mask) gets done = 1 at once.
+// If ||b|| is at the round-off floor of the projected field Y
+// (||b|| <= 1e-14 ||Y||, or b = 0) the solve is skipped with dF = 0.
+__global__ __launch_bounds__(kThreads) void k_cg_init(Batch B, CgState* cg, double eta, int max_cg, int stall) {
+  const int rv = blockIdx.x;
+  CgState& s = cg[rv];
+  if (B.active && B.active[rv] == 0) {
+    if (threadIdx.x == 0) {
+      s.done = 1;
+      s.iter = 0;
+      s.status = ST_OK;
+      s.zero_rhs = 1;
+    }
+    return;
+  }
+  const int lo = kstart(B, K_ROW, rv), hi = kstart(B, K_ROW, rv + 1);
+  const double yy = reduce_range(pslot(B, SLOT_YY), lo, hi);
+  const double bb = reduce_range(pslot(B, SLOT_BB), lo, hi);
+  if (threadIdx.x == 0) {
+    s.bb = bb;
+    s.rr = bb;
+    s.rr_min = bb;
+    s.stop2 = eta * eta * bb;
+    s.alpha = 0.0;
+    s.beta = 0.0;
+    s.pw = 0.0;
+    s.iter = 0;
+    s.since_min = 0;
+    s.max_cg = max_cg;
+    s.stall_limit = stall;
+    s.status = isfinite(bb) ? ST_OK : ST_NONFINITE;
+    s.zero_rhs = (bb == 0.0 || sqrt(bb) <= 1e-14 * sqrt(yy)) ? 1 : 0;
+    s.done = (s.zero_rhs || !isfinite(bb) || bb <= s.stop2) ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_cg_alpha(Batch B, CgState* cg) {
+  const int rv = blockIdx.x;
+  CgState& s = cg[rv];
+  if (s.done) return;
+  const double pw = reduce_range(pslot(B, SLOT_PW), kstart(B, K_ROW, rv), kstart(B, K_ROW, rv + 1));
+  if (threadIdx.x == 0) {
+    s.pw = pw;
+    if (!(pw > 0.0) || !isfinite(pw)) {
+      // With the stagnation guard on (FP32 Krylov vectors), a non-positive
+      // curvature after the first iteration means the direction is round-off
+      // noise: stop and keep the last iterate, as for stagnation; the FP64
+      // Newton residual corrects the inexact update.  On the first iteration, or
+      // without the guard, it is a breakdown (indefinite tangent).
+      s.status = (s.stall_limit > 0 && s.iter > 0 && isfinite(pw)) ? ST_OK : ST_CG_BREAKDOWN;
+      s.done = 1;
+      s.alpha = 0.0;
+    } else {
+      s.alpha = s.rr / pw;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_cg_beta(Batch B, CgState* cg) {
+  const int rv = blockIdx.x;
+  CgState& s = cg[rv];
+  if (s.done) return;
+  const double rr = reduce_range(pslot(B, SLOT_RR), kstart(B, K_ELEM9, rv), kstart(B, K_ELEM9, rv + 1));
+  if (threadIdx.x == 0) {
+    s.iter += 1;
+    if (!isfinite(rr)) {
+      s.status = ST_NONFINITE;
+      s.done = 1;
+    } else if (rr <= s.stop2) {
+      s.rr = rr;
+      s.done = 1;
+    } else if (s.iter >= s.max_cg) {
+      s.rr = rr;
+      s.status = ST_CG_MAXIT;
+      s.done = 1;
+    } else {
+      s.beta = rr / s.rr;
+      s.rr = rr;
+      if (rr < s.rr_min) {
+        s.rr_min = rr;
+        s.since_min = 0;
+      } else {
+        s.since_min += 1;
+      }
+      if (s.stall_limit > 0 && s.since_min >= s.stall_limit) s.done = 1;  // stagnation: keep x
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Newton-level element-wise kernels (Alg. 1).
+// ---------------------------------------------------------------------------
+
+// Start of an increment: F = F_t (the tangent of the first solve is taken about
+// the start state, Sec. 3.1), ||F_t + dFbar||^2 for the convergence test's
+// denominator, and the FP32 copy of the linearisation point.
+__global__ __launch_bounds__(kThreads) void k_set_F(Batch B, const double* __restrict__ Ft, double* __restrict__ F,
+                                                    float* __restrict__ Flin32) {
+  int local;
+  const int rv = find_rve(B, K_VOX, blockIdx.x, local);
+  if (skip_rve(B, nullptr, rv)) return;
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_VOX, rv);
+  const long long n = g.n, off = 9 * g.vox_off;
+  const double* u = B.uni + 9 * rv;
+  double acc[1] = {0.0};
+  FOR_RVE_RANGE(v, n, local, nb) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const double ft = Ft[off + c * n + v];
+      F[off + c * n + v] = ft;
+      const double f = ft + u[c];
+      acc[0] += f * f;
+      if (Flin32) Flin32[off + c * n + v] = (float)ft;
+    }
+  }
+  double res[1];
+  block_sums<1>(acc, res);
+  if (threadIdx.x == 0) pslot(B, SLOT_FF)[blockIdx.x] = res[0];
+}
+
+// F += dF (+ dFbar on the first iteration), constitutive update P = P(F),
+// ||dF||^2 and the sums of P; the next linearisation point in FP32.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_newton_update(Batch B, Material mat, double* __restrict__ F,
+                                                            const T* __restrict__ x, double* __restrict__ P,
+                                                            float* __restrict__ Flin32, int add_uni) {
+  int local;
+  const int rv = find_rve(B, K_VOX, blockIdx.x, local);
+  if (skip_rve(B, nullptr, rv)) return;
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_VOX, rv);
+  const long long n = g.n, off = 9 * g.vox_off;
+  double u[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) u[c] = add_uni ? B.uni[9 * rv + c] : 0.0;
+  double acc[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+  FOR_RVE_RANGE(v, n, local, nb) {
+    double f[9], S[9], Pv[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      const double d = (double)x[off + c * n + v];
+      f[c] = F[off + c * n + v] + u[c] + d;
+      F[off + c * n + v] = f[c];
+      acc[0] += d * d;
+      if (Flin32) Flin32[off + c * n + v] = (float)f[c];
+    }
+    double lam, mu;
+    material_at(mat, g.vox_off + v, lam, mu);
+    svk_S<double>(f, lam, mu, S);
+    mat33<double>(f, S, Pv);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      P[off + c * n + v] = Pv[c];
+      acc[1 + c] += Pv[c];
+    }
+  }
+  double res[10];
+  block_sums<10>(acc, res);
+  if (threadIdx.x == 0) {
+    pslot(B, SLOT_DF)[blockIdx.x] = res[0];
+    for (int c = 0; c < 9; ++c) pslot(B, SLOT_PBAR + c)[blockIdx.x] = res[1 + c];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_constitutive(Batch B, Material mat, const double* __restrict__ F,
+                                                           double* __restrict__ P) {
+  int local;
+  const int rv = find_rve(B, K_VOX, blockIdx.x, local);
+  if (skip_rve(B, nullptr, rv)) return;
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_VOX, rv);
+  const long long n = g.n, off = 9 * g.vox_off;
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  FOR_RVE_RANGE(v, n, local, nb) {
+    double f[9], S[9], Pv[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) f[c] = F[off + c * n + v];
+    double lam, mu;
+    material_at(mat, g.vox_off + v, lam, mu);
+    svk_S<double>(f, lam, mu, S);
+    mat33<double>(f, S, Pv);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      P[off + c * n + v] = Pv[c];
+      acc[c] += Pv[c];
+    }
+  }
+  double res[9];
+  block_sums<9>(acc, res);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 9; ++c) pslot(B, SLOT_PBAR + c)[blockIdx.x] = res[c];
+}
+
+__global__ __launch_bounds__(kThreads) void k_field_sum(Batch B, const double* __restrict__ X, int slot0) {
+  int local;
+  const int rv = find_rve(B, K_VOX, blockIdx.x, local);
+  if (skip_rve(B, nullptr, rv)) return;
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_VOX, rv);
+  const long long n = g.n, off = 9 * g.vox_off;
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  FOR_RVE_RANGE(v, n, local, nb) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] += X[off + c * n + v];
+  }
+  double res[9];
+  block_sums<9>(acc, res);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 9; ++c) pslot(B, slot0 + c)[blockIdx.x] = res[c];
+}
+
+// out[r * NSLOT + slot0 + s]: grid (nrve, nslots)
+__global__ __launch_bounds__(kThreads) void k_reduce(Batch B, int kind, int slot0, double* out) {
+  const int rv = blockIdx.x, s = blockIdx.y;
+  const double v = reduce_range(pslot(B, slot0 + s), kstart(B, kind, rv), kstart(B, kind, rv + 1));
+  if (threadIdx.x == 0) out[rv * NSLOT + slot0 + s] = v;
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kThreads) void k_convert(const TI* __restrict__ in, TO* __restrict__ out, long long m) {
+  for (long long i = blockIdx.x * (long long)kThreads + threadIdx.x; i < m; i += (long long)gridDim.x * kThreads)
+    out[i] = (TO)in[i];
+}
+
+// F = I on every voxel (the stress-free start of Algorithm 1).
+__global__ __launch_bounds__(kThreads) void k_set_identity(Batch B, double* __restrict__ F) {
+  int local;
+  const int rv = find_rve(B, K_VOX, blockIdx.x, local);
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_VOX, rv);
+  const long long n = g.n, off = 9 * g.vox_off;
+  FOR_RVE_RANGE(v, n, local, nb) {
+#pragma unroll
+    for (int c = 0; c < 9; ++c) F[off + c * n + v] = (c % 4 == 0) ? 1.0 : 0.0;
+  }
+}
+
+// Adjoint gradient per voxel at the converged F with adjoint field w and the
+// RVE's cotangent g (Batch::uni):
+//   dL/dmu = (1/n) (g - w) : F . 2 dev(E),  dL/dK = (1/n) (g - w) : tr(E) F
+// (S = (K - 2mu/3) tr(E) I + 2 mu E).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_adjoint_grad(Batch B, const double* __restrict__ F,
+                                                           const T* __restrict__ w, double* __restrict__ dmu,
+                                                           double* __restrict__ dK) {
+  int local;
+  const int rv = find_rve(B, K_VOX, blockIdx.x, local);
+  if (skip_rve(B, nullptr, rv)) return;
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_VOX, rv);
+  const long long n = g.n, off = 9 * g.vox_off;
+  const double* gb = B.uni + 9 * rv;
+  FOR_RVE_RANGE(v, n, local, nb) {
+    double f[9], d[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      f[c] = F[off + c * n + v];
+      d[c] = gb[c] - (double)w[off + c * n + v];
+    }
+    double C[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) C[3 * i + j] = f[i] * f[j] + f[3 + i] * f[3 + j] + f[6 + i] * f[6 + j];
+    const double trE = 0.5 * (C[0] + C[4] + C[8] - 3.0);
+    double D[9];  // 2 dev E = C - I - (2/3) tr(E) I
+#pragma unroll
+    for (int c = 0; c < 9; ++c) D[c] = C[c];
+    D[0] -= 1.0 + 2.0 * trE / 3.0;
+    D[4] -= 1.0 + 2.0 * trE / 3.0;
+    D[8] -= 1.0 + 2.0 * trE / 3.0;
+    double Q[9];
+    mat33<double>(f, D, Q);
+    double smu = 0.0, sK = 0.0;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      smu += d[c] * Q[c];
+      sK += d[c] * f[c];
+    }
+    dmu[g.vox_off + v] = smu * g.inv_n;
+    if (dK) dK[g.vox_off + v] = sK * trE * g.inv_n;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_cg_update(int prec, const Launch& L, void* x, void* r, const void* p, const void* w, CgState* cg) {
+  const dim3 grid(L.nblk[K_ELEM9]), block(kThreads);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL((k_cg_update<double>), grid, block, 0, L.s, L.b, static_cast<double*>(x),
+                       static_cast<double*>(r), static_cast<const double*>(p), static_cast<const double*>(w), cg);
+  else
+    hipLaunchKernelGGL((k_cg_update<float>), grid, block, 0, L.s, L.b, static_cast<float*>(x),
+                       static_cast<float*>(r), static_cast<const float*>(p), static_cast<const float*>(w), cg);
+}
+
+void launch_cg_alpha(const Launch& L, CgState* cg) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(L.b.nrve), dim3(kThreads), 0, L.s, L.b, cg);
+}
+
+void launch_cg_beta(const Launch& L, CgState* cg) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(L.b.nrve), dim3(kThreads), 0, L.s, L.b, cg);
+}
+
+void launch_cg_init(const Launch& L, CgState* cg, double eta, int max_cg, int stall) {
+  hipLaunchKernelGGL(k_cg_init, dim3(L.b.nrve), dim3(kThreads), 0, L.s, L.b, cg, eta, max_cg, stall);
+}
+
+void launch_set_F(const Launch& L, const double* Ft, double* F, float* Flin32) {
+  hipLaunchKernelGGL(k_set_F, dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, Ft, F, Flin32);
+}
+
+void launch_newton_update(int prec, const Launch& L, const Material& mat, double* F, const void* x, double* P,
+                          float* Flin32, bool add_uni) {
+  const dim3 grid(L.nblk[K_VOX]), block(kThreads);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL((k_newton_update<double>), grid, block, 0, L.s, L.b, mat, F, static_cast<const double*>(x), P,
+                       Flin32, add_uni ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_newton_update<float>), grid, block, 0, L.s, L.b, mat, F, static_cast<const float*>(x), P,
+                       Flin32, add_uni ? 1 : 0);
+}
+
+void launch_constitutive(const Launch& L, const Material& mat, const double* F, double* P) {
+  hipLaunchKernelGGL(k_constitutive, dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, mat, F, P);
+}
+
+void launch_field_sum(const Launch& L, const double* X, int slot0) {
+  hipLaunchKernelGGL(k_field_sum, dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, X, slot0);
+}
+
+void launch_reduce(const Launch& L, int kind, int slot0, int nslots, double* out) {
+  hipLaunchKernelGGL(k_reduce, dim3(L.b.nrve, nslots), dim3(kThreads), 0, L.s, L.b, kind, slot0, out);
+}
+
+void launch_convert(int to_prec, const void* in, void* out, long long count, hipStream_t s) {
+  const int nb = elem_blocks(count);
+  if (to_prec == PREC_F32)
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(nb), dim3(kThreads), 0, s, static_cast<const double*>(in),
+                       static_cast<float*>(out), count);
+  else
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(nb), dim3(kThreads), 0, s, static_cast<const float*>(in),
+                       static_cast<double*>(out), count);
+}
+
+void launch_set_identity(const Launch& L, double* F) {
+  hipLaunchKernelGGL(k_set_identity, dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, F);
+}
+
+void launch_adjoint_grad(int prec, const Launch& L, const double* F, const void* w, double* dmu, double* dK) {
+  const dim3 grid(L.nblk[K_VOX]), block(kThreads);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL((k_adjoint_grad<double>), grid, block, 0, L.s, L.b, F, static_cast<const double*>(w), dmu, dK);
+  else
+    hipLaunchKernelGGL((k_adjoint_grad<float>), grid, block, 0, L.s, L.b, F, static_cast<const float*>(w), dmu, dK);
+}
+
+}  // namespace fftnk

@@ -16,12 +16,13 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "li
 OK, EINVAL, ESTATE, ENOMEM, EHIP, ECG_MAXIT, ECG_BREAKDOWN, ENEWTON_MAXIT, ENONFINITE, EMATERIAL, EUNSUPPORTED = range(11)
 FP64, FP32_MIXED = 0, 1
 SVK, J2 = 0, 1
+OPT_GRAPHS, OPT_CHECK_EVERY = 1, 2
 MAX_SOLVES = 64
 
 # every symbol include/fftnk.h declares
 EXPORTS = [
     "fftnk_create", "fftnk_create_batched", "fftnk_workspace_bytes", "fftnk_bind_workspace", "fftnk_set_phases",
-    "fftnk_set_material", "fftnk_set_modulus_field", "fftnk_reset_state", "fftnk_solve_increment",
+    "fftnk_set_material", "fftnk_set_modulus_field", "fftnk_set_option", "fftnk_reset_state", "fftnk_solve_increment",
     "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_adjoint",
     "fftnk_launch_pass", "fftnk_get_state",
     "fftnk_set_state", "fftnk_status_string", "fftnk_destroy",
@@ -71,6 +72,7 @@ def lib():
     L.fftnk_set_phases.argtypes = [vp, vp]
     L.fftnk_set_material.argtypes = [vp, i, i, dp]
     L.fftnk_set_modulus_field.argtypes = [vp, vp]
+    L.fftnk_set_option.argtypes = [vp, i, i]
     L.fftnk_reset_state.argtypes = [vp]
     L.fftnk_solve_increment.argtypes = [vp, dp, d, d, i, i, vp, vp, dp, ctypes.POINTER(Stats)]
     L.fftnk_set_linearization.argtypes = [vp, vp]
@@ -179,6 +181,10 @@ class Solver:
         if t.numel() != self.ntot:
             raise FftnkError(EINVAL, "set_modulus_field: %d values for %d voxels" % (t.numel(), self.ntot))
         _check(lib().fftnk_set_modulus_field(self.ctx, ctypes.c_void_p(t.data_ptr())), "fftnk_set_modulus_field")
+
+    def set_option(self, option, value):
+        """OPT_GRAPHS (replay CG iterations from HIP graphs) or OPT_CHECK_EVERY."""
+        _check(lib().fftnk_set_option(self.ctx, int(option), int(value)), "fftnk_set_option")
 
     def reset_state(self):
         _check(lib().fftnk_reset_state(self.ctx), "fftnk_reset_state")
