@@ -82,6 +82,14 @@ def lib():
         L.orc_solve_increment.restype = i
         L.orc_adjoint.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, i, dp, dp, ctypes.POINTER(i)]
         L.orc_adjoint.restype = i
+        L.orc_jacobi_eig3.argtypes = [dp, dp, dp]
+        L.orc_j2_stress.argtypes = [ctypes.c_long, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_j2_stress.restype = i
+        L.orc_j2_tangent.argtypes = [ctypes.c_long, dp, dp, dp, dp, dp, dp, dp, dp]
+        L.orc_j2_tangent.restype = i
+        L.orc_solve_increment_j2.argtypes = [i, i, i, dp, dp, dp, dp, dp, dp, dp, ctypes.c_double,
+                                             ctypes.c_double, i, i, dp, dp, ctypes.POINTER(Stats)]
+        L.orc_solve_increment_j2.restype = i
         _lib = L
     return _lib
 
@@ -223,3 +231,62 @@ def solve_increment(K, mu, F, Fbar, eta_nw=1e-5, eta_cg=1e-8, max_newton=50, max
                                        eta_nw, eta_cg, max_newton, max_cg, _p(P), _p(Pbar),
                                        ctypes.byref(st))
     return status, F, P, Pbar, st.as_dict()
+
+
+# ---------------------------------------------------------------- J2 plasticity
+def virgin_history(shape):
+    """C_p^-1 = I (xx yy zz xy yz xz) and eps_p = 0, shape (7, *grid)."""
+    h = np.zeros((7,) + tuple(shape))
+    h[0] = h[1] = h[2] = 1.0
+    return h
+
+
+def jacobi_eig3(A):
+    A = _c(np.asarray(A).reshape(9))
+    w = np.zeros(3)
+    V = np.zeros(9)
+    lib().orc_jacobi_eig3(_p(A), _p(w), _p(V))
+    return w, V.reshape(3, 3)
+
+
+def _j2_fields(F, K, mu, ty0, H):
+    F = _c(F)
+    grid = F.shape[1:]
+    b = lambda a: _c(np.broadcast_to(a, grid))
+    return F, b(K), b(mu), b(ty0), b(H), int(np.prod(grid))
+
+
+def j2_stress(F, K, mu, ty0, H, hist):
+    """(status, P, hist_new) of the return mapping at every voxel."""
+    F, K, mu, ty0, H, n = _j2_fields(F, K, mu, ty0, H)
+    hist = _c(hist)
+    P = np.zeros_like(F)
+    hn = np.zeros_like(hist)
+    st = lib().orc_j2_stress(n, _p(F), _p(K), _p(mu), _p(ty0), _p(H), _p(hist), _p(P), _p(hn))
+    return st, P, hn
+
+
+def j2_tangent(F, K, mu, ty0, H, hist, dF):
+    F, K, mu, ty0, H, n = _j2_fields(F, K, mu, ty0, H)
+    dF = _c(np.broadcast_to(dF, F.shape))
+    out = np.zeros_like(F)
+    st = lib().orc_j2_tangent(n, _p(F), _p(K), _p(mu), _p(ty0), _p(H), _c(hist).ctypes.data_as(
+        ctypes.POINTER(ctypes.c_double)), _p(dF), _p(out))
+    return st, out
+
+
+def solve_increment_j2(K, mu, ty0, H, hist, F, Fbar, eta_nw=1e-5, eta_cg=1e-8, max_newton=50, max_cg=10000):
+    """One J2 increment.  Returns (status, F_new, P, Pbar, hist_new, stats)."""
+    F = np.array(F, dtype=np.float64, copy=True, order="C")
+    grid = F.shape[1:]
+    b = lambda a: _c(np.broadcast_to(a, grid))
+    K, mu, ty0, H = b(K), b(mu), b(ty0), b(H)
+    hist = np.array(hist, dtype=np.float64, copy=True, order="C")
+    Fbar = _c(np.asarray(Fbar, dtype=np.float64).reshape(9))
+    P = np.zeros_like(F)
+    Pbar = np.zeros(9)
+    st = Stats()
+    status = lib().orc_solve_increment_j2(grid[0], grid[1], grid[2], _p(K), _p(mu), _p(ty0), _p(H), _p(hist),
+                                          _p(F), _p(Fbar), eta_nw, eta_cg, max_newton, max_cg, _p(P), _p(Pbar),
+                                          ctypes.byref(st))
+    return status, F, P, Pbar, hist, st.as_dict()

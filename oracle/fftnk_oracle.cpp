@@ -41,6 +41,7 @@ enum {
   ORC_ENEWTON_MAXIT = 3,
   ORC_ENONFINITE = 4,
   ORC_EINVAL = 5,
+  ORC_EMATERIAL = 6,
 };
 
 #define ORC_MAX_SOLVES 64
@@ -350,14 +351,22 @@ static bool all_finite(const double* a, long m) {
 }
 
 // ---------------------------------------------------------------------------
-// Material description shared by the routines below.  model 0 = St. Venant-
-// Kirchhoff with per-voxel (K, mu).
+// Material description shared by the routines below: model 0 = St. Venant-
+// Kirchhoff with per-voxel (K, mu); model 1 = finite-strain J2 plasticity with
+// per-voxel (K, mu, tau_y0, H) and the committed history hist [7][n].
 // ---------------------------------------------------------------------------
 typedef struct {
   int n0, n1, n2;
   const double* K;
   const double* mu;
+  int model;
+  const double* ty0;
+  const double* H;
+  const double* hist;
 } orc_problem;
+
+static int law_stress(const orc_problem& pb, const double* F, double* P, double* hist_new);
+static void law_tangent(const orc_problem& pb, const double* F, const double* dF, double* dP);
 
 // The projected-tangent operator of the linearised system (eq. iter:system):
 // A p = G( K_(i) applied to p ) with the tangent taken at F_lin.
@@ -391,7 +400,11 @@ static int cg_solve(const orc_problem& pb, const double* Flin, const double* b, 
   }
   while (true) {
     if (*iters >= max_cg) return ORC_ECG_MAXIT;
-    orc_apply_operator(pb.n0, pb.n1, pb.n2, pb.K, pb.mu, Flin, p.data(), w.data());
+    {
+      std::vector<double> t(m);
+      law_tangent(pb, Flin, p.data(), t.data());
+      orc_project(pb.n0, pb.n1, pb.n2, t.data(), w.data());
+    }
     ++*iters;
     const double pw = dot(p.data(), w.data(), m);
     if (!(pw > 0.0) || !std::isfinite(pw)) return ORC_ECG_BREAKDOWN;
@@ -438,11 +451,11 @@ static int cg_or_zero(const orc_problem& pb, const double* Flin, const double* b
 // F holds F_t on entry and the converged field on exit (unchanged on failure).
 // P receives the stress of the converged field and Pbar its voxel mean.
 // ---------------------------------------------------------------------------
-int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* mu, double* F,
-                        const double* Fbar, double eta_nw, double eta_cg, int max_newton, int max_cg,
-                        double* P, double* Pbar, orc_stats* st) {
+static int solve_increment_impl(const orc_problem& pb, double* F, const double* Fbar, double eta_nw,
+                                double eta_cg, int max_newton, int max_cg, double* P, double* Pbar,
+                                double* hist_new, orc_stats* st) {
+  const int n0 = pb.n0, n1 = pb.n1, n2 = pb.n2;
   const long n = (long)n0 * n1 * n2, m = 9 * n;
-  orc_problem pb{n0, n1, n2, K, mu};
   orc_stats local;
   if (!st) st = &local;
   std::memset(st, 0, sizeof(*st));
@@ -455,6 +468,7 @@ int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* m
     return ORC_ENONFINITE;
   }
   std::vector<double> Ft(F, F + m), Fc(F, F + m), Flin(F, F + m), b(m), Y(m), dF(m), Pc(m);
+  std::vector<double> hn(pb.model == 1 ? 7 * n : 0);
 
   // macroscopic increment relative to the mean of the start state
   double dFbar[9];
@@ -473,7 +487,7 @@ int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* m
     std::vector<double> U(m);
     for (int c = 0; c < 9; ++c)
       for (long v = 0; v < n; ++v) U[c * n + v] = dFbar[c];
-    orc_svk_tangent(n, Ft.data(), K, mu, U.data(), Y.data());
+    law_tangent(pb, Ft.data(), U.data(), Y.data());
     orc_project(n0, n1, n2, Y.data(), b.data());
     for (long i = 0; i < m; ++i) b[i] = -b[i];
   }
@@ -499,7 +513,8 @@ int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* m
       status = ORC_ENONFINITE;
       break;
     }
-    orc_svk_stress(n, Fc.data(), K, mu, Pc.data());
+    status = law_stress(pb, Fc.data(), Pc.data(), hn.empty() ? nullptr : hn.data());
+    if (status != ORC_OK) break;
     for (long i = 0; i < m; ++i) Y[i] = Pc[i];
     orc_project(n0, n1, n2, Pc.data(), b.data());
     for (long i = 0; i < m; ++i) b[i] = -b[i];
@@ -514,6 +529,8 @@ int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* m
     F[i] = Fc[i];
     P[i] = Pc[i];
   }
+  if (hist_new && !hn.empty())
+    for (long i = 0; i < 7 * n; ++i) hist_new[i] = hn[i];  // "store history variables" (Alg. 1)
   for (int c = 0; c < 9; ++c) {
     double s = 0.0, comp = 0.0;
     for (long v = 0; v < n; ++v) {
@@ -525,6 +542,24 @@ int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* m
     Pbar[c] = s / (double)n;
   }
   return ORC_OK;
+}
+
+int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* mu, double* F,
+                        const double* Fbar, double eta_nw, double eta_cg, int max_newton, int max_cg,
+                        double* P, double* Pbar, orc_stats* st) {
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr};
+  return solve_increment_impl(pb, F, Fbar, eta_nw, eta_cg, max_newton, max_cg, P, Pbar, nullptr, st);
+}
+
+// One increment with the J2 law (Sec. 5): hist [7][n] holds the committed
+// history on entry and, on success only, the history of the converged state.
+int orc_solve_increment_j2(int n0, int n1, int n2, const double* K, const double* mu, const double* ty0,
+                           const double* H, double* hist, double* F, const double* Fbar, double eta_nw,
+                           double eta_cg, int max_newton, int max_cg, double* P, double* Pbar, orc_stats* st) {
+  const long n = (long)n0 * n1 * n2;
+  std::vector<double> h0(hist, hist + 7 * n);
+  orc_problem pb{n0, n1, n2, K, mu, 1, ty0, H, h0.data()};
+  return solve_increment_impl(pb, F, Fbar, eta_nw, eta_cg, max_newton, max_cg, P, Pbar, hist, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -546,7 +581,7 @@ int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* m
 int orc_adjoint(int n0, int n1, int n2, const double* K, const double* mu, const double* F, const double* g,
                 double eta_cg, int max_cg, double* dLdmu, double* dLdK, int* iters) {
   const long n = (long)n0 * n1 * n2, m = 9 * n;
-  orc_problem pb{n0, n1, n2, K, mu};
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr};
   std::vector<double> U(m), Y(m), b(m), w(m);
   for (int c = 0; c < 9; ++c)
     for (long v = 0; v < n; ++v) U[c * n + v] = g[c];
@@ -586,8 +621,294 @@ int orc_adjoint(int n0, int n1, int n2, const double* K, const double* mu, const
 // Exposed for tests: plain CG on the operator at a given linearisation point.
 int orc_cg(int n0, int n1, int n2, const double* K, const double* mu, const double* Flin, const double* b,
            double* x, double eta, int max_cg, int* iters, double* relres) {
-  orc_problem pb{n0, n1, n2, K, mu};
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr};
   return cg_solve(pb, Flin, b, x, eta, max_cg, iters, relres);
 }
 
+
+// ---------------------------------------------------------------------------
+// Finite-strain J2 elasto-plasticity (Sec. 5): multiplicative split
+// F = Fe Fp, Kirchhoff stress tau = C : ln(be)/2 (logarithmic elastic strain,
+// same isotropic C as Sec. 4), von Mises yield tau_eq - (tau_y0 + H eps_p) <= 0
+// with linear hardening (Sec. 5.5), associative flow integrated implicitly by
+// the exponential map (the elastic-predictor / plastic-corrector scheme the
+// paper takes from Simo 1992), P = tau F^-T (pull-back, Sec. 5.4).
+// History: C_p^-1 (symmetric, stored xx yy zz xy yz xz) and eps_p.
+// ---------------------------------------------------------------------------
+
+typedef double M3[3][3];
+
+static void m3_mul(const M3 A, const M3 B, M3 C) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += A[i][k] * B[k][j];
+      C[i][j] = s;
+    }
+}
+static void m3_T(const M3 A, M3 B) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) B[i][j] = A[j][i];
+}
+static void m3_from9(const double* a, M3 A) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) A[i][j] = a[3 * i + j];
+}
+static double m3_det(const M3 A) {
+  return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+         A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+}
+static void m3_inv(const M3 A, M3 B) {
+  const double d = m3_det(A);
+  B[0][0] = (A[1][1] * A[2][2] - A[1][2] * A[2][1]) / d;
+  B[0][1] = (A[0][2] * A[2][1] - A[0][1] * A[2][2]) / d;
+  B[0][2] = (A[0][1] * A[1][2] - A[0][2] * A[1][1]) / d;
+  B[1][0] = (A[1][2] * A[2][0] - A[1][0] * A[2][2]) / d;
+  B[1][1] = (A[0][0] * A[2][2] - A[0][2] * A[2][0]) / d;
+  B[1][2] = (A[0][2] * A[1][0] - A[0][0] * A[1][2]) / d;
+  B[2][0] = (A[1][0] * A[2][1] - A[1][1] * A[2][0]) / d;
+  B[2][1] = (A[0][1] * A[2][0] - A[0][0] * A[2][1]) / d;
+  B[2][2] = (A[0][0] * A[1][1] - A[0][1] * A[1][0]) / d;
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric 3x3 matrix: A = V diag(w) V^T
+// (columns of V are the eigenvectors).  Each step applies the plane rotation
+// that zeroes one off-diagonal entry (tan of the angle: the small root of
+// t^2 + 2 t theta - 1 = 0, theta = (a_qq - a_pp) / (2 a_pq)); sweeps repeat
+// until the off-diagonal part is negligible against the diagonal.
+void orc_jacobi_eig3(const double* a9, double* w, double* v9) {
+  M3 A, V = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  m3_from9(a9, A);
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const double diag = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off == 0.0 || off <= 1e-36 * diag) break;
+    const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (auto& pq : pairs) {
+      const int p = pq[0], q = pq[1];
+      if (A[p][q] == 0.0) continue;
+      const double theta = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+      const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+      const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+      M3 R = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}}, RT, tmp;
+      R[p][p] = c;
+      R[q][q] = c;
+      R[p][q] = s;
+      R[q][p] = -s;
+      m3_T(R, RT);
+      m3_mul(RT, A, tmp);
+      m3_mul(tmp, R, A);
+      A[p][q] = A[q][p] = 0.0;
+      m3_mul(V, R, tmp);
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) V[i][j] = tmp[i][j];
+    }
+  }
+  for (int i = 0; i < 3; ++i) w[i] = A[i][i];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) v9[3 * i + j] = V[i][j];
+}
+
+// The divided difference of ln: (ln x - ln y) / (x - y), 1/x at x = y.
+static double log_dd(double x, double y) {
+  const double z = (x - y) / y;
+  if (std::fabs(z) < 1e-6) return (1.0 - z / 2.0 + z * z / 3.0) / y;
+  return std::log1p(z) / (x - y);
+}
+
+// The return mapping at one point, everything the tangent needs.
+typedef struct {
+  M3 F, Fi, Q;       // F, F^-1, eigenvectors of the trial be
+  double beta[3];    // eigenvalues of the trial be
+  double tau_p[3];   // principal Kirchhoff stress
+  double n_p[3];     // flow direction N = (3/2) dev tau_tr / tau_eq_tr (principal)
+  double q_tr, dgam; // trial equivalent stress, plastic multiplier
+  double eps_e[3];   // principal elastic log strain after the return
+  int plastic;
+} j2_state;
+
+static int j2_return_map(const double* F9, const double* h, double K, double mu, double ty0, double Hh,
+                         j2_state* s) {
+  m3_from9(F9, s->F);
+  const double J = m3_det(s->F);
+  if (!(J > 0.0)) return ORC_EMATERIAL;
+  m3_inv(s->F, s->Fi);
+  const M3 Cpi = {{h[0], h[3], h[5]}, {h[3], h[1], h[4]}, {h[5], h[4], h[2]}};
+  M3 FT, t1, be;
+  m3_T(s->F, FT);
+  m3_mul(s->F, Cpi, t1);
+  m3_mul(t1, FT, be);  // trial be = F Cp^-1 F^T
+  double be9[9], Q9[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) be9[3 * i + j] = 0.5 * (be[i][j] + be[j][i]);
+  orc_jacobi_eig3(be9, s->beta, Q9);
+  m3_from9(Q9, s->Q);
+  double eps[3];
+  for (int a = 0; a < 3; ++a) {
+    if (!(s->beta[a] > 0.0)) return ORC_EMATERIAL;
+    eps[a] = 0.5 * std::log(s->beta[a]);
+  }
+  const double tr = eps[0] + eps[1] + eps[2];
+  double sdev[3], q2 = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    sdev[a] = 2.0 * mu * (eps[a] - tr / 3.0);
+    q2 += sdev[a] * sdev[a];
+  }
+  s->q_tr = std::sqrt(1.5 * q2);
+  const double phi = s->q_tr - (ty0 + Hh * h[6]);
+  s->plastic = phi > 1e-12 * ty0;
+  s->dgam = 0.0;
+  for (int a = 0; a < 3; ++a) s->n_p[a] = s->q_tr > 0.0 ? 1.5 * sdev[a] / s->q_tr : 0.0;
+  if (s->plastic) {
+    if (!(3.0 * mu + Hh > 0.0)) return ORC_EMATERIAL;
+    s->dgam = phi / (3.0 * mu + Hh);
+  }
+  for (int a = 0; a < 3; ++a) {
+    s->tau_p[a] = K * tr + sdev[a] - 2.0 * mu * s->dgam * s->n_p[a];
+    s->eps_e[a] = eps[a] - s->dgam * s->n_p[a];
+  }
+  return ORC_OK;
+}
+
+// P = tau F^-T and (optionally) the updated history of one point.
+static int j2_point_stress(const double* F9, const double* h, double K, double mu, double ty0, double Hh,
+                           double* P9, double* hnew) {
+  j2_state s;
+  const int st = j2_return_map(F9, h, K, mu, ty0, Hh, &s);
+  if (st != ORC_OK) return st;
+  M3 tau = {}, FiT, P;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int a = 0; a < 3; ++a) tau[i][j] += s.Q[i][a] * s.tau_p[a] * s.Q[j][a];
+  m3_T(s.Fi, FiT);
+  m3_mul(tau, FiT, P);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) P9[3 * i + j] = P[i][j];
+  if (hnew) {
+    // be = exp(2 eps_e) (coaxial with the trial be), Cp^-1 = F^-1 be F^-T
+    M3 be = {}, t1, Cpi;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        for (int a = 0; a < 3; ++a) be[i][j] += s.Q[i][a] * std::exp(2.0 * s.eps_e[a]) * s.Q[j][a];
+    m3_mul(s.Fi, be, t1);
+    m3_mul(t1, FiT, Cpi);
+    hnew[0] = Cpi[0][0];
+    hnew[1] = Cpi[1][1];
+    hnew[2] = Cpi[2][2];
+    hnew[3] = 0.5 * (Cpi[0][1] + Cpi[1][0]);
+    hnew[4] = 0.5 * (Cpi[1][2] + Cpi[2][1]);
+    hnew[5] = 0.5 * (Cpi[0][2] + Cpi[2][0]);
+    hnew[6] = h[6] + s.dgam;
+  }
+  return ORC_OK;
+}
+
+// Consistent tangent at frozen history applied to dF (Sec. 5.3-5.4):
+//   dbe = dF Cp^-1 F^T + F Cp^-1 dF^T
+//   d eps (eigenbasis of be) = 1/2 f(beta_a, beta_b) (Q^T dbe Q)_ab,  f = divided difference of ln
+//   d tau = K tr(d eps) I + 2 mu c1 dev(d eps) - c2 (N : 2 mu dev d eps) N
+//           c1 = 1 - 3 mu dgam / q_tr, c2 = 2 mu (1/(3 mu + H) - dgam / q_tr)  (plastic; c1 = 1, c2 = 0 elastic)
+//   dP = d tau F^-T - tau F^-T dF^T F^-T
+static int j2_point_tangent(const double* F9, const double* h, double K, double mu, double ty0, double Hh,
+                            const double* dF9, double* dP9) {
+  j2_state s;
+  const int st = j2_return_map(F9, h, K, mu, ty0, Hh, &s);
+  if (st != ORC_OK) return st;
+  const M3 Cpi = {{h[0], h[3], h[5]}, {h[3], h[1], h[4]}, {h[5], h[4], h[2]}};
+  M3 dF, dFT, FT, t1, t2, dbe, QT, tmp, dbq;
+  m3_from9(dF9, dF);
+  m3_T(dF, dFT);
+  m3_T(s.F, FT);
+  m3_mul(dF, Cpi, t1);
+  m3_mul(t1, FT, t2);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) dbe[i][j] = t2[i][j] + t2[j][i];
+  m3_T(s.Q, QT);
+  m3_mul(QT, dbe, tmp);
+  m3_mul(tmp, s.Q, dbq);
+  M3 de;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) de[a][b] = 0.5 * log_dd(s.beta[a], s.beta[b]) * dbq[a][b];
+  const double tr = de[0][0] + de[1][1] + de[2][2];
+  M3 dtp;
+  double Nds = 0.0;
+  for (int a = 0; a < 3; ++a) Nds += s.n_p[a] * 2.0 * mu * (de[a][a] - tr / 3.0);
+  const double c1 = s.plastic ? 1.0 - 3.0 * mu * s.dgam / s.q_tr : 1.0;
+  const double c2 = s.plastic ? 2.0 * mu * (1.0 / (3.0 * mu + Hh) - s.dgam / s.q_tr) : 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const double devd = de[a][b] - (a == b ? tr / 3.0 : 0.0);
+      dtp[a][b] = (a == b ? K * tr : 0.0) + c1 * 2.0 * mu * devd - (a == b ? c2 * Nds * s.n_p[a] : 0.0);
+    }
+  M3 dtau, tau = {}, FiT, out1, out2, t3;
+  m3_mul(s.Q, dtp, tmp);
+  m3_mul(tmp, QT, dtau);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      for (int a = 0; a < 3; ++a) tau[i][j] += s.Q[i][a] * s.tau_p[a] * s.Q[j][a];
+  m3_T(s.Fi, FiT);
+  m3_mul(dtau, FiT, out1);
+  m3_mul(tau, FiT, t1);
+  m3_mul(t1, dFT, t2);
+  m3_mul(t2, FiT, t3);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      out2[i][j] = out1[i][j] - t3[i][j];
+      dP9[3 * i + j] = out2[i][j];
+    }
+  return ORC_OK;
+}
+
+static void hist_at(const double* hist, long n, long v, double h[7]) {
+  for (int k = 0; k < 7; ++k) h[k] = hist[k * n + v];
+}
+
+// field versions (exported for the tests)
+int orc_j2_stress(long n, const double* F, const double* K, const double* mu, const double* ty0, const double* H,
+                  const double* hist, double* P, double* hist_new) {
+  for (long v = 0; v < n; ++v) {
+    double f[9], h[7], p[9], hn[7];
+    mat_get(F, n, v, f);
+    hist_at(hist, n, v, h);
+    const int st = j2_point_stress(f, h, K[v], mu[v], ty0[v], H[v], p, hist_new ? hn : nullptr);
+    if (st != ORC_OK) return st;
+    mat_put(P, n, v, p);
+    if (hist_new)
+      for (int k = 0; k < 7; ++k) hist_new[k * n + v] = hn[k];
+  }
+  return ORC_OK;
+}
+
+int orc_j2_tangent(long n, const double* F, const double* K, const double* mu, const double* ty0, const double* H,
+                   const double* hist, const double* dF, double* dP) {
+  for (long v = 0; v < n; ++v) {
+    double f[9], h[7], d[9], o[9];
+    mat_get(F, n, v, f);
+    hist_at(hist, n, v, h);
+    mat_get(dF, n, v, d);
+    const int st = j2_point_tangent(f, h, K[v], mu[v], ty0[v], H[v], d, o);
+    if (st != ORC_OK) return st;
+    mat_put(dP, n, v, o);
+  }
+  return ORC_OK;
+}
+
+static int law_stress(const orc_problem& pb, const double* F, double* P, double* hist_new) {
+  const long n = (long)pb.n0 * pb.n1 * pb.n2;
+  if (pb.model == 0) {
+    orc_svk_stress(n, F, pb.K, pb.mu, P);
+    return ORC_OK;
+  }
+  return orc_j2_stress(n, F, pb.K, pb.mu, pb.ty0, pb.H, pb.hist, P, hist_new);
+}
+
+static void law_tangent(const orc_problem& pb, const double* F, const double* dF, double* dP) {
+  const long n = (long)pb.n0 * pb.n1 * pb.n2;
+  if (pb.model == 0) {
+    orc_svk_tangent(n, F, pb.K, pb.mu, dF, dP);
+    return;
+  }
+  if (orc_j2_tangent(n, F, pb.K, pb.mu, pb.ty0, pb.H, pb.hist, dF, dP) != ORC_OK)
+    for (long i = 0; i < 9 * n; ++i) dP[i] = std::nan("");  // a failed point poisons the solve
+}
 }  // extern "C"

@@ -74,7 +74,10 @@ int pick_m(int h, int nmax, size_t csz, int pref) {
   return m;
 }
 
-size_t row_lds(const Grid& g, size_t csz) { return csz * ((size_t)g.n2 + 2 * 5 * (size_t)g.rt * g.n2); }
+size_t row_lds(const Grid& g, size_t csz) {
+  if (g.ax[2].reg) return csz * ((size_t)g.n2 + (size_t)kThreads * kRegP);
+  return csz * ((size_t)g.n2 + 2 * 5 * (size_t)g.rt * g.n2);
+}
 size_t col_lds(const Grid& g, int axis, size_t csz) {
   const int n = axis == 0 ? g.n0 : g.n1;
   if (g.ax[axis].reg) return csz * ((size_t)n + (size_t)kThreads * kRegP);
@@ -211,14 +214,15 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
       if (nd < 2 || nd > kMaxLen) return nd > kMaxLen ? FFTNK_EUNSUPPORTED : FFTNK_EINVAL;
       if (!make_plan(nd, g.ax[d])) return FFTNK_EUNSUPPORTED;
     }
-    g.ax[2].reg = 0;  // the a2 passes always use the LDS engine
     g.h = (g.n2 % 2 == 0) ? g.n2 / 2 : (g.n2 + 1) / 2;
     g.n = (long long)g.n0 * g.n1 * g.n2;
     g.rows = (long long)g.n0 * g.n1;
     g.vox_off = vox;
     g.spec_off = spec;
     g.inv_n = 1.0 / (double)g.n;
-    g.rt = std::max(1, kThreads / g.n2);
+    // grid lines per a2 work-group: register engine, 5 pair pencils per line on
+    // kThreads / (n2/8) pencil slots; LDS engine, kThreads / n2 lines
+    g.rt = g.ax[2].reg ? (kThreads / (g.n2 / kRegP)) / 5 : std::max(1, kThreads / g.n2);
     const int nmax = std::max(g.n0, g.n1);
     g.m64 = pick_m(g.h, nmax, 16, 8);
     g.m32 = pick_m(g.h, nmax, 8, 16);

@@ -79,6 +79,10 @@ __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, cons
     first = cg[rv].iter == 0;
   }
   double acc[1] = {0.0};
+  // register engine: pencil slot m = pair * RT + line (slots >= 5 RT idle),
+  // stage the field in LDS once, transform in registers, unpack through one
+  // mirror exchange.  bufA holds one slot of N2 entries per kThreads / Tp.
+  const bool reg = g.ax[2].reg;
   for (int t = threadIdx.x; t < RT * N2; t += kThreads) {
     const int rl = t / N2, a2 = t - rl * N2;
     const long long row = row0 + rl;
@@ -121,10 +125,46 @@ __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, cons
     bufA[(4 * RT + rl) * N2 + a2] = cx<T>{d[8], (T)0};
   }
   __syncthreads();
-  const cx<T>* Z = fft_lds<T>(bufA, bufB, g.ax[2], npen, N2, 1, tw, false, false);
-
   const long long srow = g.rows * H;
   cx<T>* S = spec + g.spec_off;
+
+  if (reg) {
+    const int Tp = N2 / kRegP;
+    const int m = threadIdx.x / Tp, t = threadIdx.x - m * Tp;
+    cx<T>* xl = bufA + m * N2;
+    cx<T> v[kRegP];
+#pragma unroll
+    for (int q = 0; q < kRegP; ++q) v[q] = xl[t + Tp * q];
+    __syncthreads();
+    reg_fft<T>(v, g.ax[2], t, Tp, tw, false, xl, 1);
+#pragma unroll
+    for (int q = 0; q < kRegP; ++q) xl[t + Tp * q] = v[q];
+    __syncthreads();
+    const int pq = m / RT, rl = m - pq * RT;
+    const long long row = row0 + rl;
+    if (m < npen && row < g.rows) {
+#pragma unroll
+      for (int q = 0; q < kRegP / 2; ++q) {  // k = t + Tp q < n2 / 2 = h
+        const int k = t + Tp * q;
+        const cx<T> z = v[q];
+        const cx<T> zm = xl[k ? N2 - k : 0];
+        if (pq == 4) {
+          S[8 * srow + row * H + k] = z;
+        } else {
+          S[(2 * pq) * srow + row * H + k] = cx<T>{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)};
+          S[(2 * pq + 1) * srow + row * H + k] = cx<T>{(T)0.5 * (z.y + zm.y), (T)-0.5 * (z.x - zm.x)};
+        }
+      }
+    }
+    if (MODE != FWD_CG) {
+      double res[1];
+      block_sums<1>(acc, res);
+      if (threadIdx.x == 0) pslot(B, SLOT_YY)[blockIdx.x] = res[0];
+    }
+    return;
+  }
+
+  const cx<T>* Z = fft_lds<T>(bufA, bufB, g.ax[2], npen, N2, 1, tw, false, false);
   for (int t = threadIdx.x; t < 9 * RT * H; t += kThreads) {
     const int c = t / (RT * H);
     const int rem = t - c * RT * H;
@@ -245,7 +285,7 @@ __device__ __forceinline__ void project_point(cx<T>& a0, cx<T>& a1, cx<T>& a2, i
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_col_a0_project(Batch B, cx<T>* __restrict__ spec,
+__global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* __restrict__ spec,
                                                              const CgState* __restrict__ cg) {
   int local;
   const int rv = find_rve(B, sizeof(T) == 8 ? K_COL0_64 : K_COL0_32, blockIdx.x, local);
@@ -382,6 +422,75 @@ __global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __res
   const long long row0 = (long long)local * RT;
   const long long srow = g.rows * H;
   const cx<T>* S = spec + g.spec_off;
+
+  if (g.ax[2].reg) {
+    // register engine: pencil slot m = pair * RT + line (slots >= 5 RT idle);
+    // the pair line Z = X + iY is read straight from the half spectra (mirror
+    // half conjugated), transformed in registers, written straight out.
+    const int Tp = N2 / kRegP;
+    const int m = threadIdx.x / Tp, t = threadIdx.x - m * Tp;
+    const int pq = m / RT, rl = m - pq * RT;
+    const long long row = row0 + rl;
+    const bool valid = m < npen && row < g.rows;
+    const int c0 = pq < 4 ? 2 * pq : 8;
+    cx<T> v[kRegP];
+#pragma unroll
+    for (int q = 0; q < kRegP; ++q) {
+      const int k = t + Tp * q;
+      cx<T> z = {(T)0, (T)0};
+      if (valid && 2 * k != N2) {
+        const bool mirror = k >= H;
+        const int kk = mirror ? N2 - k : k;
+        cx<T> X = S[c0 * srow + row * H + kk];
+        cx<T> Y = pq < 4 ? S[(c0 + 1) * srow + row * H + kk] : cx<T>{(T)0, (T)0};
+        if (k == 0) {
+          X.y = (T)0;
+          Y.y = (T)0;
+        }
+        if (mirror) {
+          X.y = -X.y;
+          Y.y = -Y.y;
+        }
+        z = cx<T>{X.x - Y.y, X.y + Y.x};
+      }
+      v[q] = z;
+    }
+    reg_fft<T>(v, g.ax[2], t, Tp, tw, true, bufA + m * N2, 1);
+    double acc[1] = {0.0};
+    if (valid) {
+      const long long n = g.n;
+      const long long base = 9 * g.vox_off + row * N2;
+      const int nc = pq < 4 ? 2 : 1;
+#pragma unroll
+      for (int q = 0; q < kRegP; ++q) {
+        const long long v0 = base + t + Tp * q;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (h >= nc) break;
+          const long long idx = v0 + (c0 + h) * n;
+          const T w = h == 0 ? v[q].x : v[q].y;
+          if (MODE == INV_OUT) {
+            const T o = (T)scale * w;
+            out[idx] = (TO)o;
+            acc[0] += (double)o * (double)o;
+          } else if (MODE == INV_PW) {
+            out[idx] = (TO)w;
+            acc[0] += (double)p[idx] * (double)(TO)w;
+          } else {  // INV_RHS
+            const T o = (T)scale * w;
+            out[idx] = (TO)o;
+            x[idx] = (TO)0;
+            acc[0] += (double)o * (double)o;
+          }
+        }
+      }
+    }
+    double res[1];
+    block_sums<1>(acc, res);
+    if (threadIdx.x == 0) pslot(B, MODE == INV_PW ? SLOT_PW : SLOT_BB)[blockIdx.x] = res[0];
+    return;
+  }
+
   for (int t = threadIdx.x; t < npen * N2; t += kThreads) {
     const int pen = t / N2, k = t - pen * N2;
     const int q = pen / RT, rl = pen - q * RT;
