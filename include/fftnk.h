@@ -101,8 +101,13 @@ int fftnk_set_phases(fftnk_ctx* ctx, const uint8_t* phase_dev);
 /*
  * Material (paper Sec. 4.2 for FFTNK_SVK: S = C:E, E = (F^T F - I)/2,
  * P = F S with isotropic C from bulk modulus K and shear modulus mu,
- * lambda = K - 2 mu/3; Sec. 5.2 for FFTNK_J2).  params_host holds, per phase,
- * {K, mu} for SVK and {K, mu, tau_y0, H} for J2.  nphase <= 16.
+ * lambda = K - 2 mu/3; Sec. 5 for FFTNK_J2: F = Fe Fp, Kirchhoff stress
+ * tau = C : ln(be)/2, von Mises yield with linear hardening
+ * tau_y = tau_y0 + H eps_p, exponential-map return mapping, P = tau F^-T).
+ * params_host holds, per phase, {K, mu} for SVK and {K, mu, tau_y0, H} for
+ * J2.  nphase <= 16.  J2 needs an FFTNK_FP64 context (else
+ * FFTNK_EUNSUPPORTED); a point whose return mapping fails (det F <= 0)
+ * makes the increment fail with FFTNK_ENONFINITE.
  */
 int fftnk_set_material(fftnk_ctx* ctx, int model, int nphase, const double* params_host);
 
@@ -196,6 +201,15 @@ int fftnk_adjoint(fftnk_ctx* ctx, const double* gbar_host, double eta_cg, int ma
  * results are meaningful only when the five run in order.
  */
 int fftnk_launch_pass(fftnk_ctx* ctx, int pass);
+
+/*
+ * Checkpoint of the J2 history (Alg. 1, "store history variables"): device
+ * double [7][n] -- C_p^-1 as xx yy zz xy yz xz, then the accumulated plastic
+ * strain; batched: each of the 7 planes holds all RVEs in order.  Virgin state
+ * (after bind / reset): C_p^-1 = I, eps_p = 0.
+ */
+int fftnk_get_history(fftnk_ctx* ctx, double* hist_dev);
+int fftnk_set_history(fftnk_ctx* ctx, const double* hist_dev);
 
 /* Checkpoint: copy out / in the committed F_t (device double [9][n]). */
 int fftnk_get_state(fftnk_ctx* ctx, double* F_dev);

@@ -756,12 +756,14 @@ static int j2_return_map(const double* F9, const double* h, double K, double mu,
   }
   s->q_tr = std::sqrt(1.5 * q2);
   const double phi = s->q_tr - (ty0 + Hh * h[6]);
-  s->plastic = phi > 1e-12 * ty0;
+  // on or beyond the yield surface: plastic branch (at the surface itself,
+  // dgam = 0 and the tangent is the plastic one-sided derivative)
+  s->plastic = phi > -1e-12 * ty0 && s->q_tr > 0.0;
   s->dgam = 0.0;
   for (int a = 0; a < 3; ++a) s->n_p[a] = s->q_tr > 0.0 ? 1.5 * sdev[a] / s->q_tr : 0.0;
   if (s->plastic) {
     if (!(3.0 * mu + Hh > 0.0)) return ORC_EMATERIAL;
-    s->dgam = phi / (3.0 * mu + Hh);
+    s->dgam = phi > 0.0 ? phi / (3.0 * mu + Hh) : 0.0;
   }
   for (int a = 0; a < 3; ++a) {
     s->tau_p[a] = K * tr + sdev[a] - 2.0 * mu * s->dgam * s->n_p[a];

@@ -100,6 +100,7 @@ struct fftnk_ctx {
   int nblk[NKIND] = {};
   size_t lds[6] = {};
   // workspace layout (byte offsets)
+  size_t o_hist, o_hnew;  // J2 history: committed and of the current iterate, [7][ntot] each
   size_t o_Ft, o_F, o_P, o_x, o_r, o_p, o_w, o_F32, o_d64, o_spec, o_phase, o_mu, o_mtab, o_part, o_cg, o_red,
       o_tw64, o_tw32, o_grids, o_starts, o_active, o_uni, total = 0;
   char* ws = nullptr;
@@ -161,6 +162,9 @@ struct fftnk_ctx {
     m.phase = at<uint8_t>(o_phase);
     m.mu_field = use_mu ? at<double>(o_mu) : nullptr;
     m.table = at<double>(o_mtab);
+    m.hist = at<double>(o_hist);
+    m.hist_new = at<double>(o_hnew);
+    m.ntot = ntot;
     m.model = model;
     m.nphase = nphase;
     return m;
@@ -301,6 +305,8 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
   c->o_spec = take((size_t)spec * 16);
   c->o_phase = take((size_t)vox);
   c->o_mu = take((size_t)vox * 8);
+  c->o_hist = take((size_t)vox * 7 * 8);
+  c->o_hnew = take((size_t)vox * 7 * 8);
   c->o_mtab = take(kMaxPhase * 4 * 8);
   c->o_part = take((size_t)NSLOT * c->pstride * 8);
   c->o_cg = take((size_t)nrve * sizeof(CgState));
@@ -327,6 +333,7 @@ void drop_graphs(fftnk_ctx* c) {
 
 int reset_state(fftnk_ctx* c) {
   launch_set_identity(c->launch(), c->Ft());
+  launch_set_virgin_history(c->launch(), c->at<double>(c->o_hist), c->ntot);
   int e = check_launch();
   if (e) return e;
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -536,7 +543,8 @@ int fftnk_set_phases(fftnk_ctx* c, const uint8_t* phase_dev) {
 
 int fftnk_set_material(fftnk_ctx* c, int model, int nphase, const double* params) {
   if (!c || !params || nphase < 1 || nphase > kMaxPhase) return FFTNK_EINVAL;
-  if (model != FFTNK_SVK) return FFTNK_EUNSUPPORTED;
+  if (model != FFTNK_SVK && model != FFTNK_J2) return FFTNK_EINVAL;
+  if (model == FFTNK_J2 && c->prec != PREC_F64) return FFTNK_EUNSUPPORTED;  // J2 runs in FP64
   if (!c->ws) return FFTNK_ESTATE;
   const int np = model == FFTNK_SVK ? 2 : 4;
   for (int i = 0; i < nphase * np; ++i)
@@ -692,6 +700,12 @@ int fftnk_solve_increment(fftnk_ctx* c, const double* Fbar, double eta_nw, doubl
     HIP_TRY(hipMemcpyAsync(c->Ft() + off, c->F() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
     if (F_dev) HIP_TRY(hipMemcpyAsync(F_dev + off, c->F() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
     if (P_dev) HIP_TRY(hipMemcpyAsync(P_dev + off, c->P() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (c->model == MODEL_J2)  // store the history of the converged state (Alg. 1)
+      for (int k = 0; k < 7; ++k) {
+        const size_t o = (size_t)k * c->ntot + g.vox_off;
+        HIP_TRY(hipMemcpyAsync(c->at<double>(c->o_hist) + o, c->at<double>(c->o_hnew) + o, g.n * sizeof(double),
+                               hipMemcpyDeviceToDevice, c->stream));
+      }
     for (int k = 0; k < 9; ++k) Pbar[9 * r + k] = pbar[9 * r + k];
   }
   HIP_TRY(hipStreamSynchronize(c->stream));  // the last mask upload has read the host vector
@@ -712,6 +726,7 @@ int fftnk_adjoint(fftnk_ctx* c, const double* gbar, double eta_cg, int max_cg, d
                   fftnk_stats* stats) {
   if (!c || !gbar || !dLdmu || !(eta_cg > 0) || max_cg < 1) return FFTNK_EINVAL;
   if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
+  if (c->model != MODEL_SVK) return FFTNK_EUNSUPPORTED;  // the gradient formula is St. Venant-Kirchhoff's
   const int nr = c->nrve;
   for (int k = 0; k < 9 * nr; ++k)
     if (!std::isfinite(gbar[k])) return FFTNK_ENONFINITE;
@@ -803,6 +818,22 @@ int fftnk_launch_pass(fftnk_ctx* c, int pass) {
     default: launch_inv_a2(c->prec, INV_OUT, L, c->spec(), c->w(), c->prec, nullptr, nullptr, 1.0, nullptr); break;
   }
   return check_launch();
+}
+
+int fftnk_get_history(fftnk_ctx* c, double* hist_dev) {
+  if (!c || !hist_dev) return FFTNK_EINVAL;
+  if (!c->ws) return FFTNK_ESTATE;
+  HIP_TRY(hipMemcpyAsync(hist_dev, c->ws + c->o_hist, 7 * (size_t)c->ntot * 8, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return FFTNK_OK;
+}
+
+int fftnk_set_history(fftnk_ctx* c, const double* hist_dev) {
+  if (!c || !hist_dev) return FFTNK_EINVAL;
+  if (!c->ws) return FFTNK_ESTATE;
+  HIP_TRY(hipMemcpyAsync(c->ws + c->o_hist, hist_dev, 7 * (size_t)c->ntot * 8, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return FFTNK_OK;
 }
 
 int fftnk_get_state(fftnk_ctx* c, double* F_dev) {

@@ -9,6 +9,7 @@
 // launch kind's start table).  Power-of-two a1 / a0 axes use the register-
 // resident engine; everything else the LDS Stockham engine.
 #include "fftnk_device.h"
+#include "fftnk_j2.h"
 
 namespace fftnk {
 
@@ -52,7 +53,21 @@ int col0_blocks(const Grid& g, int prec) {
 // 8 rides alone; the half spectra are unpacked with X[k] = (Z[k] + conj Z[-k])/2
 // and Y[k] = (Z[k] - conj Z[-k]) / (2i).
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
+// Tangent action of the voxel's material law at F on the direction p.
+template <typename T, int LAW>
+__device__ __forceinline__ void tangent_at(const Material& mat, long long gv, const T* F, const T* p, T* d) {
+  if constexpr (LAW == MODEL_J2) {
+    double K, mu, ty0, H, h[7];
+    j2_point_data(mat, gv, K, mu, ty0, H, h);
+    j2_tangent(F, h, K, mu, ty0, H, p, d);
+  } else {
+    double lam, mu;
+    material_at(mat, gv, lam, mu);
+    svk_tangent<T>(F, p, (T)lam, (T)mu, d);
+  }
+}
+
+template <typename T, int MODE, int LAW>
 __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, const T* __restrict__ in,
                                                      const T* __restrict__ rvec, T* __restrict__ pvec,
                                                      const T* __restrict__ Flin, double scale,
@@ -110,9 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, cons
         }
 #pragma unroll
         for (int c = 0; c < 9; ++c) F[c] = Flin[off + c * n + v];
-        double lam, mu;
-        material_at(mat, g.vox_off + v, lam, mu);
-        svk_tangent<T>(F, p, (T)lam, (T)mu, d);
+        tangent_at<T, LAW>(mat, g.vox_off + v, F, p, d);
       }
 #pragma unroll
       for (int c = 0; c < 9; ++c) acc[0] += (double)d[c] * (double)d[c];
@@ -560,7 +573,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __res
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int LAW>
 static void fwd_a2_t(int mode, const Launch& L, const Material& mat, const void* in, const void* r, void* p,
                      const void* Flin, double scale, void* spec, const CgState* cg) {
   const dim3 grid(L.nblk[K_ROW]), block(kThreads);
@@ -571,19 +584,23 @@ static void fwd_a2_t(int mode, const Launch& L, const Material& mat, const void*
   const T* tf = static_cast<const T*>(Flin);
   cx<T>* sp = static_cast<cx<T>*>(spec);
   switch (mode) {
-    case FWD_COPY: hipLaunchKernelGGL((k_fwd_a2<T, FWD_COPY>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
-    case FWD_TANGENT: hipLaunchKernelGGL((k_fwd_a2<T, FWD_TANGENT>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
-    case FWD_TANGENT_UNI: hipLaunchKernelGGL((k_fwd_a2<T, FWD_TANGENT_UNI>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
-    default: hipLaunchKernelGGL((k_fwd_a2<T, FWD_CG>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
+    case FWD_COPY: hipLaunchKernelGGL((k_fwd_a2<T, FWD_COPY, MODEL_SVK>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
+    case FWD_TANGENT: hipLaunchKernelGGL((k_fwd_a2<T, FWD_TANGENT, LAW>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
+    case FWD_TANGENT_UNI: hipLaunchKernelGGL((k_fwd_a2<T, FWD_TANGENT_UNI, LAW>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
+    default: hipLaunchKernelGGL((k_fwd_a2<T, FWD_CG, LAW>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
   }
 }
 
 void launch_fwd_a2(int prec, int mode, const Launch& L, const Material& mat, const void* in_T, const void* r_T,
                    void* p_T, const void* Flin, double scale, void* spec, const CgState* cg) {
-  if (prec == PREC_F64)
-    fwd_a2_t<double>(mode, L, mat, in_T, r_T, p_T, Flin, scale, spec, cg);
-  else
-    fwd_a2_t<float>(mode, L, mat, in_T, r_T, p_T, Flin, scale, spec, cg);
+  if (prec == PREC_F64) {
+    if (mat.model == MODEL_J2)
+      fwd_a2_t<double, MODEL_J2>(mode, L, mat, in_T, r_T, p_T, Flin, scale, spec, cg);
+    else
+      fwd_a2_t<double, MODEL_SVK>(mode, L, mat, in_T, r_T, p_T, Flin, scale, spec, cg);
+  } else {
+    fwd_a2_t<float, MODEL_SVK>(mode, L, mat, in_T, r_T, p_T, Flin, scale, spec, cg);  // J2 runs in FP64 only
+  }
 }
 
 void launch_col_a1(int prec, bool inverse, const Launch& L, void* spec, const CgState* cg) {

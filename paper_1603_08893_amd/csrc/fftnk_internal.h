@@ -64,6 +64,9 @@ struct Material {
   const uint8_t* phase;    // [ntot] phase index per voxel
   const double* mu_field;  // [ntot] per-voxel mu, or null
   const double* table;     // [nphase][4] device table: K, mu, tau_y0, H
+  const double* hist;      // J2: committed history [7][ntot] (Cp^-1 xx yy zz xy yz xz, eps_p)
+  double* hist_new;        // J2: history of the current iterate [7][ntot]
+  long long ntot;
   int model;
   int nphase;
 };
@@ -167,6 +170,7 @@ void launch_field_sum(const Launch& L, const double* X, int slot0);
 void launch_reduce(const Launch& L, int kind, int slot0, int nslots, double* out);
 void launch_convert(int to_prec, const void* in, void* out, long long count, hipStream_t s);
 void launch_set_identity(const Launch& L, double* F);
+void launch_set_virgin_history(const Launch& L, double* hist, long long ntot);
 void launch_adjoint_grad(int prec, const Launch& L, const double* F, const void* w, double* dmu, double* dK);
 
 }  // namespace fftnk

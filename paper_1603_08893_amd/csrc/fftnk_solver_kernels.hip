@@ -10,6 +10,7 @@
 // Reductions: block partial sums in fixed slots, summed in a fixed order by one
 // work-group per RVE, so results are bitwise reproducible.
 #include "fftnk_device.h"
+#include "fftnk_j2.h"
 
 namespace fftnk {
 
@@ -166,9 +167,33 @@ __global__ __launch_bounds__(kThreads) void k_set_F(Batch B, const double* __res
   if (threadIdx.x == 0) pslot(B, SLOT_FF)[blockIdx.x] = res[0];
 }
 
+// Stress of the voxel's material law at F; J2 also writes the history of the
+// return from the committed state (hnew may be null).  NaN on failure.
+template <int LAW>
+__device__ __forceinline__ void stress_at(const Material& mat, long long gv, const double* f, double* Pv, bool hnew) {
+  if constexpr (LAW == MODEL_J2) {
+    double K, mu, ty0, H, h[7], hn[7];
+    j2_point_data(mat, gv, K, mu, ty0, H, h);
+    if (!j2_stress(f, h, K, mu, ty0, H, Pv, hn)) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) Pv[c] = __builtin_nan("");
+#pragma unroll
+      for (int k = 0; k < 7; ++k) hn[k] = h[k];
+    }
+    if (hnew)
+#pragma unroll
+      for (int k = 0; k < 7; ++k) mat.hist_new[k * mat.ntot + gv] = hn[k];
+  } else {
+    double lam, mu, S[9];
+    material_at(mat, gv, lam, mu);
+    svk_S<double>(f, lam, mu, S);
+    mat33<double>(f, S, Pv);
+  }
+}
+
 // F += dF (+ dFbar on the first iteration), constitutive update P = P(F),
 // ||dF||^2 and the sums of P; the next linearisation point in FP32.
-template <typename T>
+template <typename T, int LAW>
 __global__ __launch_bounds__(kThreads) void k_newton_update(Batch B, Material mat, double* __restrict__ F,
                                                             const T* __restrict__ x, double* __restrict__ P,
                                                             float* __restrict__ Flin32, int add_uni) {
@@ -185,7 +210,7 @@ __global__ __launch_bounds__(kThreads) void k_newton_update(Batch B, Material ma
 #pragma unroll
   for (int k = 0; k < 10; ++k) acc[k] = 0.0;
   FOR_RVE_RANGE(v, n, local, nb) {
-    double f[9], S[9], Pv[9];
+    double f[9], Pv[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       const double d = (double)x[off + c * n + v];
@@ -194,10 +219,7 @@ __global__ __launch_bounds__(kThreads) void k_newton_update(Batch B, Material ma
       acc[0] += d * d;
       if (Flin32) Flin32[off + c * n + v] = (float)f[c];
     }
-    double lam, mu;
-    material_at(mat, g.vox_off + v, lam, mu);
-    svk_S<double>(f, lam, mu, S);
-    mat33<double>(f, S, Pv);
+    stress_at<LAW>(mat, g.vox_off + v, f, Pv, true);
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       P[off + c * n + v] = Pv[c];
@@ -212,6 +234,7 @@ __global__ __launch_bounds__(kThreads) void k_newton_update(Batch B, Material ma
   }
 }
 
+template <int LAW>
 __global__ __launch_bounds__(kThreads) void k_constitutive(Batch B, Material mat, const double* __restrict__ F,
                                                            double* __restrict__ P) {
   int local;
@@ -224,13 +247,10 @@ __global__ __launch_bounds__(kThreads) void k_constitutive(Batch B, Material mat
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = 0.0;
   FOR_RVE_RANGE(v, n, local, nb) {
-    double f[9], S[9], Pv[9];
+    double f[9], Pv[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) f[c] = F[off + c * n + v];
-    double lam, mu;
-    material_at(mat, g.vox_off + v, lam, mu);
-    svk_S<double>(f, lam, mu, S);
-    mat33<double>(f, S, Pv);
+    stress_at<LAW>(mat, g.vox_off + v, f, Pv, false);
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       P[off + c * n + v] = Pv[c];
@@ -368,16 +388,33 @@ void launch_set_F(const Launch& L, const double* Ft, double* F, float* Flin32) {
 void launch_newton_update(int prec, const Launch& L, const Material& mat, double* F, const void* x, double* P,
                           float* Flin32, bool add_uni) {
   const dim3 grid(L.nblk[K_VOX]), block(kThreads);
-  if (prec == PREC_F64)
-    hipLaunchKernelGGL((k_newton_update<double>), grid, block, 0, L.s, L.b, mat, F, static_cast<const double*>(x), P,
-                       Flin32, add_uni ? 1 : 0);
+  if (mat.model == MODEL_J2)
+    hipLaunchKernelGGL((k_newton_update<double, MODEL_J2>), grid, block, 0, L.s, L.b, mat, F,
+                       static_cast<const double*>(x), P, Flin32, add_uni ? 1 : 0);
+  else if (prec == PREC_F64)
+    hipLaunchKernelGGL((k_newton_update<double, MODEL_SVK>), grid, block, 0, L.s, L.b, mat, F,
+                       static_cast<const double*>(x), P, Flin32, add_uni ? 1 : 0);
   else
-    hipLaunchKernelGGL((k_newton_update<float>), grid, block, 0, L.s, L.b, mat, F, static_cast<const float*>(x), P,
-                       Flin32, add_uni ? 1 : 0);
+    hipLaunchKernelGGL((k_newton_update<float, MODEL_SVK>), grid, block, 0, L.s, L.b, mat, F,
+                       static_cast<const float*>(x), P, Flin32, add_uni ? 1 : 0);
 }
 
 void launch_constitutive(const Launch& L, const Material& mat, const double* F, double* P) {
-  hipLaunchKernelGGL(k_constitutive, dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, mat, F, P);
+  if (mat.model == MODEL_J2)
+    hipLaunchKernelGGL((k_constitutive<MODEL_J2>), dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, mat, F, P);
+  else
+    hipLaunchKernelGGL((k_constitutive<MODEL_SVK>), dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, mat, F, P);
+}
+
+// J2 virgin state: Cp^-1 = I, eps_p = 0 ([7][ntot])
+__global__ __launch_bounds__(kThreads) void k_virgin_history(double* __restrict__ h, long long ntot) {
+  for (long long v = blockIdx.x * (long long)kThreads + threadIdx.x; v < ntot; v += (long long)gridDim.x * kThreads)
+#pragma unroll
+    for (int k = 0; k < 7; ++k) h[k * ntot + v] = k < 3 ? 1.0 : 0.0;
+}
+
+void launch_set_virgin_history(const Launch& L, double* hist, long long ntot) {
+  hipLaunchKernelGGL(k_virgin_history, dim3(elem_blocks(ntot)), dim3(kThreads), 0, L.s, hist, ntot);
 }
 
 void launch_field_sum(const Launch& L, const double* X, int slot0) {

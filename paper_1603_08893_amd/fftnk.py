@@ -24,7 +24,7 @@ EXPORTS = [
     "fftnk_create", "fftnk_create_batched", "fftnk_workspace_bytes", "fftnk_bind_workspace", "fftnk_set_phases",
     "fftnk_set_material", "fftnk_set_modulus_field", "fftnk_set_option", "fftnk_reset_state", "fftnk_solve_increment",
     "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_adjoint",
-    "fftnk_launch_pass", "fftnk_get_state",
+    "fftnk_launch_pass", "fftnk_get_history", "fftnk_set_history", "fftnk_get_state",
     "fftnk_set_state", "fftnk_status_string", "fftnk_destroy",
 ]
 
@@ -81,6 +81,8 @@ def lib():
     L.fftnk_constitutive.argtypes = [vp, vp, vp, dp]
     L.fftnk_adjoint.argtypes = [vp, dp, d, i, vp, vp, ctypes.POINTER(Stats)]
     L.fftnk_launch_pass.argtypes = [vp, i]
+    L.fftnk_get_history.argtypes = [vp, vp]
+    L.fftnk_set_history.argtypes = [vp, vp]
     L.fftnk_get_state.argtypes = [vp, vp]
     L.fftnk_set_state.argtypes = [vp, vp]
     L.fftnk_status_string.argtypes = [i]
@@ -245,6 +247,16 @@ class Solver:
     def launch_pass(self, k):
         """Enqueue pass k (1..5) of the operator alone (timing instrumentation)."""
         _check(lib().fftnk_launch_pass(self.ctx, int(k)), "fftnk_launch_pass")
+
+    def get_history(self):
+        """J2 history, [7 * ntot] device doubles (C_p^-1 xx yy zz xy yz xz, eps_p)."""
+        h = self.torch.empty(7 * self.ntot, dtype=self.torch.float64, device=self.device)
+        _check(lib().fftnk_get_history(self.ctx, ctypes.c_void_p(h.data_ptr())), "fftnk_get_history")
+        return h
+
+    def set_history(self, h):
+        h = h.to(self.device, self.torch.float64).contiguous()
+        _check(lib().fftnk_set_history(self.ctx, ctypes.c_void_p(h.data_ptr())), "fftnk_set_history")
 
     def get_state(self):
         F = self.field(self.torch.float64)

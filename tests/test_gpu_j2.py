@@ -1,0 +1,105 @@
+"""Finite-strain J2 plasticity on the GPU against the oracle (Sec. 5).
+
+* Constitutive update (return mapping from a virgin and from a plastically
+  loaded history) and the projected-tangent operator at frozen history.
+* Load increments of a two-phase sphere microstructure (random sequential
+  addition, 25 %), tau_y0 = 0.003 / 0.006, H = 0.01, same elastic K, mu in both
+  phases, simple shear in increments: equal Newton counts, CG counts within
+  +-2, P-bar within 1e-10, histories within 1e-9, committed state transactional.
+"""
+import numpy as np
+import pytest
+
+from paper_1603_08893_amd import microstructure as ms
+
+pytestmark = pytest.mark.gpu
+
+MATS = [(0.833, 0.386, 0.003, 0.01), (0.833, 0.386, 0.006, 0.01)]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _solver(shape, ph):
+    from paper_1603_08893_amd.fftnk import J2, Solver
+    s = Solver(shape, precision="fp64")
+    s.set_phases(ph)
+    s.set_material(MATS, model=J2)
+    return s
+
+
+def _fields(ph):
+    tab = np.array(MATS)
+    return [np.ascontiguousarray(tab[ph, k]) for k in range(4)]
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def test_j2_constitutive_and_operator_parity(torch_cuda, orc):
+    torch = torch_cuda
+    shape = (8, 9, 10)
+    rng = np.random.default_rng(11)
+    ph = rng.integers(0, 2, size=shape).astype(np.uint8)
+    K, mu, ty0, H = _fields(ph)
+    F0 = ms.near_identity_field(shape, seed=12, scale=0.03)
+    st, _, hist = orc.j2_stress(F0, K, mu, ty0, H, orc.virgin_history(shape))
+    assert st == 0 and hist[6].max() > 0
+    F = F0 + ms.random_field(shape, seed=13, scale=0.01)
+    s = _solver(shape, ph)
+    for h in [orc.virgin_history(shape), hist]:
+        s.set_history(torch.from_numpy(h.reshape(-1)))
+        st, Pref, _ = orc.j2_stress(F, K, mu, ty0, H, h)
+        P, Pbar = s.constitutive(torch.from_numpy(F.reshape(-1)))
+        assert _rel(P.cpu().numpy(), Pref) <= 1e-13
+        p = ms.random_field(shape, seed=14)
+        st, t = orc.j2_tangent(F, K, mu, ty0, H, h, p)
+        ref = orc.project(t)
+        s.set_linearization(torch.from_numpy(F.reshape(-1)))
+        got = s.apply_operator(torch.from_numpy(p.reshape(-1))).cpu().numpy()
+        assert _rel(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("N", [15, 16])
+def test_j2_increments_vs_oracle(torch_cuda, orc, N):
+    torch = torch_cuda
+    shape = (N, N, N)
+    ph, frac = ms.rsa_spheres(N, 0.25, seed=1604, rmin=2, rmax=4)
+    K, mu, ty0, H = _fields(ph)
+    s = _solver(shape, ph)
+    F = orc.identity_field(shape)
+    hist = orc.virgin_history(shape)
+    for t in range(1, 9):
+        Fb = ms.simple_shear(0.004 * t)
+        sto, F, Po, Pbo, hist, So = orc.solve_increment_j2(K, mu, ty0, H, hist, F, Fb)
+        assert sto == 0
+        _, Fg, Pg, Pb, S = s.solve_increment(Fb)
+        print(t, "oracle", So["cg_iters"], "gpu", S[0]["cg_iters"], flush=True)
+        assert S[0]["n_solves"] == So["n_solves"], t
+        assert all(abs(a - b) <= 2 for a, b in zip(S[0]["cg_iters"], So["cg_iters"])), t
+        assert np.max(np.abs(Pb[0] - Pbo)) <= 1e-10 * np.max(np.abs(Pbo)), t
+        assert _rel(Fg.cpu().numpy(), F) <= 1e-8
+    assert hist[6].max() > 0  # the spheres' surroundings yielded
+    assert _rel(s.get_history().cpu().numpy(), hist) <= 1e-9
+
+
+def test_j2_failed_increment_keeps_history(torch_cuda):
+    torch = torch_cuda
+    from paper_1603_08893_amd.fftnk import ECG_MAXIT
+    N = 9
+    ph, _ = ms.rsa_spheres(N, 0.25, seed=1604, rmin=2, rmax=3)
+    s = _solver((N, N, N), ph)
+    for g in (0.004, 0.008):  # the second increment flows plastically
+        s.solve_increment(ms.simple_shear(g))
+    h0 = s.get_history().clone()
+    assert h0.view(7, -1)[6].max().item() > 0
+    F0 = s.get_state().clone()
+    st, *_ = s.solve_increment(ms.simple_shear(0.012), max_cg=1, raise_on_error=False)
+    assert st == ECG_MAXIT
+    assert torch.equal(s.get_history(), h0) and torch.equal(s.get_state(), F0)
