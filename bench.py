@@ -57,7 +57,13 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--operator-only", action="store_true",
+                    help="profiling mode: only the operator passes at a synthetic linearisation point, plus one "
+                         "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     args = ap.parse_args()
+    if args.operator_only:
+        return operator_only(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the per-GPU work is one periodic cell; see DESIGN.md for how it would shard).", flush=True)
@@ -239,6 +245,52 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def operator_only(args):
+    """Operator passes alone at F = I + G(0.01 U(-1,1)) on the 128^3 two-phase cell, then a 1 GiB copy."""
+    import torch
+    from paper_1603_08893_amd import microstructure as ms
+    from paper_1603_08893_amd.fftnk import Solver
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    phase = ms.grf_threshold(N, ell=8.0, frac=0.3, seed=1603)
+    s = Solver((N, N, N), precision=args.precision)
+    s.set_phases(phase)
+    s.set_material(TABLE)
+    g64 = Solver((N, N, N), precision="fp64")
+    g64.set_phases(phase)
+    g64.set_material(TABLE)
+    fl = g64.project(torch.from_numpy(ms.random_field((N, N, N), seed=43, scale=0.01).reshape(-1)).to(dev))
+    fl.view(9, -1)[0::4] += 1.0
+    s.set_linearization(fl)
+    p = s.project(torch.from_numpy(ms.random_field((N, N, N), seed=42).reshape(-1)).to(dev))
+    out = s.field()
+    s.apply_operator(p, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {}
+    for k in range(1, 6):
+        e0.record()
+        for _ in range(args.matvec_reps):
+            s.launch_pass(k)
+        e1.record()
+        torch.cuda.synchronize()
+        res["pass%d_ms" % k] = round(e0.elapsed_time(e1) / args.matvec_reps, 5)
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0.record()
+    b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    res["copy_1GiB_ms"] = round(e0.elapsed_time(e1), 4)
+    res["copy_GB_s"] = round(2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    print(json.dumps({"operator_only": res, "precision": args.precision}), flush=True)
 
 
 if __name__ == "__main__":

@@ -69,20 +69,21 @@ int largest_pow2_leq(int x) {
 // (8 points per thread in pass 3) budgets.
 int pick_m(int h, int nmax, size_t csz, int pref) {
   int m = std::min(pref, largest_pow2_leq(std::max(1, h)));
-  while (m > 1 && ((size_t)nmax * m > (size_t)8 * kThreads || csz * ((size_t)nmax + 2 * (size_t)nmax * m) > 61440))
+  while (m > 1 && ((size_t)nmax * m > (size_t)8 * kThreads || csz * ((size_t)padded_len(nmax) + 2 * (size_t)nmax * m) > 61440))
     m /= 2;
   return m;
 }
 
 size_t row_lds(const Grid& g, size_t csz) {
-  if (g.ax[2].reg) return csz * ((size_t)g.n2 + (size_t)kThreads * kRegP);
-  return csz * ((size_t)g.n2 + 2 * 5 * (size_t)g.rt * g.n2);
+  const size_t tw = padded_len(g.n2);
+  if (g.ax[2].reg) return csz * (tw + (size_t)(kThreads / (g.n2 / kRegP)) * padded_len(g.n2));
+  return csz * (tw + 2 * 5 * (size_t)g.rt * g.n2);
 }
 size_t col_lds(const Grid& g, int axis, size_t csz) {
   const int n = axis == 0 ? g.n0 : g.n1;
-  if (g.ax[axis].reg) return csz * ((size_t)n + (size_t)kThreads * kRegP);
+  if (g.ax[axis].reg) return csz * ((size_t)padded_len(n) + (size_t)kThreads * kRegP);
   const int M = csz == 16 ? g.m64 : g.m32;
-  return csz * ((size_t)n + 2 * (size_t)n * M);
+  return csz * ((size_t)padded_len(n) + 2 * (size_t)n * M);
 }
 
 }  // namespace
@@ -227,6 +228,9 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
     // grid lines per a2 work-group: register engine, 5 pair pencils per line on
     // kThreads / (n2/8) pencil slots; LDS engine, kThreads / n2 lines
     g.rt = g.ax[2].reg ? (kThreads / (g.n2 / kRegP)) / 5 : std::max(1, kThreads / g.n2);
+    // forward pass: at most one voxel per thread in its tangent phase, so that
+    // all loads of a work-group are in flight together
+    g.rt1 = std::max(1, std::min(g.rt, kThreads / g.n2));
     const int nmax = std::max(g.n0, g.n1);
     g.m64 = pick_m(g.h, nmax, 16, 8);
     g.m32 = pick_m(g.h, nmax, 8, 16);
@@ -246,6 +250,7 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
       long long b = 0;
       switch (k) {
         case K_ROW: b = row_blocks(g); break;
+        case K_ROW1: b = row1_blocks(g); break;
         case K_COL1_64: b = col1_blocks(g, PREC_F64); break;
         case K_COL1_32: b = col1_blocks(g, PREC_F32); break;
         case K_COL0_64: b = col0_blocks(g, PREC_F64); break;
@@ -354,9 +359,9 @@ void middle_passes(int prec, const Launch& L, void* spec, const CgState* cg) {
 // in `mode` (the field in, or the tangent at Flin applied to Batch::uni).
 void rhs_pipeline(fftnk_ctx* c, int mode, const double* Y, const double* Flin, double sign) {
   const Launch L = c->launch();
-  launch_fwd_a2(PREC_F64, mode, L, c->material(), Y, nullptr, nullptr, Flin, 1.0, c->spec(), nullptr);
+  launch_fwd_a2(PREC_F64, mode, L, c->material(), Y, nullptr, nullptr, nullptr, Flin, 1.0, c->spec(), nullptr);
   middle_passes(PREC_F64, L, c->spec(), nullptr);
-  launch_inv_a2(PREC_F64, INV_RHS, L, c->spec(), c->r(), c->prec, nullptr, c->x(), sign, nullptr);
+  launch_inv_a2(PREC_F64, INV_RHS, L, c->spec(), c->r(), c->prec, c->x(), sign, nullptr);
 }
 
 // The CG solution as the Newton update.  FP64: x itself.  FP32: x rounded up to
@@ -368,20 +373,20 @@ const void* newton_update_source(fftnk_ctx* c) {
   if (c->prec == PREC_F64) return c->x();
   const Launch L = c->launch();
   launch_convert(PREC_F64, c->x(), c->d64(), 9 * c->ntot, c->stream);
-  launch_fwd_a2(PREC_F64, FWD_COPY, L, c->material(), c->d64(), nullptr, nullptr, nullptr, 1.0, c->spec(), nullptr);
+  launch_fwd_a2(PREC_F64, FWD_COPY, L, c->material(), c->d64(), nullptr, nullptr, nullptr, nullptr, 1.0, c->spec(),
+                nullptr);
   middle_passes(PREC_F64, L, c->spec(), nullptr);
-  launch_inv_a2(PREC_F64, INV_OUT, L, c->spec(), c->d64(), PREC_F64, nullptr, nullptr, 1.0, nullptr);
+  launch_inv_a2(PREC_F64, INV_OUT, L, c->spec(), c->d64(), PREC_F64, nullptr, 1.0, nullptr);
   return c->d64();
 }
 
 // one CG iteration on every RVE whose CG is still running
 void cg_iteration(fftnk_ctx* c, const Launch& L) {
   CgState* cg = c->cg();
-  launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->p(), c->flin(), 1.0, c->spec(), cg);
-  middle_passes(c->prec, L, c->spec(), cg);
-  launch_inv_a2(c->prec, INV_PW, L, c->spec(), c->w(), c->prec, c->p(), nullptr, 1.0, cg);
+  launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->p(), c->x(), c->flin(), 1.0, c->spec(), cg);
   launch_cg_alpha(L, cg);
-  launch_cg_update(c->prec, L, c->x(), c->r(), c->p(), c->w(), cg);
+  middle_passes(c->prec, L, c->spec(), cg);
+  launch_inv_a2(c->prec, INV_CGR, L, c->spec(), c->r(), c->prec, nullptr, 1.0, cg);
   launch_cg_beta(L, cg);
 }
 
@@ -447,7 +452,8 @@ int run_cg(fftnk_ctx* c, double eta, int max_cg) {
     }
     if (all) {
       if (most > 0) c->cg_estimate = most;
-      return FFTNK_OK;
+      launch_cg_finish(c->prec, L, c->x(), c->p(), c->cg());  // the last iteration's deferred x update
+      return check_launch();
     }
     if (launched > max_cg + 64) return FFTNK_ECG_MAXIT;  // unreachable: k_cg_beta stops at max_cg
     e = launch_iterations(c, c->check_every);
@@ -776,9 +782,10 @@ int fftnk_apply_operator(fftnk_ctx* c, const void* p_dev, void* Ap_dev) {
   if (!c || !p_dev || !Ap_dev || p_dev == Ap_dev) return FFTNK_EINVAL;
   if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
   const Launch L = c->launch();
-  launch_fwd_a2(c->prec, FWD_TANGENT, L, c->material(), p_dev, nullptr, nullptr, c->flin(), 1.0, c->spec(), nullptr);
+  launch_fwd_a2(c->prec, FWD_TANGENT, L, c->material(), p_dev, nullptr, nullptr, nullptr, c->flin(), 1.0, c->spec(),
+                nullptr);
   middle_passes(c->prec, L, c->spec(), nullptr);
-  launch_inv_a2(c->prec, INV_OUT, L, c->spec(), Ap_dev, c->prec, nullptr, nullptr, 1.0, nullptr);
+  launch_inv_a2(c->prec, INV_OUT, L, c->spec(), Ap_dev, c->prec, nullptr, 1.0, nullptr);
   return check_launch();
 }
 
@@ -786,9 +793,9 @@ int fftnk_project(fftnk_ctx* c, const void* a_dev, void* Ga_dev) {
   if (!c || !a_dev || !Ga_dev) return FFTNK_EINVAL;
   if (!c->ws) return FFTNK_ESTATE;
   const Launch L = c->launch();
-  launch_fwd_a2(c->prec, FWD_COPY, L, c->material(), a_dev, nullptr, nullptr, nullptr, 1.0, c->spec(), nullptr);
+  launch_fwd_a2(c->prec, FWD_COPY, L, c->material(), a_dev, nullptr, nullptr, nullptr, nullptr, 1.0, c->spec(), nullptr);
   middle_passes(c->prec, L, c->spec(), nullptr);
-  launch_inv_a2(c->prec, INV_OUT, L, c->spec(), Ga_dev, c->prec, nullptr, nullptr, 1.0, nullptr);
+  launch_inv_a2(c->prec, INV_OUT, L, c->spec(), Ga_dev, c->prec, nullptr, 1.0, nullptr);
   return check_launch();
 }
 
@@ -809,13 +816,13 @@ int fftnk_launch_pass(fftnk_ctx* c, int pass) {
   const Launch L = c->launch();
   switch (pass) {
     case 1:
-      launch_fwd_a2(c->prec, FWD_TANGENT, L, c->material(), c->p(), nullptr, nullptr, c->flin(), 1.0, c->spec(),
-                    nullptr);
+      launch_fwd_a2(c->prec, FWD_TANGENT, L, c->material(), c->p(), nullptr, nullptr, nullptr, c->flin(), 1.0,
+                    c->spec(), nullptr);
       break;
     case 2: launch_col_a1(c->prec, false, L, c->spec(), nullptr); break;
     case 3: launch_col_a0_project(c->prec, L, c->spec(), nullptr); break;
     case 4: launch_col_a1(c->prec, true, L, c->spec(), nullptr); break;
-    default: launch_inv_a2(c->prec, INV_OUT, L, c->spec(), c->w(), c->prec, nullptr, nullptr, 1.0, nullptr); break;
+    default: launch_inv_a2(c->prec, INV_OUT, L, c->spec(), c->w(), c->prec, nullptr, 1.0, nullptr); break;
   }
   return check_launch();
 }

@@ -7,6 +7,32 @@
 
 namespace fftnk {
 
+// Launch metadata that a kernel only reads (grids, start tables, masks, uniform
+// tensors, and the CG scalars, which only other launches write) is read through
+// the constant address space: uniform reads of it become scalar loads, also in
+// the tile loops of kernels that store to global memory (where the compiler
+// could not otherwise rule out aliasing and would use vector loads).
+template <typename T>
+using cptr_t = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr_t<T> cptr(const T* p) {
+  return (cptr_t<T>)p;
+}
+__device__ __forceinline__ const __attribute__((address_space(4))) Grid& grid_of(const Batch& B, int rv) {
+  return *cptr(B.grids + rv);
+}
+
+// p advanced by b bytes.  With p uniform and b a 32-bit lane offset the access
+// compiles to a scalar base plus one offset register (no 64-bit lane address).
+template <typename T>
+__device__ __forceinline__ T* byte_off(T* p, unsigned b) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + b);
+}
+template <typename T>
+__device__ __forceinline__ const T* byte_off(const T* p, unsigned b) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + b);
+}
+
 // ---------------------------------------------------------------------------
 // complex arithmetic
 // ---------------------------------------------------------------------------
@@ -39,7 +65,7 @@ __device__ __forceinline__ cx<T> rot(cx<T> a, bool inv) {
 // W_n^e from the forward table (exp(-2 pi i e / n)); conjugated for the inverse
 template <typename T>
 __device__ __forceinline__ cx<T> twid(const cx<T>* tw, int e, bool inv) {
-  cx<T> w = tw[e];
+  cx<T> w = tw[lpad(e)];
   if (inv) w.y = -w.y;
   return w;
 }
@@ -188,8 +214,8 @@ __device__ __forceinline__ void stage_lds_prime(const cx<T>* __restrict__ src, c
 // Full 1-D transform of npen pencils; buffers a (input) and b (scratch)
 // ping-pong.  Returns the buffer holding the result.  The caller synchronises
 // before (input written); the routine synchronises after every stage.
-template <typename T>
-__device__ __forceinline__ cx<T>* fft_lds(cx<T>* a, cx<T>* b, const AxisPlan& pl, int npen, int sp, int se, const cx<T>* tw,
+template <typename T, typename PL>
+__device__ __forceinline__ cx<T>* fft_lds(cx<T>* a, cx<T>* b, const PL& pl, int npen, int sp, int se, const cx<T>* tw,
                           bool inv, bool pen_fast) {
   int Ns = 1;
   for (int s = 0; s < pl.nstages; ++s) {
@@ -213,64 +239,85 @@ __device__ __forceinline__ cx<T>* fft_lds(cx<T>* a, cx<T>* b, const AxisPlan& pl
 }
 
 // ---------------------------------------------------------------------------
-// Register-resident engine (power-of-two lengths n >= 8, radices 8 / 4 / 2).
+// Register-resident engine (power-of-two lengths 8 <= n <= kMaxLen, radices
+// 8 / 4 / 2, specialised at compile time for every length so that all index
+// arithmetic is shifts and constants).
 // A pencil is split over Tp = n / kRegP threads; thread t holds
 // v[q] = x[t + Tp q], q < kRegP, for the whole transform.  In every Stockham
 // stage the butterflies of thread t are j = t + k Tp (k < kRegP / R) and their
 // inputs are exactly its own registers v[k + r kRegP/R]; only the outputs move,
-// through one LDS exchange per stage (element e of the thread's pencil at
-// xl[e * es]), and the outputs of the last stage land in natural order on the
-// same register slots, so loads from and stores to global memory need no LDS.
-// All threads of the work-group must call it (it contains barriers).
+// through one LDS exchange per stage, and the outputs of the last stage land in
+// natural order on the same register slots, so loads from and stores to global
+// memory need no LDS.  Exchange layouts: ROW == false, pencils interleaved
+// (element e of the thread's pencil at xl[e * ES], ES = kThreads / Tp pencils,
+// consecutive lanes own consecutive pencils); ROW == true, one unit-stride line
+// per pencil (element e at xl[lpad(e)], the slot spans padded_len(n) entries).
+// The radix sequence splits log2 n into ceil(log2 n / 3) near-equal stages,
+// larger radices first.  All threads of the work-group must call it (it
+// contains barriers).
 // ---------------------------------------------------------------------------
-template <typename T, int R>
-__device__ __forceinline__ void reg_stage(cx<T> (&v)[kRegP], int t, int Tp, int n, int Ns, const cx<T>* tw, bool inv,
-                                          cx<T>* xl, int es, bool last) {
-  constexpr int B = kRegP / R;
-  const int tws = n / (Ns * R);
+constexpr int ct_log2(int n) { return n <= 1 ? 0 : 1 + ct_log2(n >> 1); }
+constexpr int ct_nstages(int n) { return (ct_log2(n) + 2) / 3; }
+constexpr int ct_radix(int n, int s) {
+  return 1 << (ct_log2(n) / ct_nstages(n) + (s < ct_log2(n) % ct_nstages(n) ? 1 : 0));
+}
+constexpr int ct_span(int n, int s) { return s == 0 ? 1 : ct_span(n, s - 1) * ct_radix(n, s - 1); }
+
+template <int N, bool ROW>
+__device__ __forceinline__ int xslot(int e) {
+  if constexpr (ROW)
+    return lpad(e);
+  else
+    return e * (kThreads * kRegP / N);
+}
+
+template <typename T, int N, bool ROW, int S>
+__device__ __forceinline__ void reg_stages(cx<T> (&v)[kRegP], int t, const cx<T>* tw, bool inv, cx<T>* xl) {
+  if constexpr (S < ct_nstages(N)) {
+    constexpr int R = ct_radix(N, S), NS = ct_span(N, S), Tp = N / kRegP, B = kRegP / R, TWS = N / (NS * R);
+    constexpr bool LAST = S + 1 == ct_nstages(N);
 #pragma unroll
-  for (int k = 0; k < B; ++k) {
-    cx<T> a[R];
+    for (int k = 0; k < B; ++k) {
+      cx<T> a[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) a[r] = v[k + r * B];
-    const int j = t + k * Tp;
-    const int kk = j & (Ns - 1);  // Ns is a power of two
-    if (kk != 0) {
+      for (int r = 0; r < R; ++r) a[r] = v[k + r * B];
+      const int j = t + k * Tp;
+      const int kk = j & (NS - 1);
+      if constexpr (NS > 1) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) a[r] = cmul(a[r], twid(tw, kk * r * tws, inv));
+        for (int r = 1; r < R; ++r) a[r] = cmul(a[r], twid(tw, kk * (r * TWS), inv));
+      }
+      SmallDft<T, R>::run(a, tw, N, inv);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[k + r * B] = a[r];
+      } else {
+        const int base = (j - kk) * R + kk;
+#pragma unroll
+        for (int r = 0; r < R; ++r) xl[xslot<N, ROW>(base + r * NS)] = a[r];
+      }
     }
-    SmallDft<T, R>::run(a, tw, n, inv);
-    if (last) {
+    if constexpr (!LAST) {
+      __syncthreads();
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[k + r * B] = a[r];
-    } else {
-      const int base = (j - kk) * R + kk;
-#pragma unroll
-      for (int r = 0; r < R; ++r) xl[(base + r * Ns) * es] = a[r];
+      for (int q = 0; q < kRegP; ++q) v[q] = xl[xslot<N, ROW>(t + Tp * q)];
+      __syncthreads();
+      reg_stages<T, N, ROW, S + 1>(v, t, tw, inv, xl);
     }
-  }
-  if (!last) {
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kRegP; ++q) v[q] = xl[(t + Tp * q) * es];
-    __syncthreads();
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void reg_fft(cx<T> (&v)[kRegP], const AxisPlan& pl, int t, int Tp, const cx<T>* tw,
-                                        bool inv, cx<T>* xl, int es) {
-  int Ns = 1;
-  for (int s = 0; s < pl.nstages; ++s) {
-    const int R = pl.radix[s];
-    const bool last = s == pl.nstages - 1;
-    if (R == 8)
-      reg_stage<T, 8>(v, t, Tp, pl.n, Ns, tw, inv, xl, es, last);
-    else if (R == 4)
-      reg_stage<T, 4>(v, t, Tp, pl.n, Ns, tw, inv, xl, es, last);
-    else
-      reg_stage<T, 2>(v, t, Tp, pl.n, Ns, tw, inv, xl, es, last);
-    Ns *= R;
+// Transform of length n (a power of two in [8, kMaxLen]); t in [0, n / kRegP).
+template <typename T, bool ROW>
+__device__ __forceinline__ void reg_fft(cx<T> (&v)[kRegP], int n, int t, const cx<T>* tw, bool inv, cx<T>* xl) {
+  static_assert(kMaxLen == 256, "length dispatch covers 8..256");
+  switch (n) {
+    case 8: reg_stages<T, 8, ROW, 0>(v, t, tw, inv, xl); break;
+    case 16: reg_stages<T, 16, ROW, 0>(v, t, tw, inv, xl); break;
+    case 32: reg_stages<T, 32, ROW, 0>(v, t, tw, inv, xl); break;
+    case 64: reg_stages<T, 64, ROW, 0>(v, t, tw, inv, xl); break;
+    case 128: reg_stages<T, 128, ROW, 0>(v, t, tw, inv, xl); break;
+    default: reg_stages<T, 256, ROW, 0>(v, t, tw, inv, xl); break;
   }
 }
 
@@ -282,14 +329,15 @@ __device__ __forceinline__ const cx<T>* table_of(const Batch& B) {
 template <typename T>
 __device__ __forceinline__ void load_twiddles(cx<T>* dst, const Batch& B, int off, int n) {
   const cx<T>* src = table_of<T>(B) + off;
-  for (int i = threadIdx.x; i < n; i += kThreads) dst[i] = src[i];
+  for (int i = threadIdx.x; i < n; i += kThreads) dst[lpad(i)] = src[i];
 }
+
 
 // ---------------------------------------------------------------------------
 // work-group -> RVE (binary search in the launch kind's start table)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int find_rve(const Batch& B, int kind, int b, int& local) {
-  const int* s = B.starts + kind * (B.nrve + 1);
+  const auto s = cptr(B.starts + kind * (B.nrve + 1));
   int lo = 0, hi = B.nrve;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -303,15 +351,15 @@ __device__ __forceinline__ int find_rve(const Batch& B, int kind, int b, int& lo
 }
 
 __device__ __forceinline__ int rve_blocks(const Batch& B, int kind, int r) {
-  const int* s = B.starts + kind * (B.nrve + 1);
+  const auto s = cptr(B.starts + kind * (B.nrve + 1));
   return s[r + 1] - s[r];
 }
 
 // skip rule of a launch: CG launches skip RVEs whose CG is done, Newton-level
 // launches skip RVEs that have finished the increment
 __device__ __forceinline__ bool skip_rve(const Batch& B, const CgState* cg, int r) {
-  if (cg) return cg[r].done != 0;
-  return B.active && B.active[r] == 0;
+  if (cg) return cptr(cg)[r].done != 0;
+  return B.active && cptr(B.active)[r] == 0;
 }
 
 // ---------------------------------------------------------------------------

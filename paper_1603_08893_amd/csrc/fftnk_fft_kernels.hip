@@ -24,6 +24,7 @@ int elem_blocks(long long m) {
 }
 
 int row_blocks(const Grid& g) { return (int)((g.rows + g.rt - 1) / g.rt); }
+int row1_blocks(const Grid& g) { return (int)((g.rows + g.rt1 - 1) / g.rt1); }
 
 static int reg_pencils(int n) { return kThreads / (n / kRegP); }  // pencils per work-group, register engine
 
@@ -47,7 +48,7 @@ int col0_blocks(const Grid& g, int prec) {
 
 // ---------------------------------------------------------------------------
 // Pass 1: a2 forward transform of the 9 components, fused with the production
-// of the field being transformed.  Each work-group owns g.rt consecutive grid
+// of the field being transformed.  Each work-group owns g.rt1 consecutive grid
 // lines.  Component pairs (0,1) (2,3) (4,5) (6,7) are packed as x + i y into
 // one complex transform (two real transforms for the price of one), component
 // 8 rides alone; the half spectra are unpacked with X[k] = (Z[k] + conj Z[-k])/2
@@ -68,74 +69,103 @@ __device__ __forceinline__ void tangent_at(const Material& mat, long long gv, co
 }
 
 template <typename T, int MODE, int LAW>
-__global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, const T* __restrict__ in,
-                                                     const T* __restrict__ rvec, T* __restrict__ pvec,
-                                                     const T* __restrict__ Flin, double scale,
-                                                     cx<T>* __restrict__ spec, const CgState* __restrict__ cg) {
+__device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat, const T* __restrict__ in,
+                                            const T* __restrict__ rvec, T* __restrict__ pvec, T* __restrict__ xvec,
+                                            const T* __restrict__ Flin, double scale, cx<T>* __restrict__ spec,
+                                            const CgState* __restrict__ cg, const int b) {
   int local;
-  const int rv = find_rve(B, K_ROW, blockIdx.x, local);
+  const int rv = find_rve(B, K_ROW1, b, local);
   if (skip_rve(B, MODE == FWD_CG ? cg : nullptr, rv)) return;
-  const Grid& g = B.grids[rv];
+  const auto& g = grid_of(B, rv);
   extern __shared__ unsigned char smem_raw[];
-  const int N2 = g.n2, RT = g.rt, H = g.h;
+  const int N2 = g.n2, RT = g.rt1, H = g.h;
   const int npen = 5 * RT;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* bufA = tw + N2;
+  cx<T>* bufA = tw + padded_len(N2);
   cx<T>* bufB = bufA + npen * N2;
   load_twiddles<T>(tw, B, g.ax[2].tw, N2);
 
   const long long n = g.n;
   const long long off = 9 * g.vox_off;
   const long long row0 = (long long)local * RT;
-  double beta = 0.0;
-  bool first = false;
-  if (MODE == FWD_CG) {
-    beta = cg[rv].beta;
-    first = cg[rv].iter == 0;
-  }
+  // partial sum: <p, K p> (FWD_CG) or ||K p||^2 / ||field||^2 (the projected field's norm)
   double acc[1] = {0.0};
   // register engine: pencil slot m = pair * RT + line (slots >= 5 RT idle),
   // stage the field in LDS once, transform in registers, unpack through one
   // mirror exchange.  bufA holds one slot of N2 entries per kThreads / Tp.
   const bool reg = g.ax[2].reg;
-  for (int t = threadIdx.x; t < RT * N2; t += kThreads) {
+  const int SL = reg ? padded_len(N2) : N2;  // LDS slot of one line
+  if ((int)threadIdx.x < RT * N2) {  // rt1 * n2 <= kThreads: at most one voxel per thread
+    const int t = threadIdx.x;
     const int rl = t / N2, a2 = t - rl * N2;
     const long long row = row0 + rl;
     T d[9];
     if (row < g.rows) {
       const long long v = row * N2 + a2;
+      // uniform component base + 32-bit byte offset of the voxel (n <= 2^24);
+      // every load below is issued before any arithmetic uses it
+      const unsigned vb = (unsigned)v * (unsigned)sizeof(T);
       if (MODE == FWD_COPY) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) d[c] = (T)scale * in[off + c * n + v];
+        for (int c = 0; c < 9; ++c) d[c] = (T)scale * *byte_off(in + off + c * n, vb);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[0] += (double)d[c] * (double)d[c];
       } else {
         T p[9], F[9];
         if (MODE == FWD_TANGENT_UNI) {
 #pragma unroll
-          for (int c = 0; c < 9; ++c) p[c] = (T)B.uni[9 * rv + c];
+          for (int c = 0; c < 9; ++c) p[c] = (T)cptr(B.uni)[9 * rv + c];
+#pragma unroll
+          for (int c = 0; c < 9; ++c) F[c] = *byte_off(Flin + off + c * n, vb);
         } else if (MODE == FWD_TANGENT) {
 #pragma unroll
-          for (int c = 0; c < 9; ++c) p[c] = in[off + c * n + v];
+          for (int c = 0; c < 9; ++c) p[c] = *byte_off(in + off + c * n, vb);
+#pragma unroll
+          for (int c = 0; c < 9; ++c) F[c] = *byte_off(Flin + off + c * n, vb);
         } else {  // FWD_CG
+          const bool first = cptr(cg)[rv].iter == 0;
+          if (first) {  // p_0 = r_0, x_0 = 0
 #pragma unroll
-          for (int c = 0; c < 9; ++c) {
-            const T r = rvec[off + c * n + v];
-            p[c] = first ? r : r + (T)beta * pvec[off + c * n + v];
-            pvec[off + c * n + v] = p[c];
+            for (int c = 0; c < 9; ++c) p[c] = *byte_off(rvec + off + c * n, vb);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) F[c] = *byte_off(Flin + off + c * n, vb);
+          } else {  // x += alpha p_old (previous iteration), p = r + beta p_old
+            const T alpha = (T)cptr(cg)[rv].alpha, beta = (T)cptr(cg)[rv].beta;
+            T po[9], xo[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+              p[c] = *byte_off(rvec + off + c * n, vb);
+              po[c] = *byte_off(pvec + off + c * n, vb);
+              xo[c] = *byte_off(xvec + off + c * n, vb);
+            }
+#pragma unroll
+            for (int c = 0; c < 9; ++c) F[c] = *byte_off(Flin + off + c * n, vb);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+              *byte_off(xvec + off + c * n, vb) = xo[c] + alpha * po[c];
+              p[c] = p[c] + beta * po[c];
+            }
           }
+#pragma unroll
+          for (int c = 0; c < 9; ++c) *byte_off(pvec + off + c * n, vb) = p[c];
         }
-#pragma unroll
-        for (int c = 0; c < 9; ++c) F[c] = Flin[off + c * n + v];
         tangent_at<T, LAW>(mat, g.vox_off + v, F, p, d);
-      }
+        if (MODE == FWD_CG) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) acc[0] += (double)d[c] * (double)d[c];
+          for (int c = 0; c < 9; ++c) acc[0] += (double)p[c] * (double)d[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) acc[0] += (double)d[c] * (double)d[c];
+        }
+      }
     } else {
 #pragma unroll
       for (int c = 0; c < 9; ++c) d[c] = (T)0;
     }
+    const int ea = reg ? lpad(a2) : a2;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) bufA[(q * RT + rl) * N2 + a2] = cx<T>{d[2 * q], d[2 * q + 1]};
-    bufA[(4 * RT + rl) * N2 + a2] = cx<T>{d[8], (T)0};
+    for (int q = 0; q < 4; ++q) bufA[(q * RT + rl) * SL + ea] = cx<T>{d[2 * q], d[2 * q + 1]};
+    bufA[(4 * RT + rl) * SL + ea] = cx<T>{d[8], (T)0};
   }
   __syncthreads();
   const long long srow = g.rows * H;
@@ -144,14 +174,14 @@ __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, cons
   if (reg) {
     const int Tp = N2 / kRegP;
     const int m = threadIdx.x / Tp, t = threadIdx.x - m * Tp;
-    cx<T>* xl = bufA + m * N2;
+    cx<T>* xl = bufA + m * SL;
     cx<T> v[kRegP];
 #pragma unroll
-    for (int q = 0; q < kRegP; ++q) v[q] = xl[t + Tp * q];
+    for (int q = 0; q < kRegP; ++q) v[q] = xl[lpad(t + Tp * q)];
     __syncthreads();
-    reg_fft<T>(v, g.ax[2], t, Tp, tw, false, xl, 1);
+    reg_fft<T, true>(v, N2, t, tw, false, xl);
 #pragma unroll
-    for (int q = 0; q < kRegP; ++q) xl[t + Tp * q] = v[q];
+    for (int q = 0; q < kRegP; ++q) xl[lpad(t + Tp * q)] = v[q];
     __syncthreads();
     const int pq = m / RT, rl = m - pq * RT;
     const long long row = row0 + rl;
@@ -160,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, cons
       for (int q = 0; q < kRegP / 2; ++q) {  // k = t + Tp q < n2 / 2 = h
         const int k = t + Tp * q;
         const cx<T> z = v[q];
-        const cx<T> zm = xl[k ? N2 - k : 0];
+        const cx<T> zm = xl[lpad(k ? N2 - k : 0)];
         if (pq == 4) {
           S[8 * srow + row * H + k] = z;
         } else {
@@ -169,11 +199,9 @@ __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, cons
         }
       }
     }
-    if (MODE != FWD_CG) {
-      double res[1];
-      block_sums<1>(acc, res);
-      if (threadIdx.x == 0) pslot(B, SLOT_YY)[blockIdx.x] = res[0];
-    }
+    double res[1];
+    block_sums<1>(acc, res);
+    if (threadIdx.x == 0) pslot(B, MODE == FWD_CG ? SLOT_PW : SLOT_YY)[b] = res[0];
     return;
   }
 
@@ -197,11 +225,17 @@ __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, cons
     }
     S[c * srow + row * H + k] = o;
   }
-  if (MODE != FWD_CG) {
-    double res[1];
-    block_sums<1>(acc, res);
-    if (threadIdx.x == 0) pslot(B, SLOT_YY)[blockIdx.x] = res[0];
-  }
+  double res[1];
+  block_sums<1>(acc, res);
+  if (threadIdx.x == 0) pslot(B, MODE == FWD_CG ? SLOT_PW : SLOT_YY)[b] = res[0];
+}
+
+template <typename T, int MODE, int LAW>
+__global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, const T* __restrict__ in,
+                                                     const T* __restrict__ rvec, T* __restrict__ pvec,
+                                                     T* __restrict__ xvec, const T* __restrict__ Flin, double scale,
+                                                     cx<T>* __restrict__ spec, const CgState* __restrict__ cg) {
+  tile_fwd_a2<T, MODE, LAW>(B, mat, in, rvec, pvec, xvec, Flin, scale, spec, cg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -212,12 +246,12 @@ __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, cons
 // (component, a0) plane.
 // ---------------------------------------------------------------------------
 template <typename T, bool INV>
-__global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict__ spec,
-                                                     const CgState* __restrict__ cg) {
+__device__ __forceinline__ void tile_col_a1(const Batch& B, cx<T>* __restrict__ spec,
+                                                     const CgState* __restrict__ cg, const int b) {
   int local;
-  const int rv = find_rve(B, sizeof(T) == 8 ? K_COL1_64 : K_COL1_32, blockIdx.x, local);
+  const int rv = find_rve(B, sizeof(T) == 8 ? K_COL1_64 : K_COL1_32, b, local);
   if (skip_rve(B, cg, rv)) return;
-  const Grid& g = B.grids[rv];
+  const auto& g = grid_of(B, rv);
   extern __shared__ unsigned char smem_raw[];
   const int N1 = g.n1, H = g.h;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
@@ -225,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict_
   cx<T>* S0 = spec + g.spec_off;
 
   if (g.ax[1].reg) {
-    cx<T>* xl = tw + N1;
+    cx<T>* xl = tw + padded_len(N1);
     const int Tp = N1 / kRegP, Mb = kThreads / Tp;
     const int m = threadIdx.x % Mb, t = threadIdx.x / Mb;
     const long long npen = 9LL * g.n0 * H;
@@ -237,7 +271,7 @@ __global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict_
     cx<T> v[kRegP];
 #pragma unroll
     for (int q = 0; q < kRegP; ++q) v[q] = valid ? base[(long long)(t + Tp * q) * H] : cx<T>{(T)0, (T)0};
-    reg_fft<T>(v, g.ax[1], t, Tp, tw, INV, xl + m, Mb);
+    reg_fft<T, false>(v, N1, t, tw, INV, xl + m);
     if (valid) {
 #pragma unroll
       for (int q = 0; q < kRegP; ++q) base[(long long)(t + Tp * q) * H] = v[q];
@@ -246,7 +280,7 @@ __global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict_
   }
 
   const int M = sizeof(T) == 8 ? g.m64 : g.m32;
-  cx<T>* bufA = tw + N1;
+  cx<T>* bufA = tw + padded_len(N1);
   cx<T>* bufB = bufA + N1 * M;
   const int nkb = (H + M - 1) / M;
   const int c = local / (g.n0 * nkb);
@@ -266,6 +300,11 @@ __global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict_
   }
 }
 
+template <typename T, bool INV>
+__global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict__ spec, const CgState* __restrict__ cg) {
+  tile_col_a1<T, INV>(B, spec, cg, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Pass 3: a0 forward transform, projection, a0 inverse transform.  A pencil is
 // one (tensor row i, k1, k2) triple carrying the three components 3i..3i+2:
@@ -277,9 +316,9 @@ __global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict_
 // ---------------------------------------------------------------------------
 constexpr int kMaxPpt = 8;  // points per thread of an LDS-engine pass-3 tile (n0 * m <= kMaxPpt * kThreads)
 
-template <typename T>
+template <typename T, typename G>
 __device__ __forceinline__ void project_point(cx<T>& a0, cx<T>& a1, cx<T>& a2, int k0, int k1, int k2,
-                                              const Grid& g) {
+                                              const G& g, T rn0, T rn1, T rn2 /* 1 / N_d */) {
   const int f0 = signed_freq(k0, g.n0), f1 = signed_freq(k1, g.n1);
   const bool zero = (f0 == 0 && f1 == 0 && k2 == 0) || ((g.n0 % 2 == 0) && (2 * k0 == g.n0)) ||
                     ((g.n1 % 2 == 0) && (2 * k1 == g.n1));
@@ -287,7 +326,7 @@ __device__ __forceinline__ void project_point(cx<T>& a0, cx<T>& a1, cx<T>& a2, i
     a0 = a1 = a2 = cx<T>{(T)0, (T)0};
     return;
   }
-  const T xi0 = (T)f0 / (T)g.n0, xi1 = (T)f1 / (T)g.n1, xi2 = (T)k2 / (T)g.n2;
+  const T xi0 = (T)f0 * rn0, xi1 = (T)f1 * rn1, xi2 = (T)k2 * rn2;
   const T coef = (T)g.inv_n / (xi0 * xi0 + xi1 * xi1 + xi2 * xi2);
   cx<T> s = cscale(a0, xi0);
   s = s + cscale(a1, xi1);
@@ -298,12 +337,12 @@ __device__ __forceinline__ void project_point(cx<T>& a0, cx<T>& a1, cx<T>& a2, i
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* __restrict__ spec,
-                                                             const CgState* __restrict__ cg) {
+__device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __restrict__ spec,
+                                                             const CgState* __restrict__ cg, const int b) {
   int local;
-  const int rv = find_rve(B, sizeof(T) == 8 ? K_COL0_64 : K_COL0_32, blockIdx.x, local);
+  const int rv = find_rve(B, sizeof(T) == 8 ? K_COL0_64 : K_COL0_32, b, local);
   if (skip_rve(B, cg, rv)) return;
-  const Grid& g = B.grids[rv];
+  const auto& g = grid_of(B, rv);
   extern __shared__ unsigned char smem_raw[];
   const int N0 = g.n0, N1 = g.n1, H = g.h;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
@@ -311,9 +350,10 @@ __global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* 
   cx<T>* S0 = spec + g.spec_off;
   const long long S = (long long)N1 * H;  // element stride along a0
   const long long cstride = g.rows * H;
+  const T rn0 = (T)1 / (T)N0, rn1 = (T)1 / (T)N1, rn2 = (T)1 / (T)g.n2;
 
   if (g.ax[0].reg) {
-    cx<T>* xl = tw + N0;
+    cx<T>* xl = tw + padded_len(N0);
     const int Tp = N0 / kRegP, Mb = kThreads / Tp;
     const int m = threadIdx.x % Mb, t = threadIdx.x / Mb;
     const long long npen = 3LL * N1 * H;
@@ -323,37 +363,64 @@ __global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* 
     const long long qq = pen / H;
     const int k2 = (int)(pen - qq * H);
     const int i = (int)(qq / N1), k1 = (int)(qq - (long long)i * N1);
-    cx<T>* base = S0 + (long long)(3 * i) * cstride + (long long)k1 * H + k2;
-    cx<T> v0[kRegP], v1[kRegP], v2[kRegP];
+    // byte offset of the lane's first element inside the cell's spectrum (32
+    // bits: at most 9 n0 n1 h entries); the per-(component, q) parts are
+    // uniform, so loads and stores use a scalar base plus this one register
+    const unsigned lo =
+        (unsigned)(((long long)(3 * i) * cstride + (long long)k1 * H + k2 + (long long)t * S) * (long long)sizeof(cx<T>));
+    char* sb = reinterpret_cast<char*>(S0);
+    auto at = [&](int c, int q) {
+      return reinterpret_cast<cx<T>*>(sb + ((long long)c * cstride + (long long)q * Tp * S) * (long long)sizeof(cx<T>) + lo);
+    };
+    // Along the pencil k1, k2 are fixed, so xi_1, xi_2 are constants and the
+    // a0 transform commutes with them: with s = sum_l xi_l A_il,
+    //   s = xi_0 FFT(a_i0) + FFT(xi_1 a_i1 + xi_2 a_i2),
+    //   out_i0 = IFFT(xi_0 c s),  out_i1 = xi_1 IFFT(c s),  out_i2 = xi_2 IFFT(c s),
+    // c = (1/n) / |xi|^2 (zero at k = 0 and at an even axis' Nyquist index):
+    // two forward and two inverse transforms instead of three of each.
+    const int f1 = signed_freq(k1, N1);
+    const T xi1 = (T)f1 * rn1, xi2 = (T)k2 * rn2;
+    const bool pen_zero = (N1 % 2 == 0) && (2 * k1 == N1);
+    cx<T> v0[kRegP], v1[kRegP];
+    {
+      cx<T> v2[kRegP];
+#pragma unroll
+      for (int q = 0; q < kRegP; ++q) {
+        v0[q] = valid ? *at(0, q) : cx<T>{(T)0, (T)0};
+        v1[q] = valid ? *at(1, q) : cx<T>{(T)0, (T)0};
+        v2[q] = valid ? *at(2, q) : cx<T>{(T)0, (T)0};
+      }
+#pragma unroll
+      for (int q = 0; q < kRegP; ++q) v1[q] = cscale(v1[q], xi1) + cscale(v2[q], xi2);
+    }
+    reg_fft<T, false>(v1, N0, t, tw, false, xl + m);
+    reg_fft<T, false>(v0, N0, t, tw, false, xl + m);
 #pragma unroll
     for (int q = 0; q < kRegP; ++q) {
-      const long long e = (long long)(t + Tp * q) * S;
-      v0[q] = valid ? base[e] : cx<T>{(T)0, (T)0};
-      v1[q] = valid ? base[cstride + e] : cx<T>{(T)0, (T)0};
-      v2[q] = valid ? base[2 * cstride + e] : cx<T>{(T)0, (T)0};
+      const int k0 = t + Tp * q;
+      const int f0 = signed_freq(k0, N0);
+      const T xi0 = (T)f0 * rn0;
+      const bool zero = pen_zero || (f0 == 0 && f1 == 0 && k2 == 0) || ((N0 % 2 == 0) && (2 * k0 == N0));
+      const T c = zero ? (T)0 : (T)g.inv_n / (xi0 * xi0 + xi1 * xi1 + xi2 * xi2);
+      const cx<T> sc = cscale(cscale(v0[q], xi0) + v1[q], c);
+      v0[q] = cscale(sc, xi0);
+      v1[q] = sc;
     }
-    reg_fft<T>(v0, g.ax[0], t, Tp, tw, false, xl + m, Mb);
-    reg_fft<T>(v1, g.ax[0], t, Tp, tw, false, xl + m, Mb);
-    reg_fft<T>(v2, g.ax[0], t, Tp, tw, false, xl + m, Mb);
-#pragma unroll
-    for (int q = 0; q < kRegP; ++q) project_point<T>(v0[q], v1[q], v2[q], t + Tp * q, k1, k2, g);
-    reg_fft<T>(v0, g.ax[0], t, Tp, tw, true, xl + m, Mb);
-    reg_fft<T>(v1, g.ax[0], t, Tp, tw, true, xl + m, Mb);
-    reg_fft<T>(v2, g.ax[0], t, Tp, tw, true, xl + m, Mb);
+    reg_fft<T, false>(v0, N0, t, tw, true, xl + m);
+    reg_fft<T, false>(v1, N0, t, tw, true, xl + m);
     if (valid) {
 #pragma unroll
       for (int q = 0; q < kRegP; ++q) {
-        const long long e = (long long)(t + Tp * q) * S;
-        base[e] = v0[q];
-        base[cstride + e] = v1[q];
-        base[2 * cstride + e] = v2[q];
+        *at(0, q) = v0[q];
+        *at(1, q) = cscale(v1[q], xi1);
+        *at(2, q) = cscale(v1[q], xi2);
       }
     }
     return;
   }
 
   const int M = sizeof(T) == 8 ? g.m64 : g.m32;
-  cx<T>* bufA = tw + N0;
+  cx<T>* bufA = tw + padded_len(N0);
   cx<T>* bufB = bufA + N0 * M;
   const int nkb = (H + M - 1) / M;
   const int i = local / (N1 * nkb);
@@ -386,7 +453,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* 
     if (t < total) {
       const int k0 = t / M, m = t - k0 * M;
       if (m < Mt)
-        project_point<T>(reg[0][pt], reg[1][pt], reg[2][pt], k0, k1, kb * M + m, g);
+        project_point<T>(reg[0][pt], reg[1][pt], reg[2][pt], k0, k1, kb * M + m, g, rn0, rn1, rn2);
       else
         reg[0][pt] = reg[1][pt] = reg[2][pt] = cx<T>{(T)0, (T)0};
     }
@@ -409,6 +476,11 @@ __global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* 
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* __restrict__ spec, const CgState* __restrict__ cg) {
+  tile_col_a0_project<T>(B, spec, cg, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Pass 5: the a2 inverse (complex-to-real) transform.  The half spectra of a
 // component pair are recombined as Z = X + iY over the full line using the
@@ -417,18 +489,18 @@ __global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* 
 // Re / Im give the two real components.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, typename TO>
-__global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __restrict__ spec, TO* __restrict__ out,
-                                                     const TO* __restrict__ p, TO* __restrict__ x, double scale,
-                                                     const CgState* __restrict__ cg) {
+__device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restrict__ spec, TO* __restrict__ out,
+                                            TO* __restrict__ x, double scale,
+                                                     const CgState* __restrict__ cg, const int b) {
   int local;
-  const int rv = find_rve(B, K_ROW, blockIdx.x, local);
-  if (skip_rve(B, MODE == INV_PW ? cg : nullptr, rv)) return;
-  const Grid& g = B.grids[rv];
+  const int rv = find_rve(B, K_ROW, b, local);
+  if (skip_rve(B, MODE == INV_CGR ? cg : nullptr, rv)) return;
+  const auto& g = grid_of(B, rv);
   extern __shared__ unsigned char smem_raw[];
   const int N2 = g.n2, RT = g.rt, H = g.h;
   const int npen = 5 * RT;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
-  cx<T>* bufA = tw + N2;
+  cx<T>* bufA = tw + padded_len(N2);
   cx<T>* bufB = bufA + npen * N2;
   load_twiddles<T>(tw, B, g.ax[2].tw, N2);
 
@@ -446,34 +518,57 @@ __global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __res
     const long long row = row0 + rl;
     const bool valid = m < npen && row < g.rows;
     const int c0 = pq < 4 ? 2 * pq : 8;
+    // Thread t loads the stored half line at k = t + Tp q, q < kRegP / 2 (all
+    // of k < h = n2 / 2, each entry once, addresses clamped into the cell).
+    // The upper half k = n2 - k' needs conj X[k'], held by lane (Tp - t) mod Tp
+    // of the same pencil at q' = kRegP - 1 - q (lane 0 holds its own at
+    // q' = kRegP - q; q = kRegP / 2 is the Nyquist index, zero).
+    constexpr int P2 = kRegP / 2;
+    const cx<T>* SX = S + c0 * srow + (valid ? row : row0) * H;
+    const cx<T>* SY = pq < 4 ? SX + srow : SX;
+    cx<T> X[P2], Y[P2];
+#pragma unroll
+    for (int q = 0; q < P2; ++q) {
+      X[q] = SX[t + Tp * q];
+      Y[q] = SY[t + Tp * q];
+    }
+    const T yon = pq < 4 ? (T)1 : (T)0;  // component 8 rides alone
     cx<T> v[kRegP];
 #pragma unroll
-    for (int q = 0; q < kRegP; ++q) {
-      const int k = t + Tp * q;
-      cx<T> z = {(T)0, (T)0};
-      if (valid && 2 * k != N2) {
-        const bool mirror = k >= H;
-        const int kk = mirror ? N2 - k : k;
-        cx<T> X = S[c0 * srow + row * H + kk];
-        cx<T> Y = pq < 4 ? S[(c0 + 1) * srow + row * H + kk] : cx<T>{(T)0, (T)0};
-        if (k == 0) {
-          X.y = (T)0;
-          Y.y = (T)0;
-        }
-        if (mirror) {
-          X.y = -X.y;
-          Y.y = -Y.y;
-        }
-        z = cx<T>{X.x - Y.y, X.y + Y.x};
-      }
-      v[q] = z;
+    for (int q = 0; q < P2; ++q) {
+      const T xi = (t == 0 && q == 0) ? (T)0 : X[q].y;  // k = 0 taken real
+      const T yi = (t == 0 && q == 0) ? (T)0 : yon * Y[q].y;
+      v[q] = valid ? cx<T>{X[q].x - yi, xi + yon * Y[q].x} : cx<T>{(T)0, (T)0};
     }
-    reg_fft<T>(v, g.ax[2], t, Tp, tw, true, bufA + m * N2, 1);
+    const int src = (Tp - t) & (Tp - 1);
+#pragma unroll
+    for (int q = P2; q < kRegP; ++q) {
+      cx<T> xm, ym;
+      xm.x = __shfl(X[kRegP - 1 - q].x, src, Tp);
+      xm.y = __shfl(X[kRegP - 1 - q].y, src, Tp);
+      ym.x = __shfl(Y[kRegP - 1 - q].x, src, Tp);
+      ym.y = __shfl(Y[kRegP - 1 - q].y, src, Tp);
+      if (t == 0) {
+        xm = q == P2 ? cx<T>{(T)0, (T)0} : X[q == P2 ? 0 : kRegP - q];
+        ym = q == P2 ? cx<T>{(T)0, (T)0} : Y[q == P2 ? 0 : kRegP - q];
+      }
+      const T xi = -xm.y, yi = -yon * ym.y;  // conjugated
+      v[q] = valid ? cx<T>{xm.x - yi, xi + yon * ym.x} : cx<T>{(T)0, (T)0};
+    }
+    reg_fft<T, true>(v, N2, t, tw, true, bufA + m * padded_len(N2));
     double acc[1] = {0.0};
     if (valid) {
       const long long n = g.n;
       const long long base = 9 * g.vox_off + row * N2;
       const int nc = pq < 4 ? 2 : 1;
+      const T alpha = MODE == INV_CGR ? (T)cptr(cg)[rv].alpha : (T)0;
+      TO rin[kRegP][2];  // INV_CGR: the residual, all loads issued before use
+      if (MODE == INV_CGR) {
+#pragma unroll
+        for (int q = 0; q < kRegP; ++q)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) rin[q][h] = h < nc ? out[base + t + Tp * q + (c0 + h) * n] : (TO)0;
+      }
 #pragma unroll
       for (int q = 0; q < kRegP; ++q) {
         const long long v0 = base + t + Tp * q;
@@ -486,9 +581,10 @@ __global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __res
             const T o = (T)scale * w;
             out[idx] = (TO)o;
             acc[0] += (double)o * (double)o;
-          } else if (MODE == INV_PW) {
-            out[idx] = (TO)w;
-            acc[0] += (double)p[idx] * (double)(TO)w;
+          } else if (MODE == INV_CGR) {
+            const TO rn = (TO)((T)rin[q][h] - alpha * w);
+            out[idx] = rn;
+            acc[0] += (double)rn * (double)rn;
           } else {  // INV_RHS
             const T o = (T)scale * w;
             out[idx] = (TO)o;
@@ -500,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __res
     }
     double res[1];
     block_sums<1>(acc, res);
-    if (threadIdx.x == 0) pslot(B, MODE == INV_PW ? SLOT_PW : SLOT_BB)[blockIdx.x] = res[0];
+    if (threadIdx.x == 0) pslot(B, MODE == INV_CGR ? SLOT_RR : SLOT_BB)[b] = res[0];
     return;
   }
 
@@ -547,6 +643,11 @@ __global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __res
       w[2 * q + 1] = z.y;
     }
     w[8] = Z[(4 * RT + rl) * N2 + a2].x;
+    TO rin[9];  // INV_CGR: the residual, all loads issued before use
+    if (MODE == INV_CGR) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) rin[c] = out[off + c * n + v];
+    }
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       const long long idx = off + c * n + v;
@@ -554,9 +655,10 @@ __global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __res
         const T o = (T)scale * w[c];
         out[idx] = (TO)o;
         acc[0] += (double)o * (double)o;
-      } else if (MODE == INV_PW) {
-        out[idx] = (TO)w[c];
-        acc[0] += (double)p[idx] * (double)(TO)w[c];
+      } else if (MODE == INV_CGR) {
+        const TO rn = (TO)((T)rin[c] - (T)cptr(cg)[rv].alpha * w[c]);
+        out[idx] = rn;
+        acc[0] += (double)rn * (double)rn;
       } else {  // INV_RHS
         const T o = (T)scale * w[c];
         out[idx] = (TO)o;
@@ -567,98 +669,112 @@ __global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __res
   }
   double res[1];
   block_sums<1>(acc, res);
-  if (threadIdx.x == 0) pslot(B, MODE == INV_PW ? SLOT_PW : SLOT_BB)[blockIdx.x] = res[0];
+  if (threadIdx.x == 0) pslot(B, MODE == INV_CGR ? SLOT_RR : SLOT_BB)[b] = res[0];
+}
+
+template <typename T, int MODE, typename TO>
+__global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __restrict__ spec, TO* __restrict__ out,
+                                                     TO* __restrict__ x, double scale,
+                                                     const CgState* __restrict__ cg) {
+  tile_inv_a2<T, MODE, TO>(B, spec, out, x, scale, cg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// One work-group per tile: the hardware dispatcher staggers the work-groups'
+// load, transform and store phases better than a resident tile loop does
+// (measured on the 128^3 operator).
+template <typename... KArgs, typename... Args>
+static void launch_tiles(void (*kernel)(KArgs...), int ntiles, size_t lds, hipStream_t s, Args... args) {
+  if (ntiles < 1) return;
+  hipLaunchKernelGGL(kernel, dim3(ntiles), dim3(kThreads), lds, s, args...);
+}
+
 template <typename T, int LAW>
 static void fwd_a2_t(int mode, const Launch& L, const Material& mat, const void* in, const void* r, void* p,
-                     const void* Flin, double scale, void* spec, const CgState* cg) {
-  const dim3 grid(L.nblk[K_ROW]), block(kThreads);
+                     void* x, const void* Flin, double scale, void* spec, const CgState* cg) {
+  const int ntiles = L.nblk[K_ROW1];
   const size_t lds = sizeof(T) == 8 ? L.lds_row64 : L.lds_row32;
   const T* ti = static_cast<const T*>(in);
   const T* tr = static_cast<const T*>(r);
   T* tp = static_cast<T*>(p);
+  T* tx = static_cast<T*>(x);
   const T* tf = static_cast<const T*>(Flin);
   cx<T>* sp = static_cast<cx<T>*>(spec);
   switch (mode) {
-    case FWD_COPY: hipLaunchKernelGGL((k_fwd_a2<T, FWD_COPY, MODEL_SVK>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
-    case FWD_TANGENT: hipLaunchKernelGGL((k_fwd_a2<T, FWD_TANGENT, LAW>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
-    case FWD_TANGENT_UNI: hipLaunchKernelGGL((k_fwd_a2<T, FWD_TANGENT_UNI, LAW>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
-    default: hipLaunchKernelGGL((k_fwd_a2<T, FWD_CG, LAW>), grid, block, lds, L.s, L.b, mat, ti, tr, tp, tf, scale, sp, cg); break;
+    case FWD_COPY: launch_tiles(&k_fwd_a2<T, FWD_COPY, MODEL_SVK>, ntiles, lds, L.s, L.b, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
+    case FWD_TANGENT: launch_tiles(&k_fwd_a2<T, FWD_TANGENT, LAW>, ntiles, lds, L.s, L.b, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
+    case FWD_TANGENT_UNI: launch_tiles(&k_fwd_a2<T, FWD_TANGENT_UNI, LAW>, ntiles, lds, L.s, L.b, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
+    default: launch_tiles(&k_fwd_a2<T, FWD_CG, LAW>, ntiles, lds, L.s, L.b, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
   }
 }
 
 void launch_fwd_a2(int prec, int mode, const Launch& L, const Material& mat, const void* in_T, const void* r_T,
-                   void* p_T, const void* Flin, double scale, void* spec, const CgState* cg) {
+                   void* p_T, void* x_T, const void* Flin, double scale, void* spec, const CgState* cg) {
   if (prec == PREC_F64) {
     if (mat.model == MODEL_J2)
-      fwd_a2_t<double, MODEL_J2>(mode, L, mat, in_T, r_T, p_T, Flin, scale, spec, cg);
+      fwd_a2_t<double, MODEL_J2>(mode, L, mat, in_T, r_T, p_T, x_T, Flin, scale, spec, cg);
     else
-      fwd_a2_t<double, MODEL_SVK>(mode, L, mat, in_T, r_T, p_T, Flin, scale, spec, cg);
+      fwd_a2_t<double, MODEL_SVK>(mode, L, mat, in_T, r_T, p_T, x_T, Flin, scale, spec, cg);
   } else {
-    fwd_a2_t<float, MODEL_SVK>(mode, L, mat, in_T, r_T, p_T, Flin, scale, spec, cg);  // J2 runs in FP64 only
+    fwd_a2_t<float, MODEL_SVK>(mode, L, mat, in_T, r_T, p_T, x_T, Flin, scale, spec, cg);  // J2 runs in FP64 only
   }
 }
 
 void launch_col_a1(int prec, bool inverse, const Launch& L, void* spec, const CgState* cg) {
-  const dim3 block(kThreads);
   if (prec == PREC_F64) {
-    const dim3 grid(L.nblk[K_COL1_64]);
+    const int ntiles = L.nblk[K_COL1_64];
     if (inverse)
-      hipLaunchKernelGGL((k_col_a1<double, true>), grid, block, L.lds_col1_64, L.s, L.b,
+      launch_tiles(&k_col_a1<double, true>, ntiles, L.lds_col1_64, L.s, L.b,
                          static_cast<cx<double>*>(spec), cg);
     else
-      hipLaunchKernelGGL((k_col_a1<double, false>), grid, block, L.lds_col1_64, L.s, L.b,
+      launch_tiles(&k_col_a1<double, false>, ntiles, L.lds_col1_64, L.s, L.b,
                          static_cast<cx<double>*>(spec), cg);
   } else {
-    const dim3 grid(L.nblk[K_COL1_32]);
+    const int ntiles = L.nblk[K_COL1_32];
     if (inverse)
-      hipLaunchKernelGGL((k_col_a1<float, true>), grid, block, L.lds_col1_32, L.s, L.b,
+      launch_tiles(&k_col_a1<float, true>, ntiles, L.lds_col1_32, L.s, L.b,
                          static_cast<cx<float>*>(spec), cg);
     else
-      hipLaunchKernelGGL((k_col_a1<float, false>), grid, block, L.lds_col1_32, L.s, L.b,
+      launch_tiles(&k_col_a1<float, false>, ntiles, L.lds_col1_32, L.s, L.b,
                          static_cast<cx<float>*>(spec), cg);
   }
 }
 
 void launch_col_a0_project(int prec, const Launch& L, void* spec, const CgState* cg) {
-  const dim3 block(kThreads);
   if (prec == PREC_F64)
-    hipLaunchKernelGGL((k_col_a0_project<double>), dim3(L.nblk[K_COL0_64]), block, L.lds_col0_64, L.s, L.b,
+    launch_tiles(&k_col_a0_project<double>, L.nblk[K_COL0_64], L.lds_col0_64, L.s, L.b,
                        static_cast<cx<double>*>(spec), cg);
   else
-    hipLaunchKernelGGL((k_col_a0_project<float>), dim3(L.nblk[K_COL0_32]), block, L.lds_col0_32, L.s, L.b,
+    launch_tiles(&k_col_a0_project<float>, L.nblk[K_COL0_32], L.lds_col0_32, L.s, L.b,
                        static_cast<cx<float>*>(spec), cg);
 }
 
 template <typename T, typename TO>
-static void inv_a2_t(int mode, const Launch& L, const void* spec, void* out, const void* p, void* x, double scale,
+static void inv_a2_t(int mode, const Launch& L, const void* spec, void* out, void* x, double scale,
                      const CgState* cg) {
-  const dim3 grid(L.nblk[K_ROW]), block(kThreads);
+  const int ntiles = L.nblk[K_ROW];
   const size_t lds = sizeof(T) == 8 ? L.lds_row64 : L.lds_row32;
   const cx<T>* sp = static_cast<const cx<T>*>(spec);
   TO* to = static_cast<TO*>(out);
-  const TO* tp = static_cast<const TO*>(p);
   TO* tx = static_cast<TO*>(x);
   switch (mode) {
-    case INV_OUT: hipLaunchKernelGGL((k_inv_a2<T, INV_OUT, TO>), grid, block, lds, L.s, L.b, sp, to, tp, tx, scale, cg); break;
-    case INV_PW: hipLaunchKernelGGL((k_inv_a2<T, INV_PW, TO>), grid, block, lds, L.s, L.b, sp, to, tp, tx, scale, cg); break;
-    default: hipLaunchKernelGGL((k_inv_a2<T, INV_RHS, TO>), grid, block, lds, L.s, L.b, sp, to, tp, tx, scale, cg); break;
+    case INV_OUT: launch_tiles(&k_inv_a2<T, INV_OUT, TO>, ntiles, lds, L.s, L.b, sp, to, tx, scale, cg); break;
+    case INV_CGR: launch_tiles(&k_inv_a2<T, INV_CGR, TO>, ntiles, lds, L.s, L.b, sp, to, tx, scale, cg); break;
+    default: launch_tiles(&k_inv_a2<T, INV_RHS, TO>, ntiles, lds, L.s, L.b, sp, to, tx, scale, cg); break;
   }
 }
 
-void launch_inv_a2(int prec, int mode, const Launch& L, const void* spec, void* out_T, int out_prec,
-                   const void* p_T, void* x_T, double scale, const CgState* cg) {
+void launch_inv_a2(int prec, int mode, const Launch& L, const void* spec, void* out_T, int out_prec, void* x_T,
+                   double scale, const CgState* cg) {
   if (prec == PREC_F64) {
     if (out_prec == PREC_F64)
-      inv_a2_t<double, double>(mode, L, spec, out_T, p_T, x_T, scale, cg);
+      inv_a2_t<double, double>(mode, L, spec, out_T, x_T, scale, cg);
     else
-      inv_a2_t<double, float>(mode, L, spec, out_T, p_T, x_T, scale, cg);
+      inv_a2_t<double, float>(mode, L, spec, out_T, x_T, scale, cg);
   } else {
-    inv_a2_t<float, float>(mode, L, spec, out_T, p_T, x_T, scale, cg);
+    inv_a2_t<float, float>(mode, L, spec, out_T, x_T, scale, cg);
   }
 }
 

@@ -17,6 +17,12 @@ constexpr int kMaxRve = 256;       // RVEs of one batched context
 constexpr int kRedBlocks = 2048;   // most work-groups of an element-wise kernel per RVE
 constexpr int kRegP = 8;           // points per thread of the register-resident FFT engine
 
+// LDS padding: entry e of a twiddle table or of a contiguous (unit-stride)
+// exchange line sits at e + e / 8, so that eight lanes touching entries 8
+// apart (the first Stockham stage writes j * 8 + r) hit distinct banks.
+__host__ __device__ constexpr int lpad(int e) { return e + (e >> 3); }
+__host__ __device__ constexpr int padded_len(int n) { return n + (n >> 3) + 1; }
+
 // Radix plan of one 1-D transform of length n: n = prod radix[s].
 struct AxisPlan {
   int n;
@@ -38,7 +44,8 @@ struct Grid {
   long long vox_off;
   long long spec_off;
   double inv_n;
-  int rt;           // grid lines per work-group in the a2 passes
+  int rt;           // grid lines per work-group in the a2 inverse pass
+  int rt1;          // grid lines per work-group in the a2 forward pass (rt1 * n2 <= kThreads)
   int m64, m32;     // pencils per work-group in the LDS-engine a1 / a0 passes (FP64 / FP32)
   AxisPlan ax[3];
 };
@@ -46,7 +53,8 @@ struct Grid {
 // Launch kinds: every kernel launch covers all RVEs of a context; work-group b
 // belongs to RVE r when starts[kind][r] <= b < starts[kind][r + 1].
 enum {
-  K_ROW = 0,     // a2 passes: grid lines
+  K_ROW = 0,     // a2 inverse pass: grid lines
+  K_ROW1,        // a2 forward pass: grid lines
   K_COL1_64,     // a1 pass, FP64
   K_COL1_32,     // a1 pass, FP32
   K_COL0_64,     // a0 + projection pass, FP64
@@ -100,7 +108,8 @@ struct CgState {
   int stall_limit; // 0: off; else stop when rr_min has not improved for this many iterations
   int since_min;
   int zero_rhs;    // 1: ||b|| at the round-off floor of the projected field, dF = 0
-  int pad;
+  int x_due;       // 1: x still lacks alpha p of the last iteration (applied by the next
+                   //    iteration's first pass, or by the finishing kernel)
 };
 
 // Everything a launch needs to find its RVE, tables and partial-sum slots.
@@ -121,12 +130,14 @@ enum {
   FWD_COPY = 0,        // transform the input field itself (scaled)
   FWD_TANGENT = 1,     // transform K(F) : p
   FWD_TANGENT_UNI = 2, // transform K(F) : U with the RVE's uniform tensor U (Batch::uni)
-  FWD_CG = 3           // p <- r + beta p (or r on the first iteration), then K(F) : p
+  FWD_CG = 3           // CG: x += alpha p (deferred update of the previous iteration),
+                       // p <- r + beta p (or r on the first iteration), then K(F) : p and
+                       // the partial <p, K(F) : p> (= <p, A p>, see k_cg_alpha)
 };
 // Modes of the last (a2, inverse) pass.
 enum {
   INV_OUT = 0,   // write the real field (scaled)
-  INV_PW = 1,    // write w = A p, partial <p, w>
+  INV_CGR = 1,   // CG residual: r <- r - alpha w for the transformed field w = A p, partial <r, r>
   INV_RHS = 2    // write r = scale * field (as b), zero x, partial <b, b>
 };
 
@@ -134,6 +145,7 @@ enum { PREC_F64 = 0, PREC_F32 = 1 };
 
 // ---- launch geometry (shared by host and kernels) --------------------------
 int row_blocks(const Grid& g);
+int row1_blocks(const Grid& g);
 int col1_blocks(const Grid& g, int prec);
 int col0_blocks(const Grid& g, int prec);
 int elem_blocks(long long m);
@@ -149,15 +161,14 @@ struct Launch {
   hipStream_t s;
 };
 void launch_fwd_a2(int prec, int mode, const Launch& L, const Material& mat, const void* in_T, const void* r_T,
-                   void* p_T, const void* Flin, double scale, void* spec, const CgState* cg);
+                   void* p_T, void* x_T, const void* Flin, double scale, void* spec, const CgState* cg);
 void launch_col_a1(int prec, bool inverse, const Launch& L, void* spec, const CgState* cg);
 void launch_col_a0_project(int prec, const Launch& L, void* spec, const CgState* cg);
-void launch_inv_a2(int prec, int mode, const Launch& L, const void* spec, void* out_T, int out_prec,
-                   const void* p_T, void* x_T, double scale, const CgState* cg);
+void launch_inv_a2(int prec, int mode, const Launch& L, const void* spec, void* out_T, int out_prec, void* x_T,
+                   double scale, const CgState* cg);
 
 // ---- launchers (fftnk_solver_kernels.hip) ---------------------------------
-void launch_cg_update(int prec, const Launch& L, void* x_T, void* r_T, const void* p_T, const void* w_T,
-                      CgState* cg);
+void launch_cg_finish(int prec, const Launch& L, void* x_T, const void* p_T, const CgState* cg);
 void launch_cg_alpha(const Launch& L, CgState* cg);
 void launch_cg_beta(const Launch& L, CgState* cg);
 void launch_cg_init(const Launch& L, CgState* cg, double eta, int max_cg, int stall);

@@ -20,28 +20,20 @@ enum { ST_OK = 0, ST_CG_MAXIT = 5, ST_CG_BREAKDOWN = 6, ST_NONFINITE = 8 };
 #define FOR_RVE_RANGE(i, m, local, nb) \
   for (long long i = (long long)(local) * kThreads + threadIdx.x; i < (m); i += (long long)(nb) * kThreads)
 
+// Iteration k's update x += alpha_k p_k is deferred: the first pass of
+// iteration k + 1 applies it while it reads p_k anyway.  After the last
+// iteration of a solve this kernel applies the one still due (x_due).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cg_update(Batch B, T* __restrict__ x, T* __restrict__ r,
-                                                        const T* __restrict__ p, const T* __restrict__ w,
+__global__ __launch_bounds__(kThreads) void k_cg_finish(Batch B, T* __restrict__ x, const T* __restrict__ p,
                                                         const CgState* __restrict__ cg) {
   int local;
   const int rv = find_rve(B, K_ELEM9, blockIdx.x, local);
-  if (cg[rv].done) return;
-  const Grid& g = B.grids[rv];
+  if (!cptr(cg)[rv].x_due) return;
+  const auto& g = grid_of(B, rv);
   const int nb = rve_blocks(B, K_ELEM9, rv);
   const long long m = 9 * g.n, off = 9 * g.vox_off;
-  const T alpha = (T)cg[rv].alpha;
-  double acc[1] = {0.0};
-  FOR_RVE_RANGE(i, m, local, nb) {
-    const T xi = x[off + i] + alpha * p[off + i];
-    const T ri = r[off + i] - alpha * w[off + i];
-    x[off + i] = xi;
-    r[off + i] = ri;
-    acc[0] += (double)ri * (double)ri;
-  }
-  double res[1];
-  block_sums<1>(acc, res);
-  if (threadIdx.x == 0) pslot(B, SLOT_RR)[blockIdx.x] = res[0];
+  const T alpha = (T)cptr(cg)[rv].alpha;
+  FOR_RVE_RANGE(i, m, local, nb) x[off + i] += alpha * p[off + i];
 }
 
 __device__ __forceinline__ int kstart(const Batch& B, int kind, int r) { return B.starts[kind * (B.nrve + 1) + r]; }
@@ -58,12 +50,12 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(Batch B, CgState* cg, doub
       s.iter = 0;
       s.status = ST_OK;
       s.zero_rhs = 1;
+      s.x_due = 0;
     }
     return;
   }
-  const int lo = kstart(B, K_ROW, rv), hi = kstart(B, K_ROW, rv + 1);
-  const double yy = reduce_range(pslot(B, SLOT_YY), lo, hi);
-  const double bb = reduce_range(pslot(B, SLOT_BB), lo, hi);
+  const double yy = reduce_range(pslot(B, SLOT_YY), kstart(B, K_ROW1, rv), kstart(B, K_ROW1, rv + 1));
+  const double bb = reduce_range(pslot(B, SLOT_BB), kstart(B, K_ROW, rv), kstart(B, K_ROW, rv + 1));
   if (threadIdx.x == 0) {
     s.bb = bb;
     s.rr = bb;
@@ -78,15 +70,20 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(Batch B, CgState* cg, doub
     s.stall_limit = stall;
     s.status = isfinite(bb) ? ST_OK : ST_NONFINITE;
     s.zero_rhs = (bb == 0.0 || sqrt(bb) <= 1e-14 * sqrt(yy)) ? 1 : 0;
+    s.x_due = 0;
     s.done = (s.zero_rhs || !isfinite(bb) || bb <= s.stop2) ? 1 : 0;
   }
 }
 
+// alpha = <r, r> / <p, A p>, run right after the first pass.  With A = G K and
+// G the orthogonal projection (symmetric, p in its range as every Krylov
+// direction is), <p, A p> = <G p, K p> = <p, K p>: the first pass sums it from
+// p and K p in registers, so the last pass never reads p again.
 __global__ __launch_bounds__(kThreads) void k_cg_alpha(Batch B, CgState* cg) {
   const int rv = blockIdx.x;
   CgState& s = cg[rv];
   if (s.done) return;
-  const double pw = reduce_range(pslot(B, SLOT_PW), kstart(B, K_ROW, rv), kstart(B, K_ROW, rv + 1));
+  const double pw = reduce_range(pslot(B, SLOT_PW), kstart(B, K_ROW1, rv), kstart(B, K_ROW1, rv + 1));
   if (threadIdx.x == 0) {
     s.pw = pw;
     if (!(pw > 0.0) || !isfinite(pw)) {
@@ -98,8 +95,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_alpha(Batch B, CgState* cg) {
       s.status = (s.stall_limit > 0 && s.iter > 0 && isfinite(pw)) ? ST_OK : ST_CG_BREAKDOWN;
       s.done = 1;
       s.alpha = 0.0;
+      s.x_due = 0;  // this iteration's first pass applied the previous update
     } else {
       s.alpha = s.rr / pw;
+      s.x_due = 1;
     }
   }
 }
@@ -108,7 +107,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_beta(Batch B, CgState* cg) {
   const int rv = blockIdx.x;
   CgState& s = cg[rv];
   if (s.done) return;
-  const double rr = reduce_range(pslot(B, SLOT_RR), kstart(B, K_ELEM9, rv), kstart(B, K_ELEM9, rv + 1));
+  const double rr = reduce_range(pslot(B, SLOT_RR), kstart(B, K_ROW, rv), kstart(B, K_ROW, rv + 1));
   if (threadIdx.x == 0) {
     s.iter += 1;
     if (!isfinite(rr)) {
@@ -359,14 +358,14 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_grad(Batch B, const double
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-void launch_cg_update(int prec, const Launch& L, void* x, void* r, const void* p, const void* w, CgState* cg) {
+void launch_cg_finish(int prec, const Launch& L, void* x, const void* p, const CgState* cg) {
   const dim3 grid(L.nblk[K_ELEM9]), block(kThreads);
   if (prec == PREC_F64)
-    hipLaunchKernelGGL((k_cg_update<double>), grid, block, 0, L.s, L.b, static_cast<double*>(x),
-                       static_cast<double*>(r), static_cast<const double*>(p), static_cast<const double*>(w), cg);
+    hipLaunchKernelGGL((k_cg_finish<double>), grid, block, 0, L.s, L.b, static_cast<double*>(x),
+                       static_cast<const double*>(p), cg);
   else
-    hipLaunchKernelGGL((k_cg_update<float>), grid, block, 0, L.s, L.b, static_cast<float*>(x),
-                       static_cast<float*>(r), static_cast<const float*>(p), static_cast<const float*>(w), cg);
+    hipLaunchKernelGGL((k_cg_finish<float>), grid, block, 0, L.s, L.b, static_cast<float*>(x),
+                       static_cast<const float*>(p), cg);
 }
 
 void launch_cg_alpha(const Launch& L, CgState* cg) {
