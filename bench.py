@@ -12,9 +12,13 @@ iteration (projected-tangent operator: tangent action, 3-D FFT, projection,
 inverse FFT; fused vector updates) and the Newton update.  The timed steps run
 the 5-increment schedule from the stress-free state (repeating it if --steps
 exceeds 5).  `value` is projected-tangent operator applications per second over
-the timed steps.  Besides that line's fields the JSON carries the operator
-alone (back-to-back applications), every pass's measured bandwidth, the
-FP32-mixed solve of the same increments, and the CPU oracle's rate.
+the timed steps.  Besides that line's fields the JSON carries one CG
+iteration kernel by kernel (stream events around every launch; `roofline`
+is its slowest kernel, with the hardware-counter traffic recorded for these
+kernel sources under profiles/ when it matches), the operator alone
+(back-to-back applications) pass by pass, a plain 1 GiB device copy for
+reference, the FP32-mixed solve of the same increments, and the CPU oracle's
+rate.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -47,6 +51,51 @@ def pass_bytes_per_voxel(prec_bytes, n2):
     spec = 9 * 2 * prec_bytes * h / n2
     field = 9 * prec_bytes
     return {1: 2 * field + 1 + spec, 2: 2 * spec, 3: 2 * spec, 4: 2 * spec, 5: spec + field}
+
+
+def cg_bytes_per_voxel(prec_bytes, n2):
+    """Algorithmic HBM bytes per voxel of each kernel of one CG iteration (after
+    the first): pass 1 reads r, the previous p, x and the linearisation point F
+    (and one phase byte), writes x (deferred update), p and the spectrum; passes
+    2-4 read and write the spectrum; pass 5 reads the spectrum and r, writes r;
+    alpha and beta touch only per-cell scalars and block partial sums."""
+    op = pass_bytes_per_voxel(prec_bytes, n2)
+    field = 9 * prec_bytes
+    spec = op[2] / 2
+    return {"pass1": 4 * field + 1 + 2 * field + spec, "alpha": 0.0, "pass2": op[2], "pass3": op[3],
+            "pass4": op[4], "pass5": spec + 2 * field, "beta": 0.0}
+
+
+KERNEL_NAMES = {"pass1": "k_fwd_a2<double,FWD_CG>", "pass2": "k_col_a1<double,fwd>", "pass3": "k_col_a0_project<double>",
+                "pass4": "k_col_a1<double,inv>", "pass5": "k_inv_a2<double,INV_CGR>", "alpha": "k_cg_alpha",
+                "beta": "k_cg_beta"}
+
+
+def kernel_sources_digest():
+    """sha256 over the HIP sources: hardware-counter traffic recorded for other
+    sources no longer describes these kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1603_08893_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when it was taken on other kernel sources (or is absent)."""
+    path = os.path.join(ROOT, "profiles", "traffic_c2_128.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("sources_sha256") != kernel_sources_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
 
 
 def main():
@@ -116,8 +165,27 @@ def main():
     print("# fp64 steps: %.1f ms, %d CG iterations, %d solves, wall %.2fs" % (ms_total, cg64, solves64, wall),
           file=sys.stderr, flush=True)
 
+    # ------------------------------------------------------------ the CG iteration kernel by kernel
+    # (HIP events on the library's stream around every launch, at the converged
+    # state of the last timed increment)
+    F_lin = s64.get_state()
+    n = N ** 3
+    cgk = s64.profile_cg(20)
+    cgb = cg_bytes_per_voxel(8, N)
+    cg_rows = {}
+    for k, t in cgk.items():
+        row = {"ms": round(t, 5), "bytes_per_voxel": round(cgb[k], 3)}
+        if cgb[k] > 0:
+            gbs = cgb[k] * n / (t * 1e-3) / 1e9
+            row.update({"GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        cg_rows[k] = row
+    cg_iter_ms = sum(cgk.values())
+    dom = max(cgk, key=lambda k: cgk[k])
+    achieved = cgb[dom] * n / (cgk[dom] * 1e-3) / 1e9
+    print("# CG iteration %.3f ms: %s" % (cg_iter_ms, {k: round(v, 4) for k, v in cgk.items()}), file=sys.stderr,
+          flush=True)
+
     # ------------------------------------------------------------ operator alone + per-pass timing
-    F_lin = s64.get_state()  # converged state of the last timed increment
     res = {}
 
     def operator_bench(s, reps):
@@ -149,7 +217,6 @@ def main():
             passes[k] = e0.elapsed_time(e1) / reps
         return t_mv, passes
 
-    n = N ** 3
     t_mv64, passes64 = operator_bench(s64, args.matvec_reps)
     bpv64 = pass_bytes_per_voxel(8, N)
     mv_bytes64 = sum(bpv64.values()) * n
@@ -158,10 +225,6 @@ def main():
         gbs = bpv64[k] * n / (passes64[k] * 1e-3) / 1e9
         pass_rows["pass%d" % k] = {"ms": round(passes64[k], 5), "bytes_per_voxel": round(bpv64[k], 3),
                                    "GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    dom = max(range(1, 6), key=lambda k: passes64[k])
-    dom_names = {1: "k_fwd_a2<double,FWD_TANGENT>", 2: "k_col_a1<double,fwd>", 3: "k_col_a0_project<double>",
-                 4: "k_col_a1<double,inv>", 5: "k_inv_a2<double,INV_OUT>"}
-    achieved = bpv64[dom] * n / (passes64[dom] * 1e-3) / 1e9
     print("# fp64 operator %.3f ms (%.0f GB/s over the 5-pass bytes); passes %s" %
           (t_mv64, mv_bytes64 / (t_mv64 * 1e-3) / 1e9, {k: round(v, 4) for k, v in passes64.items()}),
           file=sys.stderr, flush=True)
@@ -193,6 +256,22 @@ def main():
             "speedup_vs_fp64": round((min(args.steps, 5) / sec32) / (args.steps / sec), 3),
         }
         del s32
+
+    # ------------------------------------------------------------ reference: a plain 1 GiB device copy
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_ref = {"ms": round(e0.elapsed_time(e1), 4),
+                "GB_s": round(2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)}
+    del a, b
 
     # ------------------------------------------------------------ CPU oracle on a bounded sample
     cpu = None
@@ -238,9 +317,13 @@ def main():
                      "GB_s": round(mv_bytes64 / (t_mv64 * 1e-3) / 1e9, 1),
                      "frac_of_hbm_peak": round(mv_bytes64 / (t_mv64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "passes": pass_rows,
-        "roofline": {"bound": "hbm", "kernel": dom_names[dom], "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": recorded_traffic(KERNEL_NAMES[dom]),
+                     "algorithmic_bytes_per_launch": int(round(cgb[dom] * n)), "launch_ms": round(cgk[dom], 5)},
+        "cg_iteration": {"ms": round(cg_iter_ms, 4), "bytes_per_voxel": round(sum(cgb.values()), 2),
+                         "GB_s": round(sum(cgb.values()) * n / (cg_iter_ms * 1e-3) / 1e9, 1), "kernels": cg_rows},
+        "copy_1GiB": copy_ref,
         "fp32_mixed": fp32,
         "cpu_baseline": cpu,
     }

@@ -203,6 +203,21 @@ int fftnk_adjoint(fftnk_ctx* ctx, const double* gbar_host, double eta_cg, int ma
 int fftnk_launch_pass(fftnk_ctx* ctx, int pass);
 
 /*
+ * Instrumentation: time each kernel of a CG iteration (Sec. 2.6) at the
+ * current iterate.  The right-hand side is -G(P) of the current iterate's
+ * stress (so call it after a solve); the CG runs with tolerance 0 and no
+ * iteration cap, two whole iterations untimed, then every kernel `iters` times
+ * back to back between two stream events (the repeated launches keep the
+ * work of an iteration, not its values: the context's Krylov vectors x, r, p
+ * are clobbered, the committed state is not).  ms_host[7] (host) receives the
+ * mean time of one launch of: 0 pass 1 (p update, deferred x update, tangent
+ * action, a2 forward), 1 alpha, 2 pass 2, 3 pass 3, 4 pass 4, 5 pass 5 (a2
+ * inverse, residual update), 6 beta.  1 <= iters <= 10000.  FFTNK_ESTATE if a
+ * cell's right-hand side is zero (nothing to iterate on); synchronises.
+ */
+int fftnk_profile_cg(fftnk_ctx* ctx, int iters, double* ms_host);
+
+/*
  * Checkpoint of the J2 history (Alg. 1, "store history variables"): device
  * double [7][n] -- C_p^-1 as xx yy zz xy yz xz, then the accumulated plastic
  * strain; batched: each of the 7 planes holds all RVEs in order.  Virgin state

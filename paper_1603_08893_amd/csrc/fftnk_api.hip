@@ -827,6 +827,58 @@ int fftnk_launch_pass(fftnk_ctx* c, int pass) {
   return check_launch();
 }
 
+int fftnk_profile_cg(fftnk_ctx* c, int iters, double* ms) {
+  if (!c || !ms || iters < 1 || iters > 10000) return FFTNK_EINVAL;
+  if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
+  const Launch L = c->launch();
+  CgState* cg = c->cg();
+  rhs_pipeline(c, FWD_COPY, c->P(), nullptr, -1.0);
+  // tolerance 0, no stagnation stop, iteration cap far beyond the launches below
+  launch_cg_init(L, cg, 0.0, 1 << 30, 0);
+  int e = fetch(c, cg, c->nrve * sizeof(CgState));
+  if (e) return e;
+  for (int r = 0; r < c->nrve; ++r)
+    if (c->host_cg()[r].done) return FFTNK_ESTATE;
+  // two whole iterations: afterwards every kernel sees a previous direction
+  for (int i = 0; i < 2; ++i) cg_iteration(c, L);
+  auto kernel = [&](int k) {
+    switch (k) {
+      case 0:
+        launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->p(), c->x(), c->flin(), 1.0, c->spec(),
+                      cg);
+        break;
+      case 1: launch_cg_alpha(L, cg); break;
+      case 2: launch_col_a1(c->prec, false, L, c->spec(), cg); break;
+      case 3: launch_col_a0_project(c->prec, L, c->spec(), cg); break;
+      case 4: launch_col_a1(c->prec, true, L, c->spec(), cg); break;
+      case 5: launch_inv_a2(c->prec, INV_CGR, L, c->spec(), c->r(), c->prec, nullptr, 1.0, cg); break;
+      default: launch_cg_beta(L, cg); break;
+    }
+  };
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return FFTNK_EHIP;
+  }
+  int err = check_launch();
+  // each kernel `iters` times back to back between two events (beta last: it
+  // advances the iteration counter)
+  for (int k = 0; k < 7 && !err; ++k) {
+    (void)hipEventRecord(e0, c->stream);
+    for (int i = 0; i < iters; ++i) kernel(k);
+    (void)hipEventRecord(e1, c->stream);
+    err = check_launch();
+    float t = 0.f;
+    if (!err && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+      err = FFTNK_EHIP;
+    ms[k] = (double)t / iters;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return err;
+}
+
 int fftnk_get_history(fftnk_ctx* c, double* hist_dev) {
   if (!c || !hist_dev) return FFTNK_EINVAL;
   if (!c->ws) return FFTNK_ESTATE;

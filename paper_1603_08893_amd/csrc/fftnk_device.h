@@ -394,9 +394,16 @@ __device__ __forceinline__ void block_sums(double (&v)[K], double* out /* K resu
 __device__ __forceinline__ double* pslot(const Batch& B, int slot) { return B.partials + (long long)slot * B.pstride; }
 
 // Fixed-order sum of partials[lo, hi) by one work-group; result in every thread.
+// Eight independent accumulators per thread keep eight loads in flight.
 __device__ __forceinline__ double reduce_range(const double* part, int lo, int hi) {
-  double s[1] = {0.0};
-  for (int i = lo + threadIdx.x; i < hi; i += kThreads) s[0] += part[i];
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int i = lo + threadIdx.x;
+  for (; i + 7 * kThreads < hi; i += 8 * kThreads) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += part[i + u * kThreads];
+  }
+  for (; i < hi; i += kThreads) a[0] += part[i];
+  double s[1] = {((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]))};
   double res[1];
   block_sums<1>(s, res);
   __shared__ double bc;

@@ -24,7 +24,7 @@ EXPORTS = [
     "fftnk_create", "fftnk_create_batched", "fftnk_workspace_bytes", "fftnk_bind_workspace", "fftnk_set_phases",
     "fftnk_set_material", "fftnk_set_modulus_field", "fftnk_set_option", "fftnk_reset_state", "fftnk_solve_increment",
     "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_adjoint",
-    "fftnk_launch_pass", "fftnk_get_history", "fftnk_set_history", "fftnk_get_state",
+    "fftnk_launch_pass", "fftnk_profile_cg", "fftnk_get_history", "fftnk_set_history", "fftnk_get_state",
     "fftnk_set_state", "fftnk_status_string", "fftnk_destroy",
 ]
 
@@ -81,6 +81,7 @@ def lib():
     L.fftnk_constitutive.argtypes = [vp, vp, vp, dp]
     L.fftnk_adjoint.argtypes = [vp, dp, d, i, vp, vp, ctypes.POINTER(Stats)]
     L.fftnk_launch_pass.argtypes = [vp, i]
+    L.fftnk_profile_cg.argtypes = [vp, i, vp]
     L.fftnk_get_history.argtypes = [vp, vp]
     L.fftnk_set_history.argtypes = [vp, vp]
     L.fftnk_get_state.argtypes = [vp, vp]
@@ -247,6 +248,15 @@ class Solver:
     def launch_pass(self, k):
         """Enqueue pass k (1..5) of the operator alone (timing instrumentation)."""
         _check(lib().fftnk_launch_pass(self.ctx, int(k)), "fftnk_launch_pass")
+
+    CG_KERNELS = ("pass1", "alpha", "pass2", "pass3", "pass4", "pass5", "beta")
+
+    def profile_cg(self, iters=20):
+        """Mean ms per launch of each kernel of a CG iteration at the current iterate
+        (timing instrumentation; call after a solve, clobbers the Krylov vectors)."""
+        ms = np.zeros(7, dtype=np.float64)
+        _check(lib().fftnk_profile_cg(self.ctx, int(iters), ms.ctypes.data), "fftnk_profile_cg")
+        return dict(zip(self.CG_KERNELS, ms.tolist()))
 
     def get_history(self):
         """J2 history, [7 * ntot] device doubles (C_p^-1 xx yy zz xy yz xz, eps_p)."""
