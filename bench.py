@@ -110,9 +110,14 @@ def main():
                     help="profiling mode: only the operator passes at a synthetic linearisation point, plus one "
                          "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--extra", default="",
+                    help="comma list of sizes,c3,c4,c5: instead of the headline line, one JSON line per extra "
+                         "measurement (operator at 96^3..256^3; 64 batched cells; J2 at 96^3; adjoint 8 x 192^3)")
     args = ap.parse_args()
     if args.operator_only:
         return operator_only(args)
+    if args.extra:
+        return extra(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the per-GPU work is one periodic cell; see DESIGN.md for how it would shard).", flush=True)
@@ -374,6 +379,188 @@ def operator_only(args):
     res["copy_1GiB_ms"] = round(e0.elapsed_time(e1), 4)
     res["copy_GB_s"] = round(2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
     print(json.dumps({"operator_only": res, "precision": args.precision}), flush=True)
+
+
+def extra(args):
+    """Measurements beyond the headline: each prints one JSON line."""
+    import torch
+    from paper_1603_08893_amd import microstructure as ms
+    from paper_1603_08893_amd.fftnk import J2, Solver, homogenized_stress
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    which = [w.strip() for w in args.extra.split(",") if w.strip()]
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    def emit(d):
+        print(json.dumps(d), flush=True)
+
+    if "sizes" in which:
+        # the operator alone at several grid sizes: from 192^3 on, the FP64
+        # half spectrum (>= 515 MB) exceeds the 256 MB last-level cache
+        for n_ in (96, 192, 256):
+            phase = ms.grf_threshold(n_, ell=8.0, frac=0.3, seed=1603)
+            for prec in ("fp64", "fp32"):
+                s = Solver((n_,) * 3, precision=prec)
+                s.set_phases(phase)
+                s.set_material(TABLE)
+                fl = torch.from_numpy(ms.random_field((n_,) * 3, seed=43, scale=0.01).reshape(-1)).to(dev)
+                g = Solver((n_,) * 3, precision="fp64")
+                g.set_phases(phase)
+                g.set_material(TABLE)
+                fl = g.project(fl)
+                del g
+                fl.view(9, -1)[0::4] += 1.0
+                s.set_linearization(fl)
+                p = s.project(torch.from_numpy(ms.random_field((n_,) * 3, seed=42).reshape(-1)).to(dev))
+                out = s.field()
+                for _ in range(3):
+                    s.apply_operator(p, out)
+                reps = 20
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    s.apply_operator(p, out)
+                e1.record()
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) / reps
+                bpv = sum(pass_bytes_per_voxel(8 if prec == "fp64" else 4, n_).values())
+                gbs = bpv * n_ ** 3 / (t * 1e-3) / 1e9
+                emit({"extra": "operator", "grid": n_, "precision": prec, "ms": round(t, 4),
+                      "matvecs_per_s": round(1e3 / t, 1), "bytes_per_voxel": round(bpv, 2), "GB_s": round(gbs, 1),
+                      "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
+                del s, fl, p, out
+                torch.cuda.empty_cache()
+
+    if "c3" in which:
+        # 64 cells of four sizes, each with its own spheres, contrast and load,
+        # one increment.  In two cells (33 and 41, 64^3, contrast 16 and 13)
+        # the St. Venant-Kirchhoff tangent turns indefinite before the full
+        # load is reached (compressive loads; the model is not rank-one convex
+        # under strong compression): CG breaks down there, the oracle breaks
+        # down in the same iteration, and load steps do not help (in four
+        # steps cell 33 fails in the last one).  They are reported as failed.
+        t0 = time.perf_counter()
+        items = ms.c3_batch()
+        print("# c3 inputs %.1fs" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+        dims = [(it["N"],) * 3 for it in items]
+        ph = np.concatenate([(it["phase"].reshape(-1) + 2 * r).astype(np.uint8) for r, it in enumerate(items)])
+        table = [row for it in items for row in it["table"]]
+        nsub = 1
+        Fb = [np.array([(np.eye(3).reshape(9) + (k + 1) / nsub * (it["Fbar"] - np.eye(3).reshape(9)))
+                        for it in items]) for k in range(nsub)]
+        res = {"extra": "c3_batched", "cells": len(items), "increments": nsub,
+               "voxels": int(sum(np.prod(d) for d in dims)),
+               "volume_fractions": [round(it["frac"], 4) for it in items]}
+
+        def run(s):
+            s.reset_state()
+            out = []
+            for k in range(nsub):
+                out.append(s.solve_increment(Fb[k], fields=False, raise_on_error=False))
+            return out
+
+        pbars = {}
+        for prec in ("fp64", "fp32"):
+            s = Solver(dims, precision=prec)
+            s.set_phases(ph)
+            s.set_material(table)
+            run(s)  # warm-up: graphs, caches
+            outs, sec = timed(lambda: run(s))
+            stats = [x for o in outs for x in o[4]]
+            pbars[prec] = outs[-1][3]
+            res[prec] = {"seconds": round(sec, 4), "cell_increments_per_s": round(nsub * len(items) / sec, 2),
+                         "failed_cells": [r for r in range(len(items)) if any(o[4][r]["status"] for o in outs)],
+                         "newton_solves": int(sum(x["n_solves"] for x in stats)),
+                         "cg_iterations": int(sum(sum(x["cg_iters"]) for x in stats)),
+                         "max_cg_per_solve": int(max(max(x["cg_iters"]) for x in stats))}
+            print("# c3 %s %.2fs" % (prec, sec), file=sys.stderr, flush=True)
+            del s
+            torch.cuda.empty_cache()
+        ok = [r for r in range(len(items)) if r not in res["fp64"]["failed_cells"] + res["fp32"]["failed_cells"]]
+        res["fp32_pbar_rel_diff_vs_fp64"] = float(max(np.max(np.abs(pbars["fp32"][r] - pbars["fp64"][r])) /
+                                                  np.max(np.abs(pbars["fp64"][r])) for r in ok))
+
+        # the plain FP64 path: the same cells one after another, one context per size
+        def one_by_one():
+            for n_ in sorted(set(it["N"] for it in items)):
+                s = Solver((n_,) * 3, precision="fp64")
+                for r, it in enumerate(items):
+                    if it["N"] != n_:
+                        continue
+                    s.set_phases(it["phase"])
+                    s.set_material(it["table"])
+                    s.reset_state()
+                    for k in range(nsub):
+                        s.solve_increment(Fb[k][r], fields=False, raise_on_error=False)
+                del s
+        one_by_one()  # warm-up
+        _, sec1 = timed(one_by_one)
+        res["fp64_one_by_one"] = {"seconds": round(sec1, 4), "cell_increments_per_s": round(nsub * len(items) / sec1, 2)}
+        res["speedup_batched_fp32_vs_one_by_one_fp64"] = round(sec1 / res["fp32"]["seconds"], 3)
+        res["speedup_batched_fp64_vs_one_by_one_fp64"] = round(sec1 / res["fp64"]["seconds"], 3)
+        emit(res)
+        torch.cuda.empty_cache()
+
+    if "c4" in which:
+        # finite-strain J2 at 96^3: spheres at 25 %, simple shear to 0.1 in 20 increments
+        ph, frac = ms.rsa_spheres(96, 0.25, seed=1604)
+        s = Solver((96,) * 3, precision="fp64")
+        s.set_phases(ph)
+        s.set_material([(ms.K_SOFT, ms.MU_SOFT, 0.003, 0.01), (ms.K_SOFT, ms.MU_SOFT, 0.006, 0.01)], model=J2)
+        sched = ms.c4_schedule(20, 0.1)
+        s.solve_increment(sched[0], fields=False)  # warm-up
+        s.reset_state()
+        solves, cgs, status, done = [], [], 0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for Fbar in sched:
+            st, _, _, Pb, stats = s.solve_increment(Fbar, fields=False, raise_on_error=False)
+            if st:
+                status = st
+                break
+            done += 1
+            solves.append(stats[0]["n_solves"])
+            cgs.append(int(sum(stats[0]["cg_iters"])))
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        eps_p = s.get_history().view(7, -1)[6]
+        emit({"extra": "c4_j2", "grid": 96, "sphere_fraction": round(frac, 4), "increments_done": done,
+              "status": int(status), "seconds": round(sec, 3), "increments_per_s": round(done / sec, 3),
+              "newton_solves_per_increment": solves, "cg_iterations_per_increment": cgs,
+              "pbar_last": [float(v) for v in Pb[0]], "plastic_voxel_fraction": float((eps_p > 0).float().mean()),
+              "max_eps_p": float(eps_p.max())})
+        del s
+        torch.cuda.empty_cache()
+
+    if "c5" in which:
+        # adjoint: 8 load cases on 192^3 with a log-normal shear-modulus field
+        n_ = 192
+        mu = torch.from_numpy(ms.lognormal_field(n_, 0.5, 8.0, seed=1605)).to(dev)
+        mu_t = torch.from_numpy(ms.lognormal_field(n_, 0.5, 8.0, seed=1606)).to(dev)
+        cases = np.array(ms.c5_load_cases(0.05))
+        s = Solver([(n_,) * 3] * len(cases), precision="fp64")
+        s.set_phases(np.zeros(len(cases) * n_ ** 3, dtype=np.uint8))
+        s.set_material([(ms.K_SOFT, ms.MU_SOFT)])
+        with torch.no_grad():
+            target, sec_t = timed(lambda: homogenized_stress(mu_t, s, cases))
+        m = mu.clone().requires_grad_(True)
+        Pb, sec_f = timed(lambda: homogenized_stress(m, s, cases))
+        loss = ((Pb - target) ** 2).sum()
+        _, sec_b = timed(lambda: loss.backward())
+        emit({"extra": "c5_adjoint", "grid": n_, "load_cases": len(cases),
+              "forward_seconds": round(sec_f, 3), "backward_seconds": round(sec_b, 3),
+              "target_forward_seconds": round(sec_t, 3),
+              "forward_cell_solves_per_s": round(len(cases) / sec_f, 3),
+              "backward_over_forward": round(sec_b / sec_f, 3), "loss": float(loss.detach()),
+              "grad_norm": float(m.grad.norm()), "grad_abs_max": float(m.grad.abs().max())})
 
 
 if __name__ == "__main__":

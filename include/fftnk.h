@@ -105,9 +105,9 @@ int fftnk_set_phases(fftnk_ctx* ctx, const uint8_t* phase_dev);
  * tau = C : ln(be)/2, von Mises yield with linear hardening
  * tau_y = tau_y0 + H eps_p, exponential-map return mapping, P = tau F^-T).
  * params_host holds, per phase, {K, mu} for SVK and {K, mu, tau_y0, H} for
- * J2.  nphase <= 16.  J2 needs an FFTNK_FP64 context (else
- * FFTNK_EUNSUPPORTED); a point whose return mapping fails (det F <= 0)
- * makes the increment fail with FFTNK_ENONFINITE.
+ * J2.  nphase <= 256 (a batch may give every cell its own phases).  J2 needs
+ * an FFTNK_FP64 context (else FFTNK_EUNSUPPORTED); a point whose return
+ * mapping fails (det F <= 0) makes the increment fail with FFTNK_ENONFINITE.
  */
 int fftnk_set_material(fftnk_ctx* ctx, int model, int nphase, const double* params_host);
 

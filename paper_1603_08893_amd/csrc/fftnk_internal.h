@@ -11,7 +11,7 @@ namespace fftnk {
 
 constexpr int kThreads = 256;      // work-group size of every kernel
 constexpr int kMaxStages = 12;     // radix stages of one 1-D transform
-constexpr int kMaxPhase = 16;      // material phases
+constexpr int kMaxPhase = 256;     // material phases (every value of the one-byte phase index)
 constexpr int kMaxLen = 256;       // longest supported grid axis
 constexpr int kMaxRve = 256;       // RVEs of one batched context
 constexpr int kRedBlocks = 2048;   // most work-groups of an element-wise kernel per RVE
@@ -100,12 +100,12 @@ struct CgState {
   double bb;       // <b, b>
   double stop2;    // (eta ||b||)^2
   double alpha, beta, pw;
-  double rr_min;
+  double rr_min;   // last recorded minimum of <r, r> (stagnation guard)
   int iter;
   int done;        // 1 once converged or failed: every CG kernel of this RVE is a no-op
   int status;      // 0 running/ok, else an FFTNK_E* code
   int max_cg;
-  int stall_limit; // 0: off; else stop when rr_min has not improved for this many iterations
+  int stall_limit; // 0: off; else stop when <r, r> has not dropped below 0.75 rr_min for this many iterations
   int since_min;
   int zero_rhs;    // 1: ||b|| at the round-off floor of the projected field, dF = 0
   int x_due;       // 1: x still lacks alpha p of the last iteration (applied by the next

@@ -56,11 +56,18 @@ def grf_threshold(N=128, ell=8.0, frac=0.3, seed=1603):
 
 
 def rsa_spheres(N, target_frac, seed, rmin=3, rmax=10, max_attempts=100000):
-    """Returns (phase map, achieved volume fraction)."""
+    """Random sequential addition of periodic spheres.  Returns (phase map,
+    achieved volume fraction).
+
+    Each attempt draws a radius U{rmin..rmax} and a centre U[0, N)^3, and is
+    rejected if the periodic centre distance to any placed sphere is below the
+    sum of the radii; a voxel (centre at index + 1/2) is inside a sphere if
+    its periodic distance to the centre is at most the radius.  Stops at the
+    target fraction or after max_attempts."""
     rng = np.random.default_rng(seed)
-    centres, radii = [], []
+    centres = np.zeros((0, 3))
+    radii = np.zeros(0)
     ph = np.zeros((N, N, N), dtype=np.uint8)
-    idx = np.arange(N, dtype=np.float64) + 0.5
     filled = 0
     target = target_frac * N ** 3
     for _ in range(max_attempts):
@@ -68,21 +75,29 @@ def rsa_spheres(N, target_frac, seed, rmin=3, rmax=10, max_attempts=100000):
             break
         r = int(rng.integers(rmin, rmax + 1))
         c = rng.uniform(0.0, N, size=3)
-        ok = True
-        for c2, r2 in zip(centres, radii):
-            d = np.abs(c - c2)
+        if len(radii):
+            d = np.abs(centres - c)
             d = np.minimum(d, N - d)
-            if np.sqrt((d ** 2).sum()) < r + r2:
-                ok = False
-                break
-        if not ok:
-            continue
-        centres.append(c)
-        radii.append(r)
-        d = [np.minimum(np.abs(idx - c[a]), N - np.abs(idx - c[a])) for a in range(3)]
-        inside = (d[0][:, None, None] ** 2 + d[1][None, :, None] ** 2 + d[2][None, None, :] ** 2) <= r * r
-        ph[inside] = 1
-        filled = int(ph.sum())
+            if np.any(np.sqrt((d ** 2).sum(axis=1)) < r + radii):
+                continue
+        centres = np.vstack([centres, c])
+        radii = np.append(radii, r)
+        # voxels within the sphere's periodic bounding box (the whole axis if
+        # the box would wrap onto itself)
+        axes = []
+        for a in range(3):
+            if 2 * r + 3 >= N:
+                ix = np.arange(N)
+            else:
+                ix = np.arange(int(np.floor(c[a] - r - 1)), int(np.ceil(c[a] + r + 1)) + 1) % N
+            x = ix + 0.5
+            axes.append((ix, np.minimum(np.abs(x - c[a]), N - np.abs(x - c[a]))))
+        (i0, d0), (i1, d1), (i2, d2) = axes
+        inside = (d0[:, None, None] ** 2 + d1[None, :, None] ** 2 + d2[None, None, :] ** 2) <= r * r
+        box = ph[np.ix_(i0, i1, i2)]
+        filled += int(np.count_nonzero(inside & (box == 0)))
+        box[inside] = 1
+        ph[np.ix_(i0, i1, i2)] = box
     return ph, float(ph.mean())
 
 
