@@ -74,10 +74,13 @@ int pick_m(int h, int nmax, size_t csz, int pref) {
   return m;
 }
 
-size_t row_lds(const Grid& g, size_t csz) {
+// a2 passes: twiddles + pencil buffers for `rt` lines (5 pencils each): one
+// padded slot per pencil plus one spare slot shared by the idle pencil slots
+// (register engine), or two ping-pong buffers (LDS engine)
+size_t row_lds(const Grid& g, int rt, size_t csz) {
   const size_t tw = padded_len(g.n2);
-  if (g.ax[2].reg) return csz * (tw + (size_t)(kThreads / (g.n2 / kRegP)) * padded_len(g.n2));
-  return csz * (tw + 2 * 5 * (size_t)g.rt * g.n2);
+  if (g.ax[2].reg) return csz * (tw + (5 * (size_t)rt + 1) * padded_len(g.n2));
+  return csz * (tw + 2 * 5 * (size_t)rt * g.n2);
 }
 size_t col_lds(const Grid& g, int axis, size_t csz) {
   const int n = axis == 0 ? g.n0 : g.n1;
@@ -99,7 +102,7 @@ struct fftnk_ctx {
   int tw_total = 0;
   std::vector<int> starts;  // [NKIND][nrve + 1]
   int nblk[NKIND] = {};
-  size_t lds[6] = {};
+  size_t lds[8] = {};  // row64, row32, col1_64, col1_32, col0_64, col0_32, row1_64, row1_32
   // workspace layout (byte offsets)
   size_t o_hist, o_hnew;  // J2 history: committed and of the current iterate, [7][ntot] each
   size_t o_Ft, o_F, o_P, o_x, o_r, o_p, o_w, o_F32, o_d64, o_spec, o_phase, o_mu, o_mtab, o_part, o_cg, o_red,
@@ -154,6 +157,8 @@ struct fftnk_ctx {
     L.lds_col1_32 = lds[3];
     L.lds_col0_64 = lds[4];
     L.lds_col0_32 = lds[5];
+    L.lds_row1_64 = lds[6];
+    L.lds_row1_32 = lds[7];
     L.s = s;
     return L;
   }
@@ -266,8 +271,10 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
     c->pstride = std::max(c->pstride, acc);
   }
   for (const Grid& g : c->g) {
-    c->lds[0] = std::max(c->lds[0], row_lds(g, 16));
-    c->lds[1] = std::max(c->lds[1], row_lds(g, 8));
+    c->lds[0] = std::max(c->lds[0], row_lds(g, g.rt, 16));
+    c->lds[1] = std::max(c->lds[1], row_lds(g, g.rt, 8));
+    c->lds[6] = std::max(c->lds[6], row_lds(g, g.rt1, 16));
+    c->lds[7] = std::max(c->lds[7], row_lds(g, g.rt1, 8));
     c->lds[2] = std::max(c->lds[2], col_lds(g, 1, 16));
     c->lds[3] = std::max(c->lds[3], col_lds(g, 1, 8));
     c->lds[4] = std::max(c->lds[4], col_lds(g, 0, 16));

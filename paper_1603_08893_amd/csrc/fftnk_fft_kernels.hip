@@ -92,7 +92,7 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
   double acc[1] = {0.0};
   // register engine: pencil slot m = pair * RT + line (slots >= 5 RT idle),
   // stage the field in LDS once, transform in registers, unpack through one
-  // mirror exchange.  bufA holds one slot of N2 entries per kThreads / Tp.
+  // mirror exchange.  bufA holds one slot of padded_len(N2) entries per pencil.
   const bool reg = g.ax[2].reg;
   const int SL = reg ? padded_len(N2) : N2;  // LDS slot of one line
   if ((int)threadIdx.x < RT * N2) {  // rt1 * n2 <= kThreads: at most one voxel per thread
@@ -174,7 +174,9 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
   if (reg) {
     const int Tp = N2 / kRegP;
     const int m = threadIdx.x / Tp, t = threadIdx.x - m * Tp;
-    cx<T>* xl = bufA + m * SL;
+    // idle pencil slots (m >= 5 rt1) all work in one spare slot after the
+    // used ones: their values are never read back into anything stored
+    cx<T>* xl = bufA + min(m, npen) * SL;
     cx<T> v[kRegP];
 #pragma unroll
     for (int q = 0; q < kRegP; ++q) v[q] = xl[lpad(t + Tp * q)];
@@ -555,7 +557,7 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
       const T xi = -xm.y, yi = -yon * ym.y;  // conjugated
       v[q] = valid ? cx<T>{xm.x - yi, xi + yon * ym.x} : cx<T>{(T)0, (T)0};
     }
-    reg_fft<T, true>(v, N2, t, tw, true, bufA + m * padded_len(N2));
+    reg_fft<T, true>(v, N2, t, tw, true, bufA + min(m, npen) * padded_len(N2));  // idle slots share a spare one
     double acc[1] = {0.0};
     if (valid) {
       const long long n = g.n;
@@ -695,7 +697,7 @@ template <typename T, int LAW>
 static void fwd_a2_t(int mode, const Launch& L, const Material& mat, const void* in, const void* r, void* p,
                      void* x, const void* Flin, double scale, void* spec, const CgState* cg) {
   const int ntiles = L.nblk[K_ROW1];
-  const size_t lds = sizeof(T) == 8 ? L.lds_row64 : L.lds_row32;
+  const size_t lds = sizeof(T) == 8 ? L.lds_row1_64 : L.lds_row1_32;
   const T* ti = static_cast<const T*>(in);
   const T* tr = static_cast<const T*>(r);
   T* tp = static_cast<T*>(p);

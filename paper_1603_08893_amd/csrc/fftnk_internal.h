@@ -157,7 +157,7 @@ int elem_blocks(long long m);
 struct Launch {
   Batch b;
   int nblk[NKIND];
-  size_t lds_row64, lds_row32, lds_col1_64, lds_col1_32, lds_col0_64, lds_col0_32;
+  size_t lds_row64, lds_row32, lds_col1_64, lds_col1_32, lds_col0_64, lds_col0_32, lds_row1_64, lds_row1_32;
   hipStream_t s;
 };
 void launch_fwd_a2(int prec, int mode, const Launch& L, const Material& mat, const void* in_T, const void* r_T,
