@@ -30,7 +30,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Radix plan: the power-of-two part in as few stages of 8 / 4 / 2 as possible
 // (bits spread evenly), then 3, 5, 7 and any remaining prime (direct sum).
-bool make_plan(int n, AxisPlan& pl) {
+bool make_plan(int n, AxisPlan& pl, bool allow12) {
   pl.n = n;
   pl.nstages = 0;
   int m = n, e2 = 0;
@@ -54,7 +54,12 @@ bool make_plan(int n, AxisPlan& pl) {
       m /= p;
     }
   }
-  pl.reg = (m == 1 && e2 >= 3 && (1 << e2) == n) ? 1 : 0;
+  if ((1 << e2) == n && e2 >= 3)
+    pl.reg = 8;
+  else if (allow12 && n == 3 * (1 << e2) && e2 >= 2 && n <= 192)
+    pl.reg = 12;
+  else
+    pl.reg = 0;
   return true;
 }
 
@@ -66,10 +71,10 @@ int largest_pow2_leq(int x) {
 
 // pencils per work-group in the LDS-engine a1 / a0 passes: contiguous rows of
 // at least 128 bytes where possible, within the LDS (60 KiB) and register
-// (8 points per thread in pass 3) budgets.
+// (kMaxPpt points per thread in pass 3) budgets.
 int pick_m(int h, int nmax, size_t csz, int pref) {
   int m = std::min(pref, largest_pow2_leq(std::max(1, h)));
-  while (m > 1 && ((size_t)nmax * m > (size_t)8 * kThreads || csz * ((size_t)padded_len(nmax) + 2 * (size_t)nmax * m) > 61440))
+  while (m > 1 && ((size_t)nmax * m > (size_t)kMaxPpt * kThreads || csz * ((size_t)padded_len(nmax) + 2 * (size_t)nmax * m) > 61440))
     m /= 2;
   return m;
 }
@@ -77,14 +82,14 @@ int pick_m(int h, int nmax, size_t csz, int pref) {
 // a2 passes: twiddles + pencil buffers for `rt` lines (5 pencils each): one
 // padded slot per pencil plus one spare slot shared by the idle pencil slots
 // (register engine), or two ping-pong buffers (LDS engine)
-size_t row_lds(const Grid& g, int rt, size_t csz) {
+size_t row_lds(const Grid& g, int rt, int engine, size_t csz) {
   const size_t tw = padded_len(g.n2);
-  if (g.ax[2].reg) return csz * (tw + (5 * (size_t)rt + 1) * padded_len(g.n2));
+  if (engine) return csz * (tw + (5 * (size_t)rt + 1) * padded_len(g.n2));
   return csz * (tw + 2 * 5 * (size_t)rt * g.n2);
 }
 size_t col_lds(const Grid& g, int axis, size_t csz) {
   const int n = axis == 0 ? g.n0 : g.n1;
-  if (g.ax[axis].reg) return csz * ((size_t)padded_len(n) + (size_t)kThreads * kRegP);
+  if (g.ax[axis].reg) return csz * ((size_t)padded_len(n) + (size_t)kThreads * g.ax[axis].reg);
   const int M = csz == 16 ? g.m64 : g.m32;
   return csz * ((size_t)padded_len(n) + 2 * (size_t)n * M);
 }
@@ -103,6 +108,7 @@ struct fftnk_ctx {
   std::vector<int> starts;  // [NKIND][nrve + 1]
   int nblk[NKIND] = {};
   size_t lds[8] = {};  // row64, row32, col1_64, col1_32, col0_64, col0_32, row1_64, row1_32
+  int eng[3] = {};     // per axis: bit 0 some cell on the LDS engine, bit 1 on the 8-point, bit 2 on the 12-point one
   // workspace layout (byte offsets)
   size_t o_hist, o_hnew;  // J2 history: committed and of the current iterate, [7][ntot] each
   size_t o_Ft, o_F, o_P, o_x, o_r, o_p, o_w, o_F32, o_d64, o_spec, o_phase, o_mu, o_mtab, o_part, o_cg, o_red,
@@ -159,6 +165,7 @@ struct fftnk_ctx {
     L.lds_col0_32 = lds[5];
     L.lds_row1_64 = lds[6];
     L.lds_row1_32 = lds[7];
+    for (int d = 0; d < 3; ++d) L.eng[d] = eng[d];
     L.s = s;
     return L;
   }
@@ -222,7 +229,7 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
     for (int d = 0; d < 3; ++d) {
       const int nd = dims[3 * r + d];
       if (nd < 2 || nd > kMaxLen) return nd > kMaxLen ? FFTNK_EUNSUPPORTED : FFTNK_EINVAL;
-      if (!make_plan(nd, g.ax[d])) return FFTNK_EUNSUPPORTED;
+      if (!make_plan(nd, g.ax[d], d > 0)) return FFTNK_EUNSUPPORTED;  // pass 3 (a0) has no 12-point engine
     }
     g.h = (g.n2 % 2 == 0) ? g.n2 / 2 : (g.n2 + 1) / 2;
     g.n = (long long)g.n0 * g.n1 * g.n2;
@@ -231,11 +238,19 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
     g.spec_off = spec;
     g.inv_n = 1.0 / (double)g.n;
     // grid lines per a2 work-group: register engine, 5 pair pencils per line on
-    // kThreads / (n2/8) pencil slots; LDS engine, kThreads / n2 lines
-    g.rt = g.ax[2].reg ? (kThreads / (g.n2 / kRegP)) / 5 : std::max(1, kThreads / g.n2);
+    // kThreads / (n2/P) pencil slots, within 48 KiB of FP64 LDS (5 rt pencils +
+    // one spare slot: three work-groups per CU at least); LDS engine, kThreads / n2
+    if (g.ax[2].reg) {
+      const int slots = kThreads / (g.n2 / g.ax[2].reg);
+      const int fit = (49152 / 16 - padded_len(g.n2)) / padded_len(g.n2) - 1;
+      g.rt = std::max(1, std::min(slots / 5, fit / 5));
+    } else {
+      g.rt = std::max(1, kThreads / g.n2);
+    }
     // forward pass: at most one voxel per thread in its tangent phase, so that
-    // all loads of a work-group are in flight together
-    g.rt1 = std::max(1, std::min(g.rt, kThreads / g.n2));
+    // all loads of a work-group are in flight together (and the register-engine
+    // line count, or kThreads / n2 on the LDS engine)
+    g.rt1 = pass1_engine(g.ax[2].reg) ? std::max(1, std::min(g.rt, kThreads / g.n2)) : std::max(1, kThreads / g.n2);
     const int nmax = std::max(g.n0, g.n1);
     g.m64 = pick_m(g.h, nmax, 16, 8);
     g.m32 = pick_m(g.h, nmax, 8, 16);
@@ -271,10 +286,11 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
     c->pstride = std::max(c->pstride, acc);
   }
   for (const Grid& g : c->g) {
-    c->lds[0] = std::max(c->lds[0], row_lds(g, g.rt, 16));
-    c->lds[1] = std::max(c->lds[1], row_lds(g, g.rt, 8));
-    c->lds[6] = std::max(c->lds[6], row_lds(g, g.rt1, 16));
-    c->lds[7] = std::max(c->lds[7], row_lds(g, g.rt1, 8));
+    c->lds[0] = std::max(c->lds[0], row_lds(g, g.rt, g.ax[2].reg, 16));
+    c->lds[1] = std::max(c->lds[1], row_lds(g, g.rt, g.ax[2].reg, 8));
+    for (int d = 0; d < 3; ++d) c->eng[d] |= g.ax[d].reg == 8 ? 2 : (g.ax[d].reg == 12 ? 4 : 1);
+    c->lds[6] = std::max(c->lds[6], row_lds(g, g.rt1, pass1_engine(g.ax[2].reg), 16));
+    c->lds[7] = std::max(c->lds[7], row_lds(g, g.rt1, pass1_engine(g.ax[2].reg), 8));
     c->lds[2] = std::max(c->lds[2], col_lds(g, 1, 16));
     c->lds[3] = std::max(c->lds[3], col_lds(g, 1, 8));
     c->lds[4] = std::max(c->lds[4], col_lds(g, 0, 16));

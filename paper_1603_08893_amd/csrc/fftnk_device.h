@@ -139,6 +139,53 @@ struct SmallDft<T, 8> {
   }
 };
 
+// 3-point DFT in place: X1,2 = a0 - (a1 + a2)/2 -+ (sqrt(3)/2) i (a1 - a2)
+// (signs for the forward transform; the inverse conjugates W_3).
+template <typename T>
+__device__ __forceinline__ void dft3(cx<T>& a0, cx<T>& a1, cx<T>& a2, bool inv) {
+  const T s = (T)0.86602540378443864676;  // sqrt(3) / 2
+  const cx<T> t1 = a1 + a2;
+  const cx<T> t2 = a0 - cscale(t1, (T)0.5);
+  const cx<T> t3 = cscale(rot(a1 - a2, inv), s);
+  a0 = a0 + t1;
+  a1 = t2 + t3;
+  a2 = t2 - t3;
+}
+
+// 12-point DFT as 3 x 4: with r = r1 + 3 r2 and q = 4 q1 + q2,
+// X[q] = sum_r1 W_3^{r1 q1} (W_12^{r1 q2} B_r1[q2]), B_r1 the 4-point DFT of
+// a[r1 + 3 r2] over r2; outputs in natural order.
+template <typename T>
+struct SmallDft<T, 12> {
+  __device__ __forceinline__ static void run(cx<T>* v, const cx<T>*, int, bool inv) {
+    const T c = (T)0.86602540378443864676, h = (T)0.5;  // cos 30 deg, sin 30 deg
+    const T sg = inv ? (T)1 : (T)-1;                    // sign of the imaginary parts of W_12^k
+    cx<T> b[3][4];
+#pragma unroll
+    for (int r1 = 0; r1 < 3; ++r1) {
+      b[r1][0] = v[r1];
+      b[r1][1] = v[r1 + 3];
+      b[r1][2] = v[r1 + 6];
+      b[r1][3] = v[r1 + 9];
+      dft4(b[r1][0], b[r1][1], b[r1][2], b[r1][3], inv);
+    }
+    // W_12^1, W_12^2, W_12^3 on r1 = 1; W_12^2, W_12^4, W_12^6 on r1 = 2
+    b[1][1] = cmul(b[1][1], cx<T>{c, sg * h});
+    b[1][2] = cmul(b[1][2], cx<T>{h, sg * c});
+    b[1][3] = rot(b[1][3], inv);
+    b[2][1] = cmul(b[2][1], cx<T>{h, sg * c});
+    b[2][2] = cmul(b[2][2], cx<T>{-h, sg * c});
+    b[2][3] = cx<T>{-b[2][3].x, -b[2][3].y};
+#pragma unroll
+    for (int q2 = 0; q2 < 4; ++q2) {
+      dft3(b[0][q2], b[1][q2], b[2][q2], inv);
+      v[q2] = b[0][q2];
+      v[4 + q2] = b[1][q2];
+      v[8 + q2] = b[2][q2];
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // LDS engine (any length): Stockham autosort stages on `npen` pencils of
 // length n held in LDS, element e of pencil m at m*sp + e*se.  Ns is the
@@ -239,13 +286,14 @@ __device__ __forceinline__ cx<T>* fft_lds(cx<T>* a, cx<T>* b, const PL& pl, int 
 }
 
 // ---------------------------------------------------------------------------
-// Register-resident engine (power-of-two lengths 8 <= n <= kMaxLen, radices
-// 8 / 4 / 2, specialised at compile time for every length so that all index
-// arithmetic is shifts and constants).
-// A pencil is split over Tp = n / kRegP threads; thread t holds
-// v[q] = x[t + Tp q], q < kRegP, for the whole transform.  In every Stockham
-// stage the butterflies of thread t are j = t + k Tp (k < kRegP / R) and their
-// inputs are exactly its own registers v[k + r kRegP/R]; only the outputs move,
+// Register-resident engine, specialised at compile time for every length so
+// that all index arithmetic is shifts and constants: P = 8 points per thread
+// for powers of two 8 <= n <= kMaxLen (radices 8 / 4 / 2), P = 12 for
+// n = 3 2^k, 12 <= n <= 192 (a radix-12 stage, then radices 4 / 2).
+// A pencil is split over Tp = n / P threads; thread t holds
+// v[q] = x[t + Tp q], q < P, for the whole transform.  In every Stockham
+// stage the butterflies of thread t are j = t + k Tp (k < P / R) and their
+// inputs are exactly its own registers v[k + r P/R]; only the outputs move,
 // through one LDS exchange per stage, and the outputs of the last stage land in
 // natural order on the same register slots, so loads from and stores to global
 // memory need no LDS.  Exchange layouts: ROW == false, pencils interleaved
@@ -257,32 +305,49 @@ __device__ __forceinline__ cx<T>* fft_lds(cx<T>* a, cx<T>* b, const PL& pl, int 
 // contains barriers).
 // ---------------------------------------------------------------------------
 constexpr int ct_log2(int n) { return n <= 1 ? 0 : 1 + ct_log2(n >> 1); }
-constexpr int ct_nstages(int n) { return (ct_log2(n) + 2) / 3; }
-constexpr int ct_radix(int n, int s) {
-  return 1 << (ct_log2(n) / ct_nstages(n) + (s < ct_log2(n) % ct_nstages(n) ? 1 : 0));
+// Radix plan of the register engine.  P = 8 (n = 2^k, 8 <= n <= 256): log2 n
+// split into ceil(log2 n / 3) near-equal power-of-two stages, larger first.
+// P = 12 (n = 3 2^k, 12 <= n <= 192): one radix-12 stage, then radix 4 stages
+// (and one radix 2 for an odd power).  Every radix divides P.
+template <int P>
+constexpr int ct_nstages(int n) {
+  if constexpr (P == 8)
+    return (ct_log2(n) + 2) / 3;
+  else
+    return 1 + (ct_log2(n / 12) + 1) / 2;
 }
-constexpr int ct_span(int n, int s) { return s == 0 ? 1 : ct_span(n, s - 1) * ct_radix(n, s - 1); }
+template <int P>
+constexpr int ct_radix(int n, int s) {
+  if constexpr (P == 8) {
+    return 1 << (ct_log2(n) / ct_nstages<8>(n) + (s < ct_log2(n) % ct_nstages<8>(n) ? 1 : 0));
+  } else {
+    return s == 0 ? 12 : ((s < 1 + ct_log2(n / 12) / 2) ? 4 : 2);
+  }
+}
+template <int P>
+constexpr int ct_span(int n, int s) { return s == 0 ? 1 : ct_span<P>(n, s - 1) * ct_radix<P>(n, s - 1); }
 
-template <int N, bool ROW>
+template <int N, int P, bool ROW>
 __device__ __forceinline__ int xslot(int e) {
   if constexpr (ROW)
     return lpad(e);
   else
-    return e * (kThreads * kRegP / N);
+    return e * (kThreads * P / N);
 }
 
-template <typename T, int N, bool ROW, int S>
-__device__ __forceinline__ void reg_stages(cx<T> (&v)[kRegP], int t, const cx<T>* tw, bool inv, cx<T>* xl) {
-  if constexpr (S < ct_nstages(N)) {
-    constexpr int R = ct_radix(N, S), NS = ct_span(N, S), Tp = N / kRegP, B = kRegP / R, TWS = N / (NS * R);
-    constexpr bool LAST = S + 1 == ct_nstages(N);
+template <typename T, int N, int P, bool ROW, int S>
+__device__ __forceinline__ void reg_stages(cx<T> (&v)[P], int t, const cx<T>* tw, bool inv, cx<T>* xl) {
+  if constexpr (S < ct_nstages<P>(N)) {
+    constexpr int R = ct_radix<P>(N, S), NS = ct_span<P>(N, S), Tp = N / P, B = P / R, TWS = N / (NS * R);
+    static_assert(P % R == 0, "every radix divides the points per thread");
+    constexpr bool LAST = S + 1 == ct_nstages<P>(N);
 #pragma unroll
     for (int k = 0; k < B; ++k) {
       cx<T> a[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) a[r] = v[k + r * B];
       const int j = t + k * Tp;
-      const int kk = j & (NS - 1);
+      const int kk = (NS & (NS - 1)) == 0 ? (j & (NS - 1)) : (j % NS);
       if constexpr (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) a[r] = cmul(a[r], twid(tw, kk * (r * TWS), inv));
@@ -294,30 +359,42 @@ __device__ __forceinline__ void reg_stages(cx<T> (&v)[kRegP], int t, const cx<T>
       } else {
         const int base = (j - kk) * R + kk;
 #pragma unroll
-        for (int r = 0; r < R; ++r) xl[xslot<N, ROW>(base + r * NS)] = a[r];
+        for (int r = 0; r < R; ++r) xl[xslot<N, P, ROW>(base + r * NS)] = a[r];
       }
     }
     if constexpr (!LAST) {
       __syncthreads();
 #pragma unroll
-      for (int q = 0; q < kRegP; ++q) v[q] = xl[xslot<N, ROW>(t + Tp * q)];
+      for (int q = 0; q < P; ++q) v[q] = xl[xslot<N, P, ROW>(t + Tp * q)];
       __syncthreads();
-      reg_stages<T, N, ROW, S + 1>(v, t, tw, inv, xl);
+      reg_stages<T, N, P, ROW, S + 1>(v, t, tw, inv, xl);
     }
   }
 }
 
-// Transform of length n (a power of two in [8, kMaxLen]); t in [0, n / kRegP).
-template <typename T, bool ROW>
-__device__ __forceinline__ void reg_fft(cx<T> (&v)[kRegP], int n, int t, const cx<T>* tw, bool inv, cx<T>* xl) {
+// Transform of length n with P points per thread: P = 8 for n a power of two in
+// [8, kMaxLen], P = 12 for n = 3 2^k in [12, 192]; t in [0, n / P).
+template <typename T, bool ROW, int P>
+__device__ __forceinline__ void reg_fft(cx<T> (&v)[P], int n, int t, const cx<T>* tw, bool inv, cx<T>* xl) {
   static_assert(kMaxLen == 256, "length dispatch covers 8..256");
-  switch (n) {
-    case 8: reg_stages<T, 8, ROW, 0>(v, t, tw, inv, xl); break;
-    case 16: reg_stages<T, 16, ROW, 0>(v, t, tw, inv, xl); break;
-    case 32: reg_stages<T, 32, ROW, 0>(v, t, tw, inv, xl); break;
-    case 64: reg_stages<T, 64, ROW, 0>(v, t, tw, inv, xl); break;
-    case 128: reg_stages<T, 128, ROW, 0>(v, t, tw, inv, xl); break;
-    default: reg_stages<T, 256, ROW, 0>(v, t, tw, inv, xl); break;
+  if constexpr (P == 8) {
+    switch (n) {
+      case 8: reg_stages<T, 8, 8, ROW, 0>(v, t, tw, inv, xl); break;
+      case 16: reg_stages<T, 16, 8, ROW, 0>(v, t, tw, inv, xl); break;
+      case 32: reg_stages<T, 32, 8, ROW, 0>(v, t, tw, inv, xl); break;
+      case 64: reg_stages<T, 64, 8, ROW, 0>(v, t, tw, inv, xl); break;
+      case 128: reg_stages<T, 128, 8, ROW, 0>(v, t, tw, inv, xl); break;
+      default: reg_stages<T, 256, 8, ROW, 0>(v, t, tw, inv, xl); break;
+    }
+  } else {
+    static_assert(P == 12, "register engine: 8 or 12 points per thread");
+    switch (n) {
+      case 12: reg_stages<T, 12, 12, ROW, 0>(v, t, tw, inv, xl); break;
+      case 24: reg_stages<T, 24, 12, ROW, 0>(v, t, tw, inv, xl); break;
+      case 48: reg_stages<T, 48, 12, ROW, 0>(v, t, tw, inv, xl); break;
+      case 96: reg_stages<T, 96, 12, ROW, 0>(v, t, tw, inv, xl); break;
+      default: reg_stages<T, 192, 12, ROW, 0>(v, t, tw, inv, xl); break;
+    }
   }
 }
 

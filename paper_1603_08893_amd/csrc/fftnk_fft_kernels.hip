@@ -26,11 +26,12 @@ int elem_blocks(long long m) {
 int row_blocks(const Grid& g) { return (int)((g.rows + g.rt - 1) / g.rt); }
 int row1_blocks(const Grid& g) { return (int)((g.rows + g.rt1 - 1) / g.rt1); }
 
-static int reg_pencils(int n) { return kThreads / (n / kRegP); }  // pencils per work-group, register engine
+// pencils per work-group of the register engine (P = the axis plan's points per thread)
+static int reg_pencils(const AxisPlan& pl) { return kThreads / (pl.n / pl.reg); }
 
 int col1_blocks(const Grid& g, int prec) {
   if (g.ax[1].reg) {
-    const long long np = 9LL * g.n0 * g.h, mb = reg_pencils(g.n1);
+    const long long np = 9LL * g.n0 * g.h, mb = reg_pencils(g.ax[1]);
     return (int)((np + mb - 1) / mb);
   }
   const int M = prec == PREC_F64 ? g.m64 : g.m32;
@@ -39,7 +40,7 @@ int col1_blocks(const Grid& g, int prec) {
 
 int col0_blocks(const Grid& g, int prec) {
   if (g.ax[0].reg) {
-    const long long np = 3LL * g.n1 * g.h, mb = reg_pencils(g.n0);
+    const long long np = 3LL * g.n1 * g.h, mb = reg_pencils(g.ax[0]);
     return (int)((np + mb - 1) / mb);
   }
   const int M = prec == PREC_F64 ? g.m64 : g.m32;
@@ -68,7 +69,7 @@ __device__ __forceinline__ void tangent_at(const Material& mat, long long gv, co
   }
 }
 
-template <typename T, int MODE, int LAW>
+template <typename T, int MODE, int LAW, int ENG>
 __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat, const T* __restrict__ in,
                                             const T* __restrict__ rvec, T* __restrict__ pvec, T* __restrict__ xvec,
                                             const T* __restrict__ Flin, double scale, cx<T>* __restrict__ spec,
@@ -77,6 +78,7 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
   const int rv = find_rve(B, K_ROW1, b, local);
   if (skip_rve(B, MODE == FWD_CG ? cg : nullptr, rv)) return;
   const auto& g = grid_of(B, rv);
+  if (pass1_engine(g.ax[2].reg) != ENG) return;  // another engine's launch owns this cell
   extern __shared__ unsigned char smem_raw[];
   const int N2 = g.n2, RT = g.rt1, H = g.h;
   const int npen = 5 * RT;
@@ -93,7 +95,7 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
   // register engine: pencil slot m = pair * RT + line (slots >= 5 RT idle),
   // stage the field in LDS once, transform in registers, unpack through one
   // mirror exchange.  bufA holds one slot of padded_len(N2) entries per pencil.
-  const bool reg = g.ax[2].reg;
+  constexpr bool reg = ENG != 0;
   const int SL = reg ? padded_len(N2) : N2;  // LDS slot of one line
   if ((int)threadIdx.x < RT * N2) {  // rt1 * n2 <= kThreads: at most one voxel per thread
     const int t = threadIdx.x;
@@ -171,25 +173,26 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
   const long long srow = g.rows * H;
   cx<T>* S = spec + g.spec_off;
 
-  if (reg) {
-    const int Tp = N2 / kRegP;
+  if constexpr (ENG != 0) {
+    constexpr int P = ENG;  // points per thread of the register engine
+    const int Tp = N2 / P;
     const int m = threadIdx.x / Tp, t = threadIdx.x - m * Tp;
     // idle pencil slots (m >= 5 rt1) all work in one spare slot after the
     // used ones: their values are never read back into anything stored
     cx<T>* xl = bufA + min(m, npen) * SL;
-    cx<T> v[kRegP];
+    cx<T> v[P];
 #pragma unroll
-    for (int q = 0; q < kRegP; ++q) v[q] = xl[lpad(t + Tp * q)];
+    for (int q = 0; q < P; ++q) v[q] = xl[lpad(t + Tp * q)];
     __syncthreads();
-    reg_fft<T, true>(v, N2, t, tw, false, xl);
+    reg_fft<T, true, P>(v, N2, t, tw, false, xl);
 #pragma unroll
-    for (int q = 0; q < kRegP; ++q) xl[lpad(t + Tp * q)] = v[q];
+    for (int q = 0; q < P; ++q) xl[lpad(t + Tp * q)] = v[q];
     __syncthreads();
     const int pq = m / RT, rl = m - pq * RT;
     const long long row = row0 + rl;
     if (m < npen && row < g.rows) {
 #pragma unroll
-      for (int q = 0; q < kRegP / 2; ++q) {  // k = t + Tp q < n2 / 2 = h
+      for (int q = 0; q < P / 2; ++q) {  // k = t + Tp q < n2 / 2 = h
         const int k = t + Tp * q;
         const cx<T> z = v[q];
         const cx<T> zm = xl[lpad(k ? N2 - k : 0)];
@@ -232,12 +235,12 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
   if (threadIdx.x == 0) pslot(B, MODE == FWD_CG ? SLOT_PW : SLOT_YY)[b] = res[0];
 }
 
-template <typename T, int MODE, int LAW>
+template <typename T, int MODE, int LAW, int ENG>
 __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, const T* __restrict__ in,
                                                      const T* __restrict__ rvec, T* __restrict__ pvec,
                                                      T* __restrict__ xvec, const T* __restrict__ Flin, double scale,
                                                      cx<T>* __restrict__ spec, const CgState* __restrict__ cg) {
-  tile_fwd_a2<T, MODE, LAW>(B, mat, in, rvec, pvec, xvec, Flin, scale, spec, cg, blockIdx.x);
+  tile_fwd_a2<T, MODE, LAW, ENG>(B, mat, in, rvec, pvec, xvec, Flin, scale, spec, cg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -247,22 +250,24 @@ __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, cons
 // a run of consecutive k2.  LDS engine: g.m consecutive k2 of one
 // (component, a0) plane.
 // ---------------------------------------------------------------------------
-template <typename T, bool INV>
+template <typename T, bool INV, int ENG>
 __device__ __forceinline__ void tile_col_a1(const Batch& B, cx<T>* __restrict__ spec,
                                                      const CgState* __restrict__ cg, const int b) {
   int local;
   const int rv = find_rve(B, sizeof(T) == 8 ? K_COL1_64 : K_COL1_32, b, local);
   if (skip_rve(B, cg, rv)) return;
   const auto& g = grid_of(B, rv);
+  if (g.ax[1].reg != ENG) return;  // another engine's launch owns this cell
   extern __shared__ unsigned char smem_raw[];
   const int N1 = g.n1, H = g.h;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   load_twiddles<T>(tw, B, g.ax[1].tw, N1);
   cx<T>* S0 = spec + g.spec_off;
 
-  if (g.ax[1].reg) {
+  if constexpr (ENG != 0) {
+    constexpr int P = ENG;  // points per thread of the register engine
     cx<T>* xl = tw + padded_len(N1);
-    const int Tp = N1 / kRegP, Mb = kThreads / Tp;
+    const int Tp = N1 / P, Mb = kThreads / Tp;
     const int m = threadIdx.x % Mb, t = threadIdx.x / Mb;
     const long long npen = 9LL * g.n0 * H;
     long long pen = (long long)local * Mb + m;
@@ -270,13 +275,13 @@ __device__ __forceinline__ void tile_col_a1(const Batch& B, cx<T>* __restrict__ 
     if (!valid) pen = 0;
     const long long plane = pen / H;
     cx<T>* base = S0 + plane * N1 * H + (pen - plane * H);
-    cx<T> v[kRegP];
+    cx<T> v[P];
 #pragma unroll
-    for (int q = 0; q < kRegP; ++q) v[q] = valid ? base[(long long)(t + Tp * q) * H] : cx<T>{(T)0, (T)0};
-    reg_fft<T, false>(v, N1, t, tw, INV, xl + m);
+    for (int q = 0; q < P; ++q) v[q] = valid ? base[(long long)(t + Tp * q) * H] : cx<T>{(T)0, (T)0};
+    reg_fft<T, false, P>(v, N1, t, tw, INV, xl + m);
     if (valid) {
 #pragma unroll
-      for (int q = 0; q < kRegP; ++q) base[(long long)(t + Tp * q) * H] = v[q];
+      for (int q = 0; q < P; ++q) base[(long long)(t + Tp * q) * H] = v[q];
     }
     return;
   }
@@ -302,9 +307,9 @@ __device__ __forceinline__ void tile_col_a1(const Batch& B, cx<T>* __restrict__ 
   }
 }
 
-template <typename T, bool INV>
+template <typename T, bool INV, int ENG>
 __global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict__ spec, const CgState* __restrict__ cg) {
-  tile_col_a1<T, INV>(B, spec, cg, blockIdx.x);
+  tile_col_a1<T, INV, ENG>(B, spec, cg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -316,7 +321,6 @@ __global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict_
 // zero at k = 0 and whenever an even axis sits at its Nyquist index.  The 1/n
 // of the inverse transform is folded in here.
 // ---------------------------------------------------------------------------
-constexpr int kMaxPpt = 8;  // points per thread of an LDS-engine pass-3 tile (n0 * m <= kMaxPpt * kThreads)
 
 template <typename T, typename G>
 __device__ __forceinline__ void project_point(cx<T>& a0, cx<T>& a1, cx<T>& a2, int k0, int k1, int k2,
@@ -338,13 +342,14 @@ __device__ __forceinline__ void project_point(cx<T>& a0, cx<T>& a1, cx<T>& a2, i
   a2 = cscale(s, xi2 * coef);
 }
 
-template <typename T>
+template <typename T, int ENG>
 __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __restrict__ spec,
                                                              const CgState* __restrict__ cg, const int b) {
   int local;
   const int rv = find_rve(B, sizeof(T) == 8 ? K_COL0_64 : K_COL0_32, b, local);
   if (skip_rve(B, cg, rv)) return;
   const auto& g = grid_of(B, rv);
+  if (g.ax[0].reg != ENG) return;  // another engine's launch owns this cell
   extern __shared__ unsigned char smem_raw[];
   const int N0 = g.n0, N1 = g.n1, H = g.h;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
@@ -354,9 +359,10 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
   const long long cstride = g.rows * H;
   const T rn0 = (T)1 / (T)N0, rn1 = (T)1 / (T)N1, rn2 = (T)1 / (T)g.n2;
 
-  if (g.ax[0].reg) {
+  if constexpr (ENG != 0) {
+    constexpr int P = ENG;  // points per thread of the register engine
     cx<T>* xl = tw + padded_len(N0);
-    const int Tp = N0 / kRegP, Mb = kThreads / Tp;
+    const int Tp = N0 / P, Mb = kThreads / Tp;
     const int m = threadIdx.x % Mb, t = threadIdx.x / Mb;
     const long long npen = 3LL * N1 * H;
     long long pen = (long long)local * Mb + m;
@@ -383,22 +389,22 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
     const int f1 = signed_freq(k1, N1);
     const T xi1 = (T)f1 * rn1, xi2 = (T)k2 * rn2;
     const bool pen_zero = (N1 % 2 == 0) && (2 * k1 == N1);
-    cx<T> v0[kRegP], v1[kRegP];
+    cx<T> v0[P], v1[P];
     {
-      cx<T> v2[kRegP];
+      cx<T> v2[P];
 #pragma unroll
-      for (int q = 0; q < kRegP; ++q) {
+      for (int q = 0; q < P; ++q) {
         v0[q] = valid ? *at(0, q) : cx<T>{(T)0, (T)0};
         v1[q] = valid ? *at(1, q) : cx<T>{(T)0, (T)0};
         v2[q] = valid ? *at(2, q) : cx<T>{(T)0, (T)0};
       }
 #pragma unroll
-      for (int q = 0; q < kRegP; ++q) v1[q] = cscale(v1[q], xi1) + cscale(v2[q], xi2);
+      for (int q = 0; q < P; ++q) v1[q] = cscale(v1[q], xi1) + cscale(v2[q], xi2);
     }
-    reg_fft<T, false>(v1, N0, t, tw, false, xl + m);
-    reg_fft<T, false>(v0, N0, t, tw, false, xl + m);
+    reg_fft<T, false, P>(v1, N0, t, tw, false, xl + m);
+    reg_fft<T, false, P>(v0, N0, t, tw, false, xl + m);
 #pragma unroll
-    for (int q = 0; q < kRegP; ++q) {
+    for (int q = 0; q < P; ++q) {
       const int k0 = t + Tp * q;
       const int f0 = signed_freq(k0, N0);
       const T xi0 = (T)f0 * rn0;
@@ -408,11 +414,11 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
       v0[q] = cscale(sc, xi0);
       v1[q] = sc;
     }
-    reg_fft<T, false>(v0, N0, t, tw, true, xl + m);
-    reg_fft<T, false>(v1, N0, t, tw, true, xl + m);
+    reg_fft<T, false, P>(v0, N0, t, tw, true, xl + m);
+    reg_fft<T, false, P>(v1, N0, t, tw, true, xl + m);
     if (valid) {
 #pragma unroll
-      for (int q = 0; q < kRegP; ++q) {
+      for (int q = 0; q < P; ++q) {
         *at(0, q) = v0[q];
         *at(1, q) = cscale(v1[q], xi1);
         *at(2, q) = cscale(v1[q], xi2);
@@ -432,55 +438,86 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
   const int total = N0 * M;
   cx<T>* base0 = S0 + (long long)k1 * H + kb * M;
 
-  cx<T> reg[3][kMaxPpt];
-#pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    cx<T>* base = base0 + (3 * i + l) * cstride;
-    for (int t = threadIdx.x; t < total; t += kThreads) {
-      const int e = t / M, m = t - e * M;
-      bufA[t] = m < Mt ? base[e * S + m] : cx<T>{(T)0, (T)0};
-    }
-    __syncthreads();
-    const cx<T>* R = fft_lds<T>(bufA, bufB, g.ax[0], M, 1, M, tw, false, true);
-#pragma unroll
-    for (int pt = 0; pt < kMaxPpt; ++pt) {
-      const int t = threadIdx.x + pt * kThreads;
-      if (t < total) reg[l][pt] = R[t];
-    }
-    __syncthreads();
-  }
+  // The same two-forward / two-inverse scheme as the register engine: xi_1
+  // is fixed in this tile (one k1), xi_2 per pencil (k2 = kb M + m).  Every
+  // load is issued before the first transform.
+  const int f1 = signed_freq(k1, N1);
+  const T xi1 = (T)f1 * rn1;
+  const bool pen_zero = (N1 % 2 == 0) && (2 * k1 == N1);
+  cx<T>* b0 = base0 + (long long)(3 * i) * cstride;
+  cx<T> ra[kMaxPpt], ru[kMaxPpt];  // a_i0, then FFT(a_i0); u = xi1 a_i1 + xi2 a_i2, then FFT(u)
 #pragma unroll
   for (int pt = 0; pt < kMaxPpt; ++pt) {
     const int t = threadIdx.x + pt * kThreads;
-    if (t < total) {
-      const int k0 = t / M, m = t - k0 * M;
-      if (m < Mt)
-        project_point<T>(reg[0][pt], reg[1][pt], reg[2][pt], k0, k1, kb * M + m, g, rn0, rn1, rn2);
-      else
-        reg[0][pt] = reg[1][pt] = reg[2][pt] = cx<T>{(T)0, (T)0};
-    }
+    const int e = t / M, m = t - e * M;
+    const bool ok = t < total && m < Mt;
+    const long long o = ok ? (long long)e * S + m : 0;
+    const cx<T> a0 = b0[o], a1 = b0[cstride + o], a2 = b0[2 * cstride + o];
+    const T xi2 = (T)(kb * M + m) * rn2;
+    ra[pt] = ok ? a0 : cx<T>{(T)0, (T)0};
+    ru[pt] = ok ? cscale(a1, xi1) + cscale(a2, xi2) : cx<T>{(T)0, (T)0};
   }
 #pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    cx<T>* base = base0 + (3 * i + l) * cstride;
+  for (int l = 0; l < 2; ++l) {  // forward: u, then a_i0
+    cx<T>(&r)[kMaxPpt] = l == 0 ? ru : ra;
 #pragma unroll
     for (int pt = 0; pt < kMaxPpt; ++pt) {
       const int t = threadIdx.x + pt * kThreads;
-      if (t < total) bufA[t] = reg[l][pt];
+      if (t < total) bufA[t] = r[pt];
     }
     __syncthreads();
-    const cx<T>* R = fft_lds<T>(bufA, bufB, g.ax[0], M, 1, M, tw, true, true);
+    const cx<T>* Rz = fft_lds<T>(bufA, bufB, g.ax[0], M, 1, M, tw, false, true);
+#pragma unroll
+    for (int pt = 0; pt < kMaxPpt; ++pt) {
+      const int t = threadIdx.x + pt * kThreads;
+      if (t < total) r[pt] = Rz[t];
+    }
+    __syncthreads();
+  }
+  // s = xi0 A0 + U; ra <- xi0 c s, ru <- c s, c = (1/n) / |xi|^2 (0 on k = 0 and Nyquist)
+#pragma unroll
+  for (int pt = 0; pt < kMaxPpt; ++pt) {
+    const int t = threadIdx.x + pt * kThreads;
+    const int k0 = t / M, m = t - k0 * M;
+    const int k2 = kb * M + m;
+    const int f0 = signed_freq(k0, N0);
+    const T xi0 = (T)f0 * rn0, xi2 = (T)k2 * rn2;
+    const bool zero = pen_zero || m >= Mt || (f0 == 0 && f1 == 0 && k2 == 0) || ((N0 % 2 == 0) && (2 * k0 == N0));
+    const T c = zero ? (T)0 : (T)g.inv_n / (xi0 * xi0 + xi1 * xi1 + xi2 * xi2);
+    const cx<T> sc = cscale(cscale(ra[pt], xi0) + ru[pt], c);
+    ra[pt] = cscale(sc, xi0);
+    ru[pt] = sc;
+  }
+#pragma unroll
+  for (int l = 0; l < 2; ++l) {  // inverse: xi0 c s -> component 0; c s -> components 1 and 2
+    cx<T>(&r)[kMaxPpt] = l == 0 ? ra : ru;
+#pragma unroll
+    for (int pt = 0; pt < kMaxPpt; ++pt) {
+      const int t = threadIdx.x + pt * kThreads;
+      if (t < total) bufA[t] = r[pt];
+    }
+    __syncthreads();
+    const cx<T>* Rz = fft_lds<T>(bufA, bufB, g.ax[0], M, 1, M, tw, true, true);
     for (int t = threadIdx.x; t < total; t += kThreads) {
       const int e = t / M, m = t - e * M;
-      if (m < Mt) base[e * S + m] = R[t];
+      if (m >= Mt) continue;
+      const long long o = (long long)e * S + m;
+      if (l == 0) {
+        b0[o] = Rz[t];
+      } else {
+        const T xi2 = (T)(kb * M + m) * rn2;
+        b0[cstride + o] = cscale(Rz[t], xi1);
+        b0[2 * cstride + o] = cscale(Rz[t], xi2);
+      }
     }
     __syncthreads();
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* __restrict__ spec, const CgState* __restrict__ cg) {
-  tile_col_a0_project<T>(B, spec, cg, blockIdx.x);
+template <typename T, int ENG>
+__global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* __restrict__ spec,
+                                                             const CgState* __restrict__ cg) {
+  tile_col_a0_project<T, ENG>(B, spec, cg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -490,7 +527,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* 
 // taken real; an even line's Nyquist entry is zero), transformed back, and
 // Re / Im give the two real components.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, typename TO>
+template <typename T, int MODE, typename TO, int ENG>
 __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restrict__ spec, TO* __restrict__ out,
                                             TO* __restrict__ x, double scale,
                                                      const CgState* __restrict__ cg, const int b) {
@@ -498,6 +535,7 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
   const int rv = find_rve(B, K_ROW, b, local);
   if (skip_rve(B, MODE == INV_CGR ? cg : nullptr, rv)) return;
   const auto& g = grid_of(B, rv);
+  if (g.ax[2].reg != ENG) return;  // another engine's launch owns this cell
   extern __shared__ unsigned char smem_raw[];
   const int N2 = g.n2, RT = g.rt, H = g.h;
   const int npen = 5 * RT;
@@ -510,22 +548,23 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
   const long long srow = g.rows * H;
   const cx<T>* S = spec + g.spec_off;
 
-  if (g.ax[2].reg) {
+  if constexpr (ENG != 0) {
+    constexpr int P = ENG;  // points per thread of the register engine
     // register engine: pencil slot m = pair * RT + line (slots >= 5 RT idle);
     // the pair line Z = X + iY is read straight from the half spectra (mirror
     // half conjugated), transformed in registers, written straight out.
-    const int Tp = N2 / kRegP;
+    const int Tp = N2 / P;
     const int m = threadIdx.x / Tp, t = threadIdx.x - m * Tp;
     const int pq = m / RT, rl = m - pq * RT;
     const long long row = row0 + rl;
     const bool valid = m < npen && row < g.rows;
     const int c0 = pq < 4 ? 2 * pq : 8;
-    // Thread t loads the stored half line at k = t + Tp q, q < kRegP / 2 (all
+    // Thread t loads the stored half line at k = t + Tp q, q < P / 2 (all
     // of k < h = n2 / 2, each entry once, addresses clamped into the cell).
     // The upper half k = n2 - k' needs conj X[k'], held by lane (Tp - t) mod Tp
-    // of the same pencil at q' = kRegP - 1 - q (lane 0 holds its own at
-    // q' = kRegP - q; q = kRegP / 2 is the Nyquist index, zero).
-    constexpr int P2 = kRegP / 2;
+    // of the same pencil at q' = P - 1 - q (lane 0 holds its own at
+    // q' = P - q; q = P / 2 is the Nyquist index, zero).
+    constexpr int P2 = P / 2;
     const cx<T>* SX = S + c0 * srow + (valid ? row : row0) * H;
     const cx<T>* SY = pq < 4 ? SX + srow : SX;
     cx<T> X[P2], Y[P2];
@@ -535,7 +574,7 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
       Y[q] = SY[t + Tp * q];
     }
     const T yon = pq < 4 ? (T)1 : (T)0;  // component 8 rides alone
-    cx<T> v[kRegP];
+    cx<T> v[P];
 #pragma unroll
     for (int q = 0; q < P2; ++q) {
       const T xi = (t == 0 && q == 0) ? (T)0 : X[q].y;  // k = 0 taken real
@@ -544,35 +583,35 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
     }
     const int src = (Tp - t) & (Tp - 1);
 #pragma unroll
-    for (int q = P2; q < kRegP; ++q) {
+    for (int q = P2; q < P; ++q) {
       cx<T> xm, ym;
-      xm.x = __shfl(X[kRegP - 1 - q].x, src, Tp);
-      xm.y = __shfl(X[kRegP - 1 - q].y, src, Tp);
-      ym.x = __shfl(Y[kRegP - 1 - q].x, src, Tp);
-      ym.y = __shfl(Y[kRegP - 1 - q].y, src, Tp);
+      xm.x = __shfl(X[P - 1 - q].x, src, Tp);
+      xm.y = __shfl(X[P - 1 - q].y, src, Tp);
+      ym.x = __shfl(Y[P - 1 - q].x, src, Tp);
+      ym.y = __shfl(Y[P - 1 - q].y, src, Tp);
       if (t == 0) {
-        xm = q == P2 ? cx<T>{(T)0, (T)0} : X[q == P2 ? 0 : kRegP - q];
-        ym = q == P2 ? cx<T>{(T)0, (T)0} : Y[q == P2 ? 0 : kRegP - q];
+        xm = q == P2 ? cx<T>{(T)0, (T)0} : X[q == P2 ? 0 : P - q];
+        ym = q == P2 ? cx<T>{(T)0, (T)0} : Y[q == P2 ? 0 : P - q];
       }
       const T xi = -xm.y, yi = -yon * ym.y;  // conjugated
       v[q] = valid ? cx<T>{xm.x - yi, xi + yon * ym.x} : cx<T>{(T)0, (T)0};
     }
-    reg_fft<T, true>(v, N2, t, tw, true, bufA + min(m, npen) * padded_len(N2));  // idle slots share a spare one
+    reg_fft<T, true, P>(v, N2, t, tw, true, bufA + min(m, npen) * padded_len(N2));  // idle slots share a spare one
     double acc[1] = {0.0};
     if (valid) {
       const long long n = g.n;
       const long long base = 9 * g.vox_off + row * N2;
       const int nc = pq < 4 ? 2 : 1;
       const T alpha = MODE == INV_CGR ? (T)cptr(cg)[rv].alpha : (T)0;
-      TO rin[kRegP][2];  // INV_CGR: the residual, all loads issued before use
+      TO rin[P][2];  // INV_CGR: the residual, all loads issued before use
       if (MODE == INV_CGR) {
 #pragma unroll
-        for (int q = 0; q < kRegP; ++q)
+        for (int q = 0; q < P; ++q)
 #pragma unroll
           for (int h = 0; h < 2; ++h) rin[q][h] = h < nc ? out[base + t + Tp * q + (c0 + h) * n] : (TO)0;
       }
 #pragma unroll
-      for (int q = 0; q < kRegP; ++q) {
+      for (int q = 0; q < P; ++q) {
         const long long v0 = base + t + Tp * q;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -674,11 +713,11 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
   if (threadIdx.x == 0) pslot(B, MODE == INV_CGR ? SLOT_RR : SLOT_BB)[b] = res[0];
 }
 
-template <typename T, int MODE, typename TO>
+template <typename T, int MODE, typename TO, int ENG>
 __global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __restrict__ spec, TO* __restrict__ out,
                                                      TO* __restrict__ x, double scale,
                                                      const CgState* __restrict__ cg) {
-  tile_inv_a2<T, MODE, TO>(B, spec, out, x, scale, cg, blockIdx.x);
+  tile_inv_a2<T, MODE, TO, ENG>(B, spec, out, x, scale, cg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -693,11 +732,26 @@ static void launch_tiles(void (*kernel)(KArgs...), int ntiles, size_t lds, hipSt
   hipLaunchKernelGGL(kernel, dim3(ntiles), dim3(kThreads), lds, s, args...);
 }
 
+// Each pass has a register-engine and an LDS-engine kernel (separate, so that
+// neither carries the other's register budget); a launch starts the variants
+// the batch needs (Launch::eng, per axis: bit 0 some cell on the LDS engine,
+// bit 1 on the 8-point register engine, bit 2 on the 12-point one) and each
+// skips the others' cells.
+template <typename T, int MODE, int LAW>
+static void fwd_a2_mode(const Launch& L, const Material& mat, const T* in, const T* r, T* p, T* x, const T* Flin,
+                        double scale, cx<T>* spec, const CgState* cg) {
+  const int ntiles = L.nblk[K_ROW1];
+  const size_t lds = sizeof(T) == 8 ? L.lds_row1_64 : L.lds_row1_32;
+  // pass 1 runs 12-point axes on the LDS engine (pass1_engine)
+  if (L.eng[2] & 2)
+    launch_tiles(&k_fwd_a2<T, MODE, LAW, 8>, ntiles, lds, L.s, L.b, mat, in, r, p, x, Flin, scale, spec, cg);
+  if (L.eng[2] & 5)
+    launch_tiles(&k_fwd_a2<T, MODE, LAW, 0>, ntiles, lds, L.s, L.b, mat, in, r, p, x, Flin, scale, spec, cg);
+}
+
 template <typename T, int LAW>
 static void fwd_a2_t(int mode, const Launch& L, const Material& mat, const void* in, const void* r, void* p,
                      void* x, const void* Flin, double scale, void* spec, const CgState* cg) {
-  const int ntiles = L.nblk[K_ROW1];
-  const size_t lds = sizeof(T) == 8 ? L.lds_row1_64 : L.lds_row1_32;
   const T* ti = static_cast<const T*>(in);
   const T* tr = static_cast<const T*>(r);
   T* tp = static_cast<T*>(p);
@@ -705,10 +759,10 @@ static void fwd_a2_t(int mode, const Launch& L, const Material& mat, const void*
   const T* tf = static_cast<const T*>(Flin);
   cx<T>* sp = static_cast<cx<T>*>(spec);
   switch (mode) {
-    case FWD_COPY: launch_tiles(&k_fwd_a2<T, FWD_COPY, MODEL_SVK>, ntiles, lds, L.s, L.b, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
-    case FWD_TANGENT: launch_tiles(&k_fwd_a2<T, FWD_TANGENT, LAW>, ntiles, lds, L.s, L.b, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
-    case FWD_TANGENT_UNI: launch_tiles(&k_fwd_a2<T, FWD_TANGENT_UNI, LAW>, ntiles, lds, L.s, L.b, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
-    default: launch_tiles(&k_fwd_a2<T, FWD_CG, LAW>, ntiles, lds, L.s, L.b, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
+    case FWD_COPY: fwd_a2_mode<T, FWD_COPY, MODEL_SVK>(L, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
+    case FWD_TANGENT: fwd_a2_mode<T, FWD_TANGENT, LAW>(L, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
+    case FWD_TANGENT_UNI: fwd_a2_mode<T, FWD_TANGENT_UNI, LAW>(L, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
+    default: fwd_a2_mode<T, FWD_CG, LAW>(L, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
   }
 }
 
@@ -724,47 +778,65 @@ void launch_fwd_a2(int prec, int mode, const Launch& L, const Material& mat, con
   }
 }
 
+template <typename T, bool INV>
+static void col_a1_t(const Launch& L, void* spec, const CgState* cg) {
+  const int ntiles = L.nblk[sizeof(T) == 8 ? K_COL1_64 : K_COL1_32];
+  const size_t lds = sizeof(T) == 8 ? L.lds_col1_64 : L.lds_col1_32;
+  cx<T>* sp = static_cast<cx<T>*>(spec);
+  if (L.eng[1] & 2) launch_tiles(&k_col_a1<T, INV, 8>, ntiles, lds, L.s, L.b, sp, cg);
+  if (L.eng[1] & 4) launch_tiles(&k_col_a1<T, INV, 12>, ntiles, lds, L.s, L.b, sp, cg);
+  if (L.eng[1] & 1) launch_tiles(&k_col_a1<T, INV, 0>, ntiles, lds, L.s, L.b, sp, cg);
+}
+
 void launch_col_a1(int prec, bool inverse, const Launch& L, void* spec, const CgState* cg) {
   if (prec == PREC_F64) {
-    const int ntiles = L.nblk[K_COL1_64];
     if (inverse)
-      launch_tiles(&k_col_a1<double, true>, ntiles, L.lds_col1_64, L.s, L.b,
-                         static_cast<cx<double>*>(spec), cg);
+      col_a1_t<double, true>(L, spec, cg);
     else
-      launch_tiles(&k_col_a1<double, false>, ntiles, L.lds_col1_64, L.s, L.b,
-                         static_cast<cx<double>*>(spec), cg);
+      col_a1_t<double, false>(L, spec, cg);
   } else {
-    const int ntiles = L.nblk[K_COL1_32];
     if (inverse)
-      launch_tiles(&k_col_a1<float, true>, ntiles, L.lds_col1_32, L.s, L.b,
-                         static_cast<cx<float>*>(spec), cg);
+      col_a1_t<float, true>(L, spec, cg);
     else
-      launch_tiles(&k_col_a1<float, false>, ntiles, L.lds_col1_32, L.s, L.b,
-                         static_cast<cx<float>*>(spec), cg);
+      col_a1_t<float, false>(L, spec, cg);
   }
+}
+
+template <typename T>
+static void col_a0_t(const Launch& L, void* spec, const CgState* cg) {
+  const int ntiles = L.nblk[sizeof(T) == 8 ? K_COL0_64 : K_COL0_32];
+  const size_t lds = sizeof(T) == 8 ? L.lds_col0_64 : L.lds_col0_32;
+  cx<T>* sp = static_cast<cx<T>*>(spec);
+  if (L.eng[0] & 2) launch_tiles(&k_col_a0_project<T, 8>, ntiles, lds, L.s, L.b, sp, cg);
+  if (L.eng[0] & 1) launch_tiles(&k_col_a0_project<T, 0>, ntiles, lds, L.s, L.b, sp, cg);
 }
 
 void launch_col_a0_project(int prec, const Launch& L, void* spec, const CgState* cg) {
   if (prec == PREC_F64)
-    launch_tiles(&k_col_a0_project<double>, L.nblk[K_COL0_64], L.lds_col0_64, L.s, L.b,
-                       static_cast<cx<double>*>(spec), cg);
+    col_a0_t<double>(L, spec, cg);
   else
-    launch_tiles(&k_col_a0_project<float>, L.nblk[K_COL0_32], L.lds_col0_32, L.s, L.b,
-                       static_cast<cx<float>*>(spec), cg);
+    col_a0_t<float>(L, spec, cg);
+}
+
+template <typename T, int MODE, typename TO>
+static void inv_a2_mode(const Launch& L, const cx<T>* spec, TO* out, TO* x, double scale, const CgState* cg) {
+  const int ntiles = L.nblk[K_ROW];
+  const size_t lds = sizeof(T) == 8 ? L.lds_row64 : L.lds_row32;
+  if (L.eng[2] & 2) launch_tiles(&k_inv_a2<T, MODE, TO, 8>, ntiles, lds, L.s, L.b, spec, out, x, scale, cg);
+  if (L.eng[2] & 4) launch_tiles(&k_inv_a2<T, MODE, TO, 12>, ntiles, lds, L.s, L.b, spec, out, x, scale, cg);
+  if (L.eng[2] & 1) launch_tiles(&k_inv_a2<T, MODE, TO, 0>, ntiles, lds, L.s, L.b, spec, out, x, scale, cg);
 }
 
 template <typename T, typename TO>
 static void inv_a2_t(int mode, const Launch& L, const void* spec, void* out, void* x, double scale,
                      const CgState* cg) {
-  const int ntiles = L.nblk[K_ROW];
-  const size_t lds = sizeof(T) == 8 ? L.lds_row64 : L.lds_row32;
   const cx<T>* sp = static_cast<const cx<T>*>(spec);
   TO* to = static_cast<TO*>(out);
   TO* tx = static_cast<TO*>(x);
   switch (mode) {
-    case INV_OUT: launch_tiles(&k_inv_a2<T, INV_OUT, TO>, ntiles, lds, L.s, L.b, sp, to, tx, scale, cg); break;
-    case INV_CGR: launch_tiles(&k_inv_a2<T, INV_CGR, TO>, ntiles, lds, L.s, L.b, sp, to, tx, scale, cg); break;
-    default: launch_tiles(&k_inv_a2<T, INV_RHS, TO>, ntiles, lds, L.s, L.b, sp, to, tx, scale, cg); break;
+    case INV_OUT: inv_a2_mode<T, INV_OUT, TO>(L, sp, to, tx, scale, cg); break;
+    case INV_CGR: inv_a2_mode<T, INV_CGR, TO>(L, sp, to, tx, scale, cg); break;
+    default: inv_a2_mode<T, INV_RHS, TO>(L, sp, to, tx, scale, cg); break;
   }
 }
 

@@ -16,6 +16,7 @@ constexpr int kMaxLen = 256;       // longest supported grid axis
 constexpr int kMaxRve = 256;       // RVEs of one batched context
 constexpr int kRedBlocks = 2048;   // most work-groups of an element-wise kernel per RVE
 constexpr int kRegP = 8;           // points per thread of the register-resident FFT engine
+constexpr int kMaxPpt = 4;         // points per thread of an LDS-engine column tile (n * m <= kMaxPpt * kThreads)
 
 // LDS padding: entry e of a twiddle table or of a contiguous (unit-stride)
 // exchange line sits at e + e / 8, so that eight lanes touching entries 8
@@ -23,13 +24,20 @@ constexpr int kRegP = 8;           // points per thread of the register-resident
 __host__ __device__ constexpr int lpad(int e) { return e + (e >> 3); }
 __host__ __device__ constexpr int padded_len(int n) { return n + (n >> 3) + 1; }
 
+// Engine of the a2 forward pass for an a2 plan with `reg` points per thread:
+// the 12-point register engine measured slower there than the LDS engine
+// (its tangent phase and transform together need more registers), so pass 1
+// keeps the LDS engine for those lengths.
+__host__ __device__ constexpr int pass1_engine(int reg) { return reg == 12 ? 0 : reg; }
+
 // Radix plan of one 1-D transform of length n: n = prod radix[s].
 struct AxisPlan {
   int n;
   int nstages;
   int radix[kMaxStages];
   int tw;   // offset (in complex entries) of the length-n twiddle table W_n^e, e in [0, n)
-  int reg;  // 1: power of two >= 8, transformed by the register-resident engine
+  int reg;  // points per thread of the register-resident engine: 8 (n = 2^k >= 8), 12 (n = 3 2^k,
+            // 12..192, not on axis a0), 0 = LDS engine
 };
 
 // One periodic cell (RVE).  Real tensor fields are component-major
@@ -158,6 +166,7 @@ struct Launch {
   Batch b;
   int nblk[NKIND];
   size_t lds_row64, lds_row32, lds_col1_64, lds_col1_32, lds_col0_64, lds_col0_32, lds_row1_64, lds_row1_32;
+  int eng[3];  // per grid axis: bit 0 some cell transforms it with the LDS engine, bit 1 / 2 with the 8- / 12-point register engine
   hipStream_t s;
 };
 void launch_fwd_a2(int prec, int mode, const Launch& L, const Material& mat, const void* in_T, const void* r_T,
