@@ -71,6 +71,7 @@ def lib():
         L.orc_fft3d.argtypes = [dp, i, i, i, i]
         L.orc_dft3d_naive.argtypes = [dp, dp, i, i, i, i]
         L.orc_project.argtypes = [i, i, i, dp, dp]
+        L.orc_project_nyq.argtypes = [i, i, i, dp, dp, i]
         L.orc_svk_stress.argtypes = [ctypes.c_long, dp, dp, dp, dp]
         L.orc_svk_tangent.argtypes = [ctypes.c_long, dp, dp, dp, dp, dp]
         L.orc_apply_operator.argtypes = [i, i, i, dp, dp, dp, dp, dp]
@@ -80,6 +81,9 @@ def lib():
         L.orc_solve_increment.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                           i, i, dp, dp, ctypes.POINTER(Stats)]
         L.orc_solve_increment.restype = i
+        L.orc_solve_increment_nyq.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                              i, i, dp, dp, ctypes.POINTER(Stats), i]
+        L.orc_solve_increment_nyq.restype = i
         L.orc_adjoint.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, i, dp, dp, ctypes.POINTER(i)]
         L.orc_adjoint.restype = i
         L.orc_jacobi_eig3.argtypes = [dp, dp, dp]
@@ -135,13 +139,20 @@ def dft3d_naive(x, sign=-1):
 
 
 # ---------------------------------------------------------------- projection
-def project(A):
-    """G(A) for a tensor field A of shape (9, n0, n1, n2) (or (3, 3, n0, n1, n2))."""
+def project(A, nyq_identity=False):
+    """G(A) for a tensor field A of shape (9, n0, n1, n2) (or (3, 3, n0, n1, n2)).
+
+    nyq_identity selects the even-grid choice of App. C: False, G-hat = 0 at
+    Nyquist frequencies (compatible F); True, G-hat = identity there
+    (equilibrated stress)."""
     shp = A.shape
     A = _c(A).reshape(9, *shp[-3:])
     out = np.empty_like(A)
     n0, n1, n2 = A.shape[1:]
-    lib().orc_project(n0, n1, n2, _p(A), _p(out))
+    if nyq_identity:
+        lib().orc_project_nyq(n0, n1, n2, _p(A), _p(out), 1)
+    else:
+        lib().orc_project(n0, n1, n2, _p(A), _p(out))
     return out.reshape(shp)
 
 
@@ -217,8 +228,10 @@ def adjoint(K, mu, F, g, eta_cg=1e-8, max_cg=10000):
     return st, dmu, dK, it.value
 
 
-def solve_increment(K, mu, F, Fbar, eta_nw=1e-5, eta_cg=1e-8, max_newton=50, max_cg=10000):
-    """One increment of Algorithm 1.  Returns (status, F_new, P, Pbar, stats)."""
+def solve_increment(K, mu, F, Fbar, eta_nw=1e-5, eta_cg=1e-8, max_newton=50, max_cg=10000, nyq_identity=False):
+    """One increment of Algorithm 1.  Returns (status, F_new, P, Pbar, stats).
+
+    nyq_identity: the projection's Nyquist choice (see project)."""
     F = np.array(F, dtype=np.float64, copy=True, order="C")
     grid = F.shape[1:]
     K = _c(np.broadcast_to(K, grid))
@@ -227,9 +240,9 @@ def solve_increment(K, mu, F, Fbar, eta_nw=1e-5, eta_cg=1e-8, max_newton=50, max
     P = np.zeros_like(F)
     Pbar = np.zeros(9)
     st = Stats()
-    status = lib().orc_solve_increment(grid[0], grid[1], grid[2], _p(K), _p(mu), _p(F), _p(Fbar),
-                                       eta_nw, eta_cg, max_newton, max_cg, _p(P), _p(Pbar),
-                                       ctypes.byref(st))
+    status = lib().orc_solve_increment_nyq(grid[0], grid[1], grid[2], _p(K), _p(mu), _p(F), _p(Fbar),
+                                           eta_nw, eta_cg, max_newton, max_cg, _p(P), _p(Pbar),
+                                           ctypes.byref(st), 1 if nyq_identity else 0)
     return status, F, P, Pbar, st.as_dict()
 
 

@@ -207,14 +207,17 @@ void orc_dft3d_naive(const double* in_, double* out_, int n0, int n1, int n2, in
 // using the double contraction A:B = A_ijkl B_lk of the nomenclature and
 // G-hat_ijlm = delta_im xi_j xi_l / |xi|^2.  xi_d = k_d / N_d with k_d the signed
 // integer frequency of axis d (for cubic grids the common factor 1/N cancels).
-// G-hat is zero at k = 0 (zero-mean property) and, on an even axis, whenever that
-// axis sits at its Nyquist index N_d/2 (App. C, the "compatible F" choice).
+// G-hat is zero at k = 0 (zero-mean property).  A frequency at which some even
+// axis sits at its Nyquist index N_d/2 gets one of the two choices of App. C:
+// nyq_identity = 0, G-hat = 0 there (the choice that leaves F compatible, the
+// paper's default), or nyq_identity = 1, G-hat = identity there (the choice
+// that leaves the stress equilibrated).
 // Full complex transforms are used (no real-to-complex shortcut).
 // ---------------------------------------------------------------------------
 
 static int signed_freq(int idx, int n) { return (2 * idx > n) ? idx - n : idx; }
 
-void orc_project(int n0, int n1, int n2, const double* A, double* GA) {
+void orc_project_nyq(int n0, int n1, int n2, const double* A, double* GA, int nyq_identity) {
   const long n = (long)n0 * n1 * n2;
   std::vector<cplx> Ah(9 * n);
   for (int c = 0; c < 9; ++c) {
@@ -231,8 +234,10 @@ void orc_project(int n0, int n1, int n2, const double* A, double* GA) {
                               (double)signed_freq(i2, n2) / n2};
         const double xx = xi[0] * xi[0] + xi[1] * xi[1] + xi[2] * xi[2];
         cplx out[9];
-        if (xx == 0.0 || nyq) {
+        if (xx == 0.0) {
           for (int c = 0; c < 9; ++c) out[c] = 0.0;
+        } else if (nyq) {
+          for (int c = 0; c < 9; ++c) out[c] = nyq_identity ? Ah[c * n + v] : cplx(0.0);
         } else {
           for (int i = 0; i < 3; ++i) {
             // row i of A-hat projected on xi
@@ -248,6 +253,8 @@ void orc_project(int n0, int n1, int n2, const double* A, double* GA) {
     for (long v = 0; v < n; ++v) GA[c * n + v] = Ah[c * n + v].real() / (double)n;
   }
 }
+
+void orc_project(int n0, int n1, int n2, const double* A, double* GA) { orc_project_nyq(n0, n1, n2, A, GA, 0); }
 
 // ---------------------------------------------------------------------------
 // St. Venant-Kirchhoff hyperelasticity (Sec. 4.2):
@@ -363,6 +370,7 @@ typedef struct {
   const double* ty0;
   const double* H;
   const double* hist;
+  int nyq;  // Nyquist choice of the projection (see orc_project_nyq)
 } orc_problem;
 
 static int law_stress(const orc_problem& pb, const double* F, double* P, double* hist_new);
@@ -403,7 +411,7 @@ static int cg_solve(const orc_problem& pb, const double* Flin, const double* b, 
     {
       std::vector<double> t(m);
       law_tangent(pb, Flin, p.data(), t.data());
-      orc_project(pb.n0, pb.n1, pb.n2, t.data(), w.data());
+      orc_project_nyq(pb.n0, pb.n1, pb.n2, t.data(), w.data(), pb.nyq);
     }
     ++*iters;
     const double pw = dot(p.data(), w.data(), m);
@@ -488,7 +496,7 @@ static int solve_increment_impl(const orc_problem& pb, double* F, const double* 
     for (int c = 0; c < 9; ++c)
       for (long v = 0; v < n; ++v) U[c * n + v] = dFbar[c];
     law_tangent(pb, Ft.data(), U.data(), Y.data());
-    orc_project(n0, n1, n2, Y.data(), b.data());
+    orc_project_nyq(n0, n1, n2, Y.data(), b.data(), pb.nyq);
     for (long i = 0; i < m; ++i) b[i] = -b[i];
   }
   for (int c = 0; c < 9; ++c)
@@ -516,7 +524,7 @@ static int solve_increment_impl(const orc_problem& pb, double* F, const double* 
     status = law_stress(pb, Fc.data(), Pc.data(), hn.empty() ? nullptr : hn.data());
     if (status != ORC_OK) break;
     for (long i = 0; i < m; ++i) Y[i] = Pc[i];
-    orc_project(n0, n1, n2, Pc.data(), b.data());
+    orc_project_nyq(n0, n1, n2, Pc.data(), b.data(), pb.nyq);
     for (long i = 0; i < m; ++i) b[i] = -b[i];
     const double res = std::sqrt(dot(dF.data(), dF.data(), m)) / Fn;
     st->newton_res[it] = res;
@@ -547,7 +555,16 @@ static int solve_increment_impl(const orc_problem& pb, double* F, const double* 
 int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* mu, double* F,
                         const double* Fbar, double eta_nw, double eta_cg, int max_newton, int max_cg,
                         double* P, double* Pbar, orc_stats* st) {
-  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr};
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0};
+  return solve_increment_impl(pb, F, Fbar, eta_nw, eta_cg, max_newton, max_cg, P, Pbar, nullptr, st);
+}
+
+// The same increment with the projection's Nyquist choice nyq_identity (App. C;
+// see orc_project_nyq): 1 solves with G-hat = identity at Nyquist frequencies.
+int orc_solve_increment_nyq(int n0, int n1, int n2, const double* K, const double* mu, double* F,
+                            const double* Fbar, double eta_nw, double eta_cg, int max_newton, int max_cg,
+                            double* P, double* Pbar, orc_stats* st, int nyq_identity) {
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, nyq_identity ? 1 : 0};
   return solve_increment_impl(pb, F, Fbar, eta_nw, eta_cg, max_newton, max_cg, P, Pbar, nullptr, st);
 }
 
@@ -558,7 +575,7 @@ int orc_solve_increment_j2(int n0, int n1, int n2, const double* K, const double
                            double eta_cg, int max_newton, int max_cg, double* P, double* Pbar, orc_stats* st) {
   const long n = (long)n0 * n1 * n2;
   std::vector<double> h0(hist, hist + 7 * n);
-  orc_problem pb{n0, n1, n2, K, mu, 1, ty0, H, h0.data()};
+  orc_problem pb{n0, n1, n2, K, mu, 1, ty0, H, h0.data(), 0};
   return solve_increment_impl(pb, F, Fbar, eta_nw, eta_cg, max_newton, max_cg, P, Pbar, hist, st);
 }
 
@@ -581,7 +598,7 @@ int orc_solve_increment_j2(int n0, int n1, int n2, const double* K, const double
 int orc_adjoint(int n0, int n1, int n2, const double* K, const double* mu, const double* F, const double* g,
                 double eta_cg, int max_cg, double* dLdmu, double* dLdK, int* iters) {
   const long n = (long)n0 * n1 * n2, m = 9 * n;
-  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr};
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0};
   std::vector<double> U(m), Y(m), b(m), w(m);
   for (int c = 0; c < 9; ++c)
     for (long v = 0; v < n; ++v) U[c * n + v] = g[c];
@@ -621,7 +638,7 @@ int orc_adjoint(int n0, int n1, int n2, const double* K, const double* mu, const
 // Exposed for tests: plain CG on the operator at a given linearisation point.
 int orc_cg(int n0, int n1, int n2, const double* K, const double* mu, const double* Flin, const double* b,
            double* x, double eta, int max_cg, int* iters, double* relres) {
-  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr};
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0};
   return cg_solve(pb, Flin, b, x, eta, max_cg, iters, relres);
 }
 
