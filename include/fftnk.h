@@ -122,8 +122,17 @@ int fftnk_set_modulus_field(fftnk_ctx* ctx, const double* mu_dev);
  * the default; 0 = launch every kernel), FFTNK_OPT_CHECK_EVERY (CG iterations
  * between two host checks of the convergence flags, 1..64, default 4).  Both
  * change timing only, never results.
+ * FFTNK_OPT_NYQUIST selects the value of G-hat at the Nyquist frequencies of
+ * even axes (App. C): 0 (default) zero there, which keeps F compatible; 1 the
+ * identity there, which keeps the stress equilibrated.  It applies to every
+ * cell and to every later call (projection, operator, solves, adjoint).  With
+ * 1 the operator acts on the Nyquist rotations F W (W skew) through the
+ * geometric stiffness only: singular at F = I and indefinite wherever the
+ * stress has a compressive direction, so CG may end in FFTNK_ECG_BREAKDOWN
+ * (typically under shear), and it converges more slowly under tension.
+ * Values other than 0 / 1 give FFTNK_EINVAL.
  */
-enum { FFTNK_OPT_GRAPHS = 1, FFTNK_OPT_CHECK_EVERY = 2 };
+enum { FFTNK_OPT_GRAPHS = 1, FFTNK_OPT_CHECK_EVERY = 2, FFTNK_OPT_NYQUIST = 3 };
 int fftnk_set_option(fftnk_ctx* ctx, int option, int value);
 
 /* F_t := I (and virgin history): the start state of Algorithm 1. */
@@ -164,7 +173,8 @@ int fftnk_apply_operator(fftnk_ctx* ctx, const void* p_dev, void* Ap_dev);
 /*
  * The compatibility projection alone (Sec. 2.5; App. C for even axes):
  * Ga = Re F^-1[ G-hat : F(a) ], (G-hat : A-hat)_ij = xi_j (sum_l xi_l A-hat_il)/|xi|^2,
- * zero at k = 0 and on every even axis' Nyquist index.  a, Ga: device
+ * zero at k = 0 and on every even axis' Nyquist index (the identity there
+ * with FFTNK_OPT_NYQUIST = 1).  a, Ga: device
  * [9][n] in context precision; may alias.
  */
 int fftnk_project(fftnk_ctx* ctx, const void* a_dev, void* Ga_dev);

@@ -109,10 +109,12 @@ struct fftnk_ctx {
   int nblk[NKIND] = {};
   size_t lds[8] = {};  // row64, row32, col1_64, col1_32, col0_64, col0_32, row1_64, row1_32
   int eng[3] = {};     // per axis: bit 0 some cell on the LDS engine, bit 1 on the 8-point, bit 2 on the 12-point one
+  int nyq_id = 0;      // FFTNK_OPT_NYQUIST
   // workspace layout (byte offsets)
   size_t o_hist, o_hnew;  // J2 history: committed and of the current iterate, [7][ntot] each
   size_t o_Ft, o_F, o_P, o_x, o_r, o_p, o_w, o_F32, o_d64, o_spec, o_phase, o_mu, o_mtab, o_part, o_cg, o_red,
-      o_tw64, o_tw32, o_grids, o_starts, o_active, o_uni, total = 0;
+      o_tw64, o_tw32, o_grids, o_starts, o_active, o_uni, o_nyq, total = 0;
+  long long rows_total = 0;
   char* ws = nullptr;
   bool have_phase = false, have_mat = false, use_mu = false;
   int model = MODEL_SVK, nphase = 0;
@@ -155,6 +157,7 @@ struct fftnk_ctx {
     L.b.tw32 = ws + o_tw32;
     L.b.partials = at<double>(o_part);
     L.b.pstride = pstride;
+    L.b.nyq = ws + o_nyq;
     L.b.nrve = nrve;
     for (int k = 0; k < NKIND; ++k) L.nblk[k] = nblk[k];
     L.lds_row64 = lds[0];
@@ -166,6 +169,7 @@ struct fftnk_ctx {
     L.lds_row1_64 = lds[6];
     L.lds_row1_32 = lds[7];
     for (int d = 0; d < 3; ++d) L.eng[d] = eng[d];
+    L.nyq = nyq_id;
     L.s = s;
     return L;
   }
@@ -220,7 +224,7 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
   c->nrve = nrve;
   c->prec = precision == FFTNK_FP64 ? PREC_F64 : PREC_F32;
   c->stream = static_cast<hipStream_t>(stream);
-  long long vox = 0, spec = 0;
+  long long vox = 0, spec = 0, rows = 0;
   for (int r = 0; r < nrve; ++r) {
     Grid g{};
     g.n0 = dims[3 * r];
@@ -236,6 +240,7 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
     g.rows = (long long)g.n0 * g.n1;
     g.vox_off = vox;
     g.spec_off = spec;
+    g.row_off = rows;
     g.inv_n = 1.0 / (double)g.n;
     // grid lines per a2 work-group: register engine, 5 pair pencils per line on
     // kThreads / (n2/P) pencil slots, within 48 KiB of FP64 LDS (5 rt pencils +
@@ -256,10 +261,12 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
     g.m32 = pick_m(g.h, nmax, 8, 16);
     vox += g.n;
     spec += 9LL * g.rows * g.h;
+    rows += g.rows;
     c->g.push_back(g);
   }
   c->ntot = vox;
   c->nspec = spec;
+  c->rows_total = rows;
   // launch geometry: work-group ranges of every RVE per launch kind
   c->starts.assign((size_t)NKIND * (nrve + 1), 0);
   for (int k = 0; k < NKIND; ++k) {
@@ -345,6 +352,7 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
   c->o_starts = take(c->starts.size() * sizeof(int));
   c->o_active = take((size_t)nrve * sizeof(int));
   c->o_uni = take((size_t)nrve * 9 * sizeof(double));
+  c->o_nyq = take(9 * (size_t)rows * sizeof(double));
   c->total = o;
   c->active.assign(nrve, 1);
   c->uni.assign(9 * (size_t)nrve, 0.0);
@@ -612,6 +620,18 @@ int fftnk_set_option(fftnk_ctx* c, int option, int value) {
     case FFTNK_OPT_CHECK_EVERY:
       if (value < 1 || value > 64) return FFTNK_EINVAL;
       c->check_every = value;
+      return FFTNK_OK;
+    case FFTNK_OPT_NYQUIST:
+      if (value != 0 && value != 1) return FFTNK_EINVAL;
+      if (value == c->nyq_id) return FFTNK_OK;
+      c->nyq_id = value;
+      for (Grid& g : c->g) g.nyq_id = value;
+      drop_graphs(c);  // the graphs hold the pass-3 variant
+      if (c->ws) {
+        HIP_TRY(hipMemcpyAsync(c->ws + c->o_grids, c->g.data(), c->g.size() * sizeof(Grid), hipMemcpyHostToDevice,
+                               c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+      }
       return FFTNK_OK;
     default: return FFTNK_EINVAL;
   }

@@ -69,6 +69,29 @@ __device__ __forceinline__ void tangent_at(const Material& mat, long long gv, co
   }
 }
 
+// Identity choice at Nyquist frequencies (App. C) on an even a2 axis: the a2
+// Nyquist plane is not stored, and G-hat = identity there makes its round trip
+// through passes 2-4 return every line's own coefficient times n0 n1 / n.  So
+// pass 1 keeps z = Z[n2 / 2] of a pencil (real parts: the coefficients of the
+// pair's two components, both real) divided by n2, and pass 5 puts it back.
+template <typename T, typename G>
+__device__ __forceinline__ void put_nyquist(const Batch& B, const G& g, long long row, int pq, cx<T> z) {
+  T* ny = static_cast<T*>(B.nyq) + 9 * g.row_off + row;
+  const T s = (T)1 / (T)g.n2;
+  if (pq == 4) {
+    ny[8 * g.rows] = s * z.x;
+  } else {
+    ny[(2 * pq) * g.rows] = s * z.x;
+    ny[(2 * pq + 1) * g.rows] = s * z.y;
+  }
+}
+template <typename T, typename G>
+__device__ __forceinline__ cx<T> get_nyquist(const Batch& B, const G& g, long long row, int pq) {
+  const T* ny = static_cast<const T*>(B.nyq) + 9 * g.row_off + row;
+  if (pq == 4) return cx<T>{ny[8 * g.rows], (T)0};
+  return cx<T>{ny[(2 * pq) * g.rows], ny[(2 * pq + 1) * g.rows]};
+}
+
 template <typename T, int MODE, int LAW, int ENG>
 __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat, const T* __restrict__ in,
                                             const T* __restrict__ rvec, T* __restrict__ pvec, T* __restrict__ xvec,
@@ -203,6 +226,8 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
           S[(2 * pq + 1) * srow + row * H + k] = cx<T>{(T)0.5 * (z.y + zm.y), (T)-0.5 * (z.x - zm.x)};
         }
       }
+      // lane 0 holds k = n2 / 2 at q = P / 2: the two real Nyquist coefficients
+      if (g.nyq_id && t == 0) put_nyquist<T>(B, g, row, pq, v[P / 2]);
     }
     double res[1];
     block_sums<1>(acc, res);
@@ -229,6 +254,13 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
       o = cx<T>{(T)0.5 * (z.y + zm.y), (T)-0.5 * (z.x - zm.x)};
     }
     S[c * srow + row * H + k] = o;
+  }
+  if (g.nyq_id && (N2 & 1) == 0) {
+    for (int t = threadIdx.x; t < npen; t += kThreads) {
+      const int pq = t / RT, rl = t - pq * RT;
+      const long long row = row0 + rl;
+      if (row < g.rows) put_nyquist<T>(B, g, row, pq, Z[t * N2 + N2 / 2]);
+    }
   }
   double res[1];
   block_sums<1>(acc, res);
@@ -318,18 +350,26 @@ __global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict_
 // G-hat_ijlm = delta_im g_jl (App. D), so row i of the projected field needs
 // row i of the input only.  G-hat (Sec. 2.5; App. C for even axes):
 //   out_ij = xi_j (sum_l xi_l A_il) / |xi|^2 / n,   xi_d = k_d / N_d,
-// zero at k = 0 and whenever an even axis sits at its Nyquist index.  The 1/n
-// of the inverse transform is folded in here.
+// zero at k = 0 and whenever an even axis sits at its Nyquist index (or, with
+// the identity choice of App. C, the identity there).  The 1/n of the inverse
+// transform is folded in here.
 // ---------------------------------------------------------------------------
 
+// One frequency of the projection with the identity choice at Nyquist
+// frequencies (the a2 index of the stored half spectrum is never Nyquist).
 template <typename T, typename G>
 __device__ __forceinline__ void project_point(cx<T>& a0, cx<T>& a1, cx<T>& a2, int k0, int k1, int k2,
                                               const G& g, T rn0, T rn1, T rn2 /* 1 / N_d */) {
   const int f0 = signed_freq(k0, g.n0), f1 = signed_freq(k1, g.n1);
-  const bool zero = (f0 == 0 && f1 == 0 && k2 == 0) || ((g.n0 % 2 == 0) && (2 * k0 == g.n0)) ||
-                    ((g.n1 % 2 == 0) && (2 * k1 == g.n1));
-  if (zero) {
+  if (f0 == 0 && f1 == 0 && k2 == 0) {
     a0 = a1 = a2 = cx<T>{(T)0, (T)0};
+    return;
+  }
+  if (((g.n0 % 2 == 0) && (2 * k0 == g.n0)) || ((g.n1 % 2 == 0) && (2 * k1 == g.n1))) {
+    const T s = (T)g.inv_n;
+    a0 = cscale(a0, s);
+    a1 = cscale(a1, s);
+    a2 = cscale(a2, s);
     return;
   }
   const T xi0 = (T)f0 * rn0, xi1 = (T)f1 * rn1, xi2 = (T)k2 * rn2;
@@ -514,17 +554,134 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
   }
 }
 
+// Pass 3 with the identity choice at Nyquist frequencies (App. C): there the
+// three components of a row are kept apart, so the two-transform shortcut
+// above does not apply; three forward transforms, the projection point by
+// point, three inverse transforms.  Same tiles as the default variant.
 template <typename T, int ENG>
+__device__ __forceinline__ void tile_col_a0_project_id(const Batch& B, cx<T>* __restrict__ spec,
+                                                       const CgState* __restrict__ cg, const int b) {
+  int local;
+  const int rv = find_rve(B, sizeof(T) == 8 ? K_COL0_64 : K_COL0_32, b, local);
+  if (skip_rve(B, cg, rv)) return;
+  const auto& g = grid_of(B, rv);
+  if (g.ax[0].reg != ENG) return;  // another engine's launch owns this cell
+  extern __shared__ unsigned char smem_raw[];
+  const int N0 = g.n0, N1 = g.n1, H = g.h;
+  cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
+  load_twiddles<T>(tw, B, g.ax[0].tw, N0);
+  cx<T>* S0 = spec + g.spec_off;
+  const long long S = (long long)N1 * H;  // element stride along a0
+  const long long cstride = g.rows * H;
+  const T rn0 = (T)1 / (T)N0, rn1 = (T)1 / (T)N1, rn2 = (T)1 / (T)g.n2;
+
+  if constexpr (ENG != 0) {
+    constexpr int P = ENG;
+    cx<T>* xl = tw + padded_len(N0);
+    const int Tp = N0 / P, Mb = kThreads / Tp;
+    const int m = threadIdx.x % Mb, t = threadIdx.x / Mb;
+    const long long npen = 3LL * N1 * H;
+    long long pen = (long long)local * Mb + m;
+    const bool valid = pen < npen;
+    if (!valid) pen = 0;
+    const long long qq = pen / H;
+    const int k2 = (int)(pen - qq * H);
+    const int i = (int)(qq / N1), k1 = (int)(qq - (long long)i * N1);
+    cx<T>* p0 = S0 + (long long)(3 * i) * cstride + (long long)k1 * H + k2 + (long long)t * S;
+    cx<T> v[3][P];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int q = 0; q < P; ++q) v[c][q] = valid ? p0[c * cstride + (long long)q * Tp * S] : cx<T>{(T)0, (T)0};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) reg_fft<T, false, P>(v[c], N0, t, tw, false, xl + m);
+#pragma unroll
+    for (int q = 0; q < P; ++q) project_point(v[0][q], v[1][q], v[2][q], t + Tp * q, k1, k2, g, rn0, rn1, rn2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) reg_fft<T, false, P>(v[c], N0, t, tw, true, xl + m);
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < P; ++q) p0[c * cstride + (long long)q * Tp * S] = v[c][q];
+    }
+    return;
+  }
+
+  const int M = sizeof(T) == 8 ? g.m64 : g.m32;
+  cx<T>* bufA = tw + padded_len(N0);
+  cx<T>* bufB = bufA + N0 * M;
+  const int nkb = (H + M - 1) / M;
+  const int i = local / (N1 * nkb);
+  const int rem = local - i * N1 * nkb;
+  const int k1 = rem / nkb, kb = rem - k1 * nkb;
+  const int Mt = min(M, H - kb * M);
+  const int total = N0 * M;
+  cx<T>* b0 = S0 + (long long)k1 * H + kb * M + (long long)(3 * i) * cstride;
+  cx<T> r[3][kMaxPpt];
+#pragma unroll
+  for (int pt = 0; pt < kMaxPpt; ++pt) {
+    const int t = threadIdx.x + pt * kThreads;
+    const int e = t / M, m = t - e * M;
+    const bool ok = t < total && m < Mt;
+    const long long o = ok ? (long long)e * S + m : 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[c][pt] = ok ? b0[c * cstride + o] : cx<T>{(T)0, (T)0};
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int pt = 0; pt < kMaxPpt; ++pt) {
+      const int t = threadIdx.x + pt * kThreads;
+      if (t < total) bufA[t] = r[c][pt];
+    }
+    __syncthreads();
+    const cx<T>* Rz = fft_lds<T>(bufA, bufB, g.ax[0], M, 1, M, tw, false, true);
+#pragma unroll
+    for (int pt = 0; pt < kMaxPpt; ++pt) {
+      const int t = threadIdx.x + pt * kThreads;
+      if (t < total) r[c][pt] = Rz[t];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int pt = 0; pt < kMaxPpt; ++pt) {
+    const int t = threadIdx.x + pt * kThreads;
+    const int k0 = t / M, m = t - k0 * M;
+    if (t < total && m < Mt) project_point(r[0][pt], r[1][pt], r[2][pt], k0, k1, kb * M + m, g, rn0, rn1, rn2);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int pt = 0; pt < kMaxPpt; ++pt) {
+      const int t = threadIdx.x + pt * kThreads;
+      if (t < total) bufA[t] = r[c][pt];
+    }
+    __syncthreads();
+    const cx<T>* Rz = fft_lds<T>(bufA, bufB, g.ax[0], M, 1, M, tw, true, true);
+    for (int t = threadIdx.x; t < total; t += kThreads) {
+      const int e = t / M, m = t - e * M;
+      if (m < Mt) b0[c * cstride + (long long)e * S + m] = Rz[t];
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int ENG, bool NYQ_ID>
 __global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* __restrict__ spec,
                                                              const CgState* __restrict__ cg) {
-  tile_col_a0_project<T, ENG>(B, spec, cg, blockIdx.x);
+  if constexpr (NYQ_ID)
+    tile_col_a0_project_id<T, ENG>(B, spec, cg, blockIdx.x);
+  else
+    tile_col_a0_project<T, ENG>(B, spec, cg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // Pass 5: the a2 inverse (complex-to-real) transform.  The half spectra of a
 // component pair are recombined as Z = X + iY over the full line using the
 // Hermitian symmetry of real fields (X[-k] = conj X[k]; the k = 0 values are
-// taken real; an even line's Nyquist entry is zero), transformed back, and
+// taken real; an even line's Nyquist entry is zero, or what pass 1 kept for
+// the identity choice at Nyquist frequencies), transformed back, and
 // Re / Im give the two real components.
 // ---------------------------------------------------------------------------
 template <typename T, int MODE, typename TO, int ENG>
@@ -563,7 +720,8 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
     // of k < h = n2 / 2, each entry once, addresses clamped into the cell).
     // The upper half k = n2 - k' needs conj X[k'], held by lane (Tp - t) mod Tp
     // of the same pencil at q' = P - 1 - q (lane 0 holds its own at
-    // q' = P - q; q = P / 2 is the Nyquist index, zero).
+    // q' = P - q; q = P / 2 is the Nyquist index: zero, or with the identity
+    // choice the coefficient pass 1 kept).
     constexpr int P2 = P / 2;
     const cx<T>* SX = S + c0 * srow + (valid ? row : row0) * H;
     const cx<T>* SY = pq < 4 ? SX + srow : SX;
@@ -582,6 +740,9 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
       v[q] = valid ? cx<T>{X[q].x - yi, xi + yon * Y[q].x} : cx<T>{(T)0, (T)0};
     }
     const int src = (Tp - t) & (Tp - 1);
+    // lane 0's Nyquist entry: zero, or the kept coefficients (identity choice)
+    cx<T> zn = {(T)0, (T)0};
+    if (g.nyq_id && t == 0 && valid) zn = get_nyquist<T>(B, g, row, pq);
 #pragma unroll
     for (int q = P2; q < P; ++q) {
       cx<T> xm, ym;
@@ -590,8 +751,8 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
       ym.x = __shfl(Y[P - 1 - q].x, src, Tp);
       ym.y = __shfl(Y[P - 1 - q].y, src, Tp);
       if (t == 0) {
-        xm = q == P2 ? cx<T>{(T)0, (T)0} : X[q == P2 ? 0 : P - q];
-        ym = q == P2 ? cx<T>{(T)0, (T)0} : Y[q == P2 ? 0 : P - q];
+        xm = q == P2 ? cx<T>{zn.x, (T)0} : X[q == P2 ? 0 : P - q];
+        ym = q == P2 ? cx<T>{zn.y, (T)0} : Y[q == P2 ? 0 : P - q];
       }
       const T xi = -xm.y, yi = -yon * ym.y;  // conjugated
       v[q] = valid ? cx<T>{xm.x - yi, xi + yon * ym.x} : cx<T>{(T)0, (T)0};
@@ -662,6 +823,8 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
         Y.y = -Y.y;
       }
       z = cx<T>{X.x - Y.y, X.y + Y.x};
+    } else if (row < g.rows && g.nyq_id) {
+      z = get_nyquist<T>(B, g, row, q);
     }
     bufA[t] = z;
   }
@@ -807,8 +970,13 @@ static void col_a0_t(const Launch& L, void* spec, const CgState* cg) {
   const int ntiles = L.nblk[sizeof(T) == 8 ? K_COL0_64 : K_COL0_32];
   const size_t lds = sizeof(T) == 8 ? L.lds_col0_64 : L.lds_col0_32;
   cx<T>* sp = static_cast<cx<T>*>(spec);
-  if (L.eng[0] & 2) launch_tiles(&k_col_a0_project<T, 8>, ntiles, lds, L.s, L.b, sp, cg);
-  if (L.eng[0] & 1) launch_tiles(&k_col_a0_project<T, 0>, ntiles, lds, L.s, L.b, sp, cg);
+  if (L.nyq) {
+    if (L.eng[0] & 2) launch_tiles(&k_col_a0_project<T, 8, true>, ntiles, lds, L.s, L.b, sp, cg);
+    if (L.eng[0] & 1) launch_tiles(&k_col_a0_project<T, 0, true>, ntiles, lds, L.s, L.b, sp, cg);
+    return;
+  }
+  if (L.eng[0] & 2) launch_tiles(&k_col_a0_project<T, 8, false>, ntiles, lds, L.s, L.b, sp, cg);
+  if (L.eng[0] & 1) launch_tiles(&k_col_a0_project<T, 0, false>, ntiles, lds, L.s, L.b, sp, cg);
 }
 
 void launch_col_a0_project(int prec, const Launch& L, void* spec, const CgState* cg) {

@@ -51,10 +51,12 @@ struct Grid {
   long long rows;   // n0 * n1 grid lines along a2
   long long vox_off;
   long long spec_off;
+  long long row_off;  // grid lines of the cells before this one (Nyquist side buffer)
   double inv_n;
   int rt;           // grid lines per work-group in the a2 inverse pass
   int rt1;          // grid lines per work-group in the a2 forward pass (rt1 * n2 <= kThreads)
   int m64, m32;     // pencils per work-group in the LDS-engine a1 / a0 passes (FP64 / FP32)
+  int nyq_id;       // G-hat at Nyquist frequencies: 0 zero, 1 identity (App. C)
   AxisPlan ax[3];
 };
 
@@ -130,6 +132,11 @@ struct Batch {
   const void* tw32;     // float2 twiddle tables
   double* partials;     // [NSLOT][pstride]
   long long pstride;
+  // identity choice at Nyquist frequencies, even n2: the a2 Nyquist coefficient
+  // of every grid line, divided by n2 (pass 1 writes it, pass 5 adds it back;
+  // the half spectrum never holds that plane).  Elements of the field type,
+  // cell block at 9 row_off, component c of line l at c rows + l.
+  void* nyq;
   int nrve;
 };
 
@@ -167,6 +174,7 @@ struct Launch {
   int nblk[NKIND];
   size_t lds_row64, lds_row32, lds_col1_64, lds_col1_32, lds_col0_64, lds_col0_32, lds_row1_64, lds_row1_32;
   int eng[3];  // per grid axis: bit 0 some cell transforms it with the LDS engine, bit 1 / 2 with the 8- / 12-point register engine
+  int nyq;     // 1: the cells use the identity choice at Nyquist frequencies (pass 3 variant)
   hipStream_t s;
 };
 void launch_fwd_a2(int prec, int mode, const Launch& L, const Material& mat, const void* in_T, const void* r_T,

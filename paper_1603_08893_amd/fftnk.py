@@ -16,7 +16,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "li
 OK, EINVAL, ESTATE, ENOMEM, EHIP, ECG_MAXIT, ECG_BREAKDOWN, ENEWTON_MAXIT, ENONFINITE, EMATERIAL, EUNSUPPORTED = range(11)
 FP64, FP32_MIXED = 0, 1
 SVK, J2 = 0, 1
-OPT_GRAPHS, OPT_CHECK_EVERY = 1, 2
+OPT_GRAPHS, OPT_CHECK_EVERY, OPT_NYQUIST = 1, 2, 3
 MAX_SOLVES = 64
 
 # every symbol include/fftnk.h declares
@@ -186,7 +186,8 @@ class Solver:
         _check(lib().fftnk_set_modulus_field(self.ctx, ctypes.c_void_p(t.data_ptr())), "fftnk_set_modulus_field")
 
     def set_option(self, option, value):
-        """OPT_GRAPHS (replay CG iterations from HIP graphs) or OPT_CHECK_EVERY."""
+        """OPT_GRAPHS (replay CG iterations from HIP graphs), OPT_CHECK_EVERY, or
+        OPT_NYQUIST (0: G-hat zero at Nyquist frequencies, 1: identity there)."""
         _check(lib().fftnk_set_option(self.ctx, int(option), int(value)), "fftnk_set_option")
 
     def reset_state(self):

@@ -1,0 +1,142 @@
+"""Parity of the identity choice at Nyquist frequencies (App. C) with the
+oracle, through the C-ABI (FFTNK_OPT_NYQUIST = 1).
+
+Kernel level: the projection and the projected-tangent operator on shapes that
+put even axes on every engine (8-point and 12-point register engines, LDS
+engine; even a0 only, even a1 only, even a2 only: the a2 Nyquist coefficients
+travel through the side buffer of passes 1 and 5), single and batched cells,
+FP64 (relative L2 <= 1e-13) and FP32 (<= 5e-6).  Switching the option back
+gives the default projection again.
+
+Solve level: one tensile increment, FP64 (P-bar within 1e-10 relative, equal
+Newton counts) and FP32-mixed (P-bar within 1e-5); a shear increment, where the
+operator becomes indefinite with this choice, ends in a CG breakdown on both
+sides with the committed state untouched.
+"""
+import numpy as np
+import pytest
+
+from paper_1603_08893_amd import microstructure as ms
+
+pytestmark = pytest.mark.gpu
+
+TABLE = [(ms.K_SOFT, ms.MU_SOFT), (ms.K_HARD, ms.MU_HARD)]
+TENSION = np.array([[1.03, 0.004, 0.0], [0.002, 1.02, 0.003], [0.0, -0.002, 1.025]]).reshape(9)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _solver(dims, prec, phase, table=TABLE, nyq=1):
+    from paper_1603_08893_amd.fftnk import OPT_NYQUIST, Solver
+    s = Solver(dims, precision=prec)
+    s.set_phases(phase)
+    s.set_material(table)
+    s.set_option(OPT_NYQUIST, nyq)
+    return s
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+SHAPES = [(8, 8, 8), (64, 64, 64), (24, 24, 24), (12, 10, 16), (7, 6, 9), (6, 7, 9), (5, 5, 8), (48, 40, 36),
+          (3, 64, 4), (10, 48, 12), (6, 12, 96), (4, 6, 192), (2, 2, 2)]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_project_identity_choice(torch_cuda, orc, shape, prec, tol):
+    torch = torch_cuda
+    print("project nyq", shape, prec, flush=True)
+    A = ms.random_field(shape, seed=sum(shape) + 1)
+    ref = orc.project(A, nyq_identity=True)
+    s = _solver(shape, prec, np.zeros(shape, dtype=np.uint8))
+    got = s.project(torch.from_numpy(A.reshape(-1))).double().cpu().numpy()
+    assert _rel(got, ref) <= tol
+    from paper_1603_08893_amd.fftnk import OPT_NYQUIST
+    s.set_option(OPT_NYQUIST, 0)
+    got0 = s.project(torch.from_numpy(A.reshape(-1))).double().cpu().numpy()
+    assert _rel(got0, orc.project(A)) <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])
+@pytest.mark.parametrize("shape", [(8, 8, 8), (24, 24, 24), (12, 10, 16), (6, 12, 96), (32, 32, 32)])
+def test_apply_operator_identity_choice(torch_cuda, orc, shape, prec, tol):
+    torch = torch_cuda
+    print("apply_operator nyq", shape, prec, flush=True)
+    rng = np.random.default_rng(17)
+    ph = rng.integers(0, 2, size=shape).astype(np.uint8)
+    K, mu = ms.phase_moduli(ph, TABLE)
+    F = ms.near_identity_field(shape, seed=13, scale=0.05)
+    p = ms.random_field(shape, seed=14)
+    ref = orc.project(orc.svk_tangent(F, K, mu, p), nyq_identity=True)
+    s = _solver(shape, prec, ph)
+    s.set_linearization(torch.from_numpy(F.reshape(-1)))
+    got = s.apply_operator(torch.from_numpy(p.reshape(-1))).double().cpu().numpy()
+    assert _rel(got, ref) <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])
+def test_project_identity_choice_batched(torch_cuda, orc, prec, tol):
+    torch = torch_cuda
+    dims = [(8, 8, 8), (6, 10, 12), (5, 7, 9), (16, 16, 16)]
+    print("project nyq batched", dims, prec, flush=True)
+    fields = [ms.random_field(d, seed=31 + r) for r, d in enumerate(dims)]
+    ph = np.zeros(sum(int(np.prod(d)) for d in dims), dtype=np.uint8)
+    s = _solver(dims, prec, ph)
+    flat = np.concatenate([f.reshape(-1) for f in fields])
+    got = s.project(torch.from_numpy(flat)).double().cpu().numpy()
+    off = 0
+    for d, f in zip(dims, fields):
+        m = 9 * int(np.prod(d))
+        assert _rel(got[off:off + m], orc.project(f, nyq_identity=True)) <= tol, d
+        off += m
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_tension_identity_choice(torch_cuda, orc, prec):
+    torch = torch_cuda
+    shape = (16, 16, 16)
+    print("solve nyq tension", shape, prec, flush=True)
+    rng = np.random.default_rng(1603)
+    ph = (rng.random(shape) < 0.3).astype(np.uint8)
+    K, mu = ms.phase_moduli(ph, TABLE)
+    st, Fo, Po, Pbo, So = orc.solve_increment(K, mu, orc.identity_field(shape), TENSION, 1e-5, 1e-8,
+                                              nyq_identity=True)
+    assert st == 0
+    s = _solver(shape, prec, ph)
+    stg, F, P, Pb, S = s.solve_increment(TENSION, 1e-5, 1e-8)
+    print("oracle", So["cg_iters"], "gpu", S[0]["cg_iters"], flush=True)
+    if prec == "fp64":
+        assert S[0]["n_solves"] == So["n_solves"]
+        assert np.max(np.abs(Pb[0] - Pbo)) <= 1e-10 * np.max(np.abs(Pbo))
+        assert _rel(F.cpu().numpy(), Fo) <= 1e-10
+    else:
+        assert np.max(np.abs(Pb[0] - Pbo)) <= 1e-5 * np.max(np.abs(Pbo))
+    # equilibrium in the identity choice's sense: G(P) = 0, here via the GPU projection
+    GP = s.project(P).double().cpu().numpy()
+    assert np.linalg.norm(GP) <= (1e-9 if prec == "fp64" else 1e-4) * np.linalg.norm(P.cpu().numpy())
+
+
+def test_shear_breaks_down_with_identity_choice(torch_cuda, orc):
+    torch = torch_cuda
+    shape = (8, 8, 8)
+    print("solve nyq shear", shape, flush=True)
+    rng = np.random.default_rng(2)
+    ph = rng.integers(0, 2, size=shape).astype(np.uint8)
+    K, mu = ms.phase_moduli(ph, TABLE)
+    st, *_ = orc.solve_increment(K, mu, orc.identity_field(shape), ms.simple_shear(0.05), 1e-5, 1e-8,
+                                 nyq_identity=True)
+    assert st == 2  # the oracle's CG breakdown
+    from paper_1603_08893_amd import fftnk
+    s = _solver(shape, "fp64", ph)
+    before = s.get_state().cpu().numpy()
+    stg, F, P, Pb, S = s.solve_increment(ms.simple_shear(0.05), 1e-5, 1e-8, raise_on_error=False)
+    assert stg == fftnk.ECG_BREAKDOWN
+    assert np.array_equal(s.get_state().cpu().numpy(), before)
