@@ -84,6 +84,17 @@ def lib():
         L.orc_solve_increment_nyq.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                               i, i, dp, dp, ctypes.POINTER(Stats), i]
         L.orc_solve_increment_nyq.restype = i
+        ip = ctypes.POINTER(i)
+        L.orc_macro_tangent.argtypes = [i, i, i, dp, dp, dp, ip, ctypes.c_double, i, dp]
+        L.orc_macro_tangent.restype = i
+        L.orc_solve_increment_mixed.argtypes = [i, i, i, dp, dp, dp, dp, ip, dp, ctypes.c_double, i,
+                                                ctypes.c_double, ctypes.c_double, i, i, dp, dp,
+                                                ctypes.POINTER(Stats), ip]
+        L.orc_solve_increment_mixed.restype = i
+        L.orc_solve_increment_mixed_j2.argtypes = [i, i, i, dp, dp, dp, dp, dp, dp, dp, ip, dp, ctypes.c_double,
+                                                   i, ctypes.c_double, ctypes.c_double, i, i, dp, dp,
+                                                   ctypes.POINTER(Stats), ip]
+        L.orc_solve_increment_mixed_j2.restype = i
         L.orc_adjoint.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, i, dp, dp, ctypes.POINTER(i)]
         L.orc_adjoint.restype = i
         L.orc_jacobi_eig3.argtypes = [dp, dp, dp]
@@ -244,6 +255,71 @@ def solve_increment(K, mu, F, Fbar, eta_nw=1e-5, eta_cg=1e-8, max_newton=50, max
                                            eta_nw, eta_cg, max_newton, max_cg, _p(P), _p(Pbar),
                                            ctypes.byref(st), 1 if nyq_identity else 0)
     return status, F, P, Pbar, st.as_dict()
+
+
+# ---------------------------------------------------------------- mixed control
+def _mask(mask):
+    m = np.ascontiguousarray(np.asarray(mask).reshape(9) != 0, dtype=np.int32)
+    return m, m.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def macro_tangent(K, mu, F, want=None, eta_cg=1e-10, max_cg=10000):
+    """C[i, m] = dPbar_i / dFbar_m at the equilibrium F (columns with want[m]).
+
+    Returns (status, C) with C a 9 x 9 array (unrequested columns zero)."""
+    F = _c(F)
+    grid = F.shape[1:]
+    K = _c(np.broadcast_to(K, grid))
+    mu = _c(np.broadcast_to(mu, grid))
+    w, wp = _mask(np.ones(9) if want is None else want)
+    C = np.zeros(81)
+    st = lib().orc_macro_tangent(grid[0], grid[1], grid[2], _p(K), _p(mu), _p(F), wp, eta_cg, max_cg, _p(C))
+    return st, C.reshape(9, 9)
+
+
+def solve_increment_mixed(K, mu, F, Fbar, mask, Ptarget, tol_stress=1e-10, max_outer=20, eta_nw=1e-5,
+                          eta_cg=1e-8, max_newton=50, max_cg=10000):
+    """One increment under mixed control: Pbar_m = Ptarget_m where mask[m], Fbar_m
+    elsewhere (Fbar's masked entries: the starting guess).
+
+    Returns (status, F_new, P, Pbar, Fbar_solution, stats, outer_iterations)."""
+    F = np.array(F, dtype=np.float64, copy=True, order="C")
+    grid = F.shape[1:]
+    K = _c(np.broadcast_to(K, grid))
+    mu = _c(np.broadcast_to(mu, grid))
+    Fb = np.array(np.asarray(Fbar, dtype=np.float64).reshape(9), copy=True)
+    Pt = _c(np.asarray(Ptarget, dtype=np.float64).reshape(9))
+    m, mp = _mask(mask)
+    P = np.zeros_like(F)
+    Pbar = np.zeros(9)
+    st = Stats()
+    outer = ctypes.c_int(0)
+    status = lib().orc_solve_increment_mixed(grid[0], grid[1], grid[2], _p(K), _p(mu), _p(F), _p(Fb), mp, _p(Pt),
+                                             tol_stress, max_outer, eta_nw, eta_cg, max_newton, max_cg, _p(P),
+                                             _p(Pbar), ctypes.byref(st), ctypes.byref(outer))
+    return status, F, P, Pbar, Fb, st.as_dict(), outer.value
+
+
+def solve_increment_mixed_j2(K, mu, ty0, H, hist, F, Fbar, mask, Ptarget, tol_stress=1e-10, max_outer=20,
+                             eta_nw=1e-5, eta_cg=1e-8, max_newton=50, max_cg=10000):
+    """Mixed control with the J2 law.  Returns (status, F, P, Pbar, Fbar, hist_new, stats, outer)."""
+    F = np.array(F, dtype=np.float64, copy=True, order="C")
+    grid = F.shape[1:]
+    b = lambda a: _c(np.broadcast_to(a, grid))
+    K, mu, ty0, H = b(K), b(mu), b(ty0), b(H)
+    hist = np.array(hist, dtype=np.float64, copy=True, order="C")
+    Fb = np.array(np.asarray(Fbar, dtype=np.float64).reshape(9), copy=True)
+    Pt = _c(np.asarray(Ptarget, dtype=np.float64).reshape(9))
+    m, mp = _mask(mask)
+    P = np.zeros_like(F)
+    Pbar = np.zeros(9)
+    st = Stats()
+    outer = ctypes.c_int(0)
+    status = lib().orc_solve_increment_mixed_j2(grid[0], grid[1], grid[2], _p(K), _p(mu), _p(ty0), _p(H),
+                                                _p(hist), _p(F), _p(Fb), mp, _p(Pt), tol_stress, max_outer, eta_nw,
+                                                eta_cg, max_newton, max_cg, _p(P), _p(Pbar), ctypes.byref(st),
+                                                ctypes.byref(outer))
+    return status, F, P, Pbar, Fb, hist, st.as_dict(), outer.value
 
 
 # ---------------------------------------------------------------- J2 plasticity

@@ -580,6 +580,209 @@ int orc_solve_increment_j2(int n0, int n1, int n2, const double* K, const double
 }
 
 // ---------------------------------------------------------------------------
+// Macroscopic tangent and mixed macroscopic control (not in the paper: Sec. 3.1
+// prescribes the whole macroscopic deformation gradient and leaves other cases
+// to the literature).  Both are built from the boundary-condition system of
+// Sec. 3.1 and the operator of Sec. 2.6, unchanged.
+//
+// Macroscopic tangent at an equilibrium F: a uniform increment E_m of Fbar
+// (unit in component m) spreads as E_m + dF with G:K(F):dF = -G:K(F):E_m, the
+// boundary-condition solve; so with w the solution of A w = G(K(F):E_m),
+//     dPbar/dFbar[:, m] = mean( K(F) : (E_m - w) ).
+//
+// Mixed control: components m with mask[m] != 0 prescribe Pbar_m = Ptarget_m,
+// the others Fbar_m.  Outer Newton iteration on the masked entries of Fbar:
+//   solve the deformation-controlled increment at Fbar (Algorithm 1, started
+//   from the previous iterate's equilibrium, the load step's start state at
+//   first); R = Pbar_M - Ptarget_M; stop when max |R| <= tol_stress; else
+//   Fbar_M -= C_MM^{-1} R with C_MM the masked block of the macroscopic
+//   tangent at the current equilibrium.
+// ---------------------------------------------------------------------------
+
+static void mean9(const double* X, long n, double out[9]) {
+  for (int c = 0; c < 9; ++c) {
+    double s = 0.0, comp = 0.0;
+    for (long v = 0; v < n; ++v) {
+      const double y = X[c * n + v] - comp;
+      const double t = s + y;
+      comp = (t - s) - y;
+      s = t;
+    }
+    out[c] = s / (double)n;
+  }
+}
+
+// columns m with want[m] != 0 of C[i][m] = dPbar_i / dFbar_m at F; appends
+// the CG iteration counts to st (when given).  Returns a status.
+static int macro_tangent_impl(const orc_problem& pb, const double* F, const int* want, double C[81],
+                              double eta_cg, int max_cg, orc_stats* st) {
+  const long n = (long)pb.n0 * pb.n1 * pb.n2, m9 = 9 * n;
+  std::vector<double> U(m9), Y(m9), b(m9), w(m9), D(m9);
+  for (int m = 0; m < 9; ++m) {
+    if (!want[m]) continue;
+    for (int c = 0; c < 9; ++c)
+      for (long v = 0; v < n; ++v) U[c * n + v] = (c == m) ? 1.0 : 0.0;
+    law_tangent(pb, F, U.data(), Y.data());
+    orc_project_nyq(pb.n0, pb.n1, pb.n2, Y.data(), b.data(), pb.nyq);
+    int it = 0;
+    double rel = 0.0;
+    const int s = cg_or_zero(pb, F, b.data(), Y.data(), w.data(), eta_cg, max_cg, &it, &rel);
+    if (st && st->n_solves < ORC_MAX_SOLVES) {
+      st->cg_iters[st->n_solves] = it;
+      st->cg_relres[st->n_solves] = rel;
+      ++st->n_solves;
+    }
+    if (s != ORC_OK) return s;
+    for (long i = 0; i < m9; ++i) U[i] -= w[i];
+    law_tangent(pb, F, U.data(), D.data());
+    double col[9];
+    mean9(D.data(), n, col);
+    for (int i = 0; i < 9; ++i) C[9 * i + m] = col[i];
+  }
+  return ORC_OK;
+}
+
+// Solve C x = r for the k x k system held in the leading block (row-major,
+// stride k) by Gaussian elimination with partial pivoting.  Returns false if
+// a pivot falls to 1e-12 of the largest entry (singular block: the mask leaves
+// a direction of Fbar without stress response, e.g. a rigid rotation at zero
+// stress).
+static bool small_solve(int k, double* C, double* r) {
+  double big = 0.0;
+  for (int i = 0; i < k * k; ++i) big = std::fmax(big, std::fabs(C[i]));
+  for (int j = 0; j < k; ++j) {
+    int piv = j;
+    for (int i = j + 1; i < k; ++i)
+      if (std::fabs(C[i * k + j]) > std::fabs(C[piv * k + j])) piv = i;
+    if (!(std::fabs(C[piv * k + j]) > 1e-12 * big)) return false;
+    if (piv != j) {
+      for (int c = 0; c < k; ++c) std::swap(C[j * k + c], C[piv * k + c]);
+      std::swap(r[j], r[piv]);
+    }
+    for (int i = j + 1; i < k; ++i) {
+      const double f = C[i * k + j] / C[j * k + j];
+      for (int c = j; c < k; ++c) C[i * k + c] -= f * C[j * k + c];
+      r[i] -= f * r[j];
+    }
+  }
+  for (int j = k - 1; j >= 0; --j) {
+    double s = r[j];
+    for (int c = j + 1; c < k; ++c) s -= C[j * k + c] * r[c];
+    r[j] = s / C[j * k + j];
+  }
+  return true;
+}
+
+static int solve_mixed_impl(const orc_problem& pb, double* F, double* Fbar, const int* mask, const double* Ptarget,
+                            double tol_stress, int max_outer, double eta_nw, double eta_cg, int max_newton,
+                            int max_cg, double* P, double* Pbar, double* hist_new, orc_stats* st, int* outer) {
+  const long n = (long)pb.n0 * pb.n1 * pb.n2, m9 = 9 * n;
+  orc_stats local;
+  if (!st) st = &local;
+  std::memset(st, 0, sizeof(*st));
+  if (outer) *outer = 0;
+  if (max_outer < 1 || !(tol_stress > 0.0)) {
+    st->status = ORC_EINVAL;
+    return ORC_EINVAL;
+  }
+  int idx[9], k = 0;
+  for (int m = 0; m < 9; ++m)
+    if (mask[m]) idx[k++] = m;
+  std::vector<double> Fk(F, F + m9), Pk(m9), hk(pb.model == 1 ? 7 * n : 0);
+  double Fb[9], Pb[9];
+  for (int c = 0; c < 9; ++c) Fb[c] = Fbar[c];
+  for (int it = 0; it < max_outer; ++it) {
+    if (outer) *outer = it + 1;
+    orc_stats inner;
+    const int s = solve_increment_impl(pb, Fk.data(), Fb, eta_nw, eta_cg, max_newton, max_cg, Pk.data(), Pb,
+                                       hk.empty() ? nullptr : hk.data(), &inner);
+    for (int j = 0; j < inner.n_solves && st->n_solves < ORC_MAX_SOLVES; ++j) {
+      st->cg_iters[st->n_solves] = inner.cg_iters[j];
+      st->cg_relres[st->n_solves] = inner.cg_relres[j];
+      st->newton_res[st->n_solves] = inner.newton_res[j];
+      ++st->n_solves;
+    }
+    if (s != ORC_OK) {
+      st->status = s;
+      return s;
+    }
+    double R[9], worst = 0.0;
+    for (int j = 0; j < k; ++j) {
+      R[j] = Pb[idx[j]] - Ptarget[idx[j]];
+      worst = std::fmax(worst, std::fabs(R[j]));
+    }
+    if (!std::isfinite(worst)) {
+      st->status = ORC_ENONFINITE;
+      return ORC_ENONFINITE;
+    }
+    if (worst <= tol_stress) {
+      for (long i = 0; i < m9; ++i) {
+        F[i] = Fk[i];
+        P[i] = Pk[i];
+      }
+      if (hist_new && !hk.empty())
+        for (long i = 0; i < 7 * n; ++i) hist_new[i] = hk[i];
+      for (int c = 0; c < 9; ++c) {
+        Fbar[c] = Fb[c];
+        Pbar[c] = Pb[c];
+      }
+      st->status = ORC_OK;
+      return ORC_OK;
+    }
+    if (it + 1 == max_outer) break;
+    double C[81] = {0.0};
+    const int sc = macro_tangent_impl(pb, Fk.data(), mask, C, eta_cg, max_cg, st);
+    if (sc != ORC_OK) {
+      st->status = sc;
+      return sc;
+    }
+    double Cm[81];
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) Cm[a * k + b] = C[9 * idx[a] + idx[b]];
+    if (!small_solve(k, Cm, R)) {
+      st->status = ORC_EINVAL;
+      return ORC_EINVAL;
+    }
+    for (int j = 0; j < k; ++j) Fb[idx[j]] -= R[j];
+  }
+  st->status = ORC_ENEWTON_MAXIT;
+  return ORC_ENEWTON_MAXIT;
+}
+
+// dPbar/dFbar at the equilibrium F (St. Venant-Kirchhoff), columns with want[m].
+int orc_macro_tangent(int n0, int n1, int n2, const double* K, const double* mu, const double* F, const int* want,
+                      double eta_cg, int max_cg, double* C) {
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0};
+  return macro_tangent_impl(pb, F, want, C, eta_cg, max_cg, nullptr);
+}
+
+// One increment under mixed control (St. Venant-Kirchhoff).  F: the start
+// state on entry, the equilibrium on success (unchanged on failure); Fbar: the
+// prescribed entries and the starting guess of the masked ones on entry, the
+// solution on success; *outer: outer iterations taken.
+int orc_solve_increment_mixed(int n0, int n1, int n2, const double* K, const double* mu, double* F, double* Fbar,
+                              const int* mask, const double* Ptarget, double tol_stress, int max_outer,
+                              double eta_nw, double eta_cg, int max_newton, int max_cg, double* P, double* Pbar,
+                              orc_stats* st, int* outer) {
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0};
+  return solve_mixed_impl(pb, F, Fbar, mask, Ptarget, tol_stress, max_outer, eta_nw, eta_cg, max_newton, max_cg,
+                          P, Pbar, nullptr, st, outer);
+}
+
+// The same with the J2 law: hist as in orc_solve_increment_j2.
+int orc_solve_increment_mixed_j2(int n0, int n1, int n2, const double* K, const double* mu, const double* ty0,
+                                 const double* H, double* hist, double* F, double* Fbar, const int* mask,
+                                 const double* Ptarget, double tol_stress, int max_outer, double eta_nw,
+                                 double eta_cg, int max_newton, int max_cg, double* P, double* Pbar, orc_stats* st,
+                                 int* outer) {
+  const long n = (long)n0 * n1 * n2;
+  std::vector<double> h0(hist, hist + 7 * n);
+  orc_problem pb{n0, n1, n2, K, mu, 1, ty0, H, h0.data(), 0};
+  return solve_mixed_impl(pb, F, Fbar, mask, Ptarget, tol_stress, max_outer, eta_nw, eta_cg, max_newton, max_cg,
+                          P, Pbar, hist, st, outer);
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint sensitivity of the homogenised stress (not in the paper; derived from
 // the boundary-condition system of Sec. 3.1 and the symmetry of G, Sec. 2.3).
 //
