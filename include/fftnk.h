@@ -156,6 +156,50 @@ int fftnk_solve_increment(fftnk_ctx* ctx, const double* Fbar_host, double eta_nw
                           int max_cg, double* F_dev, double* P_dev, double* Pbar_host, fftnk_stats* stats);
 
 /*
+ * One load increment under mixed macroscopic control.  Not in the paper: its
+ * Sec. 3.1 prescribes the whole macroscopic deformation gradient and leaves
+ * stress or mixed control to the literature; this builds it from the same
+ * boundary-condition system and operator.
+ *
+ * Per RVE r, components k with mask_host[9r+k] != 0 prescribe the homogenised
+ * stress, Pbar_k = Ptarget_host[9r+k]; the others prescribe Fbar_k =
+ * Fbar_host[9r+k].  Fbar_host's masked entries are the starting guess (e.g.
+ * the previous increment's values) and receive the solution (in/out, host
+ * [nrve][9]).  Outer Newton iteration on the masked entries: each pass solves
+ * the deformation-controlled increment of fftnk_solve_increment at the current
+ * Fbar (the first from the committed state, later ones from the previous
+ * pass's equilibrium); it stops when max_k |Pbar_k - Ptarget_k| <= tol_stress
+ * (absolute, stress units) over the masked k; otherwise the masked block of
+ * the macroscopic tangent (fftnk_macro_tangent, at the current equilibrium)
+ * gives the Newton step of Fbar.  outer_host (optional, [nrve]) receives the
+ * passes taken; stats (optional, [nrve]) lists every linear solve in order
+ * (Newton and tangent solves; n_solves counts them all, the arrays hold the
+ * first FFTNK_MAX_SOLVES).  The remaining arguments and the commit / failure
+ * rules are those of fftnk_solve_increment; in addition FFTNK_ENEWTON_MAXIT
+ * when max_outer passes do not reach tol_stress, and FFTNK_EINVAL when the
+ * masked tangent block is singular (the mask leaves a direction of Fbar with
+ * no stress response, e.g. rigid rotations with all nine components
+ * prescribed at zero stress).
+ */
+int fftnk_solve_increment_mixed(fftnk_ctx* ctx, double* Fbar_host, const int* mask_host, const double* Ptarget_host,
+                                double tol_stress, int max_outer, double eta_nw, double eta_cg, int max_newton,
+                                int max_cg, double* F_dev, double* P_dev, double* Pbar_host, fftnk_stats* stats,
+                                int* outer_host);
+
+/*
+ * Macroscopic (homogenised) tangent at the last committed state: C_host
+ * [nrve][9][9] receives C[r][i][m] = dPbar_i / dFbar_m for every column m with
+ * want_host[9r+m] != 0 (want_host NULL: all nine), zeros elsewhere.  A unit
+ * macroscopic increment E_m spreads as E_m + dF with the boundary-condition
+ * solve of Sec. 3.1, G:K(F_t):dF = -G:K(F_t):E_m; with A w = G(K(F_t):E_m)
+ * (one CG per column, all RVEs together), column m = mean(K(F_t) : (E_m - w)).
+ * Not in the paper.  CG parameters as in fftnk_solve_increment; stats
+ * (optional, [nrve]) lists one solve per column.
+ */
+int fftnk_macro_tangent(fftnk_ctx* ctx, const int* want_host, double eta_cg, int max_cg, double* C_host,
+                        fftnk_stats* stats);
+
+/*
  * Linearisation point of fftnk_apply_operator: F (device double [9][n]) is
  * copied into the context (and rounded to float in FP32_MIXED mode).
  */

@@ -503,6 +503,220 @@ int reduce_fetch(fftnk_ctx* c, std::initializer_list<std::pair<int, std::pair<in
 
 double red_at(fftnk_ctx* c, int r, int slot) { return c->host_red()[r * NSLOT + slot]; }
 
+// Deformation-controlled Newton iterations of Algorithm 1 (Sec. 3.1-3.2) on
+// the RVEs with run[r] (the others are left alone: masked off every launch):
+// dFbar = Fbar - mean(F_0), first solve with the tangent of F_0, then
+// G:K(F_i):dF = -G:P(F_i) until ||dF|| / ||F_0 + dFbar|| < eta_nw and i > 0.
+// F_0 is the committed state (warm = false) or the current iterate F (warm =
+// true: a further load step from an equilibrium of the same increment).
+// Writes F, P (workspace) and, per running RVE, st, status and pbar; commits
+// nothing.
+int newton_solve(fftnk_ctx* c, const double* Fbar, const std::vector<int>& run, bool warm, double eta_nw,
+                 double eta_cg, int max_newton, int max_cg, std::vector<fftnk_stats>& st, std::vector<int>& status,
+                 std::vector<double>& pbar) {
+  const int nr = c->nrve;
+  std::vector<int> done(nr, 0);
+  std::vector<double> Fn(nr, 0.0);
+  const Material mat = c->material();
+  int e = FFTNK_OK;
+  double* F0 = warm ? c->F() : c->Ft();
+  for (int r = 0; r < nr; ++r) {
+    done[r] = run[r] ? 0 : 1;
+    if (!run[r]) continue;
+    status[r] = FFTNK_OK;
+    for (int k = 0; k < 9; ++k)
+      if (!std::isfinite(Fbar[9 * r + k])) {
+        status[r] = FFTNK_ENONFINITE;
+        done[r] = 1;
+      }
+  }
+  for (int r = 0; r < nr; ++r) c->active[r] = done[r] ? 0 : 1;
+  e = upload_active(c);
+  if (e) return e;
+
+  // dFbar = Fbar - mean(F_0)  (Sec. 3.1)
+  launch_field_sum(c->launch(), F0, SLOT_FBAR);
+  e = reduce_fetch(c, {{K_VOX, {SLOT_FBAR, 9}}});
+  if (e) return e;
+  for (int r = 0; r < nr; ++r)
+    for (int k = 0; k < 9; ++k)
+      c->uni[9 * r + k] = done[r] ? 0.0 : Fbar[9 * r + k] - red_at(c, r, SLOT_FBAR + k) / (double)c->g[r].n;
+  e = upload_uni(c);
+  if (e) return e;
+
+  // boundary-condition right-hand side with the tangent of the start state;
+  // F = F_0 until the first update adds dFbar
+  rhs_pipeline(c, FWD_TANGENT_UNI, nullptr, F0, -1.0);
+  launch_set_F(c->launch(), F0, c->F(), c->F32());
+  e = reduce_fetch(c, {{K_VOX, {SLOT_FF, 1}}});
+  if (e) return e;
+  for (int r = 0; r < nr; ++r) Fn[r] = std::sqrt(red_at(c, r, SLOT_FF));
+
+  const double eta_eff = c->prec == PREC_F32 ? std::max(eta_cg, 1e-6) : eta_cg;
+  for (int it = 0; it < max_newton; ++it) {
+    bool any = false;
+    for (int r = 0; r < nr; ++r) any = any || !done[r];
+    if (!any) break;
+    e = run_cg(c, eta_eff, max_cg);
+    if (e) return e;
+    for (int r = 0; r < nr; ++r) {
+      if (done[r]) continue;
+      const CgState& s = c->host_cg()[r];
+      st[r].cg_iters[it] = s.iter;
+      st[r].cg_relres[it] = (s.bb > 0 && !s.zero_rhs) ? std::sqrt(s.rr / s.bb) : 0.0;
+      st[r].n_solves = it + 1;
+      if (s.status != FFTNK_OK) {
+        status[r] = s.status;
+        done[r] = 1;
+        c->active[r] = 0;
+      }
+    }
+    e = upload_active(c);
+    if (e) return e;
+    // F += dF (+ dFbar after the boundary-condition solve), constitutive
+    // update, new right-hand side -G(P)
+    const void* dF = newton_update_source(c);  // FP64 in both precisions
+    launch_newton_update(PREC_F64, c->launch(), mat, c->F(), dF, c->P(), c->F32(), it == 0);
+    rhs_pipeline(c, FWD_COPY, c->P(), nullptr, -1.0);
+    e = reduce_fetch(c, {{K_VOX, {SLOT_DF, 1}}, {K_VOX, {SLOT_PBAR, 9}}});
+    if (e) return e;
+    for (int r = 0; r < nr; ++r) {
+      if (done[r]) continue;
+      const double res = std::sqrt(red_at(c, r, SLOT_DF)) / Fn[r];
+      st[r].newton_res[it] = res;
+      bool finite = std::isfinite(res);
+      for (int k = 0; k < 9; ++k) {
+        pbar[9 * r + k] = red_at(c, r, SLOT_PBAR + k) / (double)c->g[r].n;
+        finite = finite && std::isfinite(pbar[9 * r + k]);
+      }
+      if (!finite) {
+        status[r] = FFTNK_ENONFINITE;
+        done[r] = 1;
+      } else if (res < eta_nw && it > 0) {
+        done[r] = 1;  // converged
+      } else if (it + 1 >= max_newton) {
+        status[r] = FFTNK_ENEWTON_MAXIT;
+        done[r] = 1;
+      }
+      if (done[r]) c->active[r] = 0;
+    }
+    e = upload_active(c);
+    if (e) return e;
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));  // the last mask upload has read the host vector
+  return FFTNK_OK;
+}
+
+// Commit the RVEs with status OK (transactional per RVE: F_t, J2 history),
+// copy their F and P out, restore the all-active mask.  *worst: first failure.
+int commit_rves(fftnk_ctx* c, const std::vector<int>& status, double* F_dev, double* P_dev, int* worst) {
+  *worst = FFTNK_OK;
+  for (int r = 0; r < c->nrve; ++r) {
+    if (status[r]) {
+      if (!*worst) *worst = status[r];
+      continue;
+    }
+    const Grid& g = c->g[r];
+    const size_t off = 9 * (size_t)g.vox_off, bytes = 9 * (size_t)g.n * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(c->Ft() + off, c->F() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (F_dev) HIP_TRY(hipMemcpyAsync(F_dev + off, c->F() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (P_dev) HIP_TRY(hipMemcpyAsync(P_dev + off, c->P() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
+    if (c->model == MODEL_J2)  // store the history of the converged state (Alg. 1)
+      for (int k = 0; k < 7; ++k) {
+        const size_t o = (size_t)k * c->ntot + g.vox_off;
+        HIP_TRY(hipMemcpyAsync(c->at<double>(c->o_hist) + o, c->at<double>(c->o_hnew) + o, g.n * sizeof(double),
+                               hipMemcpyDeviceToDevice, c->stream));
+      }
+  }
+  std::fill(c->active.begin(), c->active.end(), 1);
+  int e = upload_active(c);
+  if (e) return e;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return FFTNK_OK;
+}
+
+// Columns m of the macroscopic tangent C[r][i][m] = dPbar_i / dFbar_m at the
+// current iterate F (with its FP32 copy) for every (r, m) with want[9 r + m]:
+// a unit macroscopic increment E_m spreads as E_m + dF with the boundary-
+// condition solve G:K(F):dF = -G:K(F):E_m (Sec. 3.1), so with A w = G(K(F):E_m),
+// column m = mean(K(F) : (E_m - w)).  One CG per column index, over all RVEs
+// that want it.  Appends one solve per column to st; a failed CG sets status.
+int macro_tangent_columns(fftnk_ctx* c, const int* want, double eta_cg, int max_cg, double* C,
+                          std::vector<fftnk_stats>& st, std::vector<int>& status) {
+  const int nr = c->nrve;
+  const double eta_eff = c->prec == PREC_F32 ? std::max(eta_cg, 1e-6) : eta_cg;
+  int e = FFTNK_OK;
+  for (int m = 0; m < 9; ++m) {
+    bool any = false;
+    for (int r = 0; r < nr; ++r) {
+      c->active[r] = (want[9 * r + m] && !status[r]) ? 1 : 0;
+      any = any || c->active[r];
+      for (int k = 0; k < 9; ++k) c->uni[9 * r + k] = (c->active[r] && k == m) ? 1.0 : 0.0;
+    }
+    if (!any) continue;
+    e = upload_active(c);
+    if (!e) e = upload_uni(c);
+    if (e) return e;
+    rhs_pipeline(c, FWD_TANGENT_UNI, nullptr, c->F(), +1.0);
+    e = run_cg(c, eta_eff, max_cg);
+    if (e) return e;
+    // the CG outcome, read before the next fetch reuses the host staging buffer
+    for (int r = 0; r < nr; ++r) {
+      if (!c->active[r]) continue;
+      const CgState& s = c->host_cg()[r];
+      const int at = st[r].n_solves++;
+      if (at < FFTNK_MAX_SOLVES) {
+        st[r].cg_iters[at] = s.iter;
+        st[r].cg_relres[at] = (s.bb > 0 && !s.zero_rhs) ? std::sqrt(s.rr / s.bb) : 0.0;
+      }
+      if (s.status != FFTNK_OK) status[r] = s.status;
+    }
+    const void* w = newton_update_source(c);  // FP64 in both precisions
+    launch_tangent_sum(c->launch(), c->material(), c->F(), static_cast<const double*>(w));
+    e = reduce_fetch(c, {{K_VOX, {SLOT_PBAR, 9}}});
+    if (e) return e;
+    for (int r = 0; r < nr; ++r) {
+      if (!c->active[r] || status[r]) continue;
+      for (int i = 0; i < 9; ++i) C[81 * (size_t)r + 9 * i + m] = red_at(c, r, SLOT_PBAR + i) / (double)c->g[r].n;
+    }
+  }
+  std::fill(c->active.begin(), c->active.end(), 1);
+  std::fill(c->uni.begin(), c->uni.end(), 0.0);
+  e = upload_active(c);
+  if (e) return e;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return FFTNK_OK;
+}
+
+// Solve the k x k system A x = r (row-major, stride k) in place in r by
+// Gaussian elimination with partial pivoting; false when a pivot falls to
+// 1e-12 of the largest entry.
+bool solve_small(int k, double* A, double* r) {
+  double big = 0.0;
+  for (int i = 0; i < k * k; ++i) big = std::fmax(big, std::fabs(A[i]));
+  for (int j = 0; j < k; ++j) {
+    int piv = j;
+    for (int i = j + 1; i < k; ++i)
+      if (std::fabs(A[i * k + j]) > std::fabs(A[piv * k + j])) piv = i;
+    if (!(std::fabs(A[piv * k + j]) > 1e-12 * big)) return false;
+    if (piv != j) {
+      for (int q = 0; q < k; ++q) std::swap(A[j * k + q], A[piv * k + q]);
+      std::swap(r[j], r[piv]);
+    }
+    for (int i = j + 1; i < k; ++i) {
+      const double f = A[i * k + j] / A[j * k + j];
+      for (int q = j; q < k; ++q) A[i * k + q] -= f * A[j * k + q];
+      r[i] -= f * r[j];
+    }
+  }
+  for (int j = k - 1; j >= 0; --j) {
+    double v = r[j];
+    for (int q = j + 1; q < k; ++q) v -= A[j * k + q] * r[q];
+    r[j] = v / A[j * k + j];
+  }
+  return true;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -653,121 +867,162 @@ int fftnk_solve_increment(fftnk_ctx* c, const double* Fbar, double eta_nw, doubl
   const int nr = c->nrve;
   std::vector<fftnk_stats> st(nr);
   std::memset(st.data(), 0, nr * sizeof(fftnk_stats));
-  std::vector<int> status(nr, FFTNK_OK), done(nr, 0);
-  std::vector<double> Fn(nr, 0.0), pbar(9 * (size_t)nr, 0.0);
-  const Material mat = c->material();
-  int e = FFTNK_OK;
-
-  for (int r = 0; r < nr; ++r)
-    for (int k = 0; k < 9; ++k)
-      if (!std::isfinite(Fbar[9 * r + k])) {
-        status[r] = FFTNK_ENONFINITE;
-        done[r] = 1;
-      }
-  for (int r = 0; r < nr; ++r) c->active[r] = done[r] ? 0 : 1;
-  e = upload_active(c);
+  std::vector<int> status(nr, FFTNK_OK), run(nr, 1);
+  std::vector<double> pbar(9 * (size_t)nr, 0.0);
+  int e = newton_solve(c, Fbar, run, false, eta_nw, eta_cg, max_newton, max_cg, st, status, pbar);
   if (e) return e;
-
-  // dFbar = Fbar - mean(F_t)  (Sec. 3.1)
-  launch_field_sum(c->launch(), c->Ft(), SLOT_FBAR);
-  e = reduce_fetch(c, {{K_VOX, {SLOT_FBAR, 9}}});
-  if (e) return e;
-  for (int r = 0; r < nr; ++r)
-    for (int k = 0; k < 9; ++k) c->uni[9 * r + k] = Fbar[9 * r + k] - red_at(c, r, SLOT_FBAR + k) / (double)c->g[r].n;
-  e = upload_uni(c);
-  if (e) return e;
-
-  // boundary-condition right-hand side with the tangent of the start state;
-  // F = F_t until the first update adds dFbar
-  rhs_pipeline(c, FWD_TANGENT_UNI, nullptr, c->Ft(), -1.0);
-  launch_set_F(c->launch(), c->Ft(), c->F(), c->F32());
-  e = reduce_fetch(c, {{K_VOX, {SLOT_FF, 1}}});
-  if (e) return e;
-  for (int r = 0; r < nr; ++r) Fn[r] = std::sqrt(red_at(c, r, SLOT_FF));
-
-  const double eta_eff = c->prec == PREC_F32 ? std::max(eta_cg, 1e-6) : eta_cg;
-  for (int it = 0; it < max_newton; ++it) {
-    bool any = false;
-    for (int r = 0; r < nr; ++r) any = any || !done[r];
-    if (!any) break;
-    e = run_cg(c, eta_eff, max_cg);
-    if (e) return e;
-    for (int r = 0; r < nr; ++r) {
-      if (done[r]) continue;
-      const CgState& s = c->host_cg()[r];
-      st[r].cg_iters[it] = s.iter;
-      st[r].cg_relres[it] = (s.bb > 0 && !s.zero_rhs) ? std::sqrt(s.rr / s.bb) : 0.0;
-      st[r].n_solves = it + 1;
-      if (s.status != FFTNK_OK) {
-        status[r] = s.status;
-        done[r] = 1;
-        c->active[r] = 0;
-      }
-    }
-    e = upload_active(c);
-    if (e) return e;
-    // F += dF (+ dFbar after the boundary-condition solve), constitutive
-    // update, new right-hand side -G(P)
-    const void* dF = newton_update_source(c);  // FP64 in both precisions
-    launch_newton_update(PREC_F64, c->launch(), mat, c->F(), dF, c->P(), c->F32(), it == 0);
-    rhs_pipeline(c, FWD_COPY, c->P(), nullptr, -1.0);
-    e = reduce_fetch(c, {{K_VOX, {SLOT_DF, 1}}, {K_VOX, {SLOT_PBAR, 9}}});
-    if (e) return e;
-    for (int r = 0; r < nr; ++r) {
-      if (done[r]) continue;
-      const double res = std::sqrt(red_at(c, r, SLOT_DF)) / Fn[r];
-      st[r].newton_res[it] = res;
-      bool finite = std::isfinite(res);
-      for (int k = 0; k < 9; ++k) {
-        pbar[9 * r + k] = red_at(c, r, SLOT_PBAR + k) / (double)c->g[r].n;
-        finite = finite && std::isfinite(pbar[9 * r + k]);
-      }
-      if (!finite) {
-        status[r] = FFTNK_ENONFINITE;
-        done[r] = 1;
-      } else if (res < eta_nw && it > 0) {
-        done[r] = 1;  // converged
-      } else if (it + 1 >= max_newton) {
-        status[r] = FFTNK_ENEWTON_MAXIT;
-        done[r] = 1;
-      }
-      if (done[r]) c->active[r] = 0;
-    }
-    e = upload_active(c);
-    if (e) return e;
-  }
-  // commit the converged RVEs (transactional per RVE), copy out
   int worst = FFTNK_OK;
-  for (int r = 0; r < nr; ++r) {
-    st[r].status = status[r];
-    if (status[r]) {
-      if (!worst) worst = status[r];
-      continue;
-    }
-    const Grid& g = c->g[r];
-    const size_t off = 9 * (size_t)g.vox_off, bytes = 9 * (size_t)g.n * sizeof(double);
-    HIP_TRY(hipMemcpyAsync(c->Ft() + off, c->F() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
-    if (F_dev) HIP_TRY(hipMemcpyAsync(F_dev + off, c->F() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
-    if (P_dev) HIP_TRY(hipMemcpyAsync(P_dev + off, c->P() + off, bytes, hipMemcpyDeviceToDevice, c->stream));
-    if (c->model == MODEL_J2)  // store the history of the converged state (Alg. 1)
-      for (int k = 0; k < 7; ++k) {
-        const size_t o = (size_t)k * c->ntot + g.vox_off;
-        HIP_TRY(hipMemcpyAsync(c->at<double>(c->o_hist) + o, c->at<double>(c->o_hnew) + o, g.n * sizeof(double),
-                               hipMemcpyDeviceToDevice, c->stream));
-      }
-    for (int k = 0; k < 9; ++k) Pbar[9 * r + k] = pbar[9 * r + k];
-  }
-  HIP_TRY(hipStreamSynchronize(c->stream));  // the last mask upload has read the host vector
-  std::fill(c->active.begin(), c->active.end(), 1);
-  e = upload_active(c);
+  e = commit_rves(c, status, F_dev, P_dev, &worst);
   if (e) return e;
-  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int r = 0; r < nr; ++r)
+    if (!status[r])
+      for (int k = 0; k < 9; ++k) Pbar[9 * r + k] = pbar[9 * r + k];
   const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (stats)
     for (int r = 0; r < nr; ++r) {
+      st[r].status = status[r];
       stats[r] = st[r];
       stats[r].t_ms = ms;
     }
+  return worst;
+}
+
+int fftnk_solve_increment_mixed(fftnk_ctx* c, double* Fbar, const int* mask, const double* Ptarget,
+                                double tol_stress, int max_outer, double eta_nw, double eta_cg, int max_newton,
+                                int max_cg, double* F_dev, double* P_dev, double* Pbar, fftnk_stats* stats,
+                                int* outer) {
+  if (!c || !Fbar || !mask || !Ptarget || !Pbar) return FFTNK_EINVAL;
+  if (!(tol_stress > 0) || max_outer < 1 || !(eta_nw > 0) || !(eta_cg > 0) || max_newton < 2 ||
+      max_newton > FFTNK_MAX_SOLVES || max_cg < 1)
+    return FFTNK_EINVAL;
+  if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int nr = c->nrve;
+  std::vector<fftnk_stats> st(nr), all(nr);
+  std::memset(all.data(), 0, nr * sizeof(fftnk_stats));
+  std::vector<int> status(nr, FFTNK_OK), run(nr, 1), nout(nr, 0);
+  std::vector<double> fb(Fbar, Fbar + 9 * (size_t)nr), pbar(9 * (size_t)nr, 0.0), C(81 * (size_t)nr, 0.0);
+  for (int r = 0; r < nr; ++r)
+    for (int k = 0; k < 9; ++k)
+      if (mask[9 * r + k] && !std::isfinite(Ptarget[9 * r + k])) {
+        status[r] = FFTNK_ENONFINITE;
+        run[r] = 0;
+      }
+  auto append = [&](int r, const fftnk_stats& s) {
+    for (int j = 0; j < s.n_solves; ++j) {
+      const int at = all[r].n_solves++;
+      if (at >= FFTNK_MAX_SOLVES) continue;
+      all[r].cg_iters[at] = s.cg_iters[j];
+      all[r].cg_relres[at] = s.cg_relres[j];
+      all[r].newton_res[at] = s.newton_res[j];
+    }
+  };
+  for (int it = 0; it < max_outer; ++it) {
+    bool any = false;
+    for (int r = 0; r < nr; ++r) any = any || run[r];
+    if (!any) break;
+    std::memset(st.data(), 0, nr * sizeof(fftnk_stats));
+    // deformation-controlled increment at the current Fbar, warm-started from
+    // the previous iterate's equilibrium after the first pass
+    int e = newton_solve(c, fb.data(), run, it > 0, eta_nw, eta_cg, max_newton, max_cg, st, status, pbar);
+    if (e) return e;
+    std::vector<int> need(nr, 0);
+    for (int r = 0; r < nr; ++r) {
+      if (!run[r]) continue;
+      append(r, st[r]);
+      nout[r] = it + 1;
+      if (status[r]) {
+        run[r] = 0;
+        continue;
+      }
+      double worst = 0.0;
+      for (int k = 0; k < 9; ++k)
+        if (mask[9 * r + k]) worst = std::fmax(worst, std::fabs(pbar[9 * r + k] - Ptarget[9 * r + k]));
+      if (worst <= tol_stress) {
+        run[r] = 0;  // converged
+      } else if (it + 1 == max_outer) {
+        status[r] = FFTNK_ENEWTON_MAXIT;
+        run[r] = 0;
+      } else {
+        need[r] = 1;
+      }
+    }
+    // masked block of the macroscopic tangent at each unconverged equilibrium,
+    // then the outer Newton step on the masked entries of Fbar
+    std::vector<int> want(9 * (size_t)nr, 0);
+    for (int r = 0; r < nr; ++r)
+      for (int k = 0; k < 9; ++k) want[9 * r + k] = need[r] && mask[9 * r + k];
+    std::memset(st.data(), 0, nr * sizeof(fftnk_stats));
+    e = macro_tangent_columns(c, want.data(), eta_cg, max_cg, C.data(), st, status);
+    if (e) return e;
+    for (int r = 0; r < nr; ++r) {
+      if (!need[r]) continue;
+      append(r, st[r]);
+      if (status[r]) {
+        run[r] = 0;
+        continue;
+      }
+      int idx[9], k = 0;
+      for (int m = 0; m < 9; ++m)
+        if (mask[9 * r + m]) idx[k++] = m;
+      double A[81], R[9];
+      for (int a2 = 0; a2 < k; ++a2) {
+        R[a2] = pbar[9 * r + idx[a2]] - Ptarget[9 * r + idx[a2]];
+        for (int b2 = 0; b2 < k; ++b2) A[a2 * k + b2] = C[81 * (size_t)r + 9 * idx[a2] + idx[b2]];
+      }
+      if (!solve_small(k, A, R)) {
+        status[r] = FFTNK_EINVAL;  // the mask leaves a direction of Fbar without stress response
+        run[r] = 0;
+        continue;
+      }
+      for (int j = 0; j < k; ++j) fb[9 * r + idx[j]] -= R[j];
+    }
+  }
+  int worst = FFTNK_OK;
+  int e = commit_rves(c, status, F_dev, P_dev, &worst);
+  if (e) return e;
+  for (int r = 0; r < nr; ++r) {
+    if (outer) outer[r] = nout[r];
+    if (status[r]) continue;
+    for (int k = 0; k < 9; ++k) {
+      Pbar[9 * r + k] = pbar[9 * r + k];
+      Fbar[9 * r + k] = fb[9 * r + k];
+    }
+  }
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats)
+    for (int r = 0; r < nr; ++r) {
+      all[r].status = status[r];
+      all[r].t_ms = ms;
+      stats[r] = all[r];
+    }
+  return worst;
+}
+
+int fftnk_macro_tangent(fftnk_ctx* c, const int* want, double eta_cg, int max_cg, double* C_host,
+                        fftnk_stats* stats) {
+  if (!c || !C_host || !(eta_cg > 0) || max_cg < 1) return FFTNK_EINVAL;
+  if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
+  const int nr = c->nrve;
+  std::vector<int> w(9 * (size_t)nr, 1), status(nr, FFTNK_OK);
+  if (want)
+    for (int k = 0; k < 9 * nr; ++k) w[k] = want[k] != 0;
+  // linearisation point: the committed state
+  const size_t bytes = 9 * (size_t)c->ntot * sizeof(double);
+  HIP_TRY(hipMemcpyAsync(c->F(), c->Ft(), bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (c->prec == PREC_F32) launch_convert(PREC_F32, c->Ft(), c->F32(), 9 * c->ntot, c->stream);
+  std::vector<fftnk_stats> st(nr);
+  std::memset(st.data(), 0, nr * sizeof(fftnk_stats));
+  std::vector<double> C(81 * (size_t)nr, 0.0);
+  int e = macro_tangent_columns(c, w.data(), eta_cg, max_cg, C.data(), st, status);
+  if (e) return e;
+  int worst = FFTNK_OK;
+  for (int r = 0; r < nr; ++r) {
+    st[r].status = status[r];
+    if (stats) stats[r] = st[r];
+    if (status[r] && !worst) worst = status[r];
+    for (int k = 0; k < 81; ++k) C_host[81 * (size_t)r + k] = w[9 * r + k % 9] ? C[81 * (size_t)r + k] : 0.0;
+  }
   return worst;
 }
 

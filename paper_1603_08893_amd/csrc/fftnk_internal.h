@@ -200,5 +200,7 @@ void launch_convert(int to_prec, const void* in, void* out, long long count, hip
 void launch_set_identity(const Launch& L, double* F);
 void launch_set_virgin_history(const Launch& L, double* hist, long long ntot);
 void launch_adjoint_grad(int prec, const Launch& L, const double* F, const void* w, double* dmu, double* dK);
+// sums of K(F) : (uni - w) per RVE into SLOT_PBAR .. + 8 (w FP64)
+void launch_tangent_sum(const Launch& L, const Material& mat, const double* F, const double* w);
 
 }  // namespace fftnk

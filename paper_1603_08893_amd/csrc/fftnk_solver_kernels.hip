@@ -144,8 +144,8 @@ __global__ __launch_bounds__(kThreads) void k_cg_beta(Batch B, CgState* cg) {
 // Start of an increment: F = F_t (the tangent of the first solve is taken about
 // the start state, Sec. 3.1), ||F_t + dFbar||^2 for the convergence test's
 // denominator, and the FP32 copy of the linearisation point.
-__global__ __launch_bounds__(kThreads) void k_set_F(Batch B, const double* __restrict__ Ft, double* __restrict__ F,
-                                                    float* __restrict__ Flin32) {
+// Ft may be F itself (a solve warm-started from the current iterate).
+__global__ __launch_bounds__(kThreads) void k_set_F(Batch B, const double* Ft, double* F, float* __restrict__ Flin32) {
   int local;
   const int rv = find_rve(B, K_VOX, blockIdx.x, local);
   if (skip_rve(B, nullptr, rv)) return;
@@ -358,6 +358,47 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_grad(Batch B, const double
   }
 }
 
+// Column of the macroscopic tangent: the sums over the cell of K(F) : (U - w)
+// with U the RVE's uniform tensor (a unit macroscopic increment) and w the
+// solution of A w = G(K(F) : U); into SLOT_PBAR .. SLOT_PBAR + 8.
+template <int LAW>
+__global__ __launch_bounds__(kThreads) void k_tangent_sum(Batch B, Material mat, const double* __restrict__ F,
+                                                          const double* __restrict__ w) {
+  int local;
+  const int rv = find_rve(B, K_VOX, blockIdx.x, local);
+  if (skip_rve(B, nullptr, rv)) return;
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_VOX, rv);
+  const long long n = g.n, off = 9 * g.vox_off;
+  const double* u = B.uni + 9 * rv;
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  FOR_RVE_RANGE(v, n, local, nb) {
+    double f[9], q[9], d[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+      f[c] = F[off + c * n + v];
+      q[c] = u[c] - w[off + c * n + v];
+    }
+    if constexpr (LAW == MODEL_J2) {
+      double K, mu, ty0, H, h[7];
+      j2_point_data(mat, g.vox_off + v, K, mu, ty0, H, h);
+      j2_tangent(f, h, K, mu, ty0, H, q, d);
+    } else {
+      double lam, mu;
+      material_at(mat, g.vox_off + v, lam, mu);
+      svk_tangent<double>(f, q, lam, mu, d);
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] += d[c];
+  }
+  double res[9];
+  block_sums<9>(acc, res);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 9; ++c) pslot(B, SLOT_PBAR + c)[blockIdx.x] = res[c];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -439,6 +480,13 @@ void launch_convert(int to_prec, const void* in, void* out, long long count, hip
 
 void launch_set_identity(const Launch& L, double* F) {
   hipLaunchKernelGGL(k_set_identity, dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, F);
+}
+
+void launch_tangent_sum(const Launch& L, const Material& mat, const double* F, const double* w) {
+  if (mat.model == MODEL_J2)
+    hipLaunchKernelGGL((k_tangent_sum<MODEL_J2>), dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, mat, F, w);
+  else
+    hipLaunchKernelGGL((k_tangent_sum<MODEL_SVK>), dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, mat, F, w);
 }
 
 void launch_adjoint_grad(int prec, const Launch& L, const double* F, const void* w, double* dmu, double* dK) {

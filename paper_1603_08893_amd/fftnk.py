@@ -23,6 +23,7 @@ MAX_SOLVES = 64
 EXPORTS = [
     "fftnk_create", "fftnk_create_batched", "fftnk_workspace_bytes", "fftnk_bind_workspace", "fftnk_set_phases",
     "fftnk_set_material", "fftnk_set_modulus_field", "fftnk_set_option", "fftnk_reset_state", "fftnk_solve_increment",
+    "fftnk_solve_increment_mixed", "fftnk_macro_tangent",
     "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_adjoint",
     "fftnk_launch_pass", "fftnk_profile_cg", "fftnk_get_history", "fftnk_set_history", "fftnk_get_state",
     "fftnk_set_state", "fftnk_status_string", "fftnk_destroy",
@@ -75,6 +76,9 @@ def lib():
     L.fftnk_set_option.argtypes = [vp, i, i]
     L.fftnk_reset_state.argtypes = [vp]
     L.fftnk_solve_increment.argtypes = [vp, dp, d, d, i, i, vp, vp, dp, ctypes.POINTER(Stats)]
+    ip = ctypes.POINTER(i)
+    L.fftnk_solve_increment_mixed.argtypes = [vp, dp, ip, dp, d, i, d, d, i, i, vp, vp, dp, ctypes.POINTER(Stats), ip]
+    L.fftnk_macro_tangent.argtypes = [vp, ip, d, i, dp, ctypes.POINTER(Stats)]
     L.fftnk_set_linearization.argtypes = [vp, vp]
     L.fftnk_apply_operator.argtypes = [vp, vp, vp]
     L.fftnk_project.argtypes = [vp, vp, vp]
@@ -209,6 +213,48 @@ class Solver:
         if raise_on_error:
             _check(st, "fftnk_solve_increment")
         return st, F, P, Pbar, [s.as_dict() for s in stats]
+
+    def solve_increment_mixed(self, Fbar, mask, Ptarget, tol_stress=1e-10, max_outer=20, eta_nw=1e-5, eta_cg=1e-8,
+                              max_newton=50, max_cg=10000, fields=True, raise_on_error=True):
+        """One increment under mixed control: Pbar_k = Ptarget_k where mask_k != 0,
+        Fbar_k elsewhere (Fbar's masked entries: the starting guess).  mask,
+        Ptarget, Fbar: [9] or [nrve, 9].
+
+        Returns (status, F, P, Pbar[nrve, 9], Fbar[nrve, 9], stats list, outer[nrve])."""
+        Fb = np.array(np.broadcast_to(np.asarray(Fbar, dtype=np.float64).reshape(-1, 9), (self.nrve, 9)),
+                      dtype=np.float64, order="C")
+        Pt = np.ascontiguousarray(np.broadcast_to(np.asarray(Ptarget, dtype=np.float64).reshape(-1, 9),
+                                                  (self.nrve, 9)))
+        mk = np.ascontiguousarray(np.broadcast_to(np.asarray(mask).reshape(-1, 9) != 0, (self.nrve, 9)),
+                                  dtype=np.int32)
+        Pbar = np.zeros((self.nrve, 9))
+        stats = (Stats * self.nrve)()
+        outer = np.zeros(self.nrve, dtype=np.int32)
+        F = self.field(self.torch.float64) if fields else None
+        P = self.field(self.torch.float64) if fields else None
+        ip = ctypes.POINTER(ctypes.c_int)
+        st = lib().fftnk_solve_increment_mixed(self.ctx, _dptr(Fb), mk.ctypes.data_as(ip), _dptr(Pt), tol_stress,
+                                               max_outer, eta_nw, eta_cg, max_newton, max_cg,
+                                               ctypes.c_void_p(F.data_ptr()) if fields else None,
+                                               ctypes.c_void_p(P.data_ptr()) if fields else None,
+                                               _dptr(Pbar), stats, outer.ctypes.data_as(ip))
+        if raise_on_error:
+            _check(st, "fftnk_solve_increment_mixed")
+        return st, F, P, Pbar, Fb, [s.as_dict() for s in stats], outer
+
+    def macro_tangent(self, want=None, eta_cg=1e-10, max_cg=10000):
+        """dPbar/dFbar at the committed state: array [nrve, 9, 9] (columns with want)."""
+        C = np.zeros((self.nrve, 9, 9))
+        stats = (Stats * self.nrve)()
+        ip = ctypes.POINTER(ctypes.c_int)
+        if want is None:
+            wp = None
+        else:
+            w = np.ascontiguousarray(np.broadcast_to(np.asarray(want).reshape(-1, 9) != 0, (self.nrve, 9)),
+                                     dtype=np.int32)
+            wp = w.ctypes.data_as(ip)
+        _check(lib().fftnk_macro_tangent(self.ctx, wp, eta_cg, max_cg, _dptr(C), stats), "fftnk_macro_tangent")
+        return C
 
     def set_linearization(self, F):
         F = F.to(self.device, self.torch.float64).contiguous()
