@@ -78,6 +78,13 @@ def lib():
         L.orc_cg.argtypes = [i, i, i, dp, dp, dp, dp, dp, ctypes.c_double, i,
                              ctypes.POINTER(i), dp]
         L.orc_cg.restype = i
+        L.orc_krylov.argtypes = [i, i, i, dp, dp, dp, dp, dp, ctypes.c_double, i, i, ctypes.c_double,
+                                 ctypes.c_double, ctypes.POINTER(i), dp]
+        L.orc_krylov.restype = i
+        L.orc_solve_increment_krylov.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                                 i, i, dp, dp, ctypes.POINTER(Stats), i, ctypes.c_double,
+                                                 ctypes.c_double]
+        L.orc_solve_increment_krylov.restype = i
         L.orc_solve_increment.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                           i, i, dp, dp, ctypes.POINTER(Stats)]
         L.orc_solve_increment.restype = i
@@ -214,6 +221,41 @@ def cg(F, K, mu, b, eta=1e-8, max_cg=10000):
     st = lib().orc_cg(n0, n1, n2, _p(K), _p(mu), _p(F), _p(b), _p(x), eta, max_cg, ctypes.byref(it),
                       ctypes.byref(rel))
     return x, st, it.value, rel.value
+
+
+METHODS = {"cg": 0, "chebyshev": 1, "richardson": 2}
+
+
+def krylov(F, K, mu, b, method="chebyshev", lo=0.0, hi=0.0, eta=1e-8, max_it=10000):
+    """One linear solve A x = b, x0 = 0, with CG, Chebyshev or Richardson
+    (spectral bounds [lo, hi] of A on range(G) for the last two).
+    Returns (x, status, iterations, final ||r|| / ||b||)."""
+    F, K, mu, n = _fields(F, K, mu)
+    b = _c(b).reshape(F.shape)
+    x = np.empty_like(F)
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    n0, n1, n2 = F.shape[-3:]
+    st = lib().orc_krylov(n0, n1, n2, _p(K), _p(mu), _p(F), _p(b), _p(x), eta, max_it, METHODS[method], lo, hi,
+                          ctypes.byref(it), ctypes.byref(rel))
+    return x, st, it.value, rel.value
+
+
+def solve_increment_krylov(K, mu, F, Fbar, method, lo, hi, eta_nw=1e-5, eta_cg=1e-8, max_newton=50,
+                           max_cg=10000):
+    """One increment whose linear solves use `method`.  Returns (status, F_new, P, Pbar, stats)."""
+    F = np.array(F, dtype=np.float64, copy=True, order="C")
+    grid = F.shape[1:]
+    K = _c(np.broadcast_to(K, grid))
+    mu = _c(np.broadcast_to(mu, grid))
+    Fbar = _c(np.asarray(Fbar, dtype=np.float64).reshape(9))
+    P = np.zeros_like(F)
+    Pbar = np.zeros(9)
+    st = Stats()
+    status = lib().orc_solve_increment_krylov(grid[0], grid[1], grid[2], _p(K), _p(mu), _p(F), _p(Fbar), eta_nw,
+                                              eta_cg, max_newton, max_cg, _p(P), _p(Pbar), ctypes.byref(st),
+                                              METHODS[method], lo, hi)
+    return status, F, P, Pbar, st.as_dict()
 
 
 def identity_field(shape):

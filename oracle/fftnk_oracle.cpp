@@ -371,6 +371,10 @@ typedef struct {
   const double* H;
   const double* hist;
   int nyq;  // Nyquist choice of the projection (see orc_project_nyq)
+  // Krylov method of the linear solves: 0 conjugate gradients; 1 Chebyshev,
+  // 2 Richardson, both with the spectral bounds [lo, hi] of A on range(G)
+  int krylov;
+  double lo, hi;
 } orc_problem;
 
 static int law_stress(const orc_problem& pb, const double* F, double* P, double* hist_new);
@@ -431,6 +435,96 @@ static int cg_solve(const orc_problem& pb, const double* Flin, const double* b, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Other Krylov methods on the same operator (the paper names CG as one choice
+// of projection-based Krylov solver, Sec. 2.6; these are the classical
+// fixed-coefficient alternatives).  Both need bounds 0 < lo <= hi of the
+// spectrum of A on range(G) and no inner product but the stopping test.
+//
+// Chebyshev iteration (Saad, Iterative Methods for Sparse Linear Systems,
+// Sec. 12.1): theta = (hi + lo)/2, delta = (hi - lo)/2, sigma = theta/delta;
+// x0 = 0, r0 = b, d0 = r0/theta, rho0 = 1/sigma; then
+//   x += d,  r -= A d,  rho' = 1/(2 sigma - rho),  d = rho' rho d + (2 rho'/delta) r.
+// The residual is r_k = T_k((theta - A)/delta) r0 / T_k(sigma) (T_k: Chebyshev
+// polynomial of the first kind).
+//
+// Richardson iteration with the optimal fixed step omega = 2/(lo + hi):
+//   x += omega r,  r -= omega A r,  so r_k = (I - omega A)^k r0.
+//
+// Stopping test, iteration count and statuses as in cg_solve.
+// ---------------------------------------------------------------------------
+static void apply_A(const orc_problem& pb, const double* Flin, const double* p, double* Ap) {
+  const long m = 9L * pb.n0 * pb.n1 * pb.n2;
+  std::vector<double> t(m);
+  law_tangent(pb, Flin, p, t.data());
+  orc_project_nyq(pb.n0, pb.n1, pb.n2, t.data(), Ap, pb.nyq);
+}
+
+static int chebyshev_solve(const orc_problem& pb, const double* Flin, const double* b, double* x, double eta,
+                           int max_it, int* iters, double* relres) {
+  const long m = 9L * pb.n0 * pb.n1 * pb.n2;
+  *iters = 0;
+  *relres = 1.0;
+  if (!(pb.lo > 0.0) || !(pb.hi > pb.lo)) return ORC_EINVAL;
+  const double theta = 0.5 * (pb.hi + pb.lo), delta = 0.5 * (pb.hi - pb.lo), sigma = theta / delta;
+  std::vector<double> r(b, b + m), d(m), Ad(m);
+  for (long i = 0; i < m; ++i) {
+    x[i] = 0.0;
+    d[i] = r[i] / theta;
+  }
+  const double bb = dot(b, b, m), stop = eta * std::sqrt(bb);
+  if (std::sqrt(bb) <= stop) {
+    *relres = 0.0;
+    return ORC_OK;
+  }
+  double rho = 1.0 / sigma;
+  while (true) {
+    if (*iters >= max_it) return ORC_ECG_MAXIT;
+    apply_A(pb, Flin, d.data(), Ad.data());
+    ++*iters;
+    for (long i = 0; i < m; ++i) {
+      x[i] += d[i];
+      r[i] -= Ad[i];
+    }
+    const double rr = dot(r.data(), r.data(), m);
+    *relres = std::sqrt(rr / bb);
+    if (!std::isfinite(rr)) return ORC_ENONFINITE;
+    if (std::sqrt(rr) <= stop) return ORC_OK;
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    for (long i = 0; i < m; ++i) d[i] = rho1 * rho * d[i] + (2.0 * rho1 / delta) * r[i];
+    rho = rho1;
+  }
+}
+
+static int richardson_solve(const orc_problem& pb, const double* Flin, const double* b, double* x, double eta,
+                            int max_it, int* iters, double* relres) {
+  const long m = 9L * pb.n0 * pb.n1 * pb.n2;
+  *iters = 0;
+  *relres = 1.0;
+  if (!(pb.lo > 0.0) || !(pb.hi >= pb.lo)) return ORC_EINVAL;
+  const double omega = 2.0 / (pb.lo + pb.hi);
+  std::vector<double> r(b, b + m), Ar(m);
+  for (long i = 0; i < m; ++i) x[i] = 0.0;
+  const double bb = dot(b, b, m), stop = eta * std::sqrt(bb);
+  if (std::sqrt(bb) <= stop) {
+    *relres = 0.0;
+    return ORC_OK;
+  }
+  while (true) {
+    if (*iters >= max_it) return ORC_ECG_MAXIT;
+    apply_A(pb, Flin, r.data(), Ar.data());
+    ++*iters;
+    for (long i = 0; i < m; ++i) {
+      x[i] += omega * r[i];
+      r[i] -= omega * Ar[i];
+    }
+    const double rr = dot(r.data(), r.data(), m);
+    *relres = std::sqrt(rr / bb);
+    if (!std::isfinite(rr)) return ORC_ENONFINITE;
+    if (std::sqrt(rr) <= stop) return ORC_OK;
+  }
+}
+
 // Solve A dF = b unless b is at the round-off floor ||b|| <= 1e-14 ||Y|| of the
 // field Y that G was applied to; then dF = 0 with zero iterations.
 static int cg_or_zero(const orc_problem& pb, const double* Flin, const double* b, const double* Y,
@@ -443,6 +537,8 @@ static int cg_or_zero(const orc_problem& pb, const double* Flin, const double* b
     *relres = 0.0;
     return ORC_OK;
   }
+  if (pb.krylov == 1) return chebyshev_solve(pb, Flin, b, x, eta, max_cg, iters, relres);
+  if (pb.krylov == 2) return richardson_solve(pb, Flin, b, x, eta, max_cg, iters, relres);
   return cg_solve(pb, Flin, b, x, eta, max_cg, iters, relres);
 }
 
@@ -555,7 +651,7 @@ static int solve_increment_impl(const orc_problem& pb, double* F, const double* 
 int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* mu, double* F,
                         const double* Fbar, double eta_nw, double eta_cg, int max_newton, int max_cg,
                         double* P, double* Pbar, orc_stats* st) {
-  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0};
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0, 0, 0.0, 0.0};
   return solve_increment_impl(pb, F, Fbar, eta_nw, eta_cg, max_newton, max_cg, P, Pbar, nullptr, st);
 }
 
@@ -564,7 +660,7 @@ int orc_solve_increment(int n0, int n1, int n2, const double* K, const double* m
 int orc_solve_increment_nyq(int n0, int n1, int n2, const double* K, const double* mu, double* F,
                             const double* Fbar, double eta_nw, double eta_cg, int max_newton, int max_cg,
                             double* P, double* Pbar, orc_stats* st, int nyq_identity) {
-  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, nyq_identity ? 1 : 0};
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, nyq_identity ? 1 : 0, 0, 0.0, 0.0};
   return solve_increment_impl(pb, F, Fbar, eta_nw, eta_cg, max_newton, max_cg, P, Pbar, nullptr, st);
 }
 
@@ -575,7 +671,7 @@ int orc_solve_increment_j2(int n0, int n1, int n2, const double* K, const double
                            double eta_cg, int max_newton, int max_cg, double* P, double* Pbar, orc_stats* st) {
   const long n = (long)n0 * n1 * n2;
   std::vector<double> h0(hist, hist + 7 * n);
-  orc_problem pb{n0, n1, n2, K, mu, 1, ty0, H, h0.data(), 0};
+  orc_problem pb{n0, n1, n2, K, mu, 1, ty0, H, h0.data(), 0, 0, 0.0, 0.0};
   return solve_increment_impl(pb, F, Fbar, eta_nw, eta_cg, max_newton, max_cg, P, Pbar, hist, st);
 }
 
@@ -752,7 +848,7 @@ static int solve_mixed_impl(const orc_problem& pb, double* F, double* Fbar, cons
 // dPbar/dFbar at the equilibrium F (St. Venant-Kirchhoff), columns with want[m].
 int orc_macro_tangent(int n0, int n1, int n2, const double* K, const double* mu, const double* F, const int* want,
                       double eta_cg, int max_cg, double* C) {
-  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0};
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0, 0, 0.0, 0.0};
   return macro_tangent_impl(pb, F, want, C, eta_cg, max_cg, nullptr);
 }
 
@@ -764,7 +860,7 @@ int orc_solve_increment_mixed(int n0, int n1, int n2, const double* K, const dou
                               const int* mask, const double* Ptarget, double tol_stress, int max_outer,
                               double eta_nw, double eta_cg, int max_newton, int max_cg, double* P, double* Pbar,
                               orc_stats* st, int* outer) {
-  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0};
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0, 0, 0.0, 0.0};
   return solve_mixed_impl(pb, F, Fbar, mask, Ptarget, tol_stress, max_outer, eta_nw, eta_cg, max_newton, max_cg,
                           P, Pbar, nullptr, st, outer);
 }
@@ -777,7 +873,7 @@ int orc_solve_increment_mixed_j2(int n0, int n1, int n2, const double* K, const 
                                  int* outer) {
   const long n = (long)n0 * n1 * n2;
   std::vector<double> h0(hist, hist + 7 * n);
-  orc_problem pb{n0, n1, n2, K, mu, 1, ty0, H, h0.data(), 0};
+  orc_problem pb{n0, n1, n2, K, mu, 1, ty0, H, h0.data(), 0, 0, 0.0, 0.0};
   return solve_mixed_impl(pb, F, Fbar, mask, Ptarget, tol_stress, max_outer, eta_nw, eta_cg, max_newton, max_cg,
                           P, Pbar, hist, st, outer);
 }
@@ -801,7 +897,7 @@ int orc_solve_increment_mixed_j2(int n0, int n1, int n2, const double* K, const 
 int orc_adjoint(int n0, int n1, int n2, const double* K, const double* mu, const double* F, const double* g,
                 double eta_cg, int max_cg, double* dLdmu, double* dLdK, int* iters) {
   const long n = (long)n0 * n1 * n2, m = 9 * n;
-  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0};
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0, 0, 0.0, 0.0};
   std::vector<double> U(m), Y(m), b(m), w(m);
   for (int c = 0; c < 9; ++c)
     for (long v = 0; v < n; ++v) U[c * n + v] = g[c];
@@ -838,10 +934,28 @@ int orc_adjoint(int n0, int n1, int n2, const double* K, const double* mu, const
   return ORC_OK;
 }
 
+// Exposed for tests: one linear solve with the Krylov method `method` (0 CG, 1
+// Chebyshev, 2 Richardson; bounds lo, hi for 1 and 2) at Flin, x0 = 0.
+int orc_krylov(int n0, int n1, int n2, const double* K, const double* mu, const double* Flin, const double* b,
+               double* x, double eta, int max_it, int method, double lo, double hi, int* iters, double* relres) {
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0, method, lo, hi};
+  if (method == 1) return chebyshev_solve(pb, Flin, b, x, eta, max_it, iters, relres);
+  if (method == 2) return richardson_solve(pb, Flin, b, x, eta, max_it, iters, relres);
+  return cg_solve(pb, Flin, b, x, eta, max_it, iters, relres);
+}
+
+// One increment (St. Venant-Kirchhoff) whose linear solves use `method`.
+int orc_solve_increment_krylov(int n0, int n1, int n2, const double* K, const double* mu, double* F,
+                               const double* Fbar, double eta_nw, double eta_cg, int max_newton, int max_cg,
+                               double* P, double* Pbar, orc_stats* st, int method, double lo, double hi) {
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0, method, lo, hi};
+  return solve_increment_impl(pb, F, Fbar, eta_nw, eta_cg, max_newton, max_cg, P, Pbar, nullptr, st);
+}
+
 // Exposed for tests: plain CG on the operator at a given linearisation point.
 int orc_cg(int n0, int n1, int n2, const double* K, const double* mu, const double* Flin, const double* b,
            double* x, double eta, int max_cg, int* iters, double* relres) {
-  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0};
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0, 0, 0.0, 0.0};
   return cg_solve(pb, Flin, b, x, eta, max_cg, iters, relres);
 }
 
