@@ -139,6 +139,29 @@ int fftnk_set_option(fftnk_ctx* ctx, int option, int value);
 int fftnk_reset_state(fftnk_ctx* ctx);
 
 /*
+ * Krylov method of every later linear solve.  Sec. 2.6 uses conjugate
+ * gradients as one choice of projection-based Krylov solver;
+ * FFTNK_KRYLOV_CG (the default) is that.  FFTNK_KRYLOV_CHEBYSHEV and
+ * FFTNK_KRYLOV_RICHARDSON are the classical fixed-coefficient alternatives
+ * on the same operator and the same fused kernels: with bounds 0 < lo < hi
+ * (Richardson: lo <= hi) of the spectrum of A on range(G),
+ *   Chebyshev (Saad, Iterative Methods for Sparse Linear Systems, Sec. 12.1):
+ *     x += gamma_k p_k, r -= gamma_k A p_k, p_{k+1} = r_{k+1} + beta_{k+1} p_k
+ *     with gamma, beta from the three-term recurrence of Chebyshev
+ *     polynomials on [lo, hi];
+ *   Richardson: x += omega r, r -= omega A r, omega = 2 / (lo + hi).
+ * They need no inner product but the stopping test's <r, r>.  Bounds that do
+ * not enclose the spectrum make them diverge (the solve then ends with
+ * FFTNK_ENONFINITE or FFTNK_ECG_MAXIT).  At F = I on gradients,
+ * mu_min <= <p, A p> / <p, p> <= 3 K_max (periodic Korn inequality and the
+ * largest local eigenvalue); finite strain and plasticity move the spectrum.
+ * Same stopping test as CG; the counts reported as cg_iters are operator
+ * applications.  Bad method or bounds: FFTNK_EINVAL.
+ */
+enum { FFTNK_KRYLOV_CG = 0, FFTNK_KRYLOV_CHEBYSHEV = 1, FFTNK_KRYLOV_RICHARDSON = 2 };
+int fftnk_set_krylov(fftnk_ctx* ctx, int method, double lo, double hi);
+
+/*
  * One load increment of Algorithm 1 (Sec. 3.1-3.2) with the macroscopic
  * deformation gradient prescribed: dFbar = Fbar - mean(F_t); the first solve
  * G:K(F_t):dF = -G:K(F_t):dFbar distributes the load with the tangent of the
@@ -213,6 +236,20 @@ int fftnk_set_linearization(fftnk_ctx* ctx, const double* F_dev);
  * they must not alias.
  */
 int fftnk_apply_operator(fftnk_ctx* ctx, const void* p_dev, void* Ap_dev);
+
+/*
+ * One linear solve A x = G(b) with the operator of fftnk_apply_operator at the
+ * linearisation point of fftnk_set_linearization, x0 = 0, by the Krylov method
+ * of fftnk_set_krylov (CG by default), stopped when ||r|| <= eta ||G(b)||
+ * (FFTNK_FP32_MIXED: eta at least 1e-6) or after max_it operator
+ * applications (FFTNK_ECG_MAXIT, x then holds the last iterate).  b_dev,
+ * x_dev: device double [9][n] (b is projected with G in FP64 first; in FP32
+ * mode x is the FP32 solution rounded up and projected again).  stats
+ * (optional, [nrve]): one solve with its iteration count and final
+ * ||r|| / ||G(b)||.  Batched contexts solve every RVE together.
+ */
+int fftnk_solve_linear(fftnk_ctx* ctx, const double* b_dev, double* x_dev, double eta, int max_it,
+                       fftnk_stats* stats);
 
 /*
  * The compatibility projection alone (Sec. 2.5; App. C for even axes):

@@ -110,6 +110,8 @@ struct fftnk_ctx {
   size_t lds[8] = {};  // row64, row32, col1_64, col1_32, col0_64, col0_32, row1_64, row1_32
   int eng[3] = {};     // per axis: bit 0 some cell on the LDS engine, bit 1 on the 8-point, bit 2 on the 12-point one
   int nyq_id = 0;      // FFTNK_OPT_NYQUIST
+  int krylov = KRYLOV_CG;  // fftnk_set_krylov
+  double k_lo = 0.0, k_hi = 0.0;
   // workspace layout (byte offsets)
   size_t o_hist, o_hnew;  // J2 history: committed and of the current iterate, [7][ntot] each
   size_t o_Ft, o_F, o_P, o_x, o_r, o_p, o_w, o_F32, o_d64, o_spec, o_phase, o_mu, o_mtab, o_part, o_cg, o_red,
@@ -466,7 +468,7 @@ int launch_iterations(fftnk_ctx* c, int k) {
 int run_cg(fftnk_ctx* c, double eta, int max_cg) {
   const Launch L = c->launch();
   const int stall = c->prec == PREC_F32 ? 50 : 0;
-  launch_cg_init(L, c->cg(), eta, max_cg, stall);
+  launch_cg_init(L, c->cg(), eta, max_cg, stall, c->krylov, c->k_lo, c->k_hi);
   int e = check_launch();
   if (e) return e;
   int launched = std::max(1, std::min(c->cg_estimate - 2, max_cg));
@@ -851,6 +853,24 @@ int fftnk_set_option(fftnk_ctx* c, int option, int value) {
   }
 }
 
+int fftnk_set_krylov(fftnk_ctx* c, int method, double lo, double hi) {
+  if (!c) return FFTNK_EINVAL;
+  switch (method) {
+    case FFTNK_KRYLOV_CG: break;
+    case FFTNK_KRYLOV_CHEBYSHEV:
+      if (!(lo > 0.0) || !(hi > lo) || !std::isfinite(hi)) return FFTNK_EINVAL;
+      break;
+    case FFTNK_KRYLOV_RICHARDSON:
+      if (!(lo > 0.0) || !(hi >= lo) || !std::isfinite(hi)) return FFTNK_EINVAL;
+      break;
+    default: return FFTNK_EINVAL;
+  }
+  c->krylov = method;
+  c->k_lo = lo;
+  c->k_hi = hi;
+  return FFTNK_OK;
+}
+
 int fftnk_reset_state(fftnk_ctx* c) {
   if (!c) return FFTNK_EINVAL;
   if (!c->ws) return FFTNK_ESTATE;
@@ -1085,6 +1105,34 @@ int fftnk_apply_operator(fftnk_ctx* c, const void* p_dev, void* Ap_dev) {
   middle_passes(c->prec, L, c->spec(), nullptr);
   launch_inv_a2(c->prec, INV_OUT, L, c->spec(), Ap_dev, c->prec, nullptr, 1.0, nullptr);
   return check_launch();
+}
+
+int fftnk_solve_linear(fftnk_ctx* c, const double* b_dev, double* x_dev, double eta, int max_it,
+                       fftnk_stats* stats) {
+  if (!c || !b_dev || !x_dev || !(eta >= 0) || max_it < 1) return FFTNK_EINVAL;
+  if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
+  // r = G(b) (FP64 projection, rounded to the context precision), x = 0
+  rhs_pipeline(c, FWD_COPY, b_dev, nullptr, +1.0);
+  const double eta_eff = c->prec == PREC_F32 ? std::max(eta, 1e-6) : eta;
+  int e = run_cg(c, eta_eff, max_it);
+  if (e) return e;
+  int worst = FFTNK_OK;
+  for (int r = 0; r < c->nrve; ++r) {
+    const CgState& q = c->host_cg()[r];
+    if (stats) {
+      std::memset(&stats[r], 0, sizeof(fftnk_stats));
+      stats[r].n_solves = 1;
+      stats[r].cg_iters[0] = q.iter;
+      stats[r].cg_relres[0] = (q.bb > 0 && !q.zero_rhs) ? std::sqrt(q.rr / q.bb) : 0.0;
+      stats[r].status = q.status;
+    }
+    if (q.status && !worst) worst = q.status;
+  }
+  const void* x = newton_update_source(c);  // FP64 in both precisions
+  HIP_TRY(hipMemcpyAsync(x_dev, x, 9 * (size_t)c->ntot * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  e = check_launch();
+  return e ? e : worst;
 }
 
 int fftnk_project(fftnk_ctx* c, const void* a_dev, void* Ga_dev) {

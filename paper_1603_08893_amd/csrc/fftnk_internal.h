@@ -120,7 +120,15 @@ struct CgState {
   int zero_rhs;    // 1: ||b|| at the round-off floor of the projected field, dF = 0
   int x_due;       // 1: x still lacks alpha p of the last iteration (applied by the next
                    //    iteration's first pass, or by the finishing kernel)
+  int method;      // KRYLOV_*: how alpha and beta are chosen
+  double lo, hi;   // spectral bounds of A on range(G) (Chebyshev, Richardson)
+  double rho, gam; // Chebyshev recurrence: rho_k and the step gamma_k of the current direction
 };
+
+// Krylov methods sharing the fused CG passes (x += alpha p deferred,
+// p = r + beta p, r -= alpha A p): CG (alpha, beta from inner products),
+// Chebyshev and Richardson (fixed coefficients from [lo, hi]).
+enum { KRYLOV_CG = 0, KRYLOV_CHEBYSHEV = 1, KRYLOV_RICHARDSON = 2 };
 
 // Everything a launch needs to find its RVE, tables and partial-sum slots.
 struct Batch {
@@ -188,7 +196,8 @@ void launch_inv_a2(int prec, int mode, const Launch& L, const void* spec, void* 
 void launch_cg_finish(int prec, const Launch& L, void* x_T, const void* p_T, const CgState* cg);
 void launch_cg_alpha(const Launch& L, CgState* cg);
 void launch_cg_beta(const Launch& L, CgState* cg);
-void launch_cg_init(const Launch& L, CgState* cg, double eta, int max_cg, int stall);
+void launch_cg_init(const Launch& L, CgState* cg, double eta, int max_cg, int stall, int method = KRYLOV_CG,
+                    double lo = 0.0, double hi = 0.0);
 void launch_set_F(const Launch& L, const double* Ft, double* F, float* Flin32);
 void launch_newton_update(int prec, const Launch& L, const Material& mat, double* F, const void* x_T, double* P,
                           float* Flin32, bool add_uni);

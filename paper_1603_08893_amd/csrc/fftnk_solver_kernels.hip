@@ -41,9 +41,19 @@ __device__ __forceinline__ int kstart(const Batch& B, int kind, int r) { return 
 // One work-group per RVE.  A finished RVE (Newton mask) gets done = 1 at once.
 // If ||b|| is at the round-off floor of the projected field Y
 // (||b|| <= 1e-14 ||Y||, or b = 0) the solve is skipped with dF = 0.
-__global__ __launch_bounds__(kThreads) void k_cg_init(Batch B, CgState* cg, double eta, int max_cg, int stall) {
+__global__ __launch_bounds__(kThreads) void k_cg_init(Batch B, CgState* cg, double eta, int max_cg, int stall,
+                                                      int method, double lo, double hi) {
   const int rv = blockIdx.x;
   CgState& s = cg[rv];
+  if (threadIdx.x == 0) {
+    // Chebyshev (Saad, Sec. 12.1): theta = (hi + lo)/2, delta = (hi - lo)/2,
+    // sigma = theta/delta, rho_0 = 1/sigma, first step gamma_0 = 1/theta
+    s.method = method;
+    s.lo = lo;
+    s.hi = hi;
+    s.rho = method == KRYLOV_CHEBYSHEV ? (hi - lo) / (hi + lo) : 0.0;
+    s.gam = method == KRYLOV_CHEBYSHEV ? 2.0 / (hi + lo) : 0.0;
+  }
   if (B.active && B.active[rv] == 0) {
     if (threadIdx.x == 0) {
       s.done = 1;
@@ -83,6 +93,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_alpha(Batch B, CgState* cg) {
   const int rv = blockIdx.x;
   CgState& s = cg[rv];
   if (s.done) return;
+  if (s.method != KRYLOV_CG) {  // fixed coefficients: the step of the recurrence
+    if (threadIdx.x == 0) {
+      s.alpha = s.method == KRYLOV_CHEBYSHEV ? s.gam : 2.0 / (s.lo + s.hi);
+      s.x_due = 1;
+    }
+    return;
+  }
   const double pw = reduce_range(pslot(B, SLOT_PW), kstart(B, K_ROW1, rv), kstart(B, K_ROW1, rv + 1));
   if (threadIdx.x == 0) {
     s.pw = pw;
@@ -121,7 +138,20 @@ __global__ __launch_bounds__(kThreads) void k_cg_beta(Batch B, CgState* cg) {
       s.status = ST_CG_MAXIT;
       s.done = 1;
     } else {
-      s.beta = rr / s.rr;
+      if (s.method == KRYLOV_CHEBYSHEV) {
+        // rho_{k+1} = 1/(2 sigma - rho_k), gamma_{k+1} = 2 rho_{k+1}/delta; with
+        // the direction p = d / gamma (d the recurrence's update),
+        // beta = rho_{k+1} rho_k gamma_k / gamma_{k+1}
+        const double sigma = (s.hi + s.lo) / (s.hi - s.lo), delta = 0.5 * (s.hi - s.lo);
+        const double rho1 = 1.0 / (2.0 * sigma - s.rho), gam1 = 2.0 * rho1 / delta;
+        s.beta = rho1 * s.rho * s.gam / gam1;
+        s.rho = rho1;
+        s.gam = gam1;
+      } else if (s.method == KRYLOV_RICHARDSON) {
+        s.beta = 0.0;
+      } else {
+        s.beta = rr / s.rr;
+      }
       s.rr = rr;
       // progress = the residual norm 13 % below the last recorded minimum
       // (rr below 0.75 of it); at the FP32 rounding floor the residual only
@@ -420,8 +450,9 @@ void launch_cg_beta(const Launch& L, CgState* cg) {
   hipLaunchKernelGGL(k_cg_beta, dim3(L.b.nrve), dim3(kThreads), 0, L.s, L.b, cg);
 }
 
-void launch_cg_init(const Launch& L, CgState* cg, double eta, int max_cg, int stall) {
-  hipLaunchKernelGGL(k_cg_init, dim3(L.b.nrve), dim3(kThreads), 0, L.s, L.b, cg, eta, max_cg, stall);
+void launch_cg_init(const Launch& L, CgState* cg, double eta, int max_cg, int stall, int method, double lo,
+                    double hi) {
+  hipLaunchKernelGGL(k_cg_init, dim3(L.b.nrve), dim3(kThreads), 0, L.s, L.b, cg, eta, max_cg, stall, method, lo, hi);
 }
 
 void launch_set_F(const Launch& L, const double* Ft, double* F, float* Flin32) {

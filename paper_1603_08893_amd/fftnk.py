@@ -17,13 +17,15 @@ OK, EINVAL, ESTATE, ENOMEM, EHIP, ECG_MAXIT, ECG_BREAKDOWN, ENEWTON_MAXIT, ENONF
 FP64, FP32_MIXED = 0, 1
 SVK, J2 = 0, 1
 OPT_GRAPHS, OPT_CHECK_EVERY, OPT_NYQUIST = 1, 2, 3
+KRYLOV = {"cg": 0, "chebyshev": 1, "richardson": 2}
 MAX_SOLVES = 64
 
 # every symbol include/fftnk.h declares
 EXPORTS = [
     "fftnk_create", "fftnk_create_batched", "fftnk_workspace_bytes", "fftnk_bind_workspace", "fftnk_set_phases",
     "fftnk_set_material", "fftnk_set_modulus_field", "fftnk_set_option", "fftnk_reset_state", "fftnk_solve_increment",
-    "fftnk_solve_increment_mixed", "fftnk_macro_tangent",
+    "fftnk_solve_increment_mixed", "fftnk_macro_tangent", "fftnk_set_krylov",
+    "fftnk_solve_linear",
     "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_adjoint",
     "fftnk_launch_pass", "fftnk_profile_cg", "fftnk_get_history", "fftnk_set_history", "fftnk_get_state",
     "fftnk_set_state", "fftnk_status_string", "fftnk_destroy",
@@ -75,6 +77,8 @@ def lib():
     L.fftnk_set_modulus_field.argtypes = [vp, vp]
     L.fftnk_set_option.argtypes = [vp, i, i]
     L.fftnk_reset_state.argtypes = [vp]
+    L.fftnk_set_krylov.argtypes = [vp, i, d, d]
+    L.fftnk_solve_linear.argtypes = [vp, vp, vp, d, i, ctypes.POINTER(Stats)]
     L.fftnk_solve_increment.argtypes = [vp, dp, d, d, i, i, vp, vp, dp, ctypes.POINTER(Stats)]
     ip = ctypes.POINTER(i)
     L.fftnk_solve_increment_mixed.argtypes = [vp, dp, ip, dp, d, i, d, d, i, i, vp, vp, dp, ctypes.POINTER(Stats), ip]
@@ -194,6 +198,18 @@ class Solver:
         OPT_NYQUIST (0: G-hat zero at Nyquist frequencies, 1: identity there)."""
         _check(lib().fftnk_set_option(self.ctx, int(option), int(value)), "fftnk_set_option")
 
+    def set_krylov(self, method="cg", lo=None, hi=None, table=None):
+        """Krylov method of later linear solves: "cg", "chebyshev" or "richardson".
+        The last two need spectral bounds [lo, hi] of A on range(G); if omitted
+        they are taken from a St. Venant-Kirchhoff table [(K, mu), ...] as
+        [0.9 min mu, 1.1 max 3K] (near F = I)."""
+        if method != "cg" and (lo is None or hi is None):
+            tab = np.asarray(table, dtype=np.float64)
+            lo = 0.9 * float(tab[:, 1].min()) if lo is None else lo
+            hi = 1.1 * 3.0 * float(tab[:, 0].max()) if hi is None else hi
+        _check(lib().fftnk_set_krylov(self.ctx, KRYLOV[method], float(lo or 0.0), float(hi or 0.0)),
+               "fftnk_set_krylov")
+
     def reset_state(self):
         _check(lib().fftnk_reset_state(self.ctx), "fftnk_reset_state")
 
@@ -266,6 +282,18 @@ class Solver:
         _check(lib().fftnk_apply_operator(self.ctx, ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(out.data_ptr())),
                "fftnk_apply_operator")
         return out
+
+    def solve_linear(self, b, eta=1e-8, max_it=10000, raise_on_error=True):
+        """x with A x = G(b) at the linearisation point (FP64 in and out).
+        Returns (status, x, stats list)."""
+        b = b.to(self.device, self.torch.float64).contiguous()
+        x = self.field(self.torch.float64)
+        stats = (Stats * self.nrve)()
+        st = lib().fftnk_solve_linear(self.ctx, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()), eta,
+                                      max_it, stats)
+        if raise_on_error and st not in (OK, ECG_MAXIT):
+            _check(st, "fftnk_solve_linear")
+        return st, x, [s.as_dict() for s in stats]
 
     def project(self, a, out=None):
         a = a.to(self.device, self.vdtype).contiguous()
