@@ -111,8 +111,10 @@ def main():
                          "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--extra", default="",
-                    help="comma list of sizes,c3,c4,c5: instead of the headline line, one JSON line per extra "
-                         "measurement (operator at 96^3..256^3; 64 batched cells; J2 at 96^3; adjoint 8 x 192^3)")
+                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov: instead of the headline line, one JSON line per extra "
+                         "measurement (operator at 96^3..256^3; 64 batched cells; J2 at 96^3; adjoint 8 x 192^3; "
+                         "the two Nyquist choices at 128^3; mixed control at 128^3; CG / Chebyshev / "
+                         "Richardson at 128^3)")
     args = ap.parse_args()
     if args.operator_only:
         return operator_only(args)
@@ -438,6 +440,109 @@ def extra(args):
                       "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
                 del s, fl, p, out
                 torch.cuda.empty_cache()
+
+    if "nyq" in which:
+        # App. C's two choices at Nyquist frequencies on the 128^3 two-phase
+        # cell: operator and CG-kernel times, and one tensile increment (with
+        # the identity choice the Nyquist rotations only have geometric
+        # stiffness: CG needs more iterations, and under shear it breaks down)
+        from paper_1603_08893_amd.fftnk import OPT_NYQUIST
+        n_ = 128
+        phase = ms.grf_threshold(n_, ell=8.0, frac=0.3, seed=1603)
+        tension = np.array([[1.03, 0.004, 0.0], [0.002, 1.02, 0.003], [0.0, -0.002, 1.025]]).reshape(9)
+        res = {"extra": "nyquist_choice", "grid": n_, "load": tension.tolist()}
+        pbars = {}
+        for choice in (0, 1):
+            s = Solver((n_,) * 3, precision="fp64")
+            s.set_phases(phase)
+            s.set_material(TABLE)
+            s.set_option(OPT_NYQUIST, choice)
+            s.solve_increment(tension, fields=False, raise_on_error=False)  # warm-up
+            s.reset_state()
+            (st, _, _, Pb, stats), sec = timed(lambda: s.solve_increment(tension, fields=False, raise_on_error=False))
+            pbars[choice] = Pb[0]
+            ms_k = s.profile_cg(20)
+            p = s.project(torch.from_numpy(ms.random_field((n_,) * 3, seed=42).reshape(-1)).to(dev))
+            out = s.field()
+            for _ in range(3):
+                s.apply_operator(p, out)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                s.apply_operator(p, out)
+            e1.record()
+            torch.cuda.synchronize()
+            res["identity" if choice else "zero"] = {
+                "status": int(st), "seconds": round(sec, 4), "newton_solves": stats[0]["n_solves"],
+                "cg_iterations": stats[0]["cg_iters"], "operator_ms": round(e0.elapsed_time(e1) / 20, 4),
+                "cg_iteration_ms": round(sum(ms_k.values()), 4), "pass3_ms": round(ms_k["pass3"], 4)}
+            del s, p, out
+            torch.cuda.empty_cache()
+        res["pbar_rel_diff"] = float(np.max(np.abs(pbars[1] - pbars[0])) / np.max(np.abs(pbars[0])))
+        emit(res)
+
+    if "mixed" in which:
+        # mixed control on the 128^3 two-phase cell: uniaxial stress (F11 =
+        # 1.02 prescribed with the lower off-diagonal entries, the other
+        # stress components zero) in one increment, against a deformation-
+        # controlled increment to the Fbar it finds; then the full macroscopic
+        # tangent (9 CG solves) at that state
+        n_ = 128
+        phase = ms.grf_threshold(n_, ell=8.0, frac=0.3, seed=1603)
+        mask = np.array([0, 1, 1, 0, 1, 1, 0, 0, 1])
+        guess = np.eye(3).reshape(9).copy()
+        guess[0] = 1.02
+        res = {"extra": "mixed_control", "grid": n_, "mask": mask.tolist(), "F11": 1.02, "tol_stress": 1e-8}
+        for prec in ("fp64", "fp32"):
+            s = Solver((n_,) * 3, precision=prec)
+            s.set_phases(phase)
+            s.set_material(TABLE)
+            s.solve_increment_mixed(guess, mask, np.zeros(9), 1e-8, fields=False, raise_on_error=False)  # warm-up
+            s.reset_state()
+            (st, _, _, Pb, Fb, stats, outer), sec = timed(
+                lambda: s.solve_increment_mixed(guess, mask, np.zeros(9), 1e-8, fields=False, raise_on_error=False))
+            s.reset_state()
+            (st2, _, _, Pb2, stats2), sec2 = timed(lambda: s.solve_increment(Fb[0], fields=False,
+                                                                            raise_on_error=False))
+            C, sec_c = timed(lambda: s.macro_tangent(eta_cg=1e-8))
+            res[prec] = {"status": int(st), "seconds": round(sec, 4), "outer_passes": int(outer[0]),
+                         "linear_solves": stats[0]["n_solves"], "cg_iterations": int(sum(stats[0]["cg_iters"])),
+                         "Fbar": [round(float(v), 8) for v in Fb[0]], "pbar": [float(v) for v in Pb[0]],
+                         "deformation_controlled_seconds": round(sec2, 4),
+                         "deformation_controlled_cg_iterations": int(sum(stats2[0]["cg_iters"])),
+                         "mixed_over_deformation_controlled": round(sec / sec2, 3),
+                         "macro_tangent_seconds": round(sec_c, 4),
+                         "macro_tangent_C11_C22_C12": [float(C[0][0, 0]), float(C[0][4, 4]), float(C[0][0, 4])]}
+            del s
+            torch.cuda.empty_cache()
+        emit(res)
+
+    if "krylov" in which:
+        # the three Krylov methods on the 128^3 two-phase cell: one C2-like
+        # increment (simple shear 0.05, eta_NW 1e-5, eta_CG 1e-8) each, with
+        # Chebyshev / Richardson bounds [0.9 min mu, 1.1 max 3K]
+        n_ = 128
+        phase = ms.grf_threshold(n_, ell=8.0, frac=0.3, seed=1603)
+        lo = 0.9 * min(m for _, m in TABLE)
+        hi = 1.1 * 3 * max(k for k, _ in TABLE)
+        res = {"extra": "krylov_methods", "grid": n_, "bounds": [lo, hi], "load": "simple shear 0.05"}
+        for prec in ("fp64", "fp32"):
+            for method in ("cg", "chebyshev", "richardson"):
+                s = Solver((n_,) * 3, precision=prec)
+                s.set_phases(phase)
+                s.set_material(TABLE)
+                s.set_krylov(method, lo, hi)
+                s.solve_increment(ms.simple_shear(0.05), fields=False, raise_on_error=False)  # warm-up
+                s.reset_state()
+                (st, _, _, Pb, stats), sec = timed(lambda: s.solve_increment(ms.simple_shear(0.05), fields=False,
+                                                                            raise_on_error=False))
+                its = stats[0]["cg_iters"]
+                res["%s_%s" % (method, prec)] = {
+                    "status": int(st), "seconds": round(sec, 4), "iterations": its,
+                    "ms_per_iteration": round(1e3 * sec / max(1, sum(its)), 4), "pbar00": float(Pb[0][0])}
+                del s
+                torch.cuda.empty_cache()
+        emit(res)
 
     if "c3" in which:
         # 64 cells of four sizes, each with its own spheres, contrast and load,

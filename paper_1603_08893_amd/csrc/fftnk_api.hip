@@ -235,7 +235,7 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
     for (int d = 0; d < 3; ++d) {
       const int nd = dims[3 * r + d];
       if (nd < 2 || nd > kMaxLen) return nd > kMaxLen ? FFTNK_EUNSUPPORTED : FFTNK_EINVAL;
-      if (!make_plan(nd, g.ax[d], d > 0)) return FFTNK_EUNSUPPORTED;  // pass 3 (a0) has no 12-point engine
+      if (!make_plan(nd, g.ax[d], true)) return FFTNK_EUNSUPPORTED;
     }
     g.h = (g.n2 % 2 == 0) ? g.n2 / 2 : (g.n2 + 1) / 2;
     g.n = (long long)g.n0 * g.n1 * g.n2;

@@ -667,9 +667,19 @@ __device__ __forceinline__ void tile_col_a0_project_id(const Batch& B, cx<T>* __
   }
 }
 
+// Three work-groups per CU, but two (256 VGPRs) where the registers of a
+// pencil's transforms do not fit otherwise: FP64 12-point pencils and the
+// identity choice's three transforms; one (accumulation registers too) for
+// the identity choice's three FP64 12-point transforms.
 template <typename T, int ENG, bool NYQ_ID>
-__global__ __launch_bounds__(kThreads, 3) void k_col_a0_project(Batch B, cx<T>* __restrict__ spec,
-                                                             const CgState* __restrict__ cg) {
+constexpr int a0_groups_per_cu() {
+  if (sizeof(T) == 8 && NYQ_ID && ENG == 12) return 1;
+  return (sizeof(T) == 8 && (ENG == 12 || (NYQ_ID && ENG != 0))) || (NYQ_ID && ENG == 12) ? 2 : 3;
+}
+
+template <typename T, int ENG, bool NYQ_ID>
+__global__ __launch_bounds__(kThreads, (a0_groups_per_cu<T, ENG, NYQ_ID>())) void k_col_a0_project(
+    Batch B, cx<T>* __restrict__ spec, const CgState* __restrict__ cg) {
   if constexpr (NYQ_ID)
     tile_col_a0_project_id<T, ENG>(B, spec, cg, blockIdx.x);
   else
@@ -972,10 +982,12 @@ static void col_a0_t(const Launch& L, void* spec, const CgState* cg) {
   cx<T>* sp = static_cast<cx<T>*>(spec);
   if (L.nyq) {
     if (L.eng[0] & 2) launch_tiles(&k_col_a0_project<T, 8, true>, ntiles, lds, L.s, L.b, sp, cg);
+    if (L.eng[0] & 4) launch_tiles(&k_col_a0_project<T, 12, true>, ntiles, lds, L.s, L.b, sp, cg);
     if (L.eng[0] & 1) launch_tiles(&k_col_a0_project<T, 0, true>, ntiles, lds, L.s, L.b, sp, cg);
     return;
   }
   if (L.eng[0] & 2) launch_tiles(&k_col_a0_project<T, 8, false>, ntiles, lds, L.s, L.b, sp, cg);
+  if (L.eng[0] & 4) launch_tiles(&k_col_a0_project<T, 12, false>, ntiles, lds, L.s, L.b, sp, cg);
   if (L.eng[0] & 1) launch_tiles(&k_col_a0_project<T, 0, false>, ntiles, lds, L.s, L.b, sp, cg);
 }
 

@@ -45,8 +45,8 @@ def _rel(a, b):
 
 SHAPES = [(5, 5, 5), (8, 8, 8), (7, 6, 9), (24, 24, 24), (31, 31, 31), (32, 32, 32), (12, 10, 17), (48, 40, 36),
           (3, 64, 4),
-          # lengths 3 * 2^k on a1 / a2 (12-point register engine: radix 12, then 4 / 2)
-          (10, 48, 12), (6, 12, 96), (3, 192, 24), (4, 6, 192)]
+          # lengths 3 * 2^k (12-point register engine: radix 12, then 4 / 2) on a1 / a2, and on a0
+          (10, 48, 12), (6, 12, 96), (3, 192, 24), (4, 6, 192), (96, 8, 10), (192, 4, 6), (12, 6, 8), (24, 5, 4)]
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])
