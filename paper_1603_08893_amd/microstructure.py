@@ -17,6 +17,12 @@ Recipes (all numpy ``default_rng`` / PCG64 with the stated seeds):
 * ``lognormal_field`` -- mu0 * exp(sigma * Z) with Z the standardised Gaussian
   random field above.
 * ``laminate`` -- two phases alternating along one axis.
+* ``micrograph_2d`` -- stand-in for the paper's thresholded 451 x 451 dual-phase
+  micrograph (Sec. 5, not available): a 2-D Gaussian random field with the same
+  periodic filter, thresholded at a hard-phase fraction, as an n x n x 2 plane-
+  strain cell (constant through the two a2 layers).
+* ``pure_shear_schedule`` -- the paper's 2-D load, Fbar = l e_x e_x + e_y e_y / l
+  (+ e_z e_z), l in equal steps to l_max.
 """
 import numpy as np
 
@@ -53,6 +59,39 @@ def grf_threshold(N=128, ell=8.0, frac=0.3, seed=1603):
     ph = np.zeros(flat.size, dtype=np.uint8)
     ph[order[:m]] = 1
     return ph.reshape(N, N, N)
+
+
+def micrograph_2d(N=451, ell=6.0, frac=0.3, seed=1701, layers=2):
+    """Plane-strain stand-in microstructure: an (N, N, layers) phase map whose
+    N x N section is a thresholded periodic 2-D Gaussian random field (phase 1,
+    the hard phase, is the top ``frac`` of pixels by rank, ties by index)."""
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((N, N))
+    k = np.fft.fftfreq(N)
+    filt = np.exp(-2.0 * np.pi ** 2 * ell ** 2 * (k[:, None] ** 2 + k[None, :] ** 2))
+    z = np.real(np.fft.ifft2(np.fft.fft2(w) * filt)).reshape(-1)
+    m = int(np.floor(frac * z.size))
+    order = np.lexsort((np.arange(z.size), -z))
+    ph = np.zeros(z.size, dtype=np.uint8)
+    ph[order[:m]] = 1
+    return np.repeat(ph.reshape(N, N)[:, :, None], layers, axis=2)
+
+
+def pure_shear(lam):
+    """Fbar = lam e_x e_x + e_y e_y / lam + e_z e_z (plane-strain pure shear)."""
+    return np.diag([lam, 1.0 / lam, 1.0]).reshape(9)
+
+
+def pure_shear_schedule(n_incr=250, lam_max=1.2):
+    return [pure_shear(1.0 + (lam_max - 1.0) * t / n_incr) for t in range(1, n_incr + 1)]
+
+
+def plane_strain_j2_table(chi, E=1.0, nu=0.3):
+    """J2 table of the 2-D example (Sec. 5): elastically homogeneous phases
+    (K, mu from E, nu), soft tau_y0 = 0.003 E, H = 0.01 E, hard = chi x soft."""
+    K = E / (3.0 * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    return [(K, mu, 0.003 * E, 0.01 * E), (K, mu, 0.003 * E * chi, 0.01 * E * chi)]
 
 
 def rsa_spheres(N, target_frac, seed, rmin=3, rmax=10, max_attempts=100000):
