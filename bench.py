@@ -111,10 +111,10 @@ def main():
                          "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--extra", default="",
-                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov: instead of the headline line, one JSON line per extra "
+                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d: instead of the headline line, one JSON line per extra "
                          "measurement (operator at 96^3..256^3; 64 batched cells; J2 at 96^3; adjoint 8 x 192^3; "
                          "the two Nyquist choices at 128^3; mixed control at 128^3; CG / Chebyshev / "
-                         "Richardson at 128^3)")
+                         "Richardson at 128^3; the 2-D plane-strain example at 451^2)")
     args = ap.parse_args()
     if args.operator_only:
         return operator_only(args)
@@ -543,6 +543,56 @@ def extra(args):
                 del s
                 torch.cuda.empty_cache()
         emit(res)
+
+    if "c2d" in which:
+        # the 2-D example (Sec. 5): plane strain on a 451 x 451 x 2 cell (the
+        # thresholded stand-in micrograph), J2 with linear hardening, pure shear
+        # to lambda = 1.2 in 250 increments, phase contrasts sqrt(2), 2, 4, 8;
+        # cumulative Newton / CG iterations and runtime against the macroscopic
+        # equivalent log strain (2 / sqrt(3)) ln(lambda)
+        n_, nincr = 451, 250
+        ph = ms.micrograph_2d(N=n_)
+        sched = ms.pure_shear_schedule(nincr, 1.2)
+        for chi in (np.sqrt(2.0), 2.0, 4.0, 8.0):
+            s = Solver(ph.shape, precision="fp64")
+            s.set_phases(ph)
+            s.set_material(ms.plane_strain_j2_table(chi), model=J2)
+            s.solve_increment(sched[0], fields=False)  # warm-up (graphs), then start over
+            s.reset_state()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            newton, cg, times, status, done = [], [], [], 0, 0
+            for k, Fbar in enumerate(sched):
+                st, _, _, Pb, stats = s.solve_increment(Fbar, fields=False, raise_on_error=False)
+                if st:
+                    status = st
+                    break
+                done += 1
+                newton.append(stats[0]["n_solves"])
+                cg.append(int(sum(stats[0]["cg_iters"])))
+                times.append(time.perf_counter() - t0)
+                if (k + 1) % 50 == 0:
+                    print("# c2d chi %.3f increment %d %.1fs" % (chi, k + 1, times[-1]), file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            eps_p = s.get_history().view(7, -1)[6].view(n_, n_, 2)[:, :, 0].cpu().numpy()
+            hard = ph[:, :, 0] == 1
+            marks = list(range(24, done, 25))
+            lam = [1.0 + 0.2 * (k + 1) / nincr for k in marks]
+            emit({"extra": "c2d_plane_strain", "grid": [n_, n_, 2], "chi": round(float(chi), 4),
+                  "hard_fraction": round(float(hard.mean()), 4), "increments_done": done, "status": int(status),
+                  "seconds": round(sec, 3), "increments_per_s": round(done / sec, 3),
+                  "newton_per_increment_mean": round(float(np.mean(newton)), 3),
+                  "newton_per_increment_max": int(max(newton)),
+                  "newton_iterations_by_increment": newton,
+                  "eps_bar": [round(2 / np.sqrt(3) * np.log(l), 5) for l in lam],
+                  "cumulative_newton": [int(np.sum(newton[:k + 1])) for k in marks],
+                  "cumulative_cg": [int(np.sum(cg[:k + 1])) for k in marks],
+                  "cumulative_seconds": [round(times[k], 3) for k in marks],
+                  "max_eps_p_soft": float(eps_p[~hard].max()), "max_eps_p_hard": float(eps_p[hard].max()),
+                  "pbar_last": [float(v) for v in Pb[0]]})
+            del s
+            torch.cuda.empty_cache()
 
     if "c3" in which:
         # 64 cells of four sizes, each with its own spheres, contrast and load,

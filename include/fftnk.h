@@ -70,9 +70,12 @@ typedef struct {
 typedef struct fftnk_ctx fftnk_ctx;
 
 /*
- * Create a context for one periodic cell of n0 x n1 x n2 voxels (each length
- * 2..256; any factorisation: radices 2, 3, 4, 5, 7, 8 run as register
- * butterflies, other primes as direct sums).  precision: FFTNK_FP64 or
+ * Create a context for one periodic cell of n0 x n1 x n2 voxels (n0, n1 in
+ * 2..512, n2 in 2..256; any factorisation: radices 2, 3, 4, 5, 7, 8 run as
+ * register butterflies, other primes as direct sums).  A plane-strain cell
+ * (the paper's 2-D example) is an n0 x n1 x 2 cell whose phases do not vary
+ * along a2 and whose Fbar has F33 = 1, F13 = F23 = F31 = F32 = 0: its fields
+ * have no a2 frequency but zero, so xi_2 = 0 and G acts as the 2-D projection.  precision: FFTNK_FP64 or
  * FFTNK_FP32_MIXED.  hip_stream: a hipStream_t (NULL = default stream).
  * Returns FFTNK_EINVAL for bad sizes.  The context owns host memory only.
  */

@@ -54,7 +54,7 @@ bool make_plan(int n, AxisPlan& pl, bool allow12) {
       m /= p;
     }
   }
-  if ((1 << e2) == n && e2 >= 3)
+  if ((1 << e2) == n && e2 >= 3 && n <= kMaxRegLen)
     pl.reg = 8;
   else if (allow12 && n == 3 * (1 << e2) && e2 >= 2 && n <= 192)
     pl.reg = 12;
@@ -234,7 +234,8 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
     g.n2 = dims[3 * r + 2];
     for (int d = 0; d < 3; ++d) {
       const int nd = dims[3 * r + d];
-      if (nd < 2 || nd > kMaxLen) return nd > kMaxLen ? FFTNK_EUNSUPPORTED : FFTNK_EINVAL;
+      const int lim = d == 2 ? kMaxLenA2 : kMaxLen;
+      if (nd < 2 || nd > lim) return nd > lim ? FFTNK_EUNSUPPORTED : FFTNK_EINVAL;
       if (!make_plan(nd, g.ax[d], true)) return FFTNK_EUNSUPPORTED;
     }
     g.h = (g.n2 % 2 == 0) ? g.n2 / 2 : (g.n2 + 1) / 2;

@@ -373,10 +373,10 @@ __device__ __forceinline__ void reg_stages(cx<T> (&v)[P], int t, const cx<T>* tw
 }
 
 // Transform of length n with P points per thread: P = 8 for n a power of two in
-// [8, kMaxLen], P = 12 for n = 3 2^k in [12, 192]; t in [0, n / P).
+// [8, kMaxRegLen], P = 12 for n = 3 2^k in [12, 192]; t in [0, n / P).
 template <typename T, bool ROW, int P>
 __device__ __forceinline__ void reg_fft(cx<T> (&v)[P], int n, int t, const cx<T>* tw, bool inv, cx<T>* xl) {
-  static_assert(kMaxLen == 256, "length dispatch covers 8..256");
+  static_assert(kMaxRegLen == 256, "length dispatch covers 8..256");
   if constexpr (P == 8) {
     switch (n) {
       case 8: reg_stages<T, 8, 8, ROW, 0>(v, t, tw, inv, xl); break;

@@ -127,7 +127,7 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
     T d[9];
     if (row < g.rows) {
       const long long v = row * N2 + a2;
-      // uniform component base + 32-bit byte offset of the voxel (n <= 2^24);
+      // uniform component base + 32-bit byte offset of the voxel (n <= 512^2 256 = 2^26);
       // every load below is issued before any arithmetic uses it
       const unsigned vb = (unsigned)v * (unsigned)sizeof(T);
       if (MODE == FWD_COPY) {

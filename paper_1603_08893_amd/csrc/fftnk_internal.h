@@ -12,7 +12,9 @@ namespace fftnk {
 constexpr int kThreads = 256;      // work-group size of every kernel
 constexpr int kMaxStages = 12;     // radix stages of one 1-D transform
 constexpr int kMaxPhase = 256;     // material phases (every value of the one-byte phase index)
-constexpr int kMaxLen = 256;       // longest supported grid axis
+constexpr int kMaxLen = 512;       // longest supported a0 / a1 axis (the LDS engine above kMaxRegLen)
+constexpr int kMaxLenA2 = 256;     // longest a2 axis (pass 1 holds a work-group's lines one voxel per thread)
+constexpr int kMaxRegLen = 256;    // longest length of the register-resident engine
 constexpr int kMaxRve = 256;       // RVEs of one batched context
 constexpr int kRedBlocks = 2048;   // most work-groups of an element-wise kernel per RVE
 constexpr int kRegP = 8;           // points per thread of the register-resident FFT engine

@@ -1,0 +1,95 @@
+"""The paper's 2-D plane-strain example on the GPU (n0 x n1 x 2 cells), and the
+a0 / a1 lengths above 256 (LDS engine, up to 512) it needs, against the oracle.
+
+* Projection parity (FP64 1e-13, FP32 5e-6) on shapes with a0 or a1 in
+  257..512, including 451 = 11 x 41 (the example's size) and 512.
+* J2 plane-strain increments through yield under pure shear (the example's
+  load and parameters, phase contrast 2): F, history and P-bar within 1e-10 of
+  the oracle on the same cell, equal Newton counts; the out-of-plane
+  components stay zero and the fields constant through the layers.
+* The full 451 x 451 x 2 cell: projection idempotent and self-adjoint.
+"""
+import numpy as np
+import pytest
+
+from paper_1603_08893_amd import microstructure as ms
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])
+@pytest.mark.parametrize("shape", [(451, 6, 2), (5, 451, 2), (300, 7, 5), (512, 4, 4), (257, 3, 256), (9, 384, 6)])
+def test_project_long_axes(torch_cuda, orc, shape, prec, tol):
+    torch = torch_cuda
+    from paper_1603_08893_amd.fftnk import Solver
+    print("project long", shape, prec, flush=True)
+    A = ms.random_field(shape, seed=sum(shape))
+    s = Solver(shape, precision=prec)
+    s.set_phases(np.zeros(shape, dtype=np.uint8))
+    s.set_material([(1.0, 1.0)])
+    got = s.project(torch.from_numpy(A.reshape(-1))).double().cpu().numpy()
+    assert _rel(got, orc.project(A)) <= tol
+
+
+def _j2_inputs(ph):
+    tab = ms.plane_strain_j2_table(2.0)
+    pick = lambda j: np.choose(ph, [tab[0][j], tab[1][j]]).astype(float)
+    return tab, pick(0), pick(1), pick(2), pick(3)
+
+
+@pytest.mark.parametrize("n0,n1", [(15, 13), (16, 12)])
+def test_plane_strain_j2_vs_oracle(torch_cuda, orc, n0, n1):
+    from paper_1603_08893_amd import fftnk
+    print("plane strain j2", n0, n1, flush=True)
+    ph = ms.micrograph_2d(N=max(n0, n1), ell=2.0, frac=0.3, seed=5)[:n0, :n1, :]
+    ph = np.ascontiguousarray(ph)
+    shape = ph.shape
+    tab, K, mu, ty0, H = _j2_inputs(ph)
+    s = fftnk.Solver(shape, precision="fp64")
+    s.set_phases(ph)
+    s.set_material(tab, model=fftnk.J2)
+    h = orc.virgin_history(shape)
+    F = orc.identity_field(shape)
+    for lam in (1.004, 1.008, 1.012, 1.02):
+        st, F, P, Pbo, h, So = orc.solve_increment_j2(K, mu, ty0, H, h, F, ms.pure_shear(lam), 1e-8, 1e-10)
+        assert st == 0
+        stg, Fg, Pg, Pb, S = s.solve_increment(ms.pure_shear(lam), 1e-8, 1e-10)
+        print(lam, "oracle", So["cg_iters"], "gpu", S[0]["cg_iters"], flush=True)
+        assert S[0]["n_solves"] == So["n_solves"]
+        Fh = Fg.cpu().numpy().reshape((9,) + shape)
+        assert _rel(Fh, F) <= 1e-10
+        assert np.max(np.abs(Pb[0] - Pbo)) <= 1e-10 * np.max(np.abs(Pbo))
+    assert _rel(s.get_history().cpu().numpy(), h) <= 1e-10
+    assert np.max(h[6]) > 0
+    for c in (2, 5, 6, 7):
+        assert np.max(np.abs(Fh[c])) < 1e-14
+    assert np.max(np.abs(Fh[8] - 1.0)) < 1e-14
+    assert np.array_equal(Fh[..., 0], Fh[..., 1])  # a 2-point transform keeps the layers identical
+
+
+def test_projection_invariants_451(torch_cuda):
+    torch = torch_cuda
+    from paper_1603_08893_amd.fftnk import Solver
+    shape = (451, 451, 2)
+    print("projection invariants", shape, flush=True)
+    s = Solver(shape, precision="fp64")
+    s.set_phases(np.zeros(shape, dtype=np.uint8))
+    s.set_material([(1.0, 1.0)])
+    A = torch.from_numpy(ms.random_field(shape, seed=1).reshape(-1)).cuda()
+    B = torch.from_numpy(ms.random_field(shape, seed=2).reshape(-1)).cuda()
+    GA, GB = s.project(A), s.project(B)
+    scale = GA.abs().max().item()
+    assert (s.project(GA) - GA).abs().max().item() <= 1e-13 * scale
+    assert abs((B * GA).sum().item() - (GB * A).sum().item()) <= 1e-11 * abs((B * GA).sum().item())
