@@ -85,6 +85,8 @@ def lib():
                                                  i, i, dp, dp, ctypes.POINTER(Stats), i, ctypes.c_double,
                                                  ctypes.c_double]
         L.orc_solve_increment_krylov.restype = i
+        L.orc_solve_increment_krylov_nyq.argtypes = L.orc_solve_increment_krylov.argtypes + [i]
+        L.orc_solve_increment_krylov_nyq.restype = i
         L.orc_solve_increment.argtypes = [i, i, i, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                           i, i, dp, dp, ctypes.POINTER(Stats)]
         L.orc_solve_increment.restype = i
@@ -223,12 +225,12 @@ def cg(F, K, mu, b, eta=1e-8, max_cg=10000):
     return x, st, it.value, rel.value
 
 
-METHODS = {"cg": 0, "chebyshev": 1, "richardson": 2}
+METHODS = {"cg": 0, "chebyshev": 1, "richardson": 2, "gmres": 3}
 
 
 def krylov(F, K, mu, b, method="chebyshev", lo=0.0, hi=0.0, eta=1e-8, max_it=10000):
-    """One linear solve A x = b, x0 = 0, with CG, Chebyshev or Richardson
-    (spectral bounds [lo, hi] of A on range(G) for the last two).
+    """One linear solve A x = b, x0 = 0, with CG, Chebyshev, Richardson
+    (spectral bounds [lo, hi] of A on range(G)) or GMRES (lo = restart length).
     Returns (x, status, iterations, final ||r|| / ||b||)."""
     F, K, mu, n = _fields(F, K, mu)
     b = _c(b).reshape(F.shape)
@@ -242,8 +244,9 @@ def krylov(F, K, mu, b, method="chebyshev", lo=0.0, hi=0.0, eta=1e-8, max_it=100
 
 
 def solve_increment_krylov(K, mu, F, Fbar, method, lo, hi, eta_nw=1e-5, eta_cg=1e-8, max_newton=50,
-                           max_cg=10000):
-    """One increment whose linear solves use `method`.  Returns (status, F_new, P, Pbar, stats)."""
+                           max_cg=10000, nyq_identity=False):
+    """One increment whose linear solves use `method` (GMRES: lo = restart length).
+    Returns (status, F_new, P, Pbar, stats)."""
     F = np.array(F, dtype=np.float64, copy=True, order="C")
     grid = F.shape[1:]
     K = _c(np.broadcast_to(K, grid))
@@ -252,9 +255,10 @@ def solve_increment_krylov(K, mu, F, Fbar, method, lo, hi, eta_nw=1e-5, eta_cg=1
     P = np.zeros_like(F)
     Pbar = np.zeros(9)
     st = Stats()
-    status = lib().orc_solve_increment_krylov(grid[0], grid[1], grid[2], _p(K), _p(mu), _p(F), _p(Fbar), eta_nw,
-                                              eta_cg, max_newton, max_cg, _p(P), _p(Pbar), ctypes.byref(st),
-                                              METHODS[method], lo, hi)
+    status = lib().orc_solve_increment_krylov_nyq(grid[0], grid[1], grid[2], _p(K), _p(mu), _p(F), _p(Fbar),
+                                                  eta_nw, eta_cg, max_newton, max_cg, _p(P), _p(Pbar),
+                                                  ctypes.byref(st), METHODS[method], lo, hi,
+                                                  1 if nyq_identity else 0)
     return status, F, P, Pbar, st.as_dict()
 
 

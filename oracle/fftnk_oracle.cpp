@@ -372,7 +372,8 @@ typedef struct {
   const double* hist;
   int nyq;  // Nyquist choice of the projection (see orc_project_nyq)
   // Krylov method of the linear solves: 0 conjugate gradients; 1 Chebyshev,
-  // 2 Richardson, both with the spectral bounds [lo, hi] of A on range(G)
+  // 2 Richardson, both with the spectral bounds [lo, hi] of A on range(G);
+  // 3 GMRES restarted every (int)lo iterations
   int krylov;
   double lo, hi;
 } orc_problem;
@@ -525,6 +526,98 @@ static int richardson_solve(const orc_problem& pb, const double* Flin, const dou
   }
 }
 
+// GMRES (Saad, Iterative Methods for Sparse Linear Systems, Alg. 6.9 with the
+// Givens-rotation update of Sec. 6.5.3), restarted every m iterations: from
+// x0, r = b - A x0, beta = ||r||, v1 = r / beta; Arnoldi with modified
+// Gram-Schmidt, w = A v_j, h_ij = <w, v_i>, w -= h_ij v_i (i = 1..j),
+// h_{j+1,j} = ||w||, v_{j+1} = w / h_{j+1,j}; the rotations keep H upper
+// triangular and |g_{j+1}| is the residual norm of the least-squares iterate;
+// at the end of a cycle (or at convergence) x = x0 + V y with H y = g.  The
+// iteration count is the number of operator applications, the restarts'
+// residual evaluations included.  Same stopping test as CG, on |g|.
+static int gmres_solve(const orc_problem& pb, const double* Flin, const double* b, double* x, double eta,
+                       int max_it, int m, int* iters, double* relres) {
+  const long n9 = 9L * pb.n0 * pb.n1 * pb.n2;
+  *iters = 0;
+  *relres = 1.0;
+  if (m < 1) return ORC_EINVAL;
+  for (long i = 0; i < n9; ++i) x[i] = 0.0;
+  const double bb = dot(b, b, n9), nb = std::sqrt(bb), stop = eta * nb;
+  if (nb <= stop || nb == 0.0) {
+    *relres = 0.0;
+    return ORC_OK;
+  }
+  std::vector<std::vector<double>> V(m + 1, std::vector<double>(n9));
+  std::vector<double> w(n9), H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  bool first = true;
+  while (true) {
+    // residual of the current iterate
+    if (first) {
+      for (long i = 0; i < n9; ++i) V[0][i] = b[i];
+      first = false;
+    } else {
+      if (*iters >= max_it) return ORC_ECG_MAXIT;
+      apply_A(pb, Flin, x, w.data());
+      ++*iters;
+      for (long i = 0; i < n9; ++i) V[0][i] = b[i] - w[i];
+    }
+    const double beta = std::sqrt(dot(V[0].data(), V[0].data(), n9));
+    *relres = beta / nb;
+    if (!std::isfinite(beta)) return ORC_ENONFINITE;
+    if (beta <= stop) return ORC_OK;
+    for (long i = 0; i < n9; ++i) V[0][i] /= beta;
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;  // columns of this cycle
+    bool done = false;
+    for (int j = 0; j < m; ++j) {
+      if (*iters >= max_it) break;
+      apply_A(pb, Flin, V[j].data(), w.data());
+      ++*iters;
+      for (int i = 0; i <= j; ++i) {
+        const double h = dot(w.data(), V[i].data(), n9);
+        H[(size_t)i * m + j] = h;
+        for (long q = 0; q < n9; ++q) w[q] -= h * V[i][q];
+      }
+      const double hn = std::sqrt(dot(w.data(), w.data(), n9));
+      H[(size_t)(j + 1) * m + j] = hn;
+      if (!std::isfinite(hn)) return ORC_ENONFINITE;
+      if (hn > 0.0)
+        for (long q = 0; q < n9; ++q) V[j + 1][q] = w[q] / hn;
+      // earlier rotations on column j, then the one that zeroes h_{j+1,j}
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], c2 = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * c2;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c2;
+      }
+      const double a = H[(size_t)j * m + j], c2 = H[(size_t)(j + 1) * m + j];
+      const double d = std::hypot(a, c2);
+      cs[j] = a / d;
+      sn[j] = c2 / d;
+      H[(size_t)j * m + j] = d;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      k = j + 1;
+      *relres = std::fabs(g[j + 1]) / nb;
+      if (std::fabs(g[j + 1]) <= stop || hn == 0.0) {
+        done = true;
+        break;
+      }
+    }
+    // x += V y, H y = g (upper triangular k x k)
+    for (int i = k - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int q = i + 1; q < k; ++q) t -= H[(size_t)i * m + q] * y[q];
+      y[i] = t / H[(size_t)i * m + i];
+    }
+    for (int i = 0; i < k; ++i)
+      for (long q = 0; q < n9; ++q) x[q] += y[i] * V[i][q];
+    if (done) return ORC_OK;
+    if (*iters >= max_it) return ORC_ECG_MAXIT;
+  }
+}
+
 // Solve A dF = b unless b is at the round-off floor ||b|| <= 1e-14 ||Y|| of the
 // field Y that G was applied to; then dF = 0 with zero iterations.
 static int cg_or_zero(const orc_problem& pb, const double* Flin, const double* b, const double* Y,
@@ -539,6 +632,7 @@ static int cg_or_zero(const orc_problem& pb, const double* Flin, const double* b
   }
   if (pb.krylov == 1) return chebyshev_solve(pb, Flin, b, x, eta, max_cg, iters, relres);
   if (pb.krylov == 2) return richardson_solve(pb, Flin, b, x, eta, max_cg, iters, relres);
+  if (pb.krylov == 3) return gmres_solve(pb, Flin, b, x, eta, max_cg, (int)pb.lo, iters, relres);
   return cg_solve(pb, Flin, b, x, eta, max_cg, iters, relres);
 }
 
@@ -935,13 +1029,25 @@ int orc_adjoint(int n0, int n1, int n2, const double* K, const double* mu, const
 }
 
 // Exposed for tests: one linear solve with the Krylov method `method` (0 CG, 1
-// Chebyshev, 2 Richardson; bounds lo, hi for 1 and 2) at Flin, x0 = 0.
+// Chebyshev, 2 Richardson; bounds lo, hi for 1 and 2; 3 GMRES restarted every
+// (int)lo iterations) at Flin, x0 = 0.
 int orc_krylov(int n0, int n1, int n2, const double* K, const double* mu, const double* Flin, const double* b,
                double* x, double eta, int max_it, int method, double lo, double hi, int* iters, double* relres) {
   orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, 0, method, lo, hi};
   if (method == 1) return chebyshev_solve(pb, Flin, b, x, eta, max_it, iters, relres);
   if (method == 2) return richardson_solve(pb, Flin, b, x, eta, max_it, iters, relres);
+  if (method == 3) return gmres_solve(pb, Flin, b, x, eta, max_it, (int)lo, iters, relres);
   return cg_solve(pb, Flin, b, x, eta, max_it, iters, relres);
+}
+
+// One increment (St. Venant-Kirchhoff) with the Nyquist choice nyq_identity and
+// linear solves by `method`.
+int orc_solve_increment_krylov_nyq(int n0, int n1, int n2, const double* K, const double* mu, double* F,
+                                   const double* Fbar, double eta_nw, double eta_cg, int max_newton, int max_cg,
+                                   double* P, double* Pbar, orc_stats* st, int method, double lo, double hi,
+                                   int nyq_identity) {
+  orc_problem pb{n0, n1, n2, K, mu, 0, nullptr, nullptr, nullptr, nyq_identity ? 1 : 0, method, lo, hi};
+  return solve_increment_impl(pb, F, Fbar, eta_nw, eta_cg, max_newton, max_cg, P, Pbar, nullptr, st);
 }
 
 // One increment (St. Venant-Kirchhoff) whose linear solves use `method`.

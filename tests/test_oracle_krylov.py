@@ -1,6 +1,6 @@
 """Pins of the oracle's other Krylov methods on the same operator: Chebyshev and
 Richardson iterations (fixed coefficients from spectral bounds [lo, hi] of A
-on range(G)), next to CG.
+on range(G)) and restarted GMRES, next to CG.
 
 What fixes the answer independently of the oracle's arithmetic:
 * a homogeneous cell linearised at F = I (S = 0): on range(G) the operator has
@@ -14,7 +14,8 @@ What fixes the answer independently of the oracle's arithmetic:
   the residual bounds ||r_k|| <= ||r0|| / T_k(sigma) and ((kappa-1)/(kappa+1))^k
   hold at every k (A symmetric on range(G)), and all three methods reach the
   same solution, checked with the operator itself;
-* a full increment solved with Chebyshev reaches the CG increment's state.
+* a full increment solved with Chebyshev reaches the CG increment's state;
+* GMRES: see the pins at the end of the file.
 """
 import numpy as np
 import pytest
@@ -118,3 +119,54 @@ def test_invalid_bounds(orc):
     for m, l, h in (("chebyshev", 0.0, 1.0), ("chebyshev", 2.0, 1.0), ("richardson", -1.0, 1.0)):
         _, st, it, _ = orc.krylov(F, K, mu, b, m, l, h)
         assert st == 5 and it == 0
+
+
+# ---------------------------------------------------------------- GMRES
+# Pins: a two-eigenvalue operator (homogeneous cell at F = I) is solved in two
+# iterations (degree of its minimal polynomial); the residual norm never grows
+# within a cycle (least-squares over nested Krylov spaces); unrestarted GMRES
+# needs no more iterations than CG (it minimises the residual over the same
+# space); restarted or not, it reaches CG's solution, checked with the operator.
+
+def test_gmres_two_eigenvalues(orc):
+    shape = (7, 9, 5)
+    K0, mu0, lo, hi, b = _homogeneous(orc, shape)
+    x, st, it, rel = orc.krylov(orc.identity_field(shape), K0, mu0, b, "gmres", 30, 0, 1e-12, 100)
+    assert st == 0 and it == 2 and rel < 1e-12
+
+
+def test_gmres_monotone_and_minimal(orc):
+    shape = (9, 7, 8)
+    K, mu, F, lo, hi, b = _hetero(orc, shape, 5)
+    prev = 1.0
+    for k in range(1, 25):
+        _, _, it, rel = orc.krylov(F, K, mu, b, "gmres", 100, 0, 1e-30, k)
+        assert it == k and rel <= prev * (1 + 1e-12), k
+        prev = rel
+    _, st_g, it_g, _ = orc.krylov(F, K, mu, b, "gmres", 500, 0, 1e-10, 5000)
+    _, st_c, it_c, _ = orc.krylov(F, K, mu, b, "cg", 0, 0, 1e-10, 5000)
+    assert st_g == st_c == 0 and it_g <= it_c
+
+
+@pytest.mark.parametrize("m", [5, 20])
+def test_gmres_restarted_solution(orc, m):
+    shape = (8, 8, 8)
+    K, mu, F, lo, hi, b = _hetero(orc, shape, 5)
+    x, st, it, rel = orc.krylov(F, K, mu, b, "gmres", m, 0, 1e-11, 20000)
+    xc, stc, itc, _ = orc.krylov(F, K, mu, b, "cg", 0, 0, 1e-11, 20000)
+    assert st == stc == 0
+    res = orc.apply_operator(F, K, mu, x) - b
+    assert np.linalg.norm(res) <= 2e-11 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xc) <= 1e-9 * np.linalg.norm(xc)
+
+
+def test_increment_with_gmres_matches_cg(orc):
+    shape = (7, 7, 7)
+    ph = ms.cubic_inclusion(7, 3)
+    K, mu = ms.phase_moduli(ph, TABLE)
+    Fbar = ms.simple_shear(0.05)
+    st0, F0, P0, Pb0, S0 = orc.solve_increment(K, mu, orc.identity_field(shape), Fbar, 1e-10, 1e-12)
+    st1, F1, P1, Pb1, S1 = orc.solve_increment_krylov(K, mu, orc.identity_field(shape), Fbar, "gmres", 20, 0,
+                                                      1e-10, 1e-12)
+    assert st0 == st1 == 0 and S0["n_solves"] == S1["n_solves"]
+    assert np.max(np.abs(F1 - F0)) < 1e-9 and np.max(np.abs(Pb1 - Pb0)) < 1e-11
