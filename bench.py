@@ -114,7 +114,7 @@ def main():
                     help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d: instead of the headline line, one JSON line per extra "
                          "measurement (operator at 96^3..256^3; 64 batched cells; J2 at 96^3; adjoint 8 x 192^3; "
                          "the two Nyquist choices at 128^3; mixed control at 128^3; CG / Chebyshev / "
-                         "Richardson at 128^3; the 2-D plane-strain example at 451^2)")
+                         "Richardson / GMRES at 128^3; the 2-D plane-strain example at 451^2)")
     args = ap.parse_args()
     if args.operator_only:
         return operator_only(args)
@@ -518,17 +518,18 @@ def extra(args):
         emit(res)
 
     if "krylov" in which:
-        # the three Krylov methods on the 128^3 two-phase cell: one C2-like
-        # increment (simple shear 0.05, eta_NW 1e-5, eta_CG 1e-8) each, with
-        # Chebyshev / Richardson bounds [0.9 min mu, 1.1 max 3K]
+        # the Krylov methods on the 128^3 two-phase cell: one C2-like increment
+        # (simple shear 0.05, eta_NW 1e-5, eta_CG 1e-8) each, with Chebyshev /
+        # Richardson bounds [0.9 min mu, 1.1 max 3K] and GMRES(30)
         n_ = 128
         phase = ms.grf_threshold(n_, ell=8.0, frac=0.3, seed=1603)
         lo = 0.9 * min(m for _, m in TABLE)
         hi = 1.1 * 3 * max(k for k, _ in TABLE)
-        res = {"extra": "krylov_methods", "grid": n_, "bounds": [lo, hi], "load": "simple shear 0.05"}
+        res = {"extra": "krylov_methods", "grid": n_, "bounds": [lo, hi], "gmres_restart": 30,
+               "load": "simple shear 0.05"}
         for prec in ("fp64", "fp32"):
-            for method in ("cg", "chebyshev", "richardson"):
-                s = Solver((n_,) * 3, precision=prec)
+            for method in ("cg", "chebyshev", "richardson", "gmres"):
+                s = Solver((n_,) * 3, precision=prec, gmres_restart=30 if method == "gmres" else 0)
                 s.set_phases(phase)
                 s.set_material(TABLE)
                 s.set_krylov(method, lo, hi)

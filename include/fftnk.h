@@ -134,8 +134,12 @@ int fftnk_set_modulus_field(fftnk_ctx* ctx, const double* mu_dev);
  * stress has a compressive direction, so CG may end in FFTNK_ECG_BREAKDOWN
  * (typically under shear), and it converges more slowly under tension.
  * Values other than 0 / 1 give FFTNK_EINVAL.
+ * FFTNK_OPT_GMRES_RESTART (1..256) reserves the Arnoldi basis of restarted
+ * GMRES (m + 1 vector fields of the context precision) in the workspace: set
+ * it after creation and before fftnk_workspace_bytes / fftnk_bind_workspace
+ * (afterwards FFTNK_ESTATE); it enables FFTNK_KRYLOV_GMRES.
  */
-enum { FFTNK_OPT_GRAPHS = 1, FFTNK_OPT_CHECK_EVERY = 2, FFTNK_OPT_NYQUIST = 3 };
+enum { FFTNK_OPT_GRAPHS = 1, FFTNK_OPT_CHECK_EVERY = 2, FFTNK_OPT_NYQUIST = 3, FFTNK_OPT_GMRES_RESTART = 4 };
 int fftnk_set_option(fftnk_ctx* ctx, int option, int value);
 
 /* F_t := I (and virgin history): the start state of Algorithm 1. */
@@ -158,10 +162,16 @@ int fftnk_reset_state(fftnk_ctx* ctx);
  * FFTNK_ENONFINITE or FFTNK_ECG_MAXIT).  At F = I on gradients,
  * mu_min <= <p, A p> / <p, p> <= 3 K_max (periodic Korn inequality and the
  * largest local eigenvalue); finite strain and plasticity move the spectrum.
- * Same stopping test as CG; the counts reported as cg_iters are operator
- * applications.  Bad method or bounds: FFTNK_EINVAL.
+ * FFTNK_KRYLOV_GMRES: restarted GMRES(m) (Saad, same book, Alg. 6.9; Arnoldi
+ * with classical Gram-Schmidt applied twice, Givens rotations, m from
+ * FFTNK_OPT_GMRES_RESTART, else FFTNK_ESTATE; lo, hi unused), for tangents
+ * that are not symmetric; it needs no bounds but stores m + 1 basis fields
+ * and synchronises with the host once per inner-product batch.
+ * Same stopping test as CG (GMRES: on its least-squares residual); the counts
+ * reported as cg_iters are operator applications.  Bad method or bounds:
+ * FFTNK_EINVAL.
  */
-enum { FFTNK_KRYLOV_CG = 0, FFTNK_KRYLOV_CHEBYSHEV = 1, FFTNK_KRYLOV_RICHARDSON = 2 };
+enum { FFTNK_KRYLOV_CG = 0, FFTNK_KRYLOV_CHEBYSHEV = 1, FFTNK_KRYLOV_RICHARDSON = 2, FFTNK_KRYLOV_GMRES = 3 };
 int fftnk_set_krylov(fftnk_ctx* ctx, int method, double lo, double hi);
 
 /*

@@ -112,10 +112,12 @@ struct fftnk_ctx {
   int nyq_id = 0;      // FFTNK_OPT_NYQUIST
   int krylov = KRYLOV_CG;  // fftnk_set_krylov
   double k_lo = 0.0, k_hi = 0.0;
+  int gm = 0;              // GMRES restart length (FFTNK_OPT_GMRES_RESTART), basis of gm + 1 vectors
+  size_t total_base = 0;   // workspace bytes without the GMRES basis
   // workspace layout (byte offsets)
   size_t o_hist, o_hnew;  // J2 history: committed and of the current iterate, [7][ntot] each
   size_t o_Ft, o_F, o_P, o_x, o_r, o_p, o_w, o_F32, o_d64, o_spec, o_phase, o_mu, o_mtab, o_part, o_cg, o_red,
-      o_tw64, o_tw32, o_grids, o_starts, o_active, o_uni, o_nyq, total = 0;
+      o_tw64, o_tw32, o_grids, o_starts, o_active, o_uni, o_nyq, o_coef, o_gm, total = 0;
   long long rows_total = 0;
   char* ws = nullptr;
   bool have_phase = false, have_mat = false, use_mu = false;
@@ -356,6 +358,9 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
   c->o_active = take((size_t)nrve * sizeof(int));
   c->o_uni = take((size_t)nrve * 9 * sizeof(double));
   c->o_nyq = take(9 * (size_t)rows * sizeof(double));
+  c->o_coef = take((size_t)nrve * kGmCoef * sizeof(double));
+  c->o_gm = o;
+  c->total_base = o;
   c->total = o;
   c->active.assign(nrve, 1);
   c->uni.assign(9 * (size_t)nrve, 0.0);
@@ -466,7 +471,10 @@ int launch_iterations(fftnk_ctx* c, int k) {
 
 // CG on every active RVE: A = G K(linearisation point), right-hand side r,
 // x = 0 on entry.  Per-RVE outcome in the device CgState array.
+int run_gmres(fftnk_ctx* c, double eta, int max_it);
+
 int run_cg(fftnk_ctx* c, double eta, int max_cg) {
+  if (c->krylov == KRYLOV_GMRES) return run_gmres(c, eta, max_cg);
   const Launch L = c->launch();
   const int stall = c->prec == PREC_F32 ? 50 : 0;
   launch_cg_init(L, c->cg(), eta, max_cg, stall, c->krylov, c->k_lo, c->k_hi);
@@ -505,6 +513,228 @@ int reduce_fetch(fftnk_ctx* c, std::initializer_list<std::pair<int, std::pair<in
 }
 
 double red_at(fftnk_ctx* c, int r, int slot) { return c->host_red()[r * NSLOT + slot]; }
+
+// GMRES(m) (Saad, Iterative Methods for Sparse Linear Systems, Alg. 6.9 with
+// the Givens update of Sec. 6.5.3) on every active RVE, in the role of run_cg:
+// right-hand side b in r (with the partial sums of the right-hand-side
+// pipeline), x = 0 on entry, solution in x, per-RVE outcome written to the
+// host CgState array that run_cg's callers read (iterations = operator
+// applications, the restarts' residual evaluations included).  Arnoldi uses
+// classical Gram-Schmidt applied twice (one pass over the basis per
+// inner-product batch instead of one per vector); the Hessenberg columns,
+// rotations and the small triangular solve live on the host.
+int run_gmres(fftnk_ctx* c, double eta, int max_it) {
+  const int nr = c->nrve, m = c->gm, prec = c->prec;
+  const size_t esz = prec == PREC_F64 ? 8 : 4;
+  const long long vstride = 9 * c->ntot;
+  auto V = [&](int j) { return static_cast<void*>(c->ws + c->o_gm + (size_t)j * vstride * esz); };
+  double* coef = c->at<double>(c->o_coef);
+  const Launch L = c->launch();
+  const Material mat = c->material();
+  const std::vector<int> act0 = c->active;  // the caller's mask, restored at the end
+  int e = reduce_fetch(c, {{K_ROW1, {SLOT_YY, 1}}, {K_ROW, {SLOT_BB, 1}}});
+  if (e) return e;
+  struct RveGm {
+    double nb = 0, res = 0;
+    int iters = 0, status = FFTNK_OK, done = 0, zero = 0, in_cycle = 0, k = 0;
+    std::vector<double> H, cs, sn, g, y, h;
+  };
+  std::vector<RveGm> R(nr);
+  for (int r = 0; r < nr; ++r) {
+    RveGm& q = R[r];
+    q.H.assign((size_t)(m + 1) * m, 0.0);
+    q.cs.assign(m, 0.0);
+    q.sn.assign(m, 0.0);
+    q.g.assign(m + 1, 0.0);
+    q.y.assign(m, 0.0);
+    q.h.assign(m + 1, 0.0);
+    const double bb = red_at(c, r, SLOT_BB), yy = red_at(c, r, SLOT_YY);
+    q.nb = std::sqrt(bb);
+    if (!act0[r]) {
+      q.done = q.zero = 1;
+    } else if (!std::isfinite(bb)) {
+      q.done = 1;
+      q.status = FFTNK_ENONFINITE;
+    } else if (bb == 0.0 || q.nb <= 1e-14 * std::sqrt(yy) || q.nb <= eta * q.nb) {
+      q.done = q.zero = 1;
+    }
+  }
+  // host staging of the per-RVE coefficients and the launch mask: both
+  // uploads complete before the host vectors are written again
+  std::vector<double> hc((size_t)nr * kGmCoef, 0.0);
+  auto upload_coef = [&]() -> int {
+    HIP_TRY(hipMemcpyAsync(coef, hc.data(), hc.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return FFTNK_OK;
+  };
+  // sets the launch mask; returns the number of active RVEs, or -status
+  auto set_active = [&](auto pred) -> int {
+    int any = 0;
+    for (int r = 0; r < nr; ++r) {
+      c->active[r] = pred(r) ? 1 : 0;
+      any += c->active[r];
+    }
+    const int e2 = upload_active(c);
+    if (e2) return -e2;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return -FFTNK_EHIP;
+    return any;
+  };
+  auto apply_A = [&](const void* v) {  // w = A v
+    launch_fwd_a2(prec, FWD_TANGENT, L, mat, v, nullptr, nullptr, nullptr, c->flin(), 1.0, c->spec(), nullptr);
+    middle_passes(prec, L, c->spec(), nullptr);
+    launch_inv_a2(prec, INV_OUT, L, c->spec(), c->w(), prec, nullptr, 1.0, nullptr);
+  };
+  bool first = true;
+  while (true) {
+    // a cycle over every RVE still running; first the residual V_0 = b - A x
+    int a = set_active([&](int r) { return !R[r].done && (first || R[r].iters < max_it); });
+    if (a < 0) return -a;
+    for (int r = 0; r < nr; ++r)
+      if (!R[r].done && !c->active[r]) {
+        R[r].done = 1;
+        R[r].status = FFTNK_ECG_MAXIT;
+      }
+    if (a == 0) break;
+    for (int r = 0; r < nr; ++r) {
+      hc[(size_t)r * kGmCoef] = 1.0;
+      hc[(size_t)r * kGmCoef + 1] = -1.0;
+    }
+    if ((e = upload_coef())) return e;
+    if (first) {
+      launch_gm_lincomb(prec, L, V(0), c->r(), nullptr, coef, true);
+    } else {
+      apply_A(c->x());
+      launch_gm_lincomb(prec, L, V(0), c->r(), c->w(), coef, true);
+      for (int r = 0; r < nr; ++r) R[r].iters += c->active[r];
+    }
+    if ((e = reduce_fetch(c, {{K_ELEM9, {SLOT_RR, 1}}}))) return e;
+    for (int r = 0; r < nr; ++r) {
+      RveGm& q = R[r];
+      q.in_cycle = 0;
+      if (!c->active[r]) continue;
+      const double beta = std::sqrt(red_at(c, r, SLOT_RR));
+      q.res = beta;
+      if (!std::isfinite(beta)) {
+        q.done = 1;
+        q.status = FFTNK_ENONFINITE;
+      } else if (beta <= eta * q.nb) {
+        q.done = 1;
+      } else {
+        q.in_cycle = 1;
+        q.k = 0;
+        std::fill(q.g.begin(), q.g.end(), 0.0);
+        q.g[0] = beta;
+        hc[(size_t)r * kGmCoef] = 1.0 / beta;
+      }
+    }
+    first = false;
+    a = set_active([&](int r) { return R[r].in_cycle != 0; });
+    if (a < 0) return -a;
+    if (a == 0) continue;
+    if ((e = upload_coef())) return e;
+    launch_gm_lincomb(prec, L, V(0), V(0), nullptr, coef, false);  // V_0 /= beta
+    for (int j = 0; j < m; ++j) {
+      a = set_active([&](int r) { return R[r].in_cycle && !R[r].done && R[r].k == j && R[r].iters < max_it; });
+      if (a < 0) return -a;
+      if (a == 0) break;
+      apply_A(V(j));
+      for (int r = 0; r < nr; ++r) {
+        R[r].iters += c->active[r];
+        std::fill(R[r].h.begin(), R[r].h.end(), 0.0);
+      }
+      // w -= sum_i h_i V_i twice (classical Gram-Schmidt, re-orthogonalised)
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int i0 = 0; i0 <= j; i0 += kGmDot) {
+          const int kk = std::min(kGmDot, j + 1 - i0);
+          launch_gm_dots(prec, L, c->w(), V(0), vstride, i0, kk);
+          if ((e = reduce_fetch(c, {{K_ELEM9, {SLOT_DOT, kk}}}))) return e;
+          for (int r = 0; r < nr; ++r)
+            for (int q2 = 0; q2 < kk; ++q2) {
+              const double d = c->active[r] ? red_at(c, r, SLOT_DOT + q2) : 0.0;
+              R[r].h[i0 + q2] += d;
+              hc[(size_t)r * kGmCoef + q2] = -d;
+            }
+          if ((e = upload_coef())) return e;
+          launch_gm_update(prec, L, c->w(), V(0), vstride, i0, kk, coef, pass == 1 && i0 + kk == j + 1);
+        }
+      }
+      if ((e = reduce_fetch(c, {{K_ELEM9, {SLOT_RR, 1}}}))) return e;
+      for (int r = 0; r < nr; ++r) {
+        if (!c->active[r]) continue;
+        RveGm& q = R[r];
+        const double hn = std::sqrt(red_at(c, r, SLOT_RR));
+        for (int i = 0; i <= j; ++i) q.H[(size_t)i * m + j] = q.h[i];
+        q.H[(size_t)(j + 1) * m + j] = hn;
+        hc[(size_t)r * kGmCoef] = hn > 0.0 ? 1.0 / hn : 0.0;
+        for (int i = 0; i < j; ++i) {
+          const double x0 = q.H[(size_t)i * m + j], x1 = q.H[(size_t)(i + 1) * m + j];
+          q.H[(size_t)i * m + j] = q.cs[i] * x0 + q.sn[i] * x1;
+          q.H[(size_t)(i + 1) * m + j] = -q.sn[i] * x0 + q.cs[i] * x1;
+        }
+        const double x0 = q.H[(size_t)j * m + j], x1 = q.H[(size_t)(j + 1) * m + j];
+        const double d = std::hypot(x0, x1);
+        q.cs[j] = x0 / d;
+        q.sn[j] = x1 / d;
+        q.H[(size_t)j * m + j] = d;
+        q.H[(size_t)(j + 1) * m + j] = 0.0;
+        q.g[j + 1] = -q.sn[j] * q.g[j];
+        q.g[j] = q.cs[j] * q.g[j];
+        q.k = j + 1;
+        q.res = std::fabs(q.g[j + 1]);
+        if (!std::isfinite(q.res) || !std::isfinite(d) || !(d > 0.0)) {
+          q.status = FFTNK_ENONFINITE;
+          q.done = 1;
+        } else if (q.res <= eta * q.nb || hn == 0.0) {
+          q.done = 1;  // converged: x is updated at the end of the cycle
+        }
+      }
+      if ((e = upload_coef())) return e;
+      launch_gm_lincomb(prec, L, V(j + 1), c->w(), nullptr, coef, false);  // V_{j+1} = w / h_{j+1,j}
+    }
+    // x += V y with H y = g (upper triangular, k x k) for every RVE of the cycle
+    int kmax = 0;
+    for (int r = 0; r < nr; ++r) {
+      RveGm& q = R[r];
+      if (!q.in_cycle || q.status) continue;
+      for (int i = q.k - 1; i >= 0; --i) {
+        double t = q.g[i];
+        for (int u = i + 1; u < q.k; ++u) t -= q.H[(size_t)i * m + u] * q.y[u];
+        q.y[i] = t / q.H[(size_t)i * m + i];
+      }
+      kmax = std::max(kmax, q.k);
+    }
+    for (int i0 = 0; i0 < kmax; i0 += kGmCoef) {
+      const int kk = std::min(kGmCoef, kmax - i0);
+      a = set_active([&](int r) { return R[r].in_cycle && !R[r].status && R[r].k > i0; });
+      if (a < 0) return -a;
+      for (int r = 0; r < nr; ++r)
+        for (int q2 = 0; q2 < kk; ++q2)
+          hc[(size_t)r * kGmCoef + q2] = (c->active[r] && i0 + q2 < R[r].k) ? R[r].y[i0 + q2] : 0.0;
+      if ((e = upload_coef())) return e;
+      launch_gm_update(prec, L, c->x(), V(0), vstride, i0, kk, coef, false);
+    }
+    e = check_launch();
+    if (e) return e;
+  }
+  // the outcome, where run_cg's callers read it
+  CgState* hs = reinterpret_cast<CgState*>(c->pinned);
+  for (int r = 0; r < nr; ++r) {
+    const RveGm& q = R[r];
+    std::memset(&hs[r], 0, sizeof(CgState));
+    hs[r].bb = q.nb * q.nb;
+    hs[r].rr = q.res * q.res;
+    hs[r].iter = q.iters;
+    hs[r].done = 1;
+    hs[r].status = q.status;
+    hs[r].zero_rhs = q.zero;
+    hs[r].method = KRYLOV_GMRES;
+  }
+  c->active = act0;
+  e = upload_active(c);
+  if (e) return e;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return check_launch();
+}
 
 // Deformation-controlled Newton iterations of Algorithm 1 (Sec. 3.1-3.2) on
 // the RVEs with run[r] (the others are left alone: masked off every launch):
@@ -838,6 +1068,14 @@ int fftnk_set_option(fftnk_ctx* c, int option, int value) {
       if (value < 1 || value > 64) return FFTNK_EINVAL;
       c->check_every = value;
       return FFTNK_OK;
+    case FFTNK_OPT_GMRES_RESTART: {
+      if (value < 1 || value > 256) return FFTNK_EINVAL;
+      if (c->ws) return FFTNK_ESTATE;  // sizes the workspace: set before binding it
+      c->gm = value;
+      const size_t fv = 9 * (size_t)c->ntot * (c->prec == PREC_F64 ? 8 : 4);
+      c->total = align_up(c->total_base + (size_t)(value + 1) * fv);
+      return FFTNK_OK;
+    }
     case FFTNK_OPT_NYQUIST:
       if (value != 0 && value != 1) return FFTNK_EINVAL;
       if (value == c->nyq_id) return FFTNK_OK;
@@ -863,6 +1101,9 @@ int fftnk_set_krylov(fftnk_ctx* c, int method, double lo, double hi) {
       break;
     case FFTNK_KRYLOV_RICHARDSON:
       if (!(lo > 0.0) || !(hi >= lo) || !std::isfinite(hi)) return FFTNK_EINVAL;
+      break;
+    case FFTNK_KRYLOV_GMRES:
+      if (c->gm < 1) return FFTNK_ESTATE;  // no basis in the workspace
       break;
     default: return FFTNK_EINVAL;
   }

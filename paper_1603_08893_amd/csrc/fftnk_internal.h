@@ -103,8 +103,11 @@ enum {
   SLOT_PBAR = 6,  // 9 slots: sum of P
   SLOT_FBAR = 15, // 9 slots: sum of F
   SLOT_AUX = 24,  // 2 spare slots
-  NSLOT = 26
+  SLOT_DOT = 26,  // kGmDot slots: GMRES inner products <w, v_i>
+  NSLOT = 42
 };
+constexpr int kGmDot = 16;   // basis vectors per GMRES inner-product / update launch
+constexpr int kGmCoef = 16;  // per-RVE coefficients of one GMRES update launch
 
 // Device-resident CG scalars of one RVE.
 struct CgState {
@@ -129,8 +132,9 @@ struct CgState {
 
 // Krylov methods sharing the fused CG passes (x += alpha p deferred,
 // p = r + beta p, r -= alpha A p): CG (alpha, beta from inner products),
-// Chebyshev and Richardson (fixed coefficients from [lo, hi]).
-enum { KRYLOV_CG = 0, KRYLOV_CHEBYSHEV = 1, KRYLOV_RICHARDSON = 2 };
+// Chebyshev and Richardson (fixed coefficients from [lo, hi]); and GMRES,
+// driven from the host over the operator passes and the kernels below.
+enum { KRYLOV_CG = 0, KRYLOV_CHEBYSHEV = 1, KRYLOV_RICHARDSON = 2, KRYLOV_GMRES = 3 };
 
 // Everything a launch needs to find its RVE, tables and partial-sum slots.
 struct Batch {
@@ -213,5 +217,16 @@ void launch_set_virgin_history(const Launch& L, double* hist, long long ntot);
 void launch_adjoint_grad(int prec, const Launch& L, const double* F, const void* w, double* dmu, double* dK);
 // sums of K(F) : (uni - w) per RVE into SLOT_PBAR .. + 8 (w FP64)
 void launch_tangent_sum(const Launch& L, const Material& mat, const double* F, const double* w);
+// GMRES, element-wise over each active RVE's 9 n values; the basis vector j
+// starts at V + j * vstride elements (vstride = 9 ntot); coef is a device
+// array [nrve][kGmCoef].  dots: partial sums of <w, V_{i0+q}>, q < k, into
+// SLOT_DOT + q.  update: y += sum_q coef[r][q] V_{i0+q}; with norm the
+// partial sums of ||y||^2 into SLOT_RR.  lincomb: dst = coef[r][0] s1 +
+// coef[r][1] s2 (s2 may be null, dst may be s1); norm as for update.
+void launch_gm_dots(int prec, const Launch& L, const void* w, const void* V, long long vstride, int i0, int k);
+void launch_gm_update(int prec, const Launch& L, void* y, const void* V, long long vstride, int i0, int k,
+                      const double* coef, bool norm);
+void launch_gm_lincomb(int prec, const Launch& L, void* dst, const void* s1, const void* s2, const double* coef,
+                       bool norm);
 
 }  // namespace fftnk

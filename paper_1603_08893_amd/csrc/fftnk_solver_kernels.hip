@@ -430,6 +430,89 @@ __global__ __launch_bounds__(kThreads) void k_tangent_sum(Batch B, Material mat,
 }
 
 // ---------------------------------------------------------------------------
+// GMRES building blocks (Arnoldi with classical Gram-Schmidt applied twice).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gm_dots(Batch B, const T* __restrict__ w, const T* __restrict__ V,
+                                                      long long vstride, int i0, int k) {
+  int local;
+  const int rv = find_rve(B, K_ELEM9, blockIdx.x, local);
+  if (skip_rve(B, nullptr, rv)) return;
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_ELEM9, rv);
+  const long long m = 9 * g.n, off = 9 * g.vox_off;
+  double acc[kGmDot];
+#pragma unroll
+  for (int q = 0; q < kGmDot; ++q) acc[q] = 0.0;
+  FOR_RVE_RANGE(i, m, local, nb) {
+    const double wi = (double)w[off + i];
+#pragma unroll
+    for (int q = 0; q < kGmDot; ++q)
+      if (q < k) acc[q] += wi * (double)V[(long long)(i0 + q) * vstride + off + i];
+  }
+  double res[kGmDot];
+  block_sums<kGmDot>(acc, res);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < k; ++q) pslot(B, SLOT_DOT + q)[blockIdx.x] = res[q];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gm_update(Batch B, T* __restrict__ y, const T* __restrict__ V,
+                                                        long long vstride, int i0, int k,
+                                                        const double* __restrict__ coef, int norm) {
+  int local;
+  const int rv = find_rve(B, K_ELEM9, blockIdx.x, local);
+  if (skip_rve(B, nullptr, rv)) return;
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_ELEM9, rv);
+  const long long m = 9 * g.n, off = 9 * g.vox_off;
+  double c[kGmCoef];
+#pragma unroll
+  for (int q = 0; q < kGmCoef; ++q) c[q] = q < k ? coef[rv * kGmCoef + q] : 0.0;
+  double acc[1] = {0.0};
+  FOR_RVE_RANGE(i, m, local, nb) {
+    double v = (double)y[off + i];
+#pragma unroll
+    for (int q = 0; q < kGmCoef; ++q)
+      if (q < k) v += c[q] * (double)V[(long long)(i0 + q) * vstride + off + i];
+    const T t = (T)v;
+    y[off + i] = t;
+    acc[0] += (double)t * (double)t;
+  }
+  if (norm) {
+    double res[1];
+    block_sums<1>(acc, res);
+    if (threadIdx.x == 0) pslot(B, SLOT_RR)[blockIdx.x] = res[0];
+  }
+}
+
+// dst may alias s1 (an in-place scaling): no restrict on those two
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gm_lincomb(Batch B, T* dst, const T* s1, const T* __restrict__ s2,
+                                                         const double* __restrict__ coef, int norm) {
+  int local;
+  const int rv = find_rve(B, K_ELEM9, blockIdx.x, local);
+  if (skip_rve(B, nullptr, rv)) return;
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_ELEM9, rv);
+  const long long m = 9 * g.n, off = 9 * g.vox_off;
+  const double a = coef[rv * kGmCoef], b = coef[rv * kGmCoef + 1];
+  double acc[1] = {0.0};
+  FOR_RVE_RANGE(i, m, local, nb) {
+    double v = a * (double)s1[off + i];
+    if (s2) v += b * (double)s2[off + i];
+    const T t = (T)v;
+    dst[off + i] = t;
+    acc[0] += (double)t * (double)t;
+  }
+  if (norm) {
+    double res[1];
+    block_sums<1>(acc, res);
+    if (threadIdx.x == 0) pslot(B, SLOT_RR)[blockIdx.x] = res[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 void launch_cg_finish(int prec, const Launch& L, void* x, const void* p, const CgState* cg) {
@@ -511,6 +594,38 @@ void launch_convert(int to_prec, const void* in, void* out, long long count, hip
 
 void launch_set_identity(const Launch& L, double* F) {
   hipLaunchKernelGGL(k_set_identity, dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, F);
+}
+
+void launch_gm_dots(int prec, const Launch& L, const void* w, const void* V, long long vstride, int i0, int k) {
+  const dim3 grid(L.nblk[K_ELEM9]), block(kThreads);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL((k_gm_dots<double>), grid, block, 0, L.s, L.b, static_cast<const double*>(w),
+                       static_cast<const double*>(V), vstride, i0, k);
+  else
+    hipLaunchKernelGGL((k_gm_dots<float>), grid, block, 0, L.s, L.b, static_cast<const float*>(w),
+                       static_cast<const float*>(V), vstride, i0, k);
+}
+
+void launch_gm_update(int prec, const Launch& L, void* y, const void* V, long long vstride, int i0, int k,
+                      const double* coef, bool norm) {
+  const dim3 grid(L.nblk[K_ELEM9]), block(kThreads);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL((k_gm_update<double>), grid, block, 0, L.s, L.b, static_cast<double*>(y),
+                       static_cast<const double*>(V), vstride, i0, k, coef, norm ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_gm_update<float>), grid, block, 0, L.s, L.b, static_cast<float*>(y),
+                       static_cast<const float*>(V), vstride, i0, k, coef, norm ? 1 : 0);
+}
+
+void launch_gm_lincomb(int prec, const Launch& L, void* dst, const void* s1, const void* s2, const double* coef,
+                       bool norm) {
+  const dim3 grid(L.nblk[K_ELEM9]), block(kThreads);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL((k_gm_lincomb<double>), grid, block, 0, L.s, L.b, static_cast<double*>(dst),
+                       static_cast<const double*>(s1), static_cast<const double*>(s2), coef, norm ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_gm_lincomb<float>), grid, block, 0, L.s, L.b, static_cast<float*>(dst),
+                       static_cast<const float*>(s1), static_cast<const float*>(s2), coef, norm ? 1 : 0);
 }
 
 void launch_tangent_sum(const Launch& L, const Material& mat, const double* F, const double* w) {

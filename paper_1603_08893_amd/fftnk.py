@@ -16,8 +16,8 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "li
 OK, EINVAL, ESTATE, ENOMEM, EHIP, ECG_MAXIT, ECG_BREAKDOWN, ENEWTON_MAXIT, ENONFINITE, EMATERIAL, EUNSUPPORTED = range(11)
 FP64, FP32_MIXED = 0, 1
 SVK, J2 = 0, 1
-OPT_GRAPHS, OPT_CHECK_EVERY, OPT_NYQUIST = 1, 2, 3
-KRYLOV = {"cg": 0, "chebyshev": 1, "richardson": 2}
+OPT_GRAPHS, OPT_CHECK_EVERY, OPT_NYQUIST, OPT_GMRES_RESTART = 1, 2, 3, 4
+KRYLOV = {"cg": 0, "chebyshev": 1, "richardson": 2, "gmres": 3}
 MAX_SOLVES = 64
 
 # every symbol include/fftnk.h declares
@@ -124,10 +124,11 @@ class Solver:
     """One fftnk context: a periodic cell (or a batch of cells) on one GPU.
 
     dims: (n0, n1, n2) or a list of them (batched).  precision: "fp64" or
-    "fp32" (FP32 Krylov solve, FP64 Newton residual).
+    "fp32" (FP32 Krylov solve, FP64 Newton residual).  gmres_restart: reserve
+    the basis of restarted GMRES with this restart length (0: none).
     """
 
-    def __init__(self, dims, precision="fp64", device="cuda", stream=None):
+    def __init__(self, dims, precision="fp64", device="cuda", stream=None, gmres_restart=0):
         import torch
         self.torch = torch
         if isinstance(dims[0], (int, np.integer)):
@@ -147,6 +148,8 @@ class Solver:
         _check(L.fftnk_create_batched(ctypes.byref(ctx), self.nrve, arr, self.prec,
                                       ctypes.c_void_p(self.stream.cuda_stream)), "fftnk_create_batched")
         self.ctx = ctx
+        if gmres_restart:
+            _check(L.fftnk_set_option(ctx, OPT_GMRES_RESTART, int(gmres_restart)), "fftnk_set_option")
         nbytes = L.fftnk_workspace_bytes(ctx)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
@@ -199,11 +202,12 @@ class Solver:
         _check(lib().fftnk_set_option(self.ctx, int(option), int(value)), "fftnk_set_option")
 
     def set_krylov(self, method="cg", lo=None, hi=None, table=None):
-        """Krylov method of later linear solves: "cg", "chebyshev" or "richardson".
-        The last two need spectral bounds [lo, hi] of A on range(G); if omitted
+        """Krylov method of later linear solves: "cg", "chebyshev", "richardson"
+        or "gmres" (needs gmres_restart at construction).  Chebyshev and
+        Richardson need spectral bounds [lo, hi] of A on range(G); if omitted
         they are taken from a St. Venant-Kirchhoff table [(K, mu), ...] as
         [0.9 min mu, 1.1 max 3K] (near F = I)."""
-        if method != "cg" and (lo is None or hi is None):
+        if method in ("chebyshev", "richardson") and (lo is None or hi is None):
             tab = np.asarray(table, dtype=np.float64)
             lo = 0.9 * float(tab[:, 1].min()) if lo is None else lo
             hi = 1.1 * 3.0 * float(tab[:, 0].max()) if hi is None else hi

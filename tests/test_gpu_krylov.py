@@ -12,6 +12,10 @@ oracle's, through the C-ABI.
   counts as the oracle (within +-1 per solve), F within 1e-10 relative (FP64);
   FP32-mixed P-bar within 1e-5; the state matches the CG increment's.
 * Bad bounds are rejected.
+* GMRES: two iterations on the two-eigenvalue operator; linear solves
+  (restart lengths 5, 20, 60) and increments (FP64, FP32-mixed, a batch of two
+  cells) with the oracle's GMRES iteration counts (+-1) and solutions; the
+  basis must be reserved before the workspace is bound.
 """
 import numpy as np
 import pytest
@@ -131,3 +135,96 @@ def test_bad_bounds_rejected(torch_cuda):
                       ("chebyshev", 1.0, float("inf"))):
         with pytest.raises(fftnk.FftnkError):
             s.set_krylov(m, lo, hi)
+
+
+# ---------------------------------------------------------------- GMRES
+def _gm_solver(dims, prec, phase, m, table=TABLE):
+    from paper_1603_08893_amd.fftnk import Solver
+    s = Solver(dims, precision=prec, gmres_restart=m)
+    s.set_phases(phase)
+    s.set_material(table)
+    s.set_krylov("gmres")
+    return s
+
+
+def test_gmres_two_eigenvalues(torch_cuda, orc):
+    torch = torch_cuda
+    shape = (9, 8, 10)
+    print("gmres closed form", flush=True)
+    K0, mu0 = ms.K_HARD, ms.MU_HARD
+    s = _gm_solver(shape, "fp64", np.zeros(shape, dtype=np.uint8), 30, table=[(K0, mu0)])
+    s.set_linearization(torch.from_numpy(orc.identity_field(shape).reshape(-1)))
+    st, x, S = s.solve_linear(torch.from_numpy(ms.random_field(shape, seed=3).reshape(-1)), 1e-12, 100)
+    assert st == 0 and S[0]["cg_iters"][0] == 2 and S[0]["cg_relres"][0] < 1e-12
+
+
+@pytest.mark.parametrize("m", [5, 20, 60])
+@pytest.mark.parametrize("shape", [(9, 7, 8), (16, 16, 16)])
+def test_gmres_linear_solve_vs_oracle(torch_cuda, orc, m, shape):
+    torch = torch_cuda
+    print("gmres linear", m, shape, flush=True)
+    rng = np.random.default_rng(5)
+    ph = (rng.random(shape) < 0.3).astype(np.uint8)
+    K, mu = ms.phase_moduli(ph, TABLE)
+    F = ms.near_identity_field(shape, seed=6, scale=0.01)
+    braw = ms.random_field(shape, seed=7)
+    xo, st, it, rel = orc.krylov(F, K, mu, orc.project(braw), "gmres", m, 0, 1e-10, 20000)
+    assert st == 0
+    s = _gm_solver(shape, "fp64", ph, m)
+    s.set_linearization(torch.from_numpy(F.reshape(-1)))
+    stg, x, S = s.solve_linear(torch.from_numpy(braw.reshape(-1)), 1e-10, 20000)
+    print("oracle", it, "gpu", S[0]["cg_iters"][0], flush=True)
+    assert stg == 0 and abs(S[0]["cg_iters"][0] - it) <= 1
+    assert _rel(x.cpu().numpy(), xo) <= 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gmres_increment_vs_oracle(torch_cuda, orc, prec):
+    shape = (12, 10, 14)
+    print("gmres increment", prec, flush=True)
+    rng = np.random.default_rng(4)
+    ph = (rng.random(shape) < 0.3).astype(np.uint8)
+    K, mu = ms.phase_moduli(ph, TABLE)
+    Fbar = ms.simple_shear(0.05)
+    st, Fo, Po, Pbo, So = orc.solve_increment_krylov(K, mu, orc.identity_field(shape), Fbar, "gmres", 20, 0, 1e-8,
+                                                     1e-10)
+    assert st == 0
+    s = _gm_solver(shape, prec, ph, 20)
+    stg, F, P, Pb, S = s.solve_increment(Fbar, 1e-8, 1e-10)
+    print("oracle", So["cg_iters"], "gpu", S[0]["cg_iters"], flush=True)
+    if prec == "fp64":
+        assert S[0]["n_solves"] == So["n_solves"]
+        assert all(abs(a - b) <= 1 for a, b in zip(S[0]["cg_iters"], So["cg_iters"]))
+        assert _rel(F.cpu().numpy(), Fo) <= 1e-10
+        assert np.max(np.abs(Pb[0] - Pbo)) <= 1e-10 * np.max(np.abs(Pbo))
+    else:
+        assert np.max(np.abs(Pb[0] - Pbo)) <= 1e-5 * np.max(np.abs(Pbo))
+
+
+def test_gmres_batched_matches_single(torch_cuda, orc):
+    from paper_1603_08893_amd.fftnk import Solver
+    dims = [(9, 9, 9), (8, 10, 6)]
+    print("gmres batched", dims, flush=True)
+    phs = [(np.random.default_rng(11 + r).random(d) < 0.3).astype(np.uint8) for r, d in enumerate(dims)]
+    Fbars = [ms.simple_shear(0.04), ms.isochoric_stretch(1.03)]
+    s = Solver(dims, precision="fp64", gmres_restart=15)
+    s.set_phases(np.concatenate([(ph.reshape(-1) + 2 * r).astype(np.uint8) for r, ph in enumerate(phs)]))
+    s.set_material(TABLE * 2)
+    s.set_krylov("gmres")
+    st, F, P, Pb, S = s.solve_increment(np.stack(Fbars), 1e-8, 1e-10)
+    for r, (d, ph, Fb) in enumerate(zip(dims, phs, Fbars)):
+        K, mu = ms.phase_moduli(ph, TABLE)
+        sto, Fo, Po, Pbo, So = orc.solve_increment_krylov(K, mu, orc.identity_field(d), Fb, "gmres", 15, 0, 1e-8,
+                                                          1e-10)
+        assert sto == 0 and S[r]["n_solves"] == So["n_solves"]
+        assert all(abs(a - b) <= 1 for a, b in zip(S[r]["cg_iters"], So["cg_iters"]))
+        assert np.max(np.abs(Pb[r] - Pbo)) <= 1e-10 * np.max(np.abs(Pbo))
+
+
+def test_gmres_option_order(torch_cuda):
+    from paper_1603_08893_amd import fftnk
+    s = _solver((4, 4, 4), "fp64", np.zeros((4, 4, 4), dtype=np.uint8))
+    with pytest.raises(fftnk.FftnkError):
+        s.set_krylov("gmres")  # no basis reserved
+    with pytest.raises(fftnk.FftnkError):
+        s.set_option(fftnk.OPT_GMRES_RESTART, 10)  # after the workspace was bound
