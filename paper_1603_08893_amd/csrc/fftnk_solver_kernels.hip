@@ -105,11 +105,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_alpha(Batch B, CgState* cg) {
     s.pw = pw;
     if (!(pw > 0.0) || !isfinite(pw)) {
       // With the stagnation guard on (FP32 Krylov vectors), a non-positive
-      // curvature after the first iteration means the direction is round-off
-      // noise: stop and keep the last iterate, as for stagnation; the FP64
-      // Newton residual corrects the inexact update.  On the first iteration, or
-      // without the guard, it is a breakdown (indefinite tangent).
-      s.status = (s.stall_limit > 0 && s.iter > 0 && isfinite(pw)) ? ST_OK : ST_CG_BREAKDOWN;
+      // curvature once the residual is near the FP32 rounding floor (relative
+      // residual <= 1e-5, after the first iteration) means the direction is
+      // round-off noise: stop and keep the last iterate, as for stagnation; the
+      // FP64 Newton residual corrects the inexact update.  Otherwise it is a
+      // breakdown (indefinite tangent), as in FP64.
+      s.status = (s.stall_limit > 0 && s.iter > 0 && isfinite(pw) && s.rr <= 1e-10 * s.bb) ? ST_OK
+                                                                                         : ST_CG_BREAKDOWN;
       s.done = 1;
       s.alpha = 0.0;
       s.x_due = 0;  // this iteration's first pass applied the previous update

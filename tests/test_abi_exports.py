@@ -38,5 +38,9 @@ def test_status_strings_and_argument_checks():
     ctx = ctypes.c_void_p()
     # invalid sizes are rejected on the host, before any device work
     assert L.fftnk_create(ctypes.byref(ctx), 1, 8, 8, 0, None) == fftnk.EINVAL
+    # axis limits: a0 / a1 up to 512, a2 up to 256
+    assert L.fftnk_create(ctypes.byref(ctx), 513, 8, 8, 0, None) == fftnk.EUNSUPPORTED
+    assert L.fftnk_create(ctypes.byref(ctx), 8, 600, 8, 0, None) == fftnk.EUNSUPPORTED
+    assert L.fftnk_create(ctypes.byref(ctx), 8, 8, 257, 0, None) == fftnk.EUNSUPPORTED
     assert L.fftnk_create(ctypes.byref(ctx), 8, 8, 300, 0, None) == fftnk.EUNSUPPORTED
     assert L.fftnk_create(ctypes.byref(ctx), 8, 8, 8, 7, None) == fftnk.EINVAL
