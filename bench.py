@@ -87,7 +87,7 @@ def kernel_sources_digest():
 def recorded_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when it was taken on other kernel sources (or is absent)."""
-    path = os.path.join(ROOT, "profiles", "traffic_c2_128.json")
+    path = os.path.join(ROOT, "profiles", "traffic_grf128.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
@@ -121,8 +121,9 @@ def main():
     if args.extra:
         return extra(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the per-GPU work is one periodic cell; see DESIGN.md for how it would shard).", flush=True)
+        print("bench.py measures one GPU only: there is no multi-GPU path (the per-GPU work is one "
+              "periodic cell; independent cells or load cases would be dealt out one per GPU, a single "
+              "large cell split into slabs along a0 with an all-to-all around the a0 pass).", flush=True)
         sys.exit(2)
 
     import torch
@@ -295,7 +296,7 @@ def main():
             t_cpu += time.perf_counter() - c0
             reps += 1
         cpu = {"value": round(reps / t_cpu, 4), "unit": "matvec/s", "cores": 1, "kind": "oracle",
-               "sample": "%d projected-tangent operator applications at 128^3 (FP64, C2 linearisation point) on one "
+               "sample": "%d projected-tangent operator applications at 128^3 (FP64, the benchmark cell's linearisation point) on one "
                          "host core, %.1f s" % (reps, t_cpu)}
 
     line = {
@@ -311,7 +312,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "C2: 128^3 two-phase GRF cell (30%, 10x contrast), St.V-K, isochoric stretch "
+        "config": {"workload": "128^3 two-phase GRF cell (30%, 10x contrast), St.V-K, isochoric stretch "
                                "1.01..1.05 in 5 increments, eta_NW 1e-5, eta_CG 1e-8", "grid": [N, N, N],
                    "precision": "fp64"},
         "newton_increments_per_s": round(args.steps / sec, 3),
@@ -518,7 +519,7 @@ def extra(args):
         emit(res)
 
     if "krylov" in which:
-        # the Krylov methods on the 128^3 two-phase cell: one C2-like increment
+        # the Krylov methods on the 128^3 two-phase cell: one increment
         # (simple shear 0.05, eta_NW 1e-5, eta_CG 1e-8) each, with Chebyshev /
         # Richardson bounds [0.9 min mu, 1.1 max 3K] and GMRES(30)
         n_ = 128

@@ -1,0 +1,27 @@
+"""Host-side checks of bench.py: the algorithmic byte model behind its
+`GB_s` and `roofline.achieved` figures, and the one-GPU contract."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_byte_model_fp64_and_fp32():
+    import bench
+    op = bench.pass_bytes_per_voxel(8, 128)
+    # pass 1: p and F (2 x 72 B), phase byte, half spectrum (9 x 64/128 x 16 B)
+    assert op == {1: 217.0, 2: 144.0, 3: 144.0, 4: 144.0, 5: 144.0}
+    assert sum(op.values()) == 793.0
+    cg = bench.cg_bytes_per_voxel(8, 128)
+    assert cg["pass1"] == 505.0 and cg["pass5"] == 216.0 and sum(cg.values()) == 1153.0
+    assert sum(bench.pass_bytes_per_voxel(4, 128).values()) == 397.0
+    # odd n2: (n2 + 1) / 2 stored half-line entries
+    assert bench.pass_bytes_per_voxel(8, 31)[2] == 2 * 9 * 16 * 16 / 31
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0 and "one GPU only" in r.stdout
