@@ -8,6 +8,8 @@ a0 / a1 lengths above 256 (LDS engine, up to 512) it needs, against the oracle.
   the oracle on the same cell, equal Newton counts; the out-of-plane
   components stay zero and the fields constant through the layers.
 * The full 451 x 451 x 2 cell: projection idempotent and self-adjoint.
+* The example's stated Newton iteration pattern over its 250 increments, on a
+  101 x 101 stand-in micrograph.
 """
 import numpy as np
 import pytest
@@ -93,3 +95,24 @@ def test_projection_invariants_451(torch_cuda):
     scale = GA.abs().max().item()
     assert (s.project(GA) - GA).abs().max().item() <= 1e-13 * scale
     assert abs((B * GA).sum().item() - (GB * A).sum().item()) <= 1e-11 * abs((B * GA).sum().item())
+
+
+def test_paper_iteration_pattern_2d(torch_cuda):
+    """The example's stated Newton behaviour (Sec. 5): on average 2.2 iterations
+    per increment over 250 pure-shear increments to lambda = 1.2, up to five
+    around the yield point and two in the plastic regime.  Here on a 101 x 101
+    stand-in micrograph (chi = 2): the mean within [2.0, 2.5], at most five,
+    and two for every increment from lambda = 1.1 on."""
+    from paper_1603_08893_amd import fftnk
+    print("paper 2-D iteration pattern", flush=True)
+    ph = ms.micrograph_2d(N=101, ell=2.0, frac=0.3, seed=1701)
+    s = fftnk.Solver(ph.shape, precision="fp64")
+    s.set_phases(ph)
+    s.set_material(ms.plane_strain_j2_table(2.0), model=fftnk.J2)
+    newton = []
+    for Fb in ms.pure_shear_schedule(250, 1.2):
+        st, _, _, Pb, S = s.solve_increment(Fb, fields=False)
+        newton.append(S[0]["n_solves"])
+    print("mean", np.mean(newton), "max", max(newton), flush=True)
+    assert 2.0 <= np.mean(newton) <= 2.5 and max(newton) <= 5
+    assert all(v == 2 for v in newton[125:])  # lambda >= 1.1
