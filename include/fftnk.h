@@ -77,7 +77,8 @@ typedef struct fftnk_ctx fftnk_ctx;
  * along a2 and whose Fbar has F33 = 1, F13 = F23 = F31 = F32 = 0: its fields
  * have no a2 frequency but zero, so xi_2 = 0 and G acts as the 2-D projection.  precision: FFTNK_FP64 or
  * FFTNK_FP32_MIXED.  hip_stream: a hipStream_t (NULL = default stream).
- * Returns FFTNK_EINVAL for bad sizes.  The context owns host memory only.
+ * Returns FFTNK_EINVAL for bad sizes.  The context owns host memory only;
+ * creation makes no HIP call.
  */
 int fftnk_create(fftnk_ctx** out, int n0, int n1, int n2, int precision, void* hip_stream);
 
@@ -90,6 +91,20 @@ int fftnk_create_batched(fftnk_ctx** out, int nrve, const int* dims, int precisi
 
 /* Bytes of device workspace the context needs (256-byte aligned start). */
 size_t fftnk_workspace_bytes(const fftnk_ctx* ctx);
+
+/*
+ * Instrumentation: the context's launch geometry as one JSON object (per cell:
+ * sizes, offsets, grid lines per a2 work-group, pencils per column
+ * work-group, work-groups per launch kind, and per axis the radix plan and
+ * the FFT engine: 8 or 12 points per thread in registers, 0 the LDS engine;
+ * per context: work-groups per launch kind, LDS bytes per kernel family,
+ * workspace bytes).  Writes a NUL-terminated string into buf (host, len
+ * bytes); *needed (optional) receives the length it needs; FFTNK_ENOMEM when
+ * len is smaller.  Makes no HIP call: a context can be created and described
+ * without a GPU (creation allocates host memory only; the host staging
+ * buffer and the capture stream come with fftnk_bind_workspace).
+ */
+int fftnk_describe(const fftnk_ctx* ctx, char* buf, size_t len, size_t* needed);
 
 /*
  * Hand the context its workspace: dev must stay valid until the context is

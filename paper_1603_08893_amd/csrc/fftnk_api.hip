@@ -16,9 +16,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 using namespace fftnk;
@@ -365,9 +367,7 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
   c->active.assign(nrve, 1);
   c->uni.assign(9 * (size_t)nrve, 0.0);
   c->pinned_bytes = std::max((size_t)nrve * NSLOT * 8, (size_t)nrve * sizeof(CgState)) + 256;
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), c->pinned_bytes) != hipSuccess) return FFTNK_EHIP;
-  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) return FFTNK_EHIP;
-  return FFTNK_OK;
+  return FFTNK_OK;  // no HIP call so far: the host staging and capture stream come with the workspace
 }
 
 void drop_graphs(fftnk_ctx* c) {
@@ -978,10 +978,57 @@ int fftnk_create_batched(fftnk_ctx** out, int nrve, const int* dims, int precisi
 
 size_t fftnk_workspace_bytes(const fftnk_ctx* c) { return c ? c->total : 0; }
 
+int fftnk_describe(const fftnk_ctx* c, char* buf, size_t len, size_t* needed) {
+  if (!c) return FFTNK_EINVAL;
+  std::string j;
+  char t[512];
+  auto add = [&](const char* fmt, auto... a) {
+    std::snprintf(t, sizeof t, fmt, a...);
+    j += t;
+  };
+  add("{\"nrve\": %d, \"precision\": %d, \"workspace_bytes\": %zu, \"workspace_base_bytes\": %zu, \"gmres_restart\": %d, ",
+      c->nrve, c->prec, c->total, c->total_base, c->gm);
+  j += "\"nblk\": [";
+  for (int k = 0; k < NKIND; ++k) add(k ? ", %d" : "%d", c->nblk[k]);
+  j += "], \"lds\": [";
+  for (int k = 0; k < 8; ++k) add(k ? ", %zu" : "%zu", c->lds[k]);
+  add("], \"eng\": [%d, %d, %d], \"cells\": [", c->eng[0], c->eng[1], c->eng[2]);
+  for (int r = 0; r < c->nrve; ++r) {
+    const Grid& g = c->g[r];
+    add("%s{\"n\": [%d, %d, %d], \"h\": %d, \"rows\": %lld, \"vox_off\": %lld, \"spec_off\": %lld, "
+        "\"row_off\": %lld, \"rt\": %d, \"rt1\": %d, \"m64\": %d, \"m32\": %d, ",
+        r ? ", " : "", g.n0, g.n1, g.n2, g.h, g.rows, g.vox_off, g.spec_off, g.row_off, g.rt, g.rt1, g.m64, g.m32);
+    add("\"blocks\": {\"row\": %d, \"row1\": %d, \"col1_64\": %d, \"col1_32\": %d, \"col0_64\": %d, "
+        "\"col0_32\": %d, \"elem9\": %d, \"vox\": %d}, \"axes\": [",
+        row_blocks(g), row1_blocks(g), col1_blocks(g, PREC_F64), col1_blocks(g, PREC_F32), col0_blocks(g, PREC_F64),
+        col0_blocks(g, PREC_F32), elem_blocks(9 * g.n), elem_blocks(g.n));
+    for (int d = 0; d < 3; ++d) {
+      add("%s{\"n\": %d, \"reg\": %d, \"tw\": %d, \"radix\": [", d ? ", " : "", g.ax[d].n, g.ax[d].reg,
+          g.ax[d].tw);
+      for (int q = 0; q < g.ax[d].nstages; ++q) add(q ? ", %d" : "%d", g.ax[d].radix[q]);
+      j += "]}";
+    }
+    j += "]}";
+  }
+  add("], \"tw_total\": %d}", c->tw_total);
+  if (needed) *needed = j.size() + 1;
+  if (!buf || len < j.size() + 1) return FFTNK_ENOMEM;
+  std::memcpy(buf, j.c_str(), j.size() + 1);
+  return FFTNK_OK;
+}
+
 int fftnk_bind_workspace(fftnk_ctx* c, void* dev, size_t bytes) {
   if (!c || !dev) return FFTNK_EINVAL;
   if ((reinterpret_cast<uintptr_t>(dev) % kAlign) != 0) return FFTNK_EINVAL;
   if (bytes < c->total) return FFTNK_ENOMEM;
+  if (!c->pinned && hipHostMalloc(reinterpret_cast<void**>(&c->pinned), c->pinned_bytes) != hipSuccess) {
+    c->pinned = nullptr;
+    return FFTNK_EHIP;
+  }
+  if (!c->cap && hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+    c->cap = nullptr;
+    return FFTNK_EHIP;
+  }
   drop_graphs(c);
   c->ws = static_cast<char*>(dev);
   // twiddle tables W_n^e = exp(-2 pi i e / n), FP64 and FP32

@@ -25,7 +25,7 @@ EXPORTS = [
     "fftnk_create", "fftnk_create_batched", "fftnk_workspace_bytes", "fftnk_bind_workspace", "fftnk_set_phases",
     "fftnk_set_material", "fftnk_set_modulus_field", "fftnk_set_option", "fftnk_reset_state", "fftnk_solve_increment",
     "fftnk_solve_increment_mixed", "fftnk_macro_tangent", "fftnk_set_krylov",
-    "fftnk_solve_linear",
+    "fftnk_solve_linear", "fftnk_describe",
     "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_adjoint",
     "fftnk_launch_pass", "fftnk_profile_cg", "fftnk_get_history", "fftnk_set_history", "fftnk_get_state",
     "fftnk_set_state", "fftnk_status_string", "fftnk_destroy",
@@ -79,6 +79,7 @@ def lib():
     L.fftnk_reset_state.argtypes = [vp]
     L.fftnk_set_krylov.argtypes = [vp, i, d, d]
     L.fftnk_solve_linear.argtypes = [vp, vp, vp, d, i, ctypes.POINTER(Stats)]
+    L.fftnk_describe.argtypes = [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]
     L.fftnk_solve_increment.argtypes = [vp, dp, d, d, i, i, vp, vp, dp, ctypes.POINTER(Stats)]
     ip = ctypes.POINTER(i)
     L.fftnk_solve_increment_mixed.argtypes = [vp, dp, ip, dp, d, i, d, d, i, i, vp, vp, dp, ctypes.POINTER(Stats), ip]
@@ -109,6 +110,29 @@ def status_string(s):
         return lib().fftnk_status_string(int(s)).decode()
     except FftnkError:
         return "status %d" % s
+
+
+def describe(dims, precision="fp64", gmres_restart=0):
+    """The launch geometry the library plans for a cell (or a batch of cells),
+    as a dict; needs no GPU (a context is created and described, never bound)."""
+    import json
+    L = lib()
+    if isinstance(dims[0], (int, np.integer)):
+        dims = [dims]
+    arr = (ctypes.c_int * (3 * len(dims)))(*[int(v) for d in dims for v in d])
+    ctx = ctypes.c_void_p()
+    _check(L.fftnk_create_batched(ctypes.byref(ctx), len(dims), arr, FP64 if precision == "fp64" else FP32_MIXED,
+                                  None), "fftnk_create_batched")
+    try:
+        if gmres_restart:
+            _check(L.fftnk_set_option(ctx, OPT_GMRES_RESTART, int(gmres_restart)), "fftnk_set_option")
+        need = ctypes.c_size_t(0)
+        L.fftnk_describe(ctx, None, 0, ctypes.byref(need))
+        buf = ctypes.create_string_buffer(need.value)
+        _check(L.fftnk_describe(ctx, buf, need.value, None), "fftnk_describe")
+        return json.loads(buf.value.decode())
+    finally:
+        L.fftnk_destroy(ctx)
 
 
 def _check(status, what):

@@ -1,0 +1,128 @@
+"""Host logic of the library on a machine without a GPU: the launch geometry a
+context plans (fftnk_describe), checked against what the kernels assume.
+
+* Radix plans multiply to the length; the register engine takes exactly the
+  lengths it is compiled for (8 points: powers of two 8..256; 12 points:
+  3 * 2^k, 12..192), everything else the LDS engine.
+* a2 work-groups: pass 1 holds one voxel per thread (rt1 * n2 <= 256); the
+  tiles of passes 1 and 5 cover every grid line exactly once.
+* Column passes: the tiles cover every pencil; LDS-engine tiles hold at most
+  4 points per thread; every kernel family's LDS fits its budget.
+* Batched contexts: per-cell offsets are cumulative, the launch sizes are the
+  sums of the cells' work-groups, the engine bits cover every cell's engine.
+* The GMRES basis adds m + 1 fields to the workspace; unsupported lengths are
+  refused.
+"""
+import math
+
+import numpy as np
+import pytest
+
+THREADS = 256
+LDS_LIMIT = 61440
+
+
+def _lib_or_skip():
+    from paper_1603_08893_amd import fftnk
+    import os
+    if not os.path.exists(fftnk._LIB_PATH):
+        pytest.skip("libfftnk.so not built")
+    return fftnk
+
+
+def _reg_engine(n):
+    if n >= 8 and n <= 256 and n & (n - 1) == 0:
+        return 8
+    k = n // 3
+    if n % 3 == 0 and 12 <= n <= 192 and k & (k - 1) == 0:
+        return 12
+    return 0
+
+
+def _check_cell(c, prec):
+    n0, n1, n2 = c["n"]
+    h = n2 // 2 if n2 % 2 == 0 else (n2 + 1) // 2
+    assert c["h"] == h and c["rows"] == n0 * n1
+    for ax, n in zip(c["axes"], (n0, n1, n2)):
+        assert ax["n"] == n and math.prod(ax["radix"]) == n, ax
+        assert ax["reg"] == _reg_engine(n), ax
+    b = c["blocks"]
+    # a2 passes: every grid line in exactly one tile; pass 1 one voxel per thread
+    for key, rt in (("row", c["rt"]), ("row1", c["rt1"])):
+        assert rt >= 1 and b[key] * rt >= c["rows"] > (b[key] - 1) * rt, (key, c)
+    assert c["rt1"] * n2 <= THREADS
+    # column passes (a1: 9 n0 h pencils, a0: 3 n1 h pencils of three components)
+    for axis, npen, k64, k32 in ((1, 9 * n0 * h, "col1_64", "col1_32"), (0, 3 * n1 * h, "col0_64", "col0_32")):
+        ax = c["axes"][axis]
+        for key, M in ((k64, c["m64"]), (k32, c["m32"])):
+            if ax["reg"]:
+                per = THREADS // (ax["n"] // ax["reg"])
+                assert b[key] * per >= npen > (b[key] - 1) * per, (key, c)
+            else:
+                assert M >= 1 and M <= h and ax["n"] * M <= 4 * THREADS
+                per_line = npen // h  # pencils per k2 line
+                assert b[key] == per_line * math.ceil(h / M), (key, c)
+    assert b["elem9"] >= 1 and b["vox"] >= 1
+
+
+SHAPES = [(8, 8, 8), (31, 31, 31), (128, 128, 128), (96, 96, 96), (192, 192, 192), (256, 256, 256),
+          (24, 24, 24), (12, 10, 16), (7, 6, 9), (3, 64, 4), (10, 48, 12), (6, 12, 96), (4, 6, 192),
+          (451, 451, 2), (512, 512, 8), (257, 3, 256), (2, 2, 2), (5, 451, 2), (300, 7, 5), (9, 384, 6),
+          (48, 40, 36), (17, 13, 11)] + [(n, 5, m) for n in (2, 3, 13, 37, 64, 100, 243) for m in (2, 9, 24, 128, 255)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_single_cell_geometry(prec):
+    fftnk = _lib_or_skip()
+    for shape in SHAPES:
+        d = fftnk.describe(shape, prec)
+        assert d["nrve"] == 1
+        c = d["cells"][0]
+        _check_cell(c, prec)
+        assert max(d["lds"]) <= LDS_LIMIT
+        b = c["blocks"]
+        assert d["nblk"] == [b["row"], b["row1"], b["col1_64"], b["col1_32"], b["col0_64"], b["col0_32"],
+                             b["elem9"], b["vox"]]
+        for axis in range(3):
+            bit = {8: 2, 12: 4, 0: 1}[c["axes"][axis]["reg"]]
+            assert d["eng"][axis] == bit, (shape, d["eng"])
+        esz = 8 if prec == "fp64" else 4
+        assert d["workspace_bytes"] >= 9 * math.prod(shape) * (3 * 8 + 4 * esz)
+
+
+def test_batched_geometry():
+    fftnk = _lib_or_skip()
+    dims = [(32, 32, 32), (48, 48, 48), (64, 64, 64), (96, 96, 96), (7, 9, 11), (451, 5, 2), (12, 24, 48)]
+    d = fftnk.describe(dims)
+    vox = spec = rows = 0
+    sums = np.zeros(8, dtype=np.int64)
+    eng = [0, 0, 0]
+    for c, shape in zip(d["cells"], dims):
+        assert c["n"] == list(shape)
+        _check_cell(c, "fp64")
+        assert (c["vox_off"], c["spec_off"], c["row_off"]) == (vox, spec, rows)
+        vox += math.prod(shape)
+        spec += 9 * c["rows"] * c["h"]
+        rows += c["rows"]
+        b = c["blocks"]
+        sums += [b["row"], b["row1"], b["col1_64"], b["col1_32"], b["col0_64"], b["col0_32"], b["elem9"], b["vox"]]
+        for axis in range(3):
+            eng[axis] |= {8: 2, 12: 4, 0: 1}[c["axes"][axis]["reg"]]
+    assert d["nblk"] == sums.tolist() and d["eng"] == eng
+    assert max(d["lds"]) <= LDS_LIMIT
+    # one twiddle table per distinct length
+    lengths = {n for shape in dims for n in shape}
+    assert d["tw_total"] == sum(lengths)
+
+
+def test_gmres_basis_and_refused_lengths():
+    fftnk = _lib_or_skip()
+    shape = (24, 20, 16)
+    for prec, esz in (("fp64", 8), ("fp32", 4)):
+        d = fftnk.describe(shape, prec, gmres_restart=12)
+        extra = d["workspace_bytes"] - d["workspace_base_bytes"]
+        need = 13 * 9 * math.prod(shape) * esz
+        assert need <= extra < need + 256
+    for bad in ((513, 4, 4), (4, 600, 4), (4, 4, 257), (1, 4, 4)):
+        with pytest.raises(fftnk.FftnkError):
+            fftnk.describe(bad)
