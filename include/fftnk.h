@@ -221,8 +221,9 @@ int fftnk_solve_increment(fftnk_ctx* ctx, const double* Fbar_host, double eta_nw
  * Fbar (the first from the committed state, later ones from the previous
  * pass's equilibrium); it stops when max_k |Pbar_k - Ptarget_k| <= tol_stress
  * (absolute, stress units) over the masked k; otherwise the masked block of
- * the macroscopic tangent (fftnk_macro_tangent, at the current equilibrium)
- * gives the Newton step of Fbar.  outer_host (optional, [nrve]) receives the
+ * the macroscopic tangent (fftnk_macro_tangent, at the current equilibrium,
+ * its columns solved to CG tolerance max(eta_cg, 1e-4): the block only steers
+ * the step) gives the Newton step of Fbar.  outer_host (optional, [nrve]) receives the
  * passes taken; stats (optional, [nrve]) lists every linear solve in order
  * (Newton and tangent solves; n_solves counts them all, the arrays hold the
  * first FFTNK_MAX_SOLVES).  The remaining arguments and the commit / failure

@@ -786,7 +786,8 @@ int orc_solve_increment_j2(int n0, int n1, int n2, const double* K, const double
 //   from the previous iterate's equilibrium, the load step's start state at
 //   first); R = Pbar_M - Ptarget_M; stop when max |R| <= tol_stress; else
 //   Fbar_M -= C_MM^{-1} R with C_MM the masked block of the macroscopic
-//   tangent at the current equilibrium.
+//   tangent at the current equilibrium, its columns solved to CG tolerance
+//   max(eta_cg, 1e-4).
 // ---------------------------------------------------------------------------
 
 static void mean9(const double* X, long n, double out[9]) {
@@ -920,8 +921,10 @@ static int solve_mixed_impl(const orc_problem& pb, double* F, double* Fbar, cons
       return ORC_OK;
     }
     if (it + 1 == max_outer) break;
+    // the masked block only steers the outer step: its columns are solved to
+    // max(eta_cg, 1e-4) (the stress test, not the tangent, decides convergence)
     double C[81] = {0.0};
-    const int sc = macro_tangent_impl(pb, Fk.data(), mask, C, eta_cg, max_cg, st);
+    const int sc = macro_tangent_impl(pb, Fk.data(), mask, C, std::fmax(eta_cg, 1e-4), max_cg, st);
     if (sc != ORC_OK) {
       st->status = sc;
       return sc;

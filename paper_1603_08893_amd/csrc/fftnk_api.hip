@@ -1262,7 +1262,8 @@ int fftnk_solve_increment_mixed(fftnk_ctx* c, double* Fbar, const int* mask, con
     for (int r = 0; r < nr; ++r)
       for (int k = 0; k < 9; ++k) want[9 * r + k] = need[r] && mask[9 * r + k];
     std::memset(st.data(), 0, nr * sizeof(fftnk_stats));
-    e = macro_tangent_columns(c, want.data(), eta_cg, max_cg, C.data(), st, status);
+    // the block only steers the outer step: columns to max(eta_cg, 1e-4)
+    e = macro_tangent_columns(c, want.data(), std::max(eta_cg, 1e-4), max_cg, C.data(), st, status);
     if (e) return e;
     for (int r = 0; r < nr; ++r) {
       if (!need[r]) continue;
