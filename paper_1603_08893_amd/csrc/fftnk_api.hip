@@ -532,6 +532,17 @@ int run_gmres(fftnk_ctx* c, double eta, int max_it) {
   const Launch L = c->launch();
   const Material mat = c->material();
   const std::vector<int> act0 = c->active;  // the caller's mask, restored at the end
+  // on an early (error) return the caller's mask is restored all the same
+  struct MaskGuard {
+    fftnk_ctx* c;
+    const std::vector<int>& saved;
+    bool armed = true;
+    ~MaskGuard() {
+      if (!armed) return;
+      c->active = saved;
+      if (upload_active(c) == FFTNK_OK) (void)hipStreamSynchronize(c->stream);
+    }
+  } guard{c, act0};
   int e = reduce_fetch(c, {{K_ROW1, {SLOT_YY, 1}}, {K_ROW, {SLOT_BB, 1}}});
   if (e) return e;
   struct RveGm {
@@ -642,27 +653,45 @@ int run_gmres(fftnk_ctx* c, double eta, int max_it) {
         R[r].iters += c->active[r];
         std::fill(R[r].h.begin(), R[r].h.end(), 0.0);
       }
-      // w -= sum_i h_i V_i twice (classical Gram-Schmidt, re-orthogonalised)
+      // w -= sum_i h_i V_i by classical Gram-Schmidt; a second pass only where
+      // the first kept less than 1/sqrt(2) of ||w|| (the "twice is enough"
+      // test of Daniel, Gragg, Kaufman and Stewart)
+      std::vector<double> w0(nr, 0.0), hn2(nr, 0.0);
+      const std::vector<int> act_j = c->active;
       for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+          a = set_active([&](int r) { return c->active[r] && hn2[r] < 0.5 * w0[r]; });
+          if (a < 0) return -a;
+          if (a == 0) break;
+        }
         for (int i0 = 0; i0 <= j; i0 += kGmDot) {
           const int kk = std::min(kGmDot, j + 1 - i0);
-          launch_gm_dots(prec, L, c->w(), V(0), vstride, i0, kk);
-          if ((e = reduce_fetch(c, {{K_ELEM9, {SLOT_DOT, kk}}}))) return e;
-          for (int r = 0; r < nr; ++r)
+          const bool ww = pass == 0 && i0 == 0;
+          launch_gm_dots(prec, L, c->w(), V(0), vstride, i0, kk, ww);
+          e = ww ? reduce_fetch(c, {{K_ELEM9, {SLOT_DOT, kk}}, {K_ELEM9, {SLOT_AUX, 1}}})
+                 : reduce_fetch(c, {{K_ELEM9, {SLOT_DOT, kk}}});
+          if (e) return e;
+          for (int r = 0; r < nr; ++r) {
+            if (ww) w0[r] = red_at(c, r, SLOT_AUX);
             for (int q2 = 0; q2 < kk; ++q2) {
               const double d = c->active[r] ? red_at(c, r, SLOT_DOT + q2) : 0.0;
               R[r].h[i0 + q2] += d;
               hc[(size_t)r * kGmCoef + q2] = -d;
             }
+          }
           if ((e = upload_coef())) return e;
-          launch_gm_update(prec, L, c->w(), V(0), vstride, i0, kk, coef, pass == 1 && i0 + kk == j + 1);
+          launch_gm_update(prec, L, c->w(), V(0), vstride, i0, kk, coef, i0 + kk == j + 1);
         }
+        if ((e = reduce_fetch(c, {{K_ELEM9, {SLOT_RR, 1}}}))) return e;
+        for (int r = 0; r < nr; ++r)
+          if (c->active[r]) hn2[r] = red_at(c, r, SLOT_RR);
       }
-      if ((e = reduce_fetch(c, {{K_ELEM9, {SLOT_RR, 1}}}))) return e;
+      a = set_active([&](int r) { return act_j[r] != 0; });
+      if (a < 0) return -a;
       for (int r = 0; r < nr; ++r) {
         if (!c->active[r]) continue;
         RveGm& q = R[r];
-        const double hn = std::sqrt(red_at(c, r, SLOT_RR));
+        const double hn = std::sqrt(hn2[r]);
         for (int i = 0; i <= j; ++i) q.H[(size_t)i * m + j] = q.h[i];
         q.H[(size_t)(j + 1) * m + j] = hn;
         hc[(size_t)r * kGmCoef] = hn > 0.0 ? 1.0 / hn : 0.0;
@@ -729,6 +758,7 @@ int run_gmres(fftnk_ctx* c, double eta, int max_it) {
     hs[r].zero_rhs = q.zero;
     hs[r].method = KRYLOV_GMRES;
   }
+  guard.armed = false;
   c->active = act0;
   e = upload_active(c);
   if (e) return e;

@@ -38,8 +38,8 @@ struct AxisPlan {
   int nstages;
   int radix[kMaxStages];
   int tw;   // offset (in complex entries) of the length-n twiddle table W_n^e, e in [0, n)
-  int reg;  // points per thread of the register-resident engine: 8 (n = 2^k >= 8), 12 (n = 3 2^k,
-            // 12..192, not on axis a0), 0 = LDS engine
+  int reg;  // points per thread of the register-resident engine: 8 (n = 2^k, 8..256), 12 (n = 3 2^k,
+            // 12..192), 0 = LDS engine
 };
 
 // One periodic cell (RVE).  Real tensor fields are component-major
@@ -220,10 +220,11 @@ void launch_tangent_sum(const Launch& L, const Material& mat, const double* F, c
 // GMRES, element-wise over each active RVE's 9 n values; the basis vector j
 // starts at V + j * vstride elements (vstride = 9 ntot); coef is a device
 // array [nrve][kGmCoef].  dots: partial sums of <w, V_{i0+q}>, q < k, into
-// SLOT_DOT + q.  update: y += sum_q coef[r][q] V_{i0+q}; with norm the
+// SLOT_DOT + q, and with ww those of ||w||^2 into SLOT_AUX.  update: y += sum_q coef[r][q] V_{i0+q}; with norm the
 // partial sums of ||y||^2 into SLOT_RR.  lincomb: dst = coef[r][0] s1 +
 // coef[r][1] s2 (s2 may be null, dst may be s1); norm as for update.
-void launch_gm_dots(int prec, const Launch& L, const void* w, const void* V, long long vstride, int i0, int k);
+void launch_gm_dots(int prec, const Launch& L, const void* w, const void* V, long long vstride, int i0, int k,
+                    bool ww);
 void launch_gm_update(int prec, const Launch& L, void* y, const void* V, long long vstride, int i0, int k,
                       const double* coef, bool norm);
 void launch_gm_lincomb(int prec, const Launch& L, void* dst, const void* s1, const void* s2, const double* coef,

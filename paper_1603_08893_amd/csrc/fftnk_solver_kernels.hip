@@ -436,26 +436,29 @@ __global__ __launch_bounds__(kThreads) void k_tangent_sum(Batch B, Material mat,
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gm_dots(Batch B, const T* __restrict__ w, const T* __restrict__ V,
-                                                      long long vstride, int i0, int k) {
+                                                      long long vstride, int i0, int k, int ww) {
   int local;
   const int rv = find_rve(B, K_ELEM9, blockIdx.x, local);
   if (skip_rve(B, nullptr, rv)) return;
   const Grid& g = B.grids[rv];
   const int nb = rve_blocks(B, K_ELEM9, rv);
   const long long m = 9 * g.n, off = 9 * g.vox_off;
-  double acc[kGmDot];
+  double acc[kGmDot + 1];
 #pragma unroll
-  for (int q = 0; q < kGmDot; ++q) acc[q] = 0.0;
+  for (int q = 0; q <= kGmDot; ++q) acc[q] = 0.0;
   FOR_RVE_RANGE(i, m, local, nb) {
     const double wi = (double)w[off + i];
 #pragma unroll
     for (int q = 0; q < kGmDot; ++q)
       if (q < k) acc[q] += wi * (double)V[(long long)(i0 + q) * vstride + off + i];
+    acc[kGmDot] += wi * wi;
   }
-  double res[kGmDot];
-  block_sums<kGmDot>(acc, res);
-  if (threadIdx.x == 0)
+  double res[kGmDot + 1];
+  block_sums<kGmDot + 1>(acc, res);
+  if (threadIdx.x == 0) {
     for (int q = 0; q < k; ++q) pslot(B, SLOT_DOT + q)[blockIdx.x] = res[q];
+    if (ww) pslot(B, SLOT_AUX)[blockIdx.x] = res[kGmDot];  // ||w||^2
+  }
 }
 
 template <typename T>
@@ -598,14 +601,15 @@ void launch_set_identity(const Launch& L, double* F) {
   hipLaunchKernelGGL(k_set_identity, dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, F);
 }
 
-void launch_gm_dots(int prec, const Launch& L, const void* w, const void* V, long long vstride, int i0, int k) {
+void launch_gm_dots(int prec, const Launch& L, const void* w, const void* V, long long vstride, int i0, int k,
+                    bool ww) {
   const dim3 grid(L.nblk[K_ELEM9]), block(kThreads);
   if (prec == PREC_F64)
     hipLaunchKernelGGL((k_gm_dots<double>), grid, block, 0, L.s, L.b, static_cast<const double*>(w),
-                       static_cast<const double*>(V), vstride, i0, k);
+                       static_cast<const double*>(V), vstride, i0, k, ww ? 1 : 0);
   else
     hipLaunchKernelGGL((k_gm_dots<float>), grid, block, 0, L.s, L.b, static_cast<const float*>(w),
-                       static_cast<const float*>(V), vstride, i0, k);
+                       static_cast<const float*>(V), vstride, i0, k, ww ? 1 : 0);
 }
 
 void launch_gm_update(int prec, const Launch& L, void* y, const void* V, long long vstride, int i0, int k,
