@@ -178,7 +178,8 @@ int fftnk_reset_state(fftnk_ctx* ctx);
  * mu_min <= <p, A p> / <p, p> <= 3 K_max (periodic Korn inequality and the
  * largest local eigenvalue); finite strain and plasticity move the spectrum.
  * FFTNK_KRYLOV_GMRES: restarted GMRES(m) (Saad, same book, Alg. 6.9; Arnoldi
- * with classical Gram-Schmidt applied twice, Givens rotations, m from
+ * with classical Gram-Schmidt, repeated where the first pass cancels more than
+ * the Daniel-Gragg-Kaufman-Stewart test allows, Givens rotations, m from
  * FFTNK_OPT_GMRES_RESTART, else FFTNK_ESTATE; lo, hi unused), for tangents
  * that are not symmetric; it needs no bounds but stores m + 1 basis fields
  * and synchronises with the host once per inner-product batch.

@@ -520,13 +520,14 @@ double red_at(fftnk_ctx* c, int r, int slot) { return c->host_red()[r * NSLOT + 
 // pipeline), x = 0 on entry, solution in x, per-RVE outcome written to the
 // host CgState array that run_cg's callers read (iterations = operator
 // applications, the restarts' residual evaluations included).  Arnoldi uses
-// classical Gram-Schmidt applied twice (one pass over the basis per
-// inner-product batch instead of one per vector); the Hessenberg columns,
-// rotations and the small triangular solve live on the host.
+// classical Gram-Schmidt (one pass over the basis per inner-product batch
+// instead of one per vector), repeated where the first pass cancelled more
+// than the test of Daniel, Gragg, Kaufman and Stewart allows; the Hessenberg
+// columns, rotations and the small triangular solve live on the host.
 int run_gmres(fftnk_ctx* c, double eta, int max_it) {
   const int nr = c->nrve, m = c->gm, prec = c->prec;
   const size_t esz = prec == PREC_F64 ? 8 : 4;
-  const long long vstride = 9 * c->ntot;
+  const long long vstride = gm_vstride(c->ntot);
   auto V = [&](int j) { return static_cast<void*>(c->ws + c->o_gm + (size_t)j * vstride * esz); };
   double* coef = c->at<double>(c->o_coef);
   const Launch L = c->launch();
@@ -658,33 +659,62 @@ int run_gmres(fftnk_ctx* c, double eta, int max_it) {
       // test of Daniel, Gragg, Kaufman and Stewart)
       std::vector<double> w0(nr, 0.0), hn2(nr, 0.0);
       const std::vector<int> act_j = c->active;
-      for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1) {
-          a = set_active([&](int r) { return c->active[r] && hn2[r] < 0.5 * w0[r]; });
-          if (a < 0) return -a;
-          if (a == 0) break;
-        }
-        for (int i0 = 0; i0 <= j; i0 += kGmDot) {
-          const int kk = std::min(kGmDot, j + 1 - i0);
-          const bool ww = pass == 0 && i0 == 0;
-          launch_gm_dots(prec, L, c->w(), V(0), vstride, i0, kk, ww);
-          e = ww ? reduce_fetch(c, {{K_ELEM9, {SLOT_DOT, kk}}, {K_ELEM9, {SLOT_AUX, 1}}})
-                 : reduce_fetch(c, {{K_ELEM9, {SLOT_DOT, kk}}});
-          if (e) return e;
-          for (int r = 0; r < nr; ++r) {
-            if (ww) w0[r] = red_at(c, r, SLOT_AUX);
-            for (int q2 = 0; q2 < kk; ++q2) {
-              const double d = c->active[r] ? red_at(c, r, SLOT_DOT + q2) : 0.0;
-              R[r].h[i0 + q2] += d;
-              hc[(size_t)r * kGmCoef + q2] = -d;
-            }
+      auto take_dots = [&](int i0, int kk) {  // h += d, next coefficients -d
+        for (int r = 0; r < nr; ++r)
+          for (int q2 = 0; q2 < kk; ++q2) {
+            const double d = c->active[r] ? red_at(c, r, SLOT_DOT + q2) : 0.0;
+            R[r].h[i0 + q2] += d;
+            hc[(size_t)r * kGmCoef + q2] = -d;
           }
-          if ((e = upload_coef())) return e;
-          launch_gm_update(prec, L, c->w(), V(0), vstride, i0, kk, coef, i0 + kk == j + 1);
-        }
-        if ((e = reduce_fetch(c, {{K_ELEM9, {SLOT_RR, 1}}}))) return e;
+      };
+      auto need_second = [&](int r) { return c->active[r] && hn2[r] < 0.5 * w0[r]; };
+      if (j + 1 <= kGmDot) {
+        // one batch: the first pass's update also takes the second pass's
+        // inner products, so the basis is read twice, or three times where
+        // the second pass is needed
+        launch_gm_dots(prec, L, c->w(), V(0), vstride, 0, j + 1, true);
+        if ((e = reduce_fetch(c, {{K_ELEM9, {SLOT_DOT, j + 1}}, {K_ELEM9, {SLOT_AUX, 1}}}))) return e;
+        for (int r = 0; r < nr; ++r) w0[r] = red_at(c, r, SLOT_AUX);
+        take_dots(0, j + 1);
+        if ((e = upload_coef())) return e;
+        launch_gm_update(prec, L, c->w(), V(0), vstride, 0, j + 1, coef, true, true);
+        if ((e = reduce_fetch(c, {{K_ELEM9, {SLOT_DOT, j + 1}}, {K_ELEM9, {SLOT_RR, 1}}}))) return e;
         for (int r = 0; r < nr; ++r)
           if (c->active[r]) hn2[r] = red_at(c, r, SLOT_RR);
+        a = set_active(need_second);
+        if (a < 0) return -a;
+        if (a > 0) {
+          take_dots(0, j + 1);
+          if ((e = upload_coef())) return e;
+          launch_gm_update(prec, L, c->w(), V(0), vstride, 0, j + 1, coef, true);
+          if ((e = reduce_fetch(c, {{K_ELEM9, {SLOT_RR, 1}}}))) return e;
+          for (int r = 0; r < nr; ++r)
+            if (c->active[r]) hn2[r] = red_at(c, r, SLOT_RR);
+        }
+      } else {
+        for (int pass = 0; pass < 2; ++pass) {
+          if (pass == 1) {
+            a = set_active(need_second);
+            if (a < 0) return -a;
+            if (a == 0) break;
+          }
+          for (int i0 = 0; i0 <= j; i0 += kGmDot) {
+            const int kk = std::min(kGmDot, j + 1 - i0);
+            const bool ww = pass == 0 && i0 == 0;
+            launch_gm_dots(prec, L, c->w(), V(0), vstride, i0, kk, ww);
+            e = ww ? reduce_fetch(c, {{K_ELEM9, {SLOT_DOT, kk}}, {K_ELEM9, {SLOT_AUX, 1}}})
+                   : reduce_fetch(c, {{K_ELEM9, {SLOT_DOT, kk}}});
+            if (e) return e;
+            if (ww)
+              for (int r = 0; r < nr; ++r) w0[r] = red_at(c, r, SLOT_AUX);
+            take_dots(i0, kk);
+            if ((e = upload_coef())) return e;
+            launch_gm_update(prec, L, c->w(), V(0), vstride, i0, kk, coef, i0 + kk == j + 1);
+          }
+          if ((e = reduce_fetch(c, {{K_ELEM9, {SLOT_RR, 1}}}))) return e;
+          for (int r = 0; r < nr; ++r)
+            if (c->active[r]) hn2[r] = red_at(c, r, SLOT_RR);
+        }
       }
       a = set_active([&](int r) { return act_j[r] != 0; });
       if (a < 0) return -a;
@@ -1149,7 +1179,7 @@ int fftnk_set_option(fftnk_ctx* c, int option, int value) {
       if (value < 1 || value > 256) return FFTNK_EINVAL;
       if (c->ws) return FFTNK_ESTATE;  // sizes the workspace: set before binding it
       c->gm = value;
-      const size_t fv = 9 * (size_t)c->ntot * (c->prec == PREC_F64 ? 8 : 4);
+      const size_t fv = (size_t)gm_vstride(c->ntot) * (c->prec == PREC_F64 ? 8 : 4);
       c->total = align_up(c->total_base + (size_t)(value + 1) * fv);
       return FFTNK_OK;
     }

@@ -16,7 +16,7 @@ constexpr int kMaxLen = 512;       // longest supported a0 / a1 axis (the LDS en
 constexpr int kMaxLenA2 = 256;     // longest a2 axis (pass 1 holds a work-group's lines one voxel per thread)
 constexpr int kMaxRegLen = 256;    // longest length of the register-resident engine
 constexpr int kMaxRve = 256;       // RVEs of one batched context
-constexpr int kRedBlocks = 2048;   // most work-groups of an element-wise kernel per RVE
+constexpr int kRedBlocks = 8192;   // most work-groups of an element-wise kernel per RVE
 constexpr int kRegP = 8;           // points per thread of the register-resident FFT engine
 constexpr int kMaxPpt = 4;         // points per thread of an LDS-engine column tile (n * m <= kMaxPpt * kThreads)
 
@@ -108,6 +108,10 @@ enum {
 };
 constexpr int kGmDot = 16;   // basis vectors per GMRES inner-product / update launch
 constexpr int kGmCoef = 16;  // per-RVE coefficients of one GMRES update launch
+// elements between consecutive GMRES basis vectors: 9 ntot rounded up to an
+// even count, so that element pairs start on 2-element boundaries in every
+// basis vector
+inline long long gm_vstride(long long ntot) { return (9 * ntot + 63) / 64 * 64; }
 
 // Device-resident CG scalars of one RVE.
 struct CgState {
@@ -218,15 +222,18 @@ void launch_adjoint_grad(int prec, const Launch& L, const double* F, const void*
 // sums of K(F) : (uni - w) per RVE into SLOT_PBAR .. + 8 (w FP64)
 void launch_tangent_sum(const Launch& L, const Material& mat, const double* F, const double* w);
 // GMRES, element-wise over each active RVE's 9 n values; the basis vector j
-// starts at V + j * vstride elements (vstride = 9 ntot); coef is a device
-// array [nrve][kGmCoef].  dots: partial sums of <w, V_{i0+q}>, q < k, into
-// SLOT_DOT + q, and with ww those of ||w||^2 into SLOT_AUX.  update: y += sum_q coef[r][q] V_{i0+q}; with norm the
-// partial sums of ||y||^2 into SLOT_RR.  lincomb: dst = coef[r][0] s1 +
-// coef[r][1] s2 (s2 may be null, dst may be s1); norm as for update.
+// starts at V + j * vstride elements (vstride = gm_vstride(ntot)); coef is a
+// device array [nrve][kGmCoef]; k (1..kGmDot) basis vectors V_{i0+q}, q < k,
+// per launch.  dots: partial sums of <w, V_{i0+q}> into SLOT_DOT + q, and with
+// ww those of ||w||^2 into SLOT_AUX.  update: y += sum_q coef[r][q] V_{i0+q};
+// with norm the partial sums of ||y||^2 into SLOT_RR; with dots also those of
+// <y, V_{i0+q}> of the updated y into SLOT_DOT + q (and ||y||^2 as with norm).
+// lincomb: dst = coef[r][0] s1 + coef[r][1] s2 (s2 may be null, dst may be
+// s1); norm as for update.
 void launch_gm_dots(int prec, const Launch& L, const void* w, const void* V, long long vstride, int i0, int k,
                     bool ww);
 void launch_gm_update(int prec, const Launch& L, void* y, const void* V, long long vstride, int i0, int k,
-                      const double* coef, bool norm);
+                      const double* coef, bool norm, bool dots = false);
 void launch_gm_lincomb(int prec, const Launch& L, void* dst, const void* s1, const void* s2, const double* coef,
                        bool norm);
 

@@ -9,6 +9,8 @@
 // and the adjoint gradient.  Every launch covers all RVEs of a context.
 // Reductions: block partial sums in fixed slots, summed in a fixed order by one
 // work-group per RVE, so results are bitwise reproducible.
+#include <utility>
+
 #include "fftnk_device.h"
 #include "fftnk_j2.h"
 
@@ -432,62 +434,148 @@ __global__ __launch_bounds__(kThreads) void k_tangent_sum(Batch B, Material mat,
 }
 
 // ---------------------------------------------------------------------------
-// GMRES building blocks (Arnoldi with classical Gram-Schmidt applied twice).
+// GMRES building blocks (Arnoldi with classical Gram-Schmidt).  Each cell's
+// 9 n values are taken in element pairs, one 2-element vector load per field
+// (the basis stride is even and every field starts on a 256-byte boundary):
+// pairs start at the first even global index of the cell; the one or two
+// elements left over at the cell's ends go to the first thread of the cell's
+// first work-group.
 // ---------------------------------------------------------------------------
 template <typename T>
+struct Pair2;
+template <>
+struct Pair2<double> { using type = double2; };
+template <>
+struct Pair2<float> { using type = float2; };
+
+struct PairRange {
+  long long s0, np, lone[2];
+  int nlone;
+  __device__ PairRange(long long off, long long m) {
+    s0 = off & 1;
+    np = (m - s0) >> 1;
+    nlone = 0;
+    if (s0 && m > 0) lone[nlone++] = 0;
+    if (m > s0 && ((m - s0) & 1)) lone[nlone++] = m - 1;
+  }
+};
+
+// K (1..kGmDot) is the number of basis vectors of the launch, fixed at
+// compile time so that all K loads of an element pair are issued before the
+// first is used.
+template <typename T, int K>
 __global__ __launch_bounds__(kThreads) void k_gm_dots(Batch B, const T* __restrict__ w, const T* __restrict__ V,
-                                                      long long vstride, int i0, int k, int ww) {
+                                                      long long vstride, int i0, int ww) {
+  using P2 = typename Pair2<T>::type;
   int local;
   const int rv = find_rve(B, K_ELEM9, blockIdx.x, local);
   if (skip_rve(B, nullptr, rv)) return;
   const Grid& g = B.grids[rv];
   const int nb = rve_blocks(B, K_ELEM9, rv);
   const long long m = 9 * g.n, off = 9 * g.vox_off;
-  double acc[kGmDot + 1];
+  const PairRange pr(off, m);
+  const T* Vq = V + (long long)i0 * vstride + off;
+  const T* wc = w + off;
+  double acc[K + 1];
 #pragma unroll
-  for (int q = 0; q <= kGmDot; ++q) acc[q] = 0.0;
-  FOR_RVE_RANGE(i, m, local, nb) {
-    const double wi = (double)w[off + i];
+  for (int q = 0; q <= K; ++q) acc[q] = 0.0;
+  FOR_RVE_RANGE(p, pr.np, local, nb) {
+    const long long e = pr.s0 + 2 * p;
+    const P2 wv = *reinterpret_cast<const P2*>(wc + e);
+    P2 v[K];
 #pragma unroll
-    for (int q = 0; q < kGmDot; ++q)
-      if (q < k) acc[q] += wi * (double)V[(long long)(i0 + q) * vstride + off + i];
-    acc[kGmDot] += wi * wi;
+    for (int q = 0; q < K; ++q) v[q] = *reinterpret_cast<const P2*>(Vq + q * vstride + e);
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] += (double)wv.x * (double)v[q].x + (double)wv.y * (double)v[q].y;
+    acc[K] += (double)wv.x * (double)wv.x + (double)wv.y * (double)wv.y;
   }
-  double res[kGmDot + 1];
-  block_sums<kGmDot + 1>(acc, res);
+  if (local == 0 && threadIdx.x == 0)
+    for (int t = 0; t < pr.nlone; ++t) {
+      const long long e = pr.lone[t];
+      const double wi = (double)wc[e];
+#pragma unroll
+      for (int q = 0; q < K; ++q) acc[q] += wi * (double)Vq[q * vstride + e];
+      acc[K] += wi * wi;
+    }
+  double res[K + 1];
+  block_sums<K + 1>(acc, res);
   if (threadIdx.x == 0) {
-    for (int q = 0; q < k; ++q) pslot(B, SLOT_DOT + q)[blockIdx.x] = res[q];
-    if (ww) pslot(B, SLOT_AUX)[blockIdx.x] = res[kGmDot];  // ||w||^2
+#pragma unroll
+    for (int q = 0; q < K; ++q) pslot(B, SLOT_DOT + q)[blockIdx.x] = res[q];
+    if (ww) pslot(B, SLOT_AUX)[blockIdx.x] = res[K];  // ||w||^2
   }
 }
 
-template <typename T>
+// y += sum_q coef[rv][q] V_{i0+q}; with norm ||y||^2 into SLOT_RR; with DOTS
+// also <y, V_{i0+q}> of the updated y into SLOT_DOT + q (the next Gram-Schmidt
+// pass's inner products, from the basis values already loaded).
+template <typename T, int K, bool DOTS>
 __global__ __launch_bounds__(kThreads) void k_gm_update(Batch B, T* __restrict__ y, const T* __restrict__ V,
-                                                        long long vstride, int i0, int k,
+                                                        long long vstride, int i0,
                                                         const double* __restrict__ coef, int norm) {
+  using P2 = typename Pair2<T>::type;
   int local;
   const int rv = find_rve(B, K_ELEM9, blockIdx.x, local);
   if (skip_rve(B, nullptr, rv)) return;
   const Grid& g = B.grids[rv];
   const int nb = rve_blocks(B, K_ELEM9, rv);
   const long long m = 9 * g.n, off = 9 * g.vox_off;
-  double c[kGmCoef];
+  const PairRange pr(off, m);
+  const T* Vq = V + (long long)i0 * vstride + off;
+  T* yc = y + off;
+  double c[K];
 #pragma unroll
-  for (int q = 0; q < kGmCoef; ++q) c[q] = q < k ? coef[rv * kGmCoef + q] : 0.0;
-  double acc[1] = {0.0};
-  FOR_RVE_RANGE(i, m, local, nb) {
-    double v = (double)y[off + i];
+  for (int q = 0; q < K; ++q) c[q] = coef[rv * kGmCoef + q];
+  constexpr int NA = DOTS ? K + 1 : 1;  // [dots..., ||y||^2]
+  double acc[NA];
 #pragma unroll
-    for (int q = 0; q < kGmCoef; ++q)
-      if (q < k) v += c[q] * (double)V[(long long)(i0 + q) * vstride + off + i];
-    const T t = (T)v;
-    y[off + i] = t;
-    acc[0] += (double)t * (double)t;
+  for (int q = 0; q < NA; ++q) acc[q] = 0.0;
+  FOR_RVE_RANGE(p, pr.np, local, nb) {
+    const long long e = pr.s0 + 2 * p;
+    const P2 yv = *reinterpret_cast<const P2*>(yc + e);
+    P2 a[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) a[q] = *reinterpret_cast<const P2*>(Vq + q * vstride + e);
+    double v0 = (double)yv.x, v1 = (double)yv.y;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      v0 += c[q] * (double)a[q].x;
+      v1 += c[q] * (double)a[q].y;
+    }
+    P2 t;
+    t.x = (T)v0;
+    t.y = (T)v1;
+    *reinterpret_cast<P2*>(yc + e) = t;
+    if constexpr (DOTS) {
+#pragma unroll
+      for (int q = 0; q < K; ++q) acc[q] += (double)t.x * (double)a[q].x + (double)t.y * (double)a[q].y;
+    }
+    acc[NA - 1] += (double)t.x * (double)t.x + (double)t.y * (double)t.y;
   }
-  if (norm) {
-    double res[1];
-    block_sums<1>(acc, res);
-    if (threadIdx.x == 0) pslot(B, SLOT_RR)[blockIdx.x] = res[0];
+  if (local == 0 && threadIdx.x == 0)
+    for (int u = 0; u < pr.nlone; ++u) {
+      const long long e = pr.lone[u];
+      double v = (double)yc[e];
+#pragma unroll
+      for (int q = 0; q < K; ++q) v += c[q] * (double)Vq[q * vstride + e];
+      const T t = (T)v;
+      yc[e] = t;
+      if constexpr (DOTS) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) acc[q] += (double)t * (double)Vq[q * vstride + e];
+      }
+      acc[NA - 1] += (double)t * (double)t;
+    }
+  if (norm || DOTS) {
+    double res[NA];
+    block_sums<NA>(acc, res);
+    if (threadIdx.x == 0) {
+      if constexpr (DOTS) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) pslot(B, SLOT_DOT + q)[blockIdx.x] = res[q];
+      }
+      pslot(B, SLOT_RR)[blockIdx.x] = res[NA - 1];
+    }
   }
 }
 
@@ -495,21 +583,43 @@ __global__ __launch_bounds__(kThreads) void k_gm_update(Batch B, T* __restrict__
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_gm_lincomb(Batch B, T* dst, const T* s1, const T* __restrict__ s2,
                                                          const double* __restrict__ coef, int norm) {
+  using P2 = typename Pair2<T>::type;
   int local;
   const int rv = find_rve(B, K_ELEM9, blockIdx.x, local);
   if (skip_rve(B, nullptr, rv)) return;
   const Grid& g = B.grids[rv];
   const int nb = rve_blocks(B, K_ELEM9, rv);
   const long long m = 9 * g.n, off = 9 * g.vox_off;
+  const PairRange pr(off, m);
   const double a = coef[rv * kGmCoef], b = coef[rv * kGmCoef + 1];
+  T* dc = dst + off;
+  const T* c1 = s1 + off;
+  const T* c2 = s2 ? s2 + off : nullptr;
   double acc[1] = {0.0};
-  FOR_RVE_RANGE(i, m, local, nb) {
-    double v = a * (double)s1[off + i];
-    if (s2) v += b * (double)s2[off + i];
-    const T t = (T)v;
-    dst[off + i] = t;
-    acc[0] += (double)t * (double)t;
+  FOR_RVE_RANGE(p, pr.np, local, nb) {
+    const long long e = pr.s0 + 2 * p;
+    const P2 u = *reinterpret_cast<const P2*>(c1 + e);
+    double v0 = a * (double)u.x, v1 = a * (double)u.y;
+    if (c2) {
+      const P2 u2 = *reinterpret_cast<const P2*>(c2 + e);
+      v0 += b * (double)u2.x;
+      v1 += b * (double)u2.y;
+    }
+    P2 t;
+    t.x = (T)v0;
+    t.y = (T)v1;
+    *reinterpret_cast<P2*>(dc + e) = t;
+    acc[0] += (double)t.x * (double)t.x + (double)t.y * (double)t.y;
   }
+  if (local == 0 && threadIdx.x == 0)
+    for (int u = 0; u < pr.nlone; ++u) {
+      const long long e = pr.lone[u];
+      double v = a * (double)c1[e];
+      if (c2) v += b * (double)c2[e];
+      const T t = (T)v;
+      dc[e] = t;
+      acc[0] += (double)t * (double)t;
+    }
   if (norm) {
     double res[1];
     block_sums<1>(acc, res);
@@ -601,26 +711,49 @@ void launch_set_identity(const Launch& L, double* F) {
   hipLaunchKernelGGL(k_set_identity, dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, F);
 }
 
+// the launch with K = k, for k in 1..kGmDot
+template <typename F, int... Ks>
+void with_k(int k, F&& f, std::integer_sequence<int, Ks...>) {
+  ((k == Ks + 1 ? f(std::integral_constant<int, Ks + 1>{}) : void()), ...);
+}
+
 void launch_gm_dots(int prec, const Launch& L, const void* w, const void* V, long long vstride, int i0, int k,
                     bool ww) {
   const dim3 grid(L.nblk[K_ELEM9]), block(kThreads);
-  if (prec == PREC_F64)
-    hipLaunchKernelGGL((k_gm_dots<double>), grid, block, 0, L.s, L.b, static_cast<const double*>(w),
-                       static_cast<const double*>(V), vstride, i0, k, ww ? 1 : 0);
-  else
-    hipLaunchKernelGGL((k_gm_dots<float>), grid, block, 0, L.s, L.b, static_cast<const float*>(w),
-                       static_cast<const float*>(V), vstride, i0, k, ww ? 1 : 0);
+  with_k(k, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    if (prec == PREC_F64)
+      hipLaunchKernelGGL((k_gm_dots<double, K>), grid, block, 0, L.s, L.b, static_cast<const double*>(w),
+                         static_cast<const double*>(V), vstride, i0, ww ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_gm_dots<float, K>), grid, block, 0, L.s, L.b, static_cast<const float*>(w),
+                         static_cast<const float*>(V), vstride, i0, ww ? 1 : 0);
+  }, std::make_integer_sequence<int, kGmDot>{});
 }
 
 void launch_gm_update(int prec, const Launch& L, void* y, const void* V, long long vstride, int i0, int k,
-                      const double* coef, bool norm) {
+                      const double* coef, bool norm, bool dots) {
   const dim3 grid(L.nblk[K_ELEM9]), block(kThreads);
-  if (prec == PREC_F64)
-    hipLaunchKernelGGL((k_gm_update<double>), grid, block, 0, L.s, L.b, static_cast<double*>(y),
-                       static_cast<const double*>(V), vstride, i0, k, coef, norm ? 1 : 0);
-  else
-    hipLaunchKernelGGL((k_gm_update<float>), grid, block, 0, L.s, L.b, static_cast<float*>(y),
-                       static_cast<const float*>(V), vstride, i0, k, coef, norm ? 1 : 0);
+  with_k(k, [&](auto kc) {
+    constexpr int K = decltype(kc)::value;
+    if (prec == PREC_F64) {
+      double* yy = static_cast<double*>(y);
+      const double* vv = static_cast<const double*>(V);
+      if (dots)
+        hipLaunchKernelGGL((k_gm_update<double, K, true>), grid, block, 0, L.s, L.b, yy, vv, vstride, i0, coef, 1);
+      else
+        hipLaunchKernelGGL((k_gm_update<double, K, false>), grid, block, 0, L.s, L.b, yy, vv, vstride, i0, coef,
+                           norm ? 1 : 0);
+    } else {
+      float* yy = static_cast<float*>(y);
+      const float* vv = static_cast<const float*>(V);
+      if (dots)
+        hipLaunchKernelGGL((k_gm_update<float, K, true>), grid, block, 0, L.s, L.b, yy, vv, vstride, i0, coef, 1);
+      else
+        hipLaunchKernelGGL((k_gm_update<float, K, false>), grid, block, 0, L.s, L.b, yy, vv, vstride, i0, coef,
+                           norm ? 1 : 0);
+    }
+  }, std::make_integer_sequence<int, kGmDot>{});
 }
 
 void launch_gm_lincomb(int prec, const Launch& L, void* dst, const void* s1, const void* s2, const double* coef,

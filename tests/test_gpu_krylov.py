@@ -201,24 +201,33 @@ def test_gmres_increment_vs_oracle(torch_cuda, orc, prec):
         assert np.max(np.abs(Pb[0] - Pbo)) <= 1e-5 * np.max(np.abs(Pbo))
 
 
-def test_gmres_batched_matches_single(torch_cuda, orc):
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_gmres_batched_matches_single(torch_cuda, orc, prec):
+    """Three cells whose 9 n values start at even, odd and odd offsets and
+    have odd, even and odd lengths: the element-pair kernels' lone first and
+    last elements on every combination."""
     from paper_1603_08893_amd.fftnk import Solver
-    dims = [(9, 9, 9), (8, 10, 6)]
-    print("gmres batched", dims, flush=True)
+    dims = [(9, 9, 9), (8, 10, 6), (7, 5, 3)]
+    print("gmres batched", dims, prec, flush=True)
     phs = [(np.random.default_rng(11 + r).random(d) < 0.3).astype(np.uint8) for r, d in enumerate(dims)]
-    Fbars = [ms.simple_shear(0.04), ms.isochoric_stretch(1.03)]
-    s = Solver(dims, precision="fp64", gmres_restart=15)
+    Fbars = [ms.simple_shear(0.04), ms.isochoric_stretch(1.03), ms.simple_shear(0.02)]
+    s = Solver(dims, precision=prec, gmres_restart=15)
     s.set_phases(np.concatenate([(ph.reshape(-1) + 2 * r).astype(np.uint8) for r, ph in enumerate(phs)]))
-    s.set_material(TABLE * 2)
+    s.set_material(TABLE * 3)
     s.set_krylov("gmres")
     st, F, P, Pb, S = s.solve_increment(np.stack(Fbars), 1e-8, 1e-10)
+    assert st == 0
     for r, (d, ph, Fb) in enumerate(zip(dims, phs, Fbars)):
         K, mu = ms.phase_moduli(ph, TABLE)
         sto, Fo, Po, Pbo, So = orc.solve_increment_krylov(K, mu, orc.identity_field(d), Fb, "gmres", 15, 0, 1e-8,
                                                           1e-10)
-        assert sto == 0 and S[r]["n_solves"] == So["n_solves"]
-        assert all(abs(a - b) <= 1 for a, b in zip(S[r]["cg_iters"], So["cg_iters"]))
-        assert np.max(np.abs(Pb[r] - Pbo)) <= 1e-10 * np.max(np.abs(Pbo))
+        assert sto == 0
+        if prec == "fp64":
+            assert S[r]["n_solves"] == So["n_solves"]
+            assert all(abs(a - b) <= 1 for a, b in zip(S[r]["cg_iters"], So["cg_iters"]))
+            assert np.max(np.abs(Pb[r] - Pbo)) <= 1e-10 * np.max(np.abs(Pbo))
+        else:
+            assert np.max(np.abs(Pb[r] - Pbo)) <= 1e-5 * np.max(np.abs(Pbo))
 
 
 def test_gmres_option_order(torch_cuda):
