@@ -111,10 +111,11 @@ def main():
                          "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--extra", default="",
-                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d: instead of the headline line, one JSON line per extra "
-                         "measurement (operator at 96^3..256^3; 64 batched cells; J2 at 96^3; adjoint 8 x 192^3; "
-                         "the two Nyquist choices at 128^3; mixed control at 128^3; CG / Chebyshev / "
-                         "Richardson / GMRES at 128^3; the 2-D plane-strain example at 451^2)")
+                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d,tune: instead of the headline line, one JSON "
+                         "line per extra measurement (operator at 96^3..256^3; 64 batched cells; J2 at 96^3; adjoint "
+                         "8 x 192^3; the two Nyquist choices at 128^3; mixed control at 128^3; CG / Chebyshev / "
+                         "Richardson / GMRES at 128^3; the 2-D plane-strain example at 451^2; the plan autotuner on "
+                         "several cells)")
     args = ap.parse_args()
     if args.operator_only:
         return operator_only(args)
@@ -388,7 +389,7 @@ def extra(args):
     """Measurements beyond the headline: each prints one JSON line."""
     import torch
     from paper_1603_08893_amd import microstructure as ms
-    from paper_1603_08893_amd.fftnk import J2, Solver, homogenized_stress
+    from paper_1603_08893_amd.fftnk import J2, Solver, describe, homogenized_stress
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
@@ -441,6 +442,60 @@ def extra(args):
                       "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
                 del s, fl, p, out
                 torch.cuda.empty_cache()
+
+    if "tune" in which:
+        # the plan autotuner: operator time under the default plan and under
+        # the policy it picks (20 back-to-back applications each), per cell
+        def op_ms(s, shape_list):
+            p = s.field()
+            p.copy_(torch.from_numpy(np.concatenate(
+                [ms.random_field(d, seed=42 + r).reshape(-1) for r, d in enumerate(shape_list)])).to(dev))
+            out = s.field()
+            for _ in range(3):
+                s.apply_operator(p, out)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(20):
+                s.apply_operator(p, out)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / 20
+
+        cases = [("128^3", [(128,) * 3], "fp64"), ("128^3", [(128,) * 3], "fp32"), ("96^3", [(96,) * 3], "fp64"),
+                 ("31^3", [(31,) * 3], "fp64"), ("192^3", [(192,) * 3], "fp64"), ("451x451x2", [(451, 451, 2)], "fp64"),
+                 ("batch 32^3+48^3+64^3+96^3", [(32,) * 3, (48,) * 3, (64,) * 3, (96,) * 3], "fp32")]
+        for label, shapes, prec in cases:
+            s = Solver(shapes if len(shapes) > 1 else shapes[0], precision=prec)
+            s.set_phases(np.concatenate([(np.random.default_rng(7 + r).random(d) < 0.3).astype(np.uint8).reshape(-1)
+                                         for r, d in enumerate(shapes)]))
+            s.set_material(TABLE)
+            s.set_linearization(torch.from_numpy(np.concatenate(
+                [ms.near_identity_field(d, seed=3 + r, scale=0.01).reshape(-1) for r, d in enumerate(shapes)])).to(dev))
+            t0 = op_ms(s, shapes)
+            (pol, tuner_ms), sec = timed(lambda: s.autotune(reps=5, use_cache=False))
+            t1 = op_ms(s, shapes)
+            rec = {"extra": "autotune", "cell": label, "precision": prec, "default_ms": round(t0, 4), "policy": pol,
+                   "tuned_ms": round(t1, 4), "speedup": round(t0 / t1, 3), "tuner_seconds": round(sec, 3)}
+            if label == "128^3" and prec == "fp64":
+                # the spread the tuner chooses from: every policy that changes the launches
+                seen, spread = set(), {}
+                for q in range(64):
+                    if (q >> 3) & 3 == 3:
+                        continue
+                    d = describe(shapes[0], prec, policy=q)["cells"][0]
+                    key = (tuple(a["reg"] for a in d["axes"]), d["rt"], d["rt1"],
+                           (d["m64"], d["m32"]) if min(d["axes"][0]["reg"], d["axes"][1]["reg"]) == 0 else None)
+                    if key in seen:
+                        continue
+                    seen.add(key)
+                    s.set_plan(q)
+                    spread[str(q)] = round(op_ms(s, shapes), 4)
+                s.set_plan(pol)
+                rec["ms_per_policy"] = spread
+            emit(rec)
+            del s
+            torch.cuda.empty_cache()
 
     if "nyq" in which:
         # App. C's two choices at Nyquist frequencies on the 128^3 two-phase

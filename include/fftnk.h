@@ -98,13 +98,46 @@ size_t fftnk_workspace_bytes(const fftnk_ctx* ctx);
  * work-group, work-groups per launch kind, and per axis the radix plan and
  * the FFT engine: 8 or 12 points per thread in registers, 0 the LDS engine;
  * per context: work-groups per launch kind, LDS bytes per kernel family,
- * workspace bytes).  Writes a NUL-terminated string into buf (host, len
+ * workspace bytes, the plan policy and the partial-sum stride).  Writes a NUL-terminated string into buf (host, len
  * bytes); *needed (optional) receives the length it needs; FFTNK_ENOMEM when
  * len is smaller.  Makes no HIP call: a context can be created and described
  * without a GPU (creation allocates host memory only; the host staging
  * buffer and the capture stream come with fftnk_bind_workspace).
  */
 int fftnk_describe(const fftnk_ctx* ctx, char* buf, size_t len, size_t* needed);
+
+/*
+ * FFT plan policy of a context: which engine and tile size each pass uses
+ * (the transforms of Sec. 2.5 are the same under every policy; results differ
+ * by rounding order only).  Bit fields of `policy`:
+ *   bits 0-2  axis d (a0, a1, a2) on the LDS engine even where its length has
+ *             a register-resident engine;
+ *   bits 3-4  s in 0..2: the LDS-engine a1 / a0 passes take at most 8 >> s
+ *             (FP64) or 16 >> s (FP32) pencils per work-group (3 is invalid);
+ *   bit 5     the register-engine a2 passes take half their default grid
+ *             lines per work-group.
+ * 0 is the default.  May be called before or after fftnk_bind_workspace (the
+ * workspace is sized for every policy); drops the captured CG graphs.
+ * FFTNK_EINVAL for an invalid code, FFTNK_EUNSUPPORTED when a kernel's LDS
+ * budget would be exceeded (the context keeps its policy).  The policy in use
+ * is reported by fftnk_describe ("policy").
+ */
+int fftnk_set_plan(fftnk_ctx* ctx, unsigned policy);
+
+/*
+ * Autotuner: times one operator application (the tangent at the committed
+ * state F_t applied to a zero field; every pass of the CG operator) under
+ * every policy that changes the context's launches, `reps` back-to-back
+ * applications, best of three rounds, and keeps the fastest.  The choice is
+ * cached per process under the context's precision, material model, Nyquist
+ * choice and cell sizes; with use_cache != 0 a cached choice is applied
+ * without timing (*ms = -1).  Needs a bound workspace, phases and material
+ * (else FFTNK_ESTATE); overwrites the CG vectors x, p, w and the spectrum
+ * (scratch between calls).  *policy (optional) receives the policy applied,
+ * *ms (optional) its milliseconds per application.  reps in 1..1000.  On a
+ * HIP error the previous policy is restored.  Synchronous.
+ */
+int fftnk_autotune(fftnk_ctx* ctx, int reps, int use_cache, unsigned* policy, double* ms);
 
 /*
  * Hand the context its workspace: dev must stay valid until the context is

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -96,6 +97,101 @@ size_t col_lds(const Grid& g, int axis, size_t csz) {
   return csz * ((size_t)padded_len(n) + 2 * (size_t)n * M);
 }
 
+// Plan policy (fftnk_set_plan): bits 0-2, axis d on the LDS engine even where
+// a register engine exists; bits 3-4, s <= 2: the LDS-engine column passes
+// take at most 8 >> s (FP64) / 16 >> s (FP32) pencils per work-group; bit 5,
+// the register-engine a2 passes take half their default grid lines per
+// work-group.  Every policy computes the same transforms; only engines and
+// tile sizes differ.
+constexpr unsigned kPolicyCodes = 64;
+bool policy_valid(unsigned pol) { return pol < kPolicyCodes && ((pol >> 3) & 3u) != 3u; }
+
+// engines and tile sizes of one cell under `pol` (radix plans and twiddle
+// offsets stay)
+void plan_cell(Grid& g, unsigned pol) {
+  for (int d = 0; d < 3; ++d) {
+    AxisPlan& a = g.ax[d];
+    const int tw = a.tw;
+    make_plan(a.n, a, true);
+    a.tw = tw;
+    if (pol & (1u << d)) a.reg = 0;
+  }
+  // grid lines per a2 work-group: register engine, 5 pair pencils per line on
+  // kThreads / (n2/P) pencil slots, within 48 KiB of FP64 LDS (5 rt pencils +
+  // one spare slot: three work-groups per CU at least); LDS engine, kThreads / n2
+  if (g.ax[2].reg) {
+    const int slots = kThreads / (g.n2 / g.ax[2].reg);
+    const int fit = (49152 / 16 - padded_len(g.n2)) / padded_len(g.n2) - 1;
+    g.rt = std::max(1, std::min(slots / 5, fit / 5));
+    if (pol & 32u) g.rt = std::max(1, g.rt / 2);
+  } else {
+    g.rt = std::max(1, kThreads / g.n2);
+  }
+  // forward pass: at most one voxel per thread in its tangent phase, so that
+  // all loads of a work-group are in flight together (and the register-engine
+  // line count, or kThreads / n2 on the LDS engine)
+  g.rt1 = pass1_engine(g.ax[2].reg) ? std::max(1, std::min(g.rt, kThreads / g.n2)) : std::max(1, kThreads / g.n2);
+  const int nmax = std::max(g.n0, g.n1);
+  const int s = (int)((pol >> 3) & 3u);
+  g.m64 = pick_m(g.h, nmax, 16, 8 >> s);
+  g.m32 = pick_m(g.h, nmax, 8, 16 >> s);
+}
+
+// launch geometry of a context's cells under one policy
+struct Geo {
+  std::vector<Grid> g;
+  std::vector<int> starts;  // [NKIND][nrve + 1]
+  int nblk[NKIND] = {};
+  size_t lds[8] = {};
+  int eng[3] = {};
+  long long pstride = 0;  // most work-groups of any launch kind
+};
+
+// EUNSUPPORTED when a kernel's LDS budget or the work-group count is exceeded
+int make_geo(const std::vector<Grid>& cells, unsigned pol, Geo& o) {
+  const int nrve = (int)cells.size();
+  o.g = cells;
+  for (Grid& g : o.g) plan_cell(g, pol);
+  o.starts.assign((size_t)NKIND * (nrve + 1), 0);
+  for (int k = 0; k < NKIND; ++k) {
+    long long acc = 0;
+    for (int r = 0; r < nrve; ++r) {
+      const Grid& g = o.g[r];
+      o.starts[k * (nrve + 1) + r] = (int)acc;
+      long long b = 0;
+      switch (k) {
+        case K_ROW: b = row_blocks(g); break;
+        case K_ROW1: b = row1_blocks(g); break;
+        case K_COL1_64: b = col1_blocks(g, PREC_F64); break;
+        case K_COL1_32: b = col1_blocks(g, PREC_F32); break;
+        case K_COL0_64: b = col0_blocks(g, PREC_F64); break;
+        case K_COL0_32: b = col0_blocks(g, PREC_F32); break;
+        case K_ELEM9: b = elem_blocks(9 * g.n); break;
+        default: b = elem_blocks(g.n); break;
+      }
+      acc += b;
+    }
+    if (acc > (1LL << 30)) return FFTNK_EUNSUPPORTED;
+    o.starts[k * (nrve + 1) + nrve] = (int)acc;
+    o.nblk[k] = (int)acc;
+    o.pstride = std::max(o.pstride, acc);
+  }
+  for (const Grid& g : o.g) {
+    o.lds[0] = std::max(o.lds[0], row_lds(g, g.rt, g.ax[2].reg, 16));
+    o.lds[1] = std::max(o.lds[1], row_lds(g, g.rt, g.ax[2].reg, 8));
+    for (int d = 0; d < 3; ++d) o.eng[d] |= g.ax[d].reg == 8 ? 2 : (g.ax[d].reg == 12 ? 4 : 1);
+    o.lds[6] = std::max(o.lds[6], row_lds(g, g.rt1, pass1_engine(g.ax[2].reg), 16));
+    o.lds[7] = std::max(o.lds[7], row_lds(g, g.rt1, pass1_engine(g.ax[2].reg), 8));
+    o.lds[2] = std::max(o.lds[2], col_lds(g, 1, 16));
+    o.lds[3] = std::max(o.lds[3], col_lds(g, 1, 8));
+    o.lds[4] = std::max(o.lds[4], col_lds(g, 0, 16));
+    o.lds[5] = std::max(o.lds[5], col_lds(g, 0, 8));
+  }
+  for (size_t b : o.lds)
+    if (b > 61440) return FFTNK_EUNSUPPORTED;
+  return FFTNK_OK;
+}
+
 }  // namespace
 
 struct fftnk_ctx {
@@ -104,7 +200,8 @@ struct fftnk_ctx {
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;  // capture stream of the CG graphs
   std::vector<Grid> g;
-  long long ntot = 0, nspec = 0, pstride = 0;
+  long long ntot = 0, nspec = 0;
+  long long pstride = 0;  // partial-sum slot stride: the most work-groups of any launch kind under any policy
   std::vector<int> tw_len, tw_off;
   int tw_total = 0;
   std::vector<int> starts;  // [NKIND][nrve + 1]
@@ -112,6 +209,7 @@ struct fftnk_ctx {
   size_t lds[8] = {};  // row64, row32, col1_64, col1_32, col0_64, col0_32, row1_64, row1_32
   int eng[3] = {};     // per axis: bit 0 some cell on the LDS engine, bit 1 on the 8-point, bit 2 on the 12-point one
   int nyq_id = 0;      // FFTNK_OPT_NYQUIST
+  unsigned policy = 0;  // fftnk_set_plan
   int krylov = KRYLOV_CG;  // fftnk_set_krylov
   double k_lo = 0.0, k_hi = 0.0;
   int gm = 0;              // GMRES restart length (FFTNK_OPT_GMRES_RESTART), basis of gm + 1 vectors
@@ -224,6 +322,14 @@ int upload_uni(fftnk_ctx* c) {
   return FFTNK_OK;
 }
 
+void apply_geo(fftnk_ctx* c, const Geo& geo) {
+  c->g = geo.g;
+  c->starts = geo.starts;
+  std::copy(geo.nblk, geo.nblk + NKIND, c->nblk);
+  std::copy(geo.lds, geo.lds + 8, c->lds);
+  std::copy(geo.eng, geo.eng + 3, c->eng);
+}
+
 int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* stream) {
   if (nrve < 1 || nrve > kMaxRve || !dims) return FFTNK_EINVAL;
   if (precision != FFTNK_FP64 && precision != FFTNK_FP32_MIXED) return FFTNK_EINVAL;
@@ -249,23 +355,6 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
     g.spec_off = spec;
     g.row_off = rows;
     g.inv_n = 1.0 / (double)g.n;
-    // grid lines per a2 work-group: register engine, 5 pair pencils per line on
-    // kThreads / (n2/P) pencil slots, within 48 KiB of FP64 LDS (5 rt pencils +
-    // one spare slot: three work-groups per CU at least); LDS engine, kThreads / n2
-    if (g.ax[2].reg) {
-      const int slots = kThreads / (g.n2 / g.ax[2].reg);
-      const int fit = (49152 / 16 - padded_len(g.n2)) / padded_len(g.n2) - 1;
-      g.rt = std::max(1, std::min(slots / 5, fit / 5));
-    } else {
-      g.rt = std::max(1, kThreads / g.n2);
-    }
-    // forward pass: at most one voxel per thread in its tangent phase, so that
-    // all loads of a work-group are in flight together (and the register-engine
-    // line count, or kThreads / n2 on the LDS engine)
-    g.rt1 = pass1_engine(g.ax[2].reg) ? std::max(1, std::min(g.rt, kThreads / g.n2)) : std::max(1, kThreads / g.n2);
-    const int nmax = std::max(g.n0, g.n1);
-    g.m64 = pick_m(g.h, nmax, 16, 8);
-    g.m32 = pick_m(g.h, nmax, 8, 16);
     vox += g.n;
     spec += 9LL * g.rows * g.h;
     rows += g.rows;
@@ -274,44 +363,6 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
   c->ntot = vox;
   c->nspec = spec;
   c->rows_total = rows;
-  // launch geometry: work-group ranges of every RVE per launch kind
-  c->starts.assign((size_t)NKIND * (nrve + 1), 0);
-  for (int k = 0; k < NKIND; ++k) {
-    long long acc = 0;
-    for (int r = 0; r < nrve; ++r) {
-      const Grid& g = c->g[r];
-      c->starts[k * (nrve + 1) + r] = (int)acc;
-      long long b = 0;
-      switch (k) {
-        case K_ROW: b = row_blocks(g); break;
-        case K_ROW1: b = row1_blocks(g); break;
-        case K_COL1_64: b = col1_blocks(g, PREC_F64); break;
-        case K_COL1_32: b = col1_blocks(g, PREC_F32); break;
-        case K_COL0_64: b = col0_blocks(g, PREC_F64); break;
-        case K_COL0_32: b = col0_blocks(g, PREC_F32); break;
-        case K_ELEM9: b = elem_blocks(9 * g.n); break;
-        default: b = elem_blocks(g.n); break;
-      }
-      acc += b;
-    }
-    if (acc > (1LL << 30)) return FFTNK_EUNSUPPORTED;
-    c->starts[k * (nrve + 1) + nrve] = (int)acc;
-    c->nblk[k] = (int)acc;
-    c->pstride = std::max(c->pstride, acc);
-  }
-  for (const Grid& g : c->g) {
-    c->lds[0] = std::max(c->lds[0], row_lds(g, g.rt, g.ax[2].reg, 16));
-    c->lds[1] = std::max(c->lds[1], row_lds(g, g.rt, g.ax[2].reg, 8));
-    for (int d = 0; d < 3; ++d) c->eng[d] |= g.ax[d].reg == 8 ? 2 : (g.ax[d].reg == 12 ? 4 : 1);
-    c->lds[6] = std::max(c->lds[6], row_lds(g, g.rt1, pass1_engine(g.ax[2].reg), 16));
-    c->lds[7] = std::max(c->lds[7], row_lds(g, g.rt1, pass1_engine(g.ax[2].reg), 8));
-    c->lds[2] = std::max(c->lds[2], col_lds(g, 1, 16));
-    c->lds[3] = std::max(c->lds[3], col_lds(g, 1, 8));
-    c->lds[4] = std::max(c->lds[4], col_lds(g, 0, 16));
-    c->lds[5] = std::max(c->lds[5], col_lds(g, 0, 8));
-  }
-  for (size_t b : c->lds)
-    if (b > 61440) return FFTNK_EUNSUPPORTED;
   // twiddle tables, one per distinct axis length
   for (auto& g : c->g)
     for (int d = 0; d < 3; ++d) {
@@ -326,6 +377,18 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
         g.ax[d].tw = c->tw_off[it - c->tw_len.begin()];
       }
     }
+  // launch geometry under the default policy; the partial-sum slots are sized
+  // for the largest launch of any policy
+  Geo geo;
+  int e = make_geo(c->g, 0, geo);
+  if (e) return e;
+  long long pmax = geo.pstride;
+  for (unsigned pol = 1; pol < kPolicyCodes; ++pol) {
+    Geo t;
+    if (policy_valid(pol) && make_geo(c->g, pol, t) == FFTNK_OK) pmax = std::max(pmax, t.pstride);
+  }
+  apply_geo(c, geo);
+  c->pstride = pmax;
   // workspace layout
   const size_t f64 = 9 * (size_t)vox * sizeof(double);
   const size_t fv = 9 * (size_t)vox * (c->prec == PREC_F64 ? 8 : 4);
@@ -1013,6 +1076,86 @@ bool solve_small(int k, double* A, double* r) {
 }  // namespace
 
 // ===========================================================================
+// ---------------------------------------------------------------------------
+// plan policies and the autotuner
+// ---------------------------------------------------------------------------
+int set_plan(fftnk_ctx* c, unsigned pol) {
+  if (!policy_valid(pol)) return FFTNK_EINVAL;
+  Geo geo;
+  const int e = make_geo(c->g, pol, geo);
+  if (e) return e;
+  if (geo.pstride > c->pstride) return FFTNK_EUNSUPPORTED;
+  apply_geo(c, geo);
+  c->policy = pol;
+  drop_graphs(c);  // the graphs hold the old launch sizes
+  if (c->ws) {
+    HIP_TRY(hipMemcpyAsync(c->ws + c->o_grids, c->g.data(), c->g.size() * sizeof(Grid), hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ws + c->o_starts, c->starts.data(), c->starts.size() * sizeof(int),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));  // the host tables may change again at once
+  }
+  return FFTNK_OK;
+}
+
+// what a policy changes in a context's launches (policies with equal keys
+// launch the same kernels on the same tiles)
+std::string geo_key(const Geo& geo) {
+  std::string k;
+  for (const Grid& g : geo.g) {
+    const bool lds_col = g.ax[0].reg == 0 || g.ax[1].reg == 0;
+    k += std::to_string(g.ax[0].reg) + "," + std::to_string(g.ax[1].reg) + "," + std::to_string(g.ax[2].reg) + "," +
+         std::to_string(g.rt) + "," + std::to_string(g.rt1) + "," + std::to_string(lds_col ? g.m64 : 0) + "," +
+         std::to_string(lds_col ? g.m32 : 0) + ";";
+  }
+  return k;
+}
+
+// key of the tuning cache: precision, material model, Nyquist choice, cells
+std::string tune_key(const fftnk_ctx* c) {
+  std::string k = std::to_string(c->prec) + "/" + std::to_string(c->model) + "/" + std::to_string(c->nyq_id);
+  for (const Grid& g : c->g)
+    k += "/" + std::to_string(g.n0) + "x" + std::to_string(g.n1) + "x" + std::to_string(g.n2);
+  return k;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, unsigned> g_tuned;  // process-wide: tuning key -> policy
+
+// milliseconds per operator application (x -> w, tangent at the committed
+// state F_t), the best of three rounds of `reps` back-to-back applications
+int time_operator(fftnk_ctx* c, int reps, const void* flin, double* ms) {
+  const Launch L = c->launch();
+  const Material mat = c->material();
+  auto apply = [&]() {
+    launch_fwd_a2(c->prec, FWD_TANGENT, L, mat, c->x(), nullptr, nullptr, nullptr, flin, 1.0, c->spec(), nullptr);
+    middle_passes(c->prec, L, c->spec(), nullptr);
+    launch_inv_a2(c->prec, INV_OUT, L, c->spec(), c->w(), c->prec, nullptr, 1.0, nullptr);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return FFTNK_EHIP;
+  }
+  int err = FFTNK_OK;
+  double best = 1e300;
+  apply();  // first launches of these kernels and tiles
+  for (int round = 0; round < 3 && !err; ++round) {
+    if (hipEventRecord(e0, c->stream) != hipSuccess) err = FFTNK_EHIP;
+    for (int k = 0; k < reps && !err; ++k) apply();
+    if (!err && hipEventRecord(e1, c->stream) != hipSuccess) err = FFTNK_EHIP;
+    if (!err) err = check_launch();
+    if (!err && hipEventSynchronize(e1) != hipSuccess) err = FFTNK_EHIP;
+    float t = 0.f;
+    if (!err && hipEventElapsedTime(&t, e0, e1) != hipSuccess) err = FFTNK_EHIP;
+    if (!err) best = std::min(best, (double)t / reps);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = best;
+  return err;
+}
+
 // C-ABI
 // ===========================================================================
 extern "C" {
@@ -1046,8 +1189,9 @@ int fftnk_describe(const fftnk_ctx* c, char* buf, size_t len, size_t* needed) {
     std::snprintf(t, sizeof t, fmt, a...);
     j += t;
   };
-  add("{\"nrve\": %d, \"precision\": %d, \"workspace_bytes\": %zu, \"workspace_base_bytes\": %zu, \"gmres_restart\": %d, ",
-      c->nrve, c->prec, c->total, c->total_base, c->gm);
+  add("{\"nrve\": %d, \"precision\": %d, \"workspace_bytes\": %zu, \"workspace_base_bytes\": %zu, \"gmres_restart\": %d, "
+      "\"policy\": %u, \"pstride\": %lld, ",
+      c->nrve, c->prec, c->total, c->total_base, c->gm, c->policy, c->pstride);
   j += "\"nblk\": [";
   for (int k = 0; k < NKIND; ++k) add(k ? ", %d" : "%d", c->nblk[k]);
   j += "], \"lds\": [";
@@ -1197,6 +1341,67 @@ int fftnk_set_option(fftnk_ctx* c, int option, int value) {
       return FFTNK_OK;
     default: return FFTNK_EINVAL;
   }
+}
+
+int fftnk_set_plan(fftnk_ctx* c, unsigned policy) {
+  if (!c) return FFTNK_EINVAL;
+  return set_plan(c, policy);
+}
+
+int fftnk_autotune(fftnk_ctx* c, int reps, int use_cache, unsigned* policy, double* ms) {
+  if (!c || reps < 1 || reps > 1000) return FFTNK_EINVAL;
+  if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
+  const std::string key = tune_key(c);
+  if (use_cache) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      const int e = set_plan(c, it->second);
+      if (policy) *policy = c->policy;
+      if (ms) *ms = -1.0;
+      return e;
+    }
+  }
+  const unsigned pol0 = c->policy;
+  // inputs: x = 0, the tangent at F_t (FP32 contexts: its FP32 copy in p)
+  const size_t esz = c->prec == PREC_F64 ? 8 : 4;
+  HIP_TRY(hipMemsetAsync(c->x(), 0, 9 * (size_t)c->ntot * esz, c->stream));
+  const void* flin = c->Ft();
+  if (c->prec == PREC_F32) {
+    launch_convert(PREC_F32, c->Ft(), c->p(), 9 * c->ntot, c->stream);
+    flin = c->p();
+  }
+  std::vector<std::string> seen;
+  unsigned best = pol0;
+  double best_ms = 1e300;
+  for (unsigned pol = 0; pol < kPolicyCodes; ++pol) {
+    if (!policy_valid(pol)) continue;
+    Geo t;
+    if (make_geo(c->g, pol, t) != FFTNK_OK || t.pstride > c->pstride) continue;
+    const std::string k = geo_key(t);
+    if (std::find(seen.begin(), seen.end(), k) != seen.end()) continue;
+    seen.push_back(k);
+    double m = 0.0;
+    int e = set_plan(c, pol);
+    if (!e) e = time_operator(c, reps, flin, &m);
+    if (e) {
+      (void)set_plan(c, pol0);
+      return e;
+    }
+    if (m < best_ms) {
+      best_ms = m;
+      best = pol;
+    }
+  }
+  const int e = set_plan(c, best);
+  if (e) return e;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = best;
+  }
+  if (policy) *policy = best;
+  if (ms) *ms = best_ms;
+  return FFTNK_OK;
 }
 
 int fftnk_set_krylov(fftnk_ctx* c, int method, double lo, double hi) {

@@ -25,7 +25,7 @@ EXPORTS = [
     "fftnk_create", "fftnk_create_batched", "fftnk_workspace_bytes", "fftnk_bind_workspace", "fftnk_set_phases",
     "fftnk_set_material", "fftnk_set_modulus_field", "fftnk_set_option", "fftnk_reset_state", "fftnk_solve_increment",
     "fftnk_solve_increment_mixed", "fftnk_macro_tangent", "fftnk_set_krylov",
-    "fftnk_solve_linear", "fftnk_describe",
+    "fftnk_solve_linear", "fftnk_describe", "fftnk_set_plan", "fftnk_autotune",
     "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_adjoint",
     "fftnk_launch_pass", "fftnk_profile_cg", "fftnk_get_history", "fftnk_set_history", "fftnk_get_state",
     "fftnk_set_state", "fftnk_status_string", "fftnk_destroy",
@@ -80,6 +80,8 @@ def lib():
     L.fftnk_set_krylov.argtypes = [vp, i, d, d]
     L.fftnk_solve_linear.argtypes = [vp, vp, vp, d, i, ctypes.POINTER(Stats)]
     L.fftnk_describe.argtypes = [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]
+    L.fftnk_set_plan.argtypes = [vp, ctypes.c_uint]
+    L.fftnk_autotune.argtypes = [vp, i, i, ctypes.POINTER(ctypes.c_uint), ctypes.POINTER(d)]
     L.fftnk_solve_increment.argtypes = [vp, dp, d, d, i, i, vp, vp, dp, ctypes.POINTER(Stats)]
     ip = ctypes.POINTER(i)
     L.fftnk_solve_increment_mixed.argtypes = [vp, dp, ip, dp, d, i, d, d, i, i, vp, vp, dp, ctypes.POINTER(Stats), ip]
@@ -112,9 +114,10 @@ def status_string(s):
         return "status %d" % s
 
 
-def describe(dims, precision="fp64", gmres_restart=0):
-    """The launch geometry the library plans for a cell (or a batch of cells),
-    as a dict; needs no GPU (a context is created and described, never bound)."""
+def describe(dims, precision="fp64", gmres_restart=0, policy=0):
+    """The launch geometry the library plans for a cell (or a batch of cells)
+    under a plan policy (fftnk_set_plan), as a dict; needs no GPU (a context is
+    created and described, never bound)."""
     import json
     L = lib()
     if isinstance(dims[0], (int, np.integer)):
@@ -126,6 +129,8 @@ def describe(dims, precision="fp64", gmres_restart=0):
     try:
         if gmres_restart:
             _check(L.fftnk_set_option(ctx, OPT_GMRES_RESTART, int(gmres_restart)), "fftnk_set_option")
+        if policy:
+            _check(L.fftnk_set_plan(ctx, int(policy)), "fftnk_set_plan")
         need = ctypes.c_size_t(0)
         L.fftnk_describe(ctx, None, 0, ctypes.byref(need))
         buf = ctypes.create_string_buffer(need.value)
@@ -224,6 +229,20 @@ class Solver:
         """OPT_GRAPHS (replay CG iterations from HIP graphs), OPT_CHECK_EVERY, or
         OPT_NYQUIST (0: G-hat zero at Nyquist frequencies, 1: identity there)."""
         _check(lib().fftnk_set_option(self.ctx, int(option), int(value)), "fftnk_set_option")
+
+    def set_plan(self, policy):
+        """FFT plan policy (engines and tile sizes; see fftnk_set_plan)."""
+        _check(lib().fftnk_set_plan(self.ctx, int(policy)), "fftnk_set_plan")
+
+    def autotune(self, reps=5, use_cache=True):
+        """Time the operator under every distinct plan policy and keep the
+        fastest; returns (policy, ms per application), ms = -1 when the choice
+        came from this process's cache."""
+        pol = ctypes.c_uint(0)
+        ms = ctypes.c_double(0.0)
+        _check(lib().fftnk_autotune(self.ctx, int(reps), 1 if use_cache else 0, ctypes.byref(pol), ctypes.byref(ms)),
+               "fftnk_autotune")
+        return int(pol.value), float(ms.value)
 
     def set_krylov(self, method="cg", lo=None, hi=None, table=None):
         """Krylov method of later linear solves: "cg", "chebyshev", "richardson"

@@ -39,13 +39,13 @@ def _reg_engine(n):
     return 0
 
 
-def _check_cell(c, prec):
+def _check_cell(c, prec, policy=0):
     n0, n1, n2 = c["n"]
     h = n2 // 2 if n2 % 2 == 0 else (n2 + 1) // 2
     assert c["h"] == h and c["rows"] == n0 * n1
-    for ax, n in zip(c["axes"], (n0, n1, n2)):
+    for d, (ax, n) in enumerate(zip(c["axes"], (n0, n1, n2))):
         assert ax["n"] == n and math.prod(ax["radix"]) == n, ax
-        assert ax["reg"] == _reg_engine(n), ax
+        assert ax["reg"] == (0 if policy >> d & 1 else _reg_engine(n)), (ax, policy)
     b = c["blocks"]
     # a2 passes: every grid line in exactly one tile; pass 1 one voxel per thread
     for key, rt in (("row", c["rt"]), ("row1", c["rt1"])):
@@ -127,3 +127,40 @@ def test_gmres_basis_and_refused_lengths():
     for bad in ((513, 4, 4), (4, 600, 4), (4, 4, 257), (1, 4, 4)):
         with pytest.raises(fftnk.FftnkError):
             fftnk.describe(bad)
+
+
+POLICY_SHAPES = [(16, 16, 16), (24, 20, 12), (31, 9, 7), (128, 128, 128), (96, 96, 96), (256, 256, 256),
+                 (192, 192, 192), (451, 451, 2), (12, 10, 16), (3, 64, 4), (6, 12, 96), (512, 512, 8), (9, 384, 6)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_every_policy_geometry(prec):
+    """Under every valid plan policy: engines as the policy bits say, the tiles
+    of every pass cover the grid lines and pencils exactly, LDS within budget,
+    and the partial-sum stride (sized at creation for all policies) covers
+    every launch; M and rt follow the policy's caps."""
+    fftnk = _lib_or_skip()
+    for shape in POLICY_SHAPES:
+        base = fftnk.describe(shape, prec)
+        for pol in range(64):
+            if (pol >> 3) & 3 == 3:
+                with pytest.raises(fftnk.FftnkError):
+                    fftnk.describe(shape, prec, policy=pol)
+                continue
+            try:
+                d = fftnk.describe(shape, prec, policy=pol)
+            except fftnk.FftnkError as e:
+                assert e.status == fftnk.EUNSUPPORTED, (shape, pol)
+                continue
+            c = d["cells"][0]
+            assert d["policy"] == pol
+            _check_cell(c, prec, pol)
+            assert max(d["lds"]) <= LDS_LIMIT
+            assert d["pstride"] == base["pstride"] >= max(d["nblk"])
+            b0 = base["cells"][0]
+            s = (pol >> 3) & 3
+            assert c["m64"] <= max(1, 8 >> s) and c["m32"] <= max(1, 16 >> s)
+            if c["axes"][2]["reg"] and b0["axes"][2]["reg"] and pol & 32:
+                assert c["rt"] == max(1, b0["rt"] // 2)
+    with pytest.raises(fftnk.FftnkError):
+        fftnk.describe((8, 8, 8), prec, policy=64)
