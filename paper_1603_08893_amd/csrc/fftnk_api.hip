@@ -66,17 +66,12 @@ bool make_plan(int n, AxisPlan& pl, bool allow12) {
   return true;
 }
 
-int largest_pow2_leq(int x) {
-  int p = 1;
-  while (p * 2 <= x) p *= 2;
-  return p;
-}
-
-// pencils per work-group in the LDS-engine a1 / a0 passes: contiguous rows of
-// at least 128 bytes where possible, within the LDS (60 KiB) and register
-// (kMaxPpt points per thread in pass 3) budgets.
-int pick_m(int h, int nmax, size_t csz, int pref) {
-  int m = std::min(pref, largest_pow2_leq(std::max(1, h)));
+// pencils per work-group in the LDS-engine a1 / a0 passes (consecutive in
+// the spectrum's k2-fastest order, so runs of at least 128 bytes where
+// possible), within the LDS (60 KiB) and register (kMaxPpt points per thread
+// in pass 3) budgets.
+int pick_m(int nmax, size_t csz, int pref) {
+  int m = pref;
   while (m > 1 && ((size_t)nmax * m > (size_t)kMaxPpt * kThreads || csz * ((size_t)padded_len(nmax) + 2 * (size_t)nmax * m) > 61440))
     m /= 2;
   return m;
@@ -133,8 +128,8 @@ void plan_cell(Grid& g, unsigned pol) {
   g.rt1 = pass1_engine(g.ax[2].reg) ? std::max(1, std::min(g.rt, kThreads / g.n2)) : std::max(1, kThreads / g.n2);
   const int nmax = std::max(g.n0, g.n1);
   const int s = (int)((pol >> 3) & 3u);
-  g.m64 = pick_m(g.h, nmax, 16, 8 >> s);
-  g.m32 = pick_m(g.h, nmax, 8, 16 >> s);
+  g.m64 = pick_m(nmax, 16, 8 >> s);
+  g.m32 = pick_m(nmax, 8, 16 >> s);
 }
 
 // launch geometry of a context's cells under one policy

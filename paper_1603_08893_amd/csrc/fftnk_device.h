@@ -247,14 +247,30 @@ __device__ __forceinline__ void stage_lds_prime(const cx<T>* __restrict__ src, c
     const int k = j % Ns;
     const int e = k * tws + q * nbf;  // < n
     const cx<T>* s = src + m * sp;
-    cx<T> acc = s[j * se];
-    int er = e;
-    for (int r = 1; r < R; ++r) {
-      acc = acc + cmul(s[(j + r * nbf) * se], twid(tw, er, inv));
+    // four partial sums, so that the reads of four terms are in flight together
+    cx<T> acc0 = s[j * se], acc1{(T)0, (T)0}, acc2{(T)0, (T)0}, acc3{(T)0, (T)0};
+    int er = e;  // (r e) mod n of the next term r
+    int r = 1;
+    for (; r + 3 < R; r += 4) {
+      int e2 = er + e;
+      if (e2 >= n) e2 -= n;
+      int e3 = e2 + e;
+      if (e3 >= n) e3 -= n;
+      int e4 = e3 + e;
+      if (e4 >= n) e4 -= n;
+      acc0 = acc0 + cmul(s[(j + r * nbf) * se], twid(tw, er, inv));
+      acc1 = acc1 + cmul(s[(j + (r + 1) * nbf) * se], twid(tw, e2, inv));
+      acc2 = acc2 + cmul(s[(j + (r + 2) * nbf) * se], twid(tw, e3, inv));
+      acc3 = acc3 + cmul(s[(j + (r + 3) * nbf) * se], twid(tw, e4, inv));
+      er = e4 + e;
+      if (er >= n) er -= n;
+    }
+    for (; r < R; ++r) {
+      acc0 = acc0 + cmul(s[(j + r * nbf) * se], twid(tw, er, inv));
       er += e;
       if (er >= n) er -= n;
     }
-    dst[m * sp + ((j - k) * R + k + q * Ns) * se] = acc;
+    dst[m * sp + ((j - k) * R + k + q * Ns) * se] = (acc0 + acc1) + (acc2 + acc3);
   }
 }
 

@@ -35,7 +35,7 @@ int col1_blocks(const Grid& g, int prec) {
     return (int)((np + mb - 1) / mb);
   }
   const int M = prec == PREC_F64 ? g.m64 : g.m32;
-  return 9 * g.n0 * ((g.h + M - 1) / M);
+  return (int)((9LL * g.n0 * g.h + M - 1) / M);
 }
 
 int col0_blocks(const Grid& g, int prec) {
@@ -44,7 +44,7 @@ int col0_blocks(const Grid& g, int prec) {
     return (int)((np + mb - 1) / mb);
   }
   const int M = prec == PREC_F64 ? g.m64 : g.m32;
-  return 3 * g.n1 * ((g.h + M - 1) / M);
+  return 3 * (int)(((long long)g.n1 * g.h + M - 1) / M);
 }
 
 // ---------------------------------------------------------------------------
@@ -281,8 +281,8 @@ __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, cons
 // Pass 2 / 4: transform along a1 (forward or inverse) in place.
 // Register engine: kThreads / (n1/8) pencils per work-group, consecutive in
 // (component, a0, k2) order so that each load / store row of the work-group is
-// a run of consecutive k2.  LDS engine: g.m consecutive k2 of one
-// (component, a0) plane.
+// a run of consecutive k2.  LDS engine: g.m pencils consecutive in the same
+// order (several planes where a plane has fewer k2).
 // ---------------------------------------------------------------------------
 template <typename T, bool INV, int ENG>
 __device__ __forceinline__ void tile_col_a1(const Batch& B, cx<T>* __restrict__ spec,
@@ -320,24 +320,30 @@ __device__ __forceinline__ void tile_col_a1(const Batch& B, cx<T>* __restrict__ 
     return;
   }
 
+  // M consecutive pencils of the (component, a0, k2) order: pencil
+  // P = plane H + k2 holds its element e at plane N1 H + e H + k2.  Loads and
+  // stores give consecutive lanes consecutive k2 (m fastest), or, where a
+  // plane holds fewer than 64 bytes of k2, consecutive elements of one pencil.
   const int M = sizeof(T) == 8 ? g.m64 : g.m32;
   cx<T>* bufA = tw + padded_len(N1);
   cx<T>* bufB = bufA + N1 * M;
-  const int nkb = (H + M - 1) / M;
-  const int c = local / (g.n0 * nkb);
-  const int rem = local - c * g.n0 * nkb;
-  const int a0 = rem / nkb, kb = rem - a0 * nkb;
-  const int Mt = min(M, H - kb * M);
-  cx<T>* base = S0 + (long long)c * g.rows * H + (long long)a0 * N1 * H + kb * M;
+  const int npen = 9 * g.n0 * H;
+  const int P0 = local * M;
+  const int Mt = min(M, npen - P0);
+  const bool efast = H * (int)sizeof(cx<T>) < 64;
+  auto at = [&](int e, int m) {
+    const int P = P0 + m, plane = P / H, k2 = P - plane * H;
+    return S0 + (long long)plane * N1 * H + (long long)e * H + k2;
+  };
   for (int t = threadIdx.x; t < N1 * M; t += kThreads) {
-    const int e = t / M, m = t - e * M;
-    bufA[t] = m < Mt ? base[(long long)e * H + m] : cx<T>{(T)0, (T)0};
+    const int m = efast ? t / N1 : t % M, e = efast ? t - m * N1 : t / M;
+    bufA[e * M + m] = m < Mt ? *at(e, m) : cx<T>{(T)0, (T)0};
   }
   __syncthreads();
   const cx<T>* R = fft_lds<T>(bufA, bufB, g.ax[1], M, 1, M, tw, INV, true);
   for (int t = threadIdx.x; t < N1 * M; t += kThreads) {
-    const int e = t / M, m = t - e * M;
-    if (m < Mt) base[(long long)e * H + m] = R[t];
+    const int m = efast ? t / N1 : t % M, e = efast ? t - m * N1 : t / M;
+    if (m < Mt) *at(e, m) = R[e * M + m];
   }
 }
 
@@ -469,24 +475,21 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
     return;
   }
 
+  // M consecutive pencils P = k1 H + k2 of one tensor row: in every a0 plane
+  // of the row's components they sit at offsets P, one run of M entries
   const int M = sizeof(T) == 8 ? g.m64 : g.m32;
   cx<T>* bufA = tw + padded_len(N0);
   cx<T>* bufB = bufA + N0 * M;
-  const int nkb = (H + M - 1) / M;
-  const int i = local / (N1 * nkb);
-  const int rem = local - i * N1 * nkb;
-  const int k1 = rem / nkb, kb = rem - k1 * nkb;
-  const int Mt = min(M, H - kb * M);
+  const int npen = N1 * H;
+  const int ntile = (npen + M - 1) / M;
+  const int i = local / ntile;
+  const int P0 = (local - i * ntile) * M;
+  const int Mt = min(M, npen - P0);
   const int total = N0 * M;
-  cx<T>* base0 = S0 + (long long)k1 * H + kb * M;
 
-  // The same two-forward / two-inverse scheme as the register engine: xi_1
-  // is fixed in this tile (one k1), xi_2 per pencil (k2 = kb M + m).  Every
-  // load is issued before the first transform.
-  const int f1 = signed_freq(k1, N1);
-  const T xi1 = (T)f1 * rn1;
-  const bool pen_zero = (N1 % 2 == 0) && (2 * k1 == N1);
-  cx<T>* b0 = base0 + (long long)(3 * i) * cstride;
+  // The same two-forward / two-inverse scheme as the register engine, with
+  // xi_1, xi_2 per pencil.  Every load is issued before the first transform.
+  cx<T>* b0 = S0 + (long long)(3 * i) * cstride + P0;
   cx<T> ra[kMaxPpt], ru[kMaxPpt];  // a_i0, then FFT(a_i0); u = xi1 a_i1 + xi2 a_i2, then FFT(u)
 #pragma unroll
   for (int pt = 0; pt < kMaxPpt; ++pt) {
@@ -495,7 +498,8 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
     const bool ok = t < total && m < Mt;
     const long long o = ok ? (long long)e * S + m : 0;
     const cx<T> a0 = b0[o], a1 = b0[cstride + o], a2 = b0[2 * cstride + o];
-    const T xi2 = (T)(kb * M + m) * rn2;
+    const int k1 = (P0 + m) / H, k2 = P0 + m - k1 * H;
+    const T xi1 = (T)signed_freq(k1, N1) * rn1, xi2 = (T)k2 * rn2;
     ra[pt] = ok ? a0 : cx<T>{(T)0, (T)0};
     ru[pt] = ok ? cscale(a1, xi1) + cscale(a2, xi2) : cx<T>{(T)0, (T)0};
   }
@@ -521,9 +525,10 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
   for (int pt = 0; pt < kMaxPpt; ++pt) {
     const int t = threadIdx.x + pt * kThreads;
     const int k0 = t / M, m = t - k0 * M;
-    const int k2 = kb * M + m;
-    const int f0 = signed_freq(k0, N0);
-    const T xi0 = (T)f0 * rn0, xi2 = (T)k2 * rn2;
+    const int k1 = (P0 + m) / H, k2 = P0 + m - k1 * H;
+    const int f0 = signed_freq(k0, N0), f1 = signed_freq(k1, N1);
+    const T xi0 = (T)f0 * rn0, xi1 = (T)f1 * rn1, xi2 = (T)k2 * rn2;
+    const bool pen_zero = (N1 % 2 == 0) && (2 * k1 == N1);
     const bool zero = pen_zero || m >= Mt || (f0 == 0 && f1 == 0 && k2 == 0) || ((N0 % 2 == 0) && (2 * k0 == N0));
     const T c = zero ? (T)0 : (T)g.inv_n / (xi0 * xi0 + xi1 * xi1 + xi2 * xi2);
     const cx<T> sc = cscale(cscale(ra[pt], xi0) + ru[pt], c);
@@ -547,7 +552,8 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
       if (l == 0) {
         b0[o] = Rz[t];
       } else {
-        const T xi2 = (T)(kb * M + m) * rn2;
+        const int k1 = (P0 + m) / H, k2 = P0 + m - k1 * H;
+        const T xi1 = (T)signed_freq(k1, N1) * rn1, xi2 = (T)k2 * rn2;
         b0[cstride + o] = cscale(Rz[t], xi1);
         b0[2 * cstride + o] = cscale(Rz[t], xi2);
       }
@@ -613,13 +619,13 @@ __device__ __forceinline__ void tile_col_a0_project_id(const Batch& B, cx<T>* __
   const int M = sizeof(T) == 8 ? g.m64 : g.m32;
   cx<T>* bufA = tw + padded_len(N0);
   cx<T>* bufB = bufA + N0 * M;
-  const int nkb = (H + M - 1) / M;
-  const int i = local / (N1 * nkb);
-  const int rem = local - i * N1 * nkb;
-  const int k1 = rem / nkb, kb = rem - k1 * nkb;
-  const int Mt = min(M, H - kb * M);
+  const int npen = N1 * H;
+  const int ntile = (npen + M - 1) / M;
+  const int i = local / ntile;
+  const int P0 = (local - i * ntile) * M;
+  const int Mt = min(M, npen - P0);
   const int total = N0 * M;
-  cx<T>* b0 = S0 + (long long)k1 * H + kb * M + (long long)(3 * i) * cstride;
+  cx<T>* b0 = S0 + (long long)(3 * i) * cstride + P0;
   cx<T> r[3][kMaxPpt];
 #pragma unroll
   for (int pt = 0; pt < kMaxPpt; ++pt) {
@@ -650,7 +656,8 @@ __device__ __forceinline__ void tile_col_a0_project_id(const Batch& B, cx<T>* __
   for (int pt = 0; pt < kMaxPpt; ++pt) {
     const int t = threadIdx.x + pt * kThreads;
     const int k0 = t / M, m = t - k0 * M;
-    if (t < total && m < Mt) project_point(r[0][pt], r[1][pt], r[2][pt], k0, k1, kb * M + m, g, rn0, rn1, rn2);
+    const int k1 = (P0 + m) / H, k2 = P0 + m - k1 * H;
+    if (t < total && m < Mt) project_point(r[0][pt], r[1][pt], r[2][pt], k0, k1, k2, g, rn0, rn1, rn2);
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) {

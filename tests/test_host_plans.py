@@ -7,7 +7,8 @@ context plans (fftnk_describe), checked against what the kernels assume.
 * a2 work-groups: pass 1 holds one voxel per thread (rt1 * n2 <= 256); the
   tiles of passes 1 and 5 cover every grid line exactly once.
 * Column passes: the tiles cover every pencil; LDS-engine tiles hold at most
-  4 points per thread; every kernel family's LDS fits its budget.
+  4 points per thread (M pencils consecutive in k2-fastest order, across k2
+  lines where h < M); every kernel family's LDS fits its budget.
 * Batched contexts: per-cell offsets are cumulative, the launch sizes are the
   sums of the cells' work-groups, the engine bits cover every cell's engine.
 * The GMRES basis adds m + 1 fields (padded to 64 elements) to the workspace;
@@ -59,9 +60,10 @@ def _check_cell(c, prec, policy=0):
                 per = THREADS // (ax["n"] // ax["reg"])
                 assert b[key] * per >= npen > (b[key] - 1) * per, (key, c)
             else:
-                assert M >= 1 and M <= h and ax["n"] * M <= 4 * THREADS
-                per_line = npen // h  # pencils per k2 line
-                assert b[key] == per_line * math.ceil(h / M), (key, c)
+                # M consecutive pencils in k2-fastest order (across k2 lines where h < M)
+                assert M >= 1 and ax["n"] * M <= 4 * THREADS
+                groups = 1 if axis == 1 else 3  # a1: one range over all pencils; a0: one per tensor row
+                assert b[key] == groups * math.ceil(npen // groups / M), (key, c)
     assert b["elem9"] >= 1 and b["vox"] >= 1
 
 
