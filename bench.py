@@ -66,6 +66,16 @@ def cg_bytes_per_voxel(prec_bytes, n2):
             "pass4": op[4], "pass5": spec + 2 * field, "beta": 0.0}
 
 
+def three_kernel_bytes_per_voxel(prec_bytes, n2):
+    """Lower-bound bytes per voxel of any operator built from three kernels:
+    the compulsory reads of p, F and the phase byte and the write of A p, plus
+    one write and one read of the 9-field half spectrum (n2/2 + 1 entries per
+    line, the Nyquist entry included) per transform direction."""
+    field = 9 * prec_bytes
+    spec = 9 * 2 * prec_bytes * (n2 // 2 + 1) / n2
+    return 3 * field + 1 + 4 * spec
+
+
 KERNEL_NAMES = {"pass1": "k_fwd_a2<double,FWD_CG>", "pass2": "k_col_a1<double,fwd>", "pass3": "k_col_a0_project<double>",
                 "pass4": "k_col_a1<double,inv>", "pass5": "k_inv_a2<double,INV_CGR>", "alpha": "k_cg_alpha",
                 "beta": "k_cg_beta"}
@@ -260,6 +270,8 @@ def main():
             "operator_ms": round(t_mv32, 4),
             "operator_matvecs_per_s": round(1e3 / t_mv32, 1),
             "operator_GB_s": round(sum(bpv32.values()) * n / (t_mv32 * 1e-3) / 1e9, 1),
+            "operator_effective_frac": round(three_kernel_bytes_per_voxel(4, N) * n / (t_mv32 * 1e-3) / 1e9
+                                             / HBM_PEAK_GBS, 4),
             "passes_ms": {k: round(v, 5) for k, v in passes32.items()},
             "pbar_rel_diff_vs_fp64_gpu": err,
             "speedup_vs_fp64": round((min(args.steps, 5) / sec32) / (args.steps / sec), 3),
@@ -324,7 +336,11 @@ def main():
         "operator": {"ms": round(t_mv64, 4), "matvecs_per_s": round(1e3 / t_mv64, 1),
                      "bytes_5pass_per_voxel": round(sum(bpv64.values()), 2),
                      "GB_s": round(mv_bytes64 / (t_mv64 * 1e-3) / 1e9, 1),
-                     "frac_of_hbm_peak": round(mv_bytes64 / (t_mv64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                     "frac_of_hbm_peak": round(mv_bytes64 / (t_mv64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     # the same time over the 3-kernel lower-bound bytes
+                     "bytes_3kernel_per_voxel": round(three_kernel_bytes_per_voxel(8, N), 2),
+                     "effective_frac": round(three_kernel_bytes_per_voxel(8, N) * n / (t_mv64 * 1e-3) / 1e9
+                                             / HBM_PEAK_GBS, 4)},
         "passes": pass_rows,
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -19,6 +19,10 @@ def test_byte_model_fp64_and_fp32():
     assert sum(bench.pass_bytes_per_voxel(4, 128).values()) == 397.0
     # odd n2: (n2 + 1) / 2 stored half-line entries
     assert bench.pass_bytes_per_voxel(8, 31)[2] == 2 * 9 * 16 * 16 / 31
+    # the 3-kernel lower bound (compulsory I/O + one round trip of the half
+    # spectrum with its Nyquist entry per direction): 509.5 B FP64, 255.25 FP32
+    assert bench.three_kernel_bytes_per_voxel(8, 128) == 509.5
+    assert bench.three_kernel_bytes_per_voxel(4, 128) == 255.25
 
 
 def test_more_than_one_gpu_is_refused():
