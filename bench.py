@@ -121,11 +121,11 @@ def main():
                          "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--extra", default="",
-                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d,tune: instead of the headline line, one JSON "
+                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d,tune,cpu_baseline: instead of the headline line, one JSON "
                          "line per extra measurement (operator at 96^3..256^3; 64 batched cells; J2 at 96^3; adjoint "
                          "8 x 192^3; the two Nyquist choices at 128^3; mixed control at 128^3; CG / Chebyshev / "
                          "Richardson / GMRES at 128^3; the 2-D plane-strain example at 451^2; the plan autotuner on "
-                         "several cells)")
+                         "several cells; the CPU oracle at several sizes and on all host cores)")
     args = ap.parse_args()
     if args.operator_only:
         return operator_only(args)
@@ -401,6 +401,22 @@ def operator_only(args):
     print(json.dumps({"operator_only": res, "precision": args.precision}), flush=True)
 
 
+def _oracle_matvecs(job):
+    """CPU-baseline worker (a separate process that never touches the GPU):
+    `reps` oracle operator applications on an N^3 two-phase cell; seconds."""
+    n_, reps, seed = job
+    import oracle
+    from paper_1603_08893_amd import microstructure as ms
+    ph = (np.random.default_rng(seed).random((n_,) * 3) < 0.3).astype(np.uint8)
+    K, mu = ms.phase_moduli(ph, TABLE)
+    F = ms.near_identity_field((n_,) * 3, seed=seed + 1, scale=0.01)
+    p = ms.random_field((n_,) * 3, seed=seed + 2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.apply_operator(F, K, mu, p)
+    return time.perf_counter() - t0
+
+
 def extra(args):
     """Measurements beyond the headline: each prints one JSON line."""
     import torch
@@ -458,6 +474,68 @@ def extra(args):
                       "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
                 del s, fl, p, out
                 torch.cuda.empty_cache()
+
+    if "cpu_baseline" in which:
+        # the oracle timed on the host beside the GPU path: operator
+        # applications at several sizes on one core (GPU operator time of the
+        # same cell beside it), the paper's first example solved on one core,
+        # and the all-core throughput of independent 64^3 applications
+        import oracle
+        import os
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        oracle.build()
+        for n_ in (32, 64, 96, 128):
+            reps = 3 if n_ >= 96 else 5
+            t_cpu = _oracle_matvecs((n_, reps, 11))
+            ph = (np.random.default_rng(11).random((n_,) * 3) < 0.3).astype(np.uint8)
+            s = Solver((n_,) * 3, precision="fp64")
+            s.set_phases(ph)
+            s.set_material(TABLE)
+            s.set_linearization(torch.from_numpy(ms.near_identity_field((n_,) * 3, seed=12, scale=0.01).reshape(-1)))
+            p = torch.from_numpy(ms.random_field((n_,) * 3, seed=13).reshape(-1)).to(dev)
+            out = s.field()
+            for _ in range(3):
+                s.apply_operator(p, out)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                s.apply_operator(p, out)
+            e1.record()
+            torch.cuda.synchronize()
+            t_gpu = e0.elapsed_time(e1) / 20
+            emit({"extra": "cpu_baseline_operator", "grid": n_, "kind": "oracle", "cores": 1,
+                  "cpu_ms": round(1e3 * t_cpu / reps, 1), "gpu_ms": round(t_gpu, 4),
+                  "ratio": round(1e3 * t_cpu / reps / t_gpu, 1)})
+            del s, p, out
+        # the paper's first example (31^3, cubic inclusion, simple shear 0.05), one core
+        ph = ms.cubic_inclusion(31, 9)
+        K, mu = ms.phase_moduli(ph, TABLE)
+        c0 = time.perf_counter()
+        st, _, _, _, so = oracle.solve_increment(K, mu, oracle.identity_field((31,) * 3), ms.simple_shear(0.05))
+        t_cpu = time.perf_counter() - c0
+        s = Solver((31,) * 3, precision="fp64")
+        s.set_phases(ph)
+        s.set_material(TABLE)
+        s.solve_increment(ms.simple_shear(0.05), fields=False)
+        s.reset_state()
+        (_, _, _, _, sg), t_gpu = timed(lambda: s.solve_increment(ms.simple_shear(0.05), fields=False))
+        emit({"extra": "cpu_baseline_solve", "grid": 31, "kind": "oracle", "cores": 1, "status": int(st),
+              "cpu_s": round(t_cpu, 3), "gpu_s": round(t_gpu, 4), "cg_iters_oracle": so["cg_iters"],
+              "cg_iters_gpu": sg[0]["cg_iters"], "ratio": round(t_cpu / t_gpu, 1)})
+        del s
+        # all cores: independent 64^3 applications in worker processes (spawned)
+        workers = max(1, min(16, os.cpu_count() or 1))
+        jobs = [(64, 3, 100 + w) for w in range(workers)]
+        c0 = time.perf_counter()
+        with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+            t_w = list(ex.map(_oracle_matvecs, jobs))
+        t_all = time.perf_counter() - c0
+        # throughput over the slowest worker's compute time; the wall time
+        # also counts starting the worker processes
+        emit({"extra": "cpu_baseline_all_cores", "grid": 64, "kind": "oracle", "cores": workers,
+              "matvecs": 3 * workers, "compute_seconds": round(max(t_w), 3),
+              "matvecs_per_s": round(3 * workers / max(t_w), 3), "wall_seconds_with_startup": round(t_all, 2)})
 
     if "tune" in which:
         # the plan autotuner: operator time under the default plan and under
