@@ -121,11 +121,12 @@ def main():
                          "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--extra", default="",
-                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d,tune,cpu_baseline: instead of the headline line, one JSON "
+                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d,tune,cpu_baseline,slab: instead of the headline line, one JSON "
                          "line per extra measurement (operator at 96^3..256^3; 64 batched cells; J2 at 96^3; adjoint "
                          "8 x 192^3; the two Nyquist choices at 128^3; mixed control at 128^3; CG / Chebyshev / "
                          "Richardson / GMRES at 128^3; the 2-D plane-strain example at 451^2; the plan autotuner on "
-                         "several cells; the CPU oracle at several sizes and on all host cores)")
+                         "several cells; the CPU oracle at several sizes and on all host cores; one GPU's slab share of "
+                         "the 128^3 operator on 8 GPUs)")
     args = ap.parse_args()
     if args.operator_only:
         return operator_only(args)
@@ -536,6 +537,50 @@ def extra(args):
         emit({"extra": "cpu_baseline_all_cores", "grid": 64, "kind": "oracle", "cores": workers,
               "matvecs": 3 * workers, "compute_seconds": round(max(t_w), 3),
               "matvecs_per_s": round(3 * workers / max(t_w), 3), "wall_seconds_with_startup": round(t_all, 2)})
+
+    if "slab" in which:
+        # one GPU's share of the 128^3 operator on 8 GPUs split into slabs
+        # along a0: passes 1, 2, 4, 5 on a 16 x 128 x 128 slab, pass 3 on the
+        # 1/8 of the a0 pencils a GPU holds after the slab -> pencil all-to-all
+        # (timed as a 128 x 16 x 128 cell); the two all-to-alls are a model
+        # (9 half-spectrum fields x 7/8 per GPU over 7 xGMI links of 153 GB/s)
+        def pass_us(shape, k_list):
+            s = Solver(shape, precision="fp64")
+            s.set_phases((np.random.default_rng(5).random(shape) < 0.3).astype(np.uint8))
+            s.set_material(TABLE)
+            s.set_linearization(torch.from_numpy(ms.near_identity_field(shape, seed=6, scale=0.01).reshape(-1)))
+            p = torch.from_numpy(ms.random_field(shape, seed=7).reshape(-1)).to(dev)
+            out = s.field()
+            s.apply_operator(p, out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            res = {}
+            for k in k_list:
+                e0.record()
+                for _ in range(50):
+                    s.launch_pass(k)
+                e1.record()
+                torch.cuda.synchronize()
+                res[k] = 1e3 * e0.elapsed_time(e1) / 50
+            del s, p, out
+            torch.cuda.empty_cache()
+            return res
+
+        full = pass_us((128, 128, 128), [1, 2, 3, 4, 5])
+        slab = pass_us((16, 128, 128), [1, 2, 4, 5])
+        pen = pass_us((128, 16, 128), [3])
+        local = sum(slab.values()) + pen[3]
+        a2a_bytes = 9 * 16 * (128 * 128 * 64) / 8 * 7 / 8  # per GPU and direction, FP64 half spectrum
+        a2a_us = a2a_bytes / (7 * 153e9) * 1e6
+        emit({"extra": "slab_share", "cell": "128^3 on 8 GPUs (model), FP64", "gpus": 8,
+              "full_cell_pass_us": {str(k): round(v, 1) for k, v in full.items()},
+              "slab_16x128x128_pass_us": {str(k): round(v, 1) for k, v in slab.items()},
+              "pencil_share_128x16x128_pass3_us": round(pen[3], 1),
+              "local_us_per_operator": round(local, 1), "full_cell_us_per_operator": round(sum(full.values()), 1),
+              "local_vs_full_over_8": round(local / (sum(full.values()) / 8), 3),
+              "all_to_all_model_us": round(2 * a2a_us, 1),
+              "operator_us_no_overlap": round(local + 2 * a2a_us, 1),
+              "operator_us_full_overlap": round(max(local, 2 * a2a_us), 1)})
 
     if "tune" in which:
         # the plan autotuner: operator time under the default plan and under
