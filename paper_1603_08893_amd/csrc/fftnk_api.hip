@@ -199,8 +199,11 @@ struct fftnk_ctx {
   long long pstride = 0;  // partial-sum slot stride: the most work-groups of any launch kind under any policy
   std::vector<int> tw_len, tw_off;
   int tw_total = 0;
-  std::vector<int> starts;  // [NKIND][nrve + 1]
+  std::vector<int> starts_full;  // [NKIND][nrve + 1] work-group ranges of every cell
+  int nblk_full[NKIND] = {};
+  std::vector<int> starts;  // the ranges launches use: those of the cells in the mask (compact_starts)
   int nblk[NKIND] = {};
+  std::vector<int> graph_active;  // the mask the CG graphs were captured under
   size_t lds[8] = {};  // row64, row32, col1_64, col1_32, col0_64, col0_32, row1_64, row1_32
   int eng[3] = {};     // per axis: bit 0 some cell on the LDS engine, bit 1 on the 8-point, bit 2 on the 12-point one
   int nyq_id = 0;      // FFTNK_OPT_NYQUIST
@@ -305,10 +308,18 @@ int fetch(fftnk_ctx* c, const void* dev, size_t bytes) {
   return FFTNK_OK;
 }
 
+void compact_starts(fftnk_ctx* c);
+
 // host arrays uploaded here stay untouched until the next stream synchronisation
+// the Newton mask and the launch tables of its cells; every Launch built
+// before this call is stale (its work-group counts)
 int upload_active(fftnk_ctx* c) {
+  compact_starts(c);
   HIP_TRY(hipMemcpyAsync(c->ws + c->o_active, c->active.data(), c->nrve * sizeof(int), hipMemcpyHostToDevice,
                          c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->o_starts, c->starts.data(), c->starts.size() * sizeof(int),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));  // the host tables may change again at once
   return FFTNK_OK;
 }
 int upload_uni(fftnk_ctx* c) {
@@ -317,10 +328,35 @@ int upload_uni(fftnk_ctx* c) {
   return FFTNK_OK;
 }
 
+// Launch tables of the cells in the Newton mask: every other cell gets an
+// empty work-group range, so a launch dispatches no work-group for it (cells
+// that have finished their increment cost nothing); the full tables when all
+// cells, or none, are in the mask.  Host side only.
+void compact_starts(fftnk_ctx* c) {
+  const int nr = c->nrve;
+  int na = 0;
+  for (int v : c->active) na += v != 0;
+  c->starts = c->starts_full;
+  std::copy(c->nblk_full, c->nblk_full + NKIND, c->nblk);
+  if (na == 0 || na == nr || (int)c->active.size() != nr) return;
+  for (int k = 0; k < NKIND; ++k) {
+    const int* f = &c->starts_full[(size_t)k * (nr + 1)];
+    int* t = &c->starts[(size_t)k * (nr + 1)];
+    int acc = 0;
+    for (int r = 0; r < nr; ++r) {
+      t[r] = acc;
+      if (c->active[r]) acc += f[r + 1] - f[r];
+    }
+    t[nr] = acc;
+    c->nblk[k] = acc;
+  }
+}
+
 void apply_geo(fftnk_ctx* c, const Geo& geo) {
   c->g = geo.g;
-  c->starts = geo.starts;
-  std::copy(geo.nblk, geo.nblk + NKIND, c->nblk);
+  c->starts_full = geo.starts;
+  std::copy(geo.nblk, geo.nblk + NKIND, c->nblk_full);
+  compact_starts(c);
   std::copy(geo.lds, geo.lds + 8, c->lds);
   std::copy(geo.eng, geo.eng + 3, c->eng);
 }
@@ -533,6 +569,10 @@ int run_gmres(fftnk_ctx* c, double eta, int max_it);
 
 int run_cg(fftnk_ctx* c, double eta, int max_cg) {
   if (c->krylov == KRYLOV_GMRES) return run_gmres(c, eta, max_cg);
+  if (c->graph_active != c->active) {  // the graphs hold the launch sizes of another mask
+    drop_graphs(c);
+    c->graph_active = c->active;
+  }
   const Launch L = c->launch();
   const int stall = c->prec == PREC_F32 ? 50 : 0;
   launch_cg_init(L, c->cg(), eta, max_cg, stall, c->krylov, c->k_lo, c->k_hi);
@@ -588,7 +628,7 @@ int run_gmres(fftnk_ctx* c, double eta, int max_it) {
   const long long vstride = gm_vstride(c->ntot);
   auto V = [&](int j) { return static_cast<void*>(c->ws + c->o_gm + (size_t)j * vstride * esz); };
   double* coef = c->at<double>(c->o_coef);
-  const Launch L = c->launch();
+  Launch L = c->launch();  // rebuilt whenever the mask changes (launch sizes)
   const Material mat = c->material();
   const std::vector<int> act0 = c->active;  // the caller's mask, restored at the end
   // on an early (error) return the caller's mask is restored all the same
@@ -646,7 +686,7 @@ int run_gmres(fftnk_ctx* c, double eta, int max_it) {
     }
     const int e2 = upload_active(c);
     if (e2) return -e2;
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return -FFTNK_EHIP;
+    L = c->launch();
     return any;
   };
   auto apply_A = [&](const void* v) {  // w = A v
@@ -925,10 +965,11 @@ int newton_solve(fftnk_ctx* c, const double* Fbar, const std::vector<int>& run, 
     e = upload_active(c);
     if (e) return e;
     // F += dF (+ dFbar after the boundary-condition solve), constitutive
-    // update, new right-hand side -G(P)
+    // update; the convergence test; then the new right-hand side -G(P) for
+    // the cells still running (its partial sums, which the next CG reads,
+    // are laid out by the launch tables of that mask)
     const void* dF = newton_update_source(c);  // FP64 in both precisions
     launch_newton_update(PREC_F64, c->launch(), mat, c->F(), dF, c->P(), c->F32(), it == 0);
-    rhs_pipeline(c, FWD_COPY, c->P(), nullptr, -1.0);
     e = reduce_fetch(c, {{K_VOX, {SLOT_DF, 1}}, {K_VOX, {SLOT_PBAR, 9}}});
     if (e) return e;
     for (int r = 0; r < nr; ++r) {
@@ -953,8 +994,10 @@ int newton_solve(fftnk_ctx* c, const double* Fbar, const std::vector<int>& run, 
     }
     e = upload_active(c);
     if (e) return e;
+    bool more = false;
+    for (int r = 0; r < nr; ++r) more = more || !done[r];
+    if (more) rhs_pipeline(c, FWD_COPY, c->P(), nullptr, -1.0);
   }
-  HIP_TRY(hipStreamSynchronize(c->stream));  // the last mask upload has read the host vector
   return FFTNK_OK;
 }
 
