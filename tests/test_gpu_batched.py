@@ -9,6 +9,9 @@ covers all RVEs), and CG iterations replayed from HIP graphs.
   program's own eager work and synchronisation in between).
 * A failing RVE (non-finite load) leaves the others converging and committing,
   and its own committed state untouched.
+* Cells leaving the Newton loop at different iterations (launches then cover
+  only the cells still running) still reproduce their single-cell solves
+  bitwise.
 
 Inputs follow the batched workload's recipe at reduced sizes: random
 sequential addition of periodic spheres (radius 3-10 voxels), per-RVE target
@@ -133,3 +136,33 @@ def test_failing_rve_leaves_others(torch_cuda):
     _, F1, _, Pb1, _ = one.solve_increment(items[0]["Fbar"])
     assert np.array_equal(Pbar[0], Pb1[0])
     assert torch.equal(Ft[:9 * n0], F1)
+
+
+def test_cells_leaving_at_different_newton_iterations(torch_cuda, orc):
+    """Cells that finish their increments after different numbers of Newton
+    solves: later launches cover only the cells still running (compacted
+    launch tables, CG graphs captured again), and every cell still
+    reproduces its single-cell solve bitwise, over two increments."""
+    torch = torch_cuda
+    items = _batch([16, 12, 20, 8], seed0=1603100)
+    items[1]["table"] = [(0.833, 0.386), (0.833, 0.386)]  # homogeneous: two solves
+    scale = [0.4, 0.3, 0.8, 0.1]  # Newton solves per increment 3, 2, 4, 3 (the oracle's, both increments)
+    loads = [[np.eye(3).reshape(9) + k * s * (it["Fbar"] - np.eye(3).reshape(9)) for it, s in zip(items, scale)]
+             for k in (1, 2)]
+    s = _batched_solver(items)
+    singles = [_single_solver(it) for it in items]
+    counts = set()
+    for k in range(2):
+        st, F, P, Pbar, stats = s.solve_increment(np.array(loads[k]))
+        assert st == 0
+        off = 0
+        for r, it in enumerate(items):
+            n = it["N"] ** 3
+            _, F1, _, Pb1, S1 = singles[r].solve_increment(loads[k][r])
+            counts.add(stats[r]["n_solves"])
+            assert stats[r]["n_solves"] == S1[0]["n_solves"] and stats[r]["cg_iters"] == S1[0]["cg_iters"], (k, r)
+            assert np.array_equal(Pbar[r], Pb1[0]), (k, r)
+            assert torch.equal(F[9 * off:9 * (off + n)], F1), (k, r)
+            off += n
+    print("Newton solves per cell seen:", sorted(counts), flush=True)
+    assert len(counts) >= 2
