@@ -5,7 +5,8 @@
   projection and operator: parity with the oracle at the usual tolerances
   (FP64 1e-13, FP32 5e-6), switching policies on one bound context.  Shapes
   cover the 8- and 12-point register engines, the LDS engine and a batch.
-* The autotuner keeps a valid policy, reports its time, caches it per
+* The autotuner keeps a valid policy (single cells and a batch of cells on
+  different engines), reports its time, caches it per
   process (a second context of the same sizes gets it without timing), and a
   solve under the tuned plan matches the oracle.
 """
@@ -129,3 +130,26 @@ def test_plan_errors(torch_cuda):
     s.set_material([(1.0, 1.0)])
     with pytest.raises(fftnk.FftnkError):
         s.autotune(reps=0)
+
+
+def test_autotune_batched_cells(torch_cuda, orc):
+    """The tuner on a batch of cells with different engines: a valid policy
+    for the batch, and each cell's increment under it matches the oracle."""
+    from paper_1603_08893_amd.fftnk import Solver
+    dims = [(16, 12, 8), (9, 7, 5), (24, 24, 12)]
+    print("autotune batched", dims, flush=True)
+    rng = np.random.default_rng(21)
+    phs = [(rng.random(d) < 0.3).astype(np.uint8) for d in dims]
+    s = Solver(dims, precision="fp64")
+    s.set_phases(np.concatenate([ph.reshape(-1) for ph in phs]))
+    s.set_material(TABLE)
+    pol, t = s.autotune(reps=2, use_cache=False)
+    assert pol in distinct_policies(dims, "fp64") and t > 0.0
+    Fbar = ms.simple_shear(0.03)
+    st, F, P, Pb, S = s.solve_increment(np.stack([Fbar] * len(dims)), 1e-8, 1e-10)
+    assert st == 0
+    for r, (d, ph) in enumerate(zip(dims, phs)):
+        K, mu = ms.phase_moduli(ph, TABLE)
+        sto, Fo, Po, Pbo, So = orc.solve_increment(K, mu, orc.identity_field(d), Fbar, 1e-8, 1e-10)
+        assert sto == 0 and S[r]["n_solves"] == So["n_solves"]
+        assert np.max(np.abs(Pb[r] - Pbo)) <= 1e-10 * np.max(np.abs(Pbo))
