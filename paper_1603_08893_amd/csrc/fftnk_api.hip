@@ -545,8 +545,8 @@ int cg_graph(fftnk_ctx* c, int k, hipGraphExec_t* out) {
   return FFTNK_OK;
 }
 
-int launch_iterations(fftnk_ctx* c, int k) {
-  if (!c->use_graphs) {
+int launch_iterations(fftnk_ctx* c, int k, bool eager = false) {
+  if (!c->use_graphs || eager) {
     const Launch L = c->launch();
     for (int i = 0; i < k; ++i) cg_iteration(c, L);
     return check_launch();
@@ -581,22 +581,47 @@ int run_cg(fftnk_ctx* c, double eta, int max_cg) {
   int launched = std::max(1, std::min(c->cg_estimate - 2, max_cg));
   e = launch_iterations(c, launched);
   if (e) return e;
+  // Once some cells have finished their CG, the iterations that follow launch
+  // over the others only: the mask is narrowed to the cells still iterating
+  // (eager launches, the graphs keep the Newton mask's sizes) and the Newton
+  // mask is restored before the last deferred x update, on every exit.
+  struct Narrowed {
+    fftnk_ctx* c;
+    std::vector<int> newton;
+    bool on = false;
+    int restore() {
+      if (!on) return FFTNK_OK;
+      on = false;
+      c->active = newton;
+      return upload_active(c);
+    }
+    ~Narrowed() { (void)restore(); }
+  } nar{c, c->active};
   while (true) {
     e = fetch(c, c->cg(), c->nrve * sizeof(CgState));
     if (e) return e;
     bool all = true;
-    int most = 0;
+    int most = 0, running = 0, masked = 0;
     for (int r = 0; r < c->nrve; ++r) {
-      all = all && c->host_cg()[r].done;
+      const bool done = c->host_cg()[r].done != 0;
+      all = all && done;
       most = std::max(most, c->host_cg()[r].iter);
+      running += !done;
+      masked += c->active[r] != 0;
     }
     if (all) {
       if (most > 0) c->cg_estimate = most;
-      launch_cg_finish(c->prec, L, c->x(), c->p(), c->cg());  // the last iteration's deferred x update
+      if ((e = nar.restore())) return e;
+      launch_cg_finish(c->prec, c->launch(), c->x(), c->p(), c->cg());  // the last iteration's deferred x update
       return check_launch();
     }
     if (launched > max_cg + 64) return FFTNK_ECG_MAXIT;  // unreachable: k_cg_beta stops at max_cg
-    e = launch_iterations(c, c->check_every);
+    if (running < masked) {
+      for (int r = 0; r < c->nrve; ++r) c->active[r] = c->host_cg()[r].done ? 0 : 1;
+      nar.on = true;
+      if ((e = upload_active(c))) return e;
+    }
+    e = launch_iterations(c, c->check_every, nar.on);
     if (e) return e;
     launched += c->check_every;
   }
