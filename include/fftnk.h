@@ -372,6 +372,26 @@ int fftnk_launch_pass(fftnk_ctx* ctx, int pass);
 int fftnk_profile_cg(fftnk_ctx* ctx, int iters, double* ms_host);
 
 /*
+ * Instrumentation, independent of any context: the achievable HBM streaming
+ * rate of the device, the ceiling for passes that move each byte of their
+ * working set once (every pass of the operator does; Sec. 3.3 names the
+ * transforms as the cost, and on this device they are bound by memory).
+ * kind: FFTNK_STREAM_READ (sum of src1, one partial per work-group written to
+ * the first doubles of dst), _WRITE (fill dst), _COPY (dst = src1), _TRIAD
+ * (dst = src1 + 0.5 src2); lane_bytes 8 or 16 (double or double2 accesses).
+ * dst, src1, src2: caller-owned device buffers of `bytes` bytes each (src1 /
+ * src2 may be NULL where the kind does not read them); bytes a multiple of
+ * lane_bytes.  One untimed launch, then `reps` (1..10000) back-to-back
+ * launches between two events on hip_stream (NULL: the default stream);
+ * ms_host receives the mean ms per launch.  Bytes moved per launch: read,
+ * write: bytes; copy: 2 bytes; triad: 3 bytes.  Synchronises the stream.
+ * FFTNK_EINVAL on a bad kind, lane width, size, count or missing pointer.
+ */
+enum { FFTNK_STREAM_READ = 0, FFTNK_STREAM_WRITE = 1, FFTNK_STREAM_COPY = 2, FFTNK_STREAM_TRIAD = 3 };
+int fftnk_stream(int kind, int lane_bytes, void* dst, const void* src1, const void* src2, size_t bytes, int reps,
+                 void* hip_stream, double* ms_host);
+
+/*
  * Checkpoint of the J2 history (Alg. 1, "store history variables"): device
  * double [7][n] -- C_p^-1 as xx yy zz xy yz xz, then the accumulated plastic
  * strain; batched: each of the 7 planes holds all RVEs in order.  Virgin state

@@ -11,8 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libfftnk.so")
-SOURCES = ["fftnk_fft_kernels.hip", "fftnk_solver_kernels.hip", "fftnk_api.hip"]
-HEADERS = ["fftnk_internal.h", "fftnk_device.h"]
+SOURCES = ["fftnk_fft_kernels.hip", "fftnk_solver_kernels.hip", "fftnk_api.hip", "fftnk_stream.hip"]
+HEADERS = ["fftnk_internal.h", "fftnk_device.h", "fftnk_j2.h"]
 
 # -packed-fp32-ops: no v_pk_*_f32 instructions anywhere in the device code.
 HIPFLAGS = [
@@ -30,20 +30,43 @@ def hipcc():
 
 
 def build(force=True, verbose=False):
+    """Compile every source to an object in parallel (one hipcc per file), then
+    link the shared library."""
     os.makedirs(LIBDIR, exist_ok=True)
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     deps = srcs + [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(ROOT, "include", "fftnk.h")]
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(os.path.getmtime(d) for d in deps):
         return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPFLAGS + ["-o", tmp] + srcs
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libfftnk")
-    os.replace(tmp, LIB)
+    objs = [os.path.join(LIBDIR, os.path.basename(s) + ".%d.o" % os.getpid()) for s in srcs]
+    compile_flags = [f for f in HIPFLAGS if f != "-shared"]
+    procs = []
+    for src, obj in zip(srcs, objs):
+        cmd = [hipcc()] + compile_flags + ["-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
+    failed = False
+    for p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out)
+            failed = True
+    try:
+        if failed:
+            raise RuntimeError("hipcc failed building libfftnk")
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking libfftnk")
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 

@@ -92,6 +92,18 @@ __device__ __forceinline__ cx<T> get_nyquist(const Batch& B, const G& g, long lo
   return cx<T>{ny[(2 * pq) * g.rows], ny[(2 * pq + 1) * g.rows]};
 }
 
+// store of one half-spectrum entry by pass 1 (non-temporal in CG mode when
+// the policy says so)
+template <int MODE, typename T>
+__device__ __forceinline__ void st_spec(cx<T>* p, cx<T> v) {
+  if constexpr (MODE == FWD_CG && (nt_policy<T>() & NT_P1_STORE_SPEC) != 0) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(v2{v.x, v.y}, reinterpret_cast<v2*>(p));
+  } else {
+    *p = v;
+  }
+}
+
 template <typename T, int MODE, int LAW, int ENG>
 __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat, const T* __restrict__ in,
                                             const T* __restrict__ rvec, T* __restrict__ pvec, T* __restrict__ xvec,
@@ -151,28 +163,28 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
           const bool first = cptr(cg)[rv].iter == 0;
           if (first) {  // p_0 = r_0, x_0 = 0
 #pragma unroll
-            for (int c = 0; c < 9; ++c) p[c] = *byte_off(rvec + off + c * n, vb);
+            for (int c = 0; c < 9; ++c) p[c] = ld_stream<NT_P1_LOAD_VEC>(byte_off(rvec + off + c * n, vb));
 #pragma unroll
-            for (int c = 0; c < 9; ++c) F[c] = *byte_off(Flin + off + c * n, vb);
+            for (int c = 0; c < 9; ++c) F[c] = ld_stream<NT_P1_LOAD_F>(byte_off(Flin + off + c * n, vb));
           } else {  // x += alpha p_old (previous iteration), p = r + beta p_old
             const T alpha = (T)cptr(cg)[rv].alpha, beta = (T)cptr(cg)[rv].beta;
             T po[9], xo[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
-              p[c] = *byte_off(rvec + off + c * n, vb);
-              po[c] = *byte_off(pvec + off + c * n, vb);
-              xo[c] = *byte_off(xvec + off + c * n, vb);
+              p[c] = ld_stream<NT_P1_LOAD_VEC>(byte_off(rvec + off + c * n, vb));
+              po[c] = ld_stream<NT_P1_LOAD_VEC>(byte_off(pvec + off + c * n, vb));
+              xo[c] = ld_stream<NT_P1_LOAD_VEC>(byte_off(xvec + off + c * n, vb));
             }
 #pragma unroll
-            for (int c = 0; c < 9; ++c) F[c] = *byte_off(Flin + off + c * n, vb);
+            for (int c = 0; c < 9; ++c) F[c] = ld_stream<NT_P1_LOAD_F>(byte_off(Flin + off + c * n, vb));
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
-              *byte_off(xvec + off + c * n, vb) = xo[c] + alpha * po[c];
+              st_stream<NT_P1_STORE_VEC>(byte_off(xvec + off + c * n, vb), xo[c] + alpha * po[c]);
               p[c] = p[c] + beta * po[c];
             }
           }
 #pragma unroll
-          for (int c = 0; c < 9; ++c) *byte_off(pvec + off + c * n, vb) = p[c];
+          for (int c = 0; c < 9; ++c) st_stream<NT_P1_STORE_VEC>(byte_off(pvec + off + c * n, vb), p[c]);
         }
         tangent_at<T, LAW>(mat, g.vox_off + v, F, p, d);
         if (MODE == FWD_CG) {
@@ -220,10 +232,10 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
         const cx<T> z = v[q];
         const cx<T> zm = xl[lpad(k ? N2 - k : 0)];
         if (pq == 4) {
-          S[8 * srow + row * H + k] = z;
+          st_spec<MODE>(S + 8 * srow + row * H + k, z);
         } else {
-          S[(2 * pq) * srow + row * H + k] = cx<T>{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)};
-          S[(2 * pq + 1) * srow + row * H + k] = cx<T>{(T)0.5 * (z.y + zm.y), (T)-0.5 * (z.x - zm.x)};
+          st_spec<MODE>(S + (2 * pq) * srow + row * H + k, cx<T>{(T)0.5 * (z.x + zm.x), (T)0.5 * (z.y - zm.y)});
+          st_spec<MODE>(S + (2 * pq + 1) * srow + row * H + k, cx<T>{(T)0.5 * (z.y + zm.y), (T)-0.5 * (z.x - zm.x)});
         }
       }
       // lane 0 holds k = n2 / 2 at q = P / 2: the two real Nyquist coefficients
@@ -793,7 +805,8 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
 #pragma unroll
         for (int q = 0; q < P; ++q)
 #pragma unroll
-          for (int h = 0; h < 2; ++h) rin[q][h] = h < nc ? out[base + t + Tp * q + (c0 + h) * n] : (TO)0;
+          for (int h = 0; h < 2; ++h)
+            rin[q][h] = h < nc ? ld_stream<NT_P5_LOAD_R>(out + base + t + Tp * q + (c0 + h) * n) : (TO)0;
       }
 #pragma unroll
       for (int q = 0; q < P; ++q) {
@@ -809,7 +822,7 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
             acc[0] += (double)o * (double)o;
           } else if (MODE == INV_CGR) {
             const TO rn = (TO)((T)rin[q][h] - alpha * w);
-            out[idx] = rn;
+            st_stream<NT_P5_STORE_R>(out + idx, rn);
             acc[0] += (double)rn * (double)rn;
           } else {  // INV_RHS
             const T o = (T)scale * w;

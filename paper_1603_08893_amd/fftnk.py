@@ -28,7 +28,7 @@ EXPORTS = [
     "fftnk_solve_linear", "fftnk_describe", "fftnk_set_plan", "fftnk_autotune",
     "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_adjoint",
     "fftnk_launch_pass", "fftnk_profile_cg", "fftnk_get_history", "fftnk_set_history", "fftnk_get_state",
-    "fftnk_set_state", "fftnk_status_string", "fftnk_destroy",
+    "fftnk_set_state", "fftnk_status_string", "fftnk_destroy", "fftnk_stream",
 ]
 
 
@@ -101,6 +101,7 @@ def lib():
     L.fftnk_status_string.restype = ctypes.c_char_p
     L.fftnk_destroy.argtypes = [vp]
     L.fftnk_destroy.restype = None
+    L.fftnk_stream.argtypes = [i, i, vp, vp, vp, sz, i, vp, dp]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -138,6 +139,23 @@ def describe(dims, precision="fp64", gmres_restart=0, policy=0):
         return json.loads(buf.value.decode())
     finally:
         L.fftnk_destroy(ctx)
+
+
+STREAM_KINDS = {"read": 0, "write": 1, "copy": 2, "triad": 3}
+STREAM_MOVES = {"read": 1, "write": 1, "copy": 2, "triad": 3}  # arrays of `bytes` moved per launch
+
+
+def stream(kind, lane_bytes, dst, src1=None, src2=None, reps=20, stream=None):
+    """Mean ms per launch of a streaming kernel (fftnk_stream) over torch CUDA
+    buffers of equal size; returns (ms, GB/s)."""
+    import torch
+    nbytes = dst.numel() * dst.element_size()
+    st = stream if stream is not None else torch.cuda.current_stream(dst.device)
+    ms = ctypes.c_double(0.0)
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    _check(lib().fftnk_stream(STREAM_KINDS[kind], int(lane_bytes), ptr(dst), ptr(src1), ptr(src2), nbytes, int(reps),
+                              ctypes.c_void_p(st.cuda_stream), ctypes.byref(ms)), "fftnk_stream")
+    return ms.value, STREAM_MOVES[kind] * nbytes / (ms.value * 1e-3) / 1e9
 
 
 def _check(status, what):

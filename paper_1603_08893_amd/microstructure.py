@@ -21,6 +21,9 @@ Recipes (all numpy ``default_rng`` / PCG64 with the stated seeds):
   micrograph (Sec. 5, not available): a 2-D Gaussian random field with the same
   periodic filter, thresholded at a hard-phase fraction, as an n x n x 2 plane-
   strain cell (constant through the two a2 layers).
+* ``extend_by_one_pixel`` -- an odd grid turned into the next even one by one
+  more pixel along the given axes (the periodic image continued by its first
+  row), the odd/even comparison of the paper's appendix on even grids.
 * ``pure_shear_schedule`` -- the paper's 2-D load, Fbar = l e_x e_x + e_y e_y / l
   (+ e_z e_z), l in equal steps to l_max.
 """
@@ -75,6 +78,15 @@ def micrograph_2d(N=451, ell=6.0, frac=0.3, seed=1701, layers=2):
     ph = np.zeros(z.size, dtype=np.uint8)
     ph[order[:m]] = 1
     return np.repeat(ph.reshape(N, N)[:, :, None], layers, axis=2)
+
+
+def extend_by_one_pixel(ph, axes=(0, 1)):
+    """The phase map with one more pixel along each of `axes`: the periodic
+    image continued by its first row (index 0 repeated at index N)."""
+    out = np.asarray(ph)
+    for a in axes:
+        out = np.concatenate([out, np.take(out, [0], axis=a)], axis=a)
+    return np.ascontiguousarray(out)
 
 
 def pure_shear(lam):
