@@ -387,6 +387,27 @@ int fftnk_profile_cg(fftnk_ctx* ctx, int iters, double* ms_host);
  * write: bytes; copy: 2 bytes; triad: 3 bytes.  Synchronises the stream.
  * FFTNK_EINVAL on a bad kind, lane width, size, count or missing pointer.
  */
+/*
+ * The projection of fftnk_project without a context and without any
+ * allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels (G-hat zero at Nyquist frequencies, default FFT plan), with the
+ * spectrum and launch tables in one statically allocated device buffer of
+ * 64 MiB per GPU that the library holds until the process ends.  a_dev /
+ * Ga_dev: caller-owned device fields [9][n0][n1][n2] of double (FFTNK_FP64)
+ * or float (FFTNK_FP32_MIXED); hip_stream: a stream of the current device
+ * (NULL: its default stream).  Cells whose spectrum and tables exceed the
+ * buffer (e.g. FP64 beyond about 96^3, FP32 beyond about 120^3) return
+ * FFTNK_ENOMEM; lengths as in fftnk_create.  The first call on a device, and
+ * every call whose grid or precision differs from the previous call's on that
+ * device, uploads the tables and synchronises the stream; other calls only
+ * enqueue.  All calls on one GPU share its buffer: calls that overlap in time
+ * on one GPU (other streams, other host threads between enqueue and
+ * completion) race.  Not capturable while the tables are uploaded (the first
+ * call on a device, or a change of grid or precision).
+ */
+int fftnk_project_noalloc(int n0, int n1, int n2, int precision, const void* a_dev, void* Ga_dev, void* hip_stream);
+
 enum { FFTNK_STREAM_READ = 0, FFTNK_STREAM_WRITE = 1, FFTNK_STREAM_COPY = 2, FFTNK_STREAM_TRIAD = 3 };
 int fftnk_stream(int kind, int lane_bytes, void* dst, const void* src1, const void* src2, size_t bytes, int reps,
                  void* hip_stream, double* ms_host);

@@ -1901,3 +1901,128 @@ void fftnk_destroy(fftnk_ctx* c) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// G projection without a context and without any allocation: the spectrum and
+// the launch tables live in one file-scope device array per GPU.  Its host-side
+// name is not a device address; the address comes from hipGetSymbolAddress,
+// once per device, with that device current.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+constexpr int kNoAllocDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+struct NoAllocDevice {
+  char* ptr = nullptr;       // device address of this GPU's copy of `scratch`
+  fftnk_ctx* ctx = nullptr;  // host geometry of the cell whose tables the scratch holds
+  int key[4] = {0, 0, 0, -1};
+};
+std::mutex g_noalloc_mu;
+NoAllocDevice g_noalloc[kNoAllocDevices];
+
+// compact layout of the projection's buffers inside the scratch; returns the
+// bytes needed
+size_t noalloc_layout(fftnk_ctx* c) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  c->o_grids = take((size_t)c->nrve * sizeof(Grid));
+  c->o_starts = take(c->starts.size() * sizeof(int));
+  c->o_active = take((size_t)c->nrve * sizeof(int));
+  c->o_uni = take((size_t)c->nrve * 9 * sizeof(double));
+  c->o_tw64 = take((size_t)c->tw_total * 16);
+  c->o_tw32 = take((size_t)c->tw_total * 8);
+  c->o_part = take((size_t)NSLOT * c->pstride * 8);
+  c->o_spec = take((size_t)c->nspec * (c->prec == PREC_F64 ? 16 : 8));
+  // buffers the projection never touches (material, state, Nyquist side
+  // buffer: G-hat is zero at Nyquist frequencies here) point at offset 0
+  c->o_Ft = c->o_F = c->o_P = c->o_x = c->o_r = c->o_p = c->o_w = c->o_F32 = c->o_d64 = 0;
+  c->o_phase = c->o_mu = c->o_hist = c->o_hnew = c->o_mtab = c->o_cg = c->o_red = c->o_nyq = c->o_coef = 0;
+  c->o_gm = o;
+  c->total = o;
+  return o;
+}
+
+// tables of a newly planned cell into the scratch (the stream is synchronised:
+// the host tables are temporaries)
+int noalloc_upload(fftnk_ctx* c) {
+  std::vector<double> t64(2 * (size_t)c->tw_total);
+  std::vector<float> t32(2 * (size_t)c->tw_total);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (size_t i = 0; i < c->tw_len.size(); ++i) {
+    const int n = c->tw_len[i];
+    for (int e = 0; e < n; ++e) {
+      const double ang = -two_pi * (double)e / (double)n;
+      const size_t k = 2 * ((size_t)c->tw_off[i] + e);
+      t64[k] = std::cos(ang);
+      t64[k + 1] = std::sin(ang);
+      t32[k] = (float)t64[k];
+      t32[k + 1] = (float)t64[k + 1];
+    }
+  }
+  const int one = 1;
+  HIP_TRY(hipMemcpyAsync(c->ws + c->o_tw64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->o_tw32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->o_grids, c->g.data(), c->g.size() * sizeof(Grid), hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->o_starts, c->starts.data(), c->starts.size() * sizeof(int),
+                         hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->ws + c->o_active, &one, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return FFTNK_OK;
+}
+
+}  // namespace
+
+extern "C" int fftnk_project_noalloc(int n0, int n1, int n2, int precision, const void* a_dev, void* Ga_dev,
+                                     void* hip_stream) {
+  if (!a_dev || !Ga_dev) return FFTNK_EINVAL;
+  if (precision != FFTNK_FP64 && precision != FFTNK_FP32_MIXED) return FFTNK_EINVAL;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocDevices) return FFTNK_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  NoAllocDevice& d = g_noalloc[dev];
+  if (!d.ptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return FFTNK_EHIP;
+    d.ptr = static_cast<char*>(p);
+  }
+  const int key[4] = {n0, n1, n2, precision};
+  if (!d.ctx || !std::equal(key, key + 4, d.key)) {
+    // plan the new cell on the host first: a refused size leaves the
+    // scratch's current tables valid
+    fftnk_ctx* c = new (std::nothrow) fftnk_ctx();
+    if (!c) return FFTNK_EINVAL;
+    const int dims[3] = {n0, n1, n2};
+    int e = init_ctx(c, 1, dims, precision, hip_stream);
+    if (!e && noalloc_layout(c) > kNoAllocBytes) e = FFTNK_ENOMEM;
+    if (e) {
+      delete c;
+      return e;
+    }
+    c->ws = d.ptr;
+    if (d.ctx) delete d.ctx;
+    d.ctx = nullptr;
+    std::fill(d.key, d.key + 4, 0);
+    d.key[3] = -1;
+    if ((e = noalloc_upload(c)) != FFTNK_OK) {
+      delete c;
+      return e;
+    }
+    d.ctx = c;
+    std::copy(key, key + 4, d.key);
+  }
+  fftnk_ctx* c = d.ctx;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  const Launch L = c->launch();
+  launch_fwd_a2(c->prec, FWD_COPY, L, c->material(), a_dev, nullptr, nullptr, nullptr, nullptr, 1.0, c->spec(), nullptr);
+  middle_passes(c->prec, L, c->spec(), nullptr);
+  launch_inv_a2(c->prec, INV_OUT, L, c->spec(), Ga_dev, c->prec, nullptr, 1.0, nullptr);
+  return check_launch();
+}

@@ -29,6 +29,7 @@ EXPORTS = [
     "fftnk_set_linearization", "fftnk_apply_operator", "fftnk_project", "fftnk_constitutive", "fftnk_adjoint",
     "fftnk_launch_pass", "fftnk_profile_cg", "fftnk_get_history", "fftnk_set_history", "fftnk_get_state",
     "fftnk_set_state", "fftnk_status_string", "fftnk_destroy", "fftnk_stream",
+    "fftnk_project_noalloc",
 ]
 
 
@@ -102,6 +103,7 @@ def lib():
     L.fftnk_destroy.argtypes = [vp]
     L.fftnk_destroy.restype = None
     L.fftnk_stream.argtypes = [i, i, vp, vp, vp, sz, i, vp, dp]
+    L.fftnk_project_noalloc.argtypes = [i, i, i, i, vp, vp, vp]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -139,6 +141,19 @@ def describe(dims, precision="fp64", gmres_restart=0, policy=0):
         return json.loads(buf.value.decode())
     finally:
         L.fftnk_destroy(ctx)
+
+
+def project_noalloc(a, dims, out=None, stream=None):
+    """G(a) through fftnk_project_noalloc (no context, no allocation inside the
+    library): a, out torch CUDA tensors of 9 n0 n1 n2 doubles or floats."""
+    import torch
+    prec = FP64 if a.dtype == torch.float64 else FP32_MIXED
+    out = torch.empty_like(a) if out is None else out
+    st = stream if stream is not None else torch.cuda.current_stream(a.device)
+    _check(lib().fftnk_project_noalloc(int(dims[0]), int(dims[1]), int(dims[2]), prec, ctypes.c_void_p(a.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(st.cuda_stream)),
+           "fftnk_project_noalloc")
+    return out
 
 
 STREAM_KINDS = {"read": 0, "write": 1, "copy": 2, "triad": 3}
