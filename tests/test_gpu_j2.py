@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 from paper_1603_08893_amd import microstructure as ms
+from tests.fieldcheck import assert_fields_close
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +64,7 @@ def test_j2_constitutive_and_operator_parity(torch_cuda, orc):
         ref = orc.project(t)
         s.set_linearization(torch.from_numpy(F.reshape(-1)))
         got = s.apply_operator(torch.from_numpy(p.reshape(-1))).cpu().numpy()
-        assert _rel(got, ref) <= 1e-12
+        assert_fields_close(got, ref, 1e-12)
 
 
 @pytest.mark.parametrize("N", [15, 16])

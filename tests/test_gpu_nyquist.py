@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 from paper_1603_08893_amd import microstructure as ms
+from tests.fieldcheck import assert_fields_close
 
 pytestmark = pytest.mark.gpu
 
@@ -58,11 +59,11 @@ def test_project_identity_choice(torch_cuda, orc, shape, prec, tol):
     ref = orc.project(A, nyq_identity=True)
     s = _solver(shape, prec, np.zeros(shape, dtype=np.uint8))
     got = s.project(torch.from_numpy(A.reshape(-1))).double().cpu().numpy()
-    assert _rel(got, ref) <= tol
+    assert_fields_close(got, ref, tol)
     from paper_1603_08893_amd.fftnk import OPT_NYQUIST
     s.set_option(OPT_NYQUIST, 0)
     got0 = s.project(torch.from_numpy(A.reshape(-1))).double().cpu().numpy()
-    assert _rel(got0, orc.project(A)) <= tol
+    assert_fields_close(got0, orc.project(A), tol)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])
@@ -79,7 +80,7 @@ def test_apply_operator_identity_choice(torch_cuda, orc, shape, prec, tol):
     s = _solver(shape, prec, ph)
     s.set_linearization(torch.from_numpy(F.reshape(-1)))
     got = s.apply_operator(torch.from_numpy(p.reshape(-1))).double().cpu().numpy()
-    assert _rel(got, ref) <= tol
+    assert_fields_close(got, ref, tol)
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])
@@ -95,7 +96,7 @@ def test_project_identity_choice_batched(torch_cuda, orc, prec, tol):
     off = 0
     for d, f in zip(dims, fields):
         m = 9 * int(np.prod(d))
-        assert _rel(got[off:off + m], orc.project(f, nyq_identity=True)) <= tol, d
+        assert_fields_close(got[off:off + m], orc.project(f, nyq_identity=True), tol, d)
         off += m
 
 

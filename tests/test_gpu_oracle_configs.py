@@ -1,0 +1,230 @@
+"""The benchmark configurations at full size against the oracle's stored
+results (``tests/golden/oracle_*.json``, written by
+``tests/golden/make_oracle_configs.py``, which calls only the oracle).
+
+Each test regenerates the configuration's seeded inputs, checks their sha256
+against the stored digest, runs the GPU in the configuration's own launch set-up
+(the 128^3 cell as the benchmark times it, the 64 cells as one batched
+context, the adjoint's 8 load cases as one batched context) and compares:
+
+* FP64: equal numbers of linear solves per increment, CG iterations within +-2
+  per solve, P-bar within 1e-10 relative (largest component difference over
+  the largest component), and at the last increment F and P at 64 sample
+  voxels and the whole-field norms of F - I and P;
+* FP32-mixed: P-bar within 1e-5 relative of the FP64 oracle;
+* the adjoint: the adjoint CG's iteration count within +-2, dL/dmu at the 64
+  sample voxels and its norm.
+
+The paper's own example (Sec. 4.4: 31^3, gamma = 1) is among them: five
+solves, as the paper states.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1603_08893_amd import microstructure as ms
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TABLE = [(ms.K_SOFT, ms.MU_SOFT), (ms.K_HARD, ms.MU_HARD)]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _golden(name):
+    path = os.path.join(GOLD, "oracle_%s.json" % name)
+    if not os.path.exists(path):
+        pytest.skip("oracle results for %s not generated" % name)
+    return json.load(open(path))
+
+
+def _digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _relmax(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _check_increment(tag, prec, st, S, Pbar, rec):
+    assert st == 0 and rec["status"] == 0, (tag, st, rec["status"])
+    err = _relmax(Pbar, rec["Pbar"])
+    print("%s %s: solves %d / %d, cg %s / %s, P-bar rel err %.2e" % (
+        tag, prec, S["n_solves"], rec["n_solves"], S["cg_iters"], rec["cg_iters"], err), flush=True)
+    if prec == "fp64":
+        assert S["n_solves"] == rec["n_solves"], tag
+        assert all(abs(a - b) <= 2 for a, b in zip(S["cg_iters"], rec["cg_iters"])), tag
+        assert err <= 1e-10, tag
+    else:
+        assert err <= 1e-5, tag
+
+
+def _check_fields(tag, F, P, n, fin):
+    """F and P (device, [9 n] FP64) against the stored samples and norms."""
+    import torch
+    idx = torch.as_tensor(fin["sample_index"], device=F.device)
+    Fs = F.view(9, n)[:, idx].cpu().numpy().T
+    Ps = P.view(9, n)[:, idx].cpu().numpy().T
+    Fo, Po = np.array(fin["F_samples"]), np.array(fin["P_samples"])
+    eF = float(np.max(np.abs(Fs - Fo)))
+    eP = _relmax(Ps, Po)
+    Fm = F.view(9, n).clone()
+    Fm[0] -= 1.0
+    Fm[4] -= 1.0
+    Fm[8] -= 1.0
+    nF = abs(Fm.norm().item() - fin["norm_F_minus_I"]) / fin["norm_F_minus_I"]
+    nP = abs(P.norm().item() - fin["norm_P"]) / fin["norm_P"]
+    print("%s fields: F samples max abs err %.2e, P samples rel err %.2e, |F - I| %.2e, |P| %.2e" % (
+        tag, eF, eP, nF, nP), flush=True)
+    assert eF <= 1e-8 and eP <= 1e-6 and nF <= 1e-8 and nP <= 1e-8, tag
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_paper_example_gamma_one(torch_cuda, prec):
+    """Sec. 4.4: the 31^3 cubic inclusion under simple shear gamma = 1 takes
+    five solves (the paper's count); the GPU matches the oracle's run."""
+    from paper_1603_08893_amd.fftnk import Solver
+    g = _golden("e1")
+    N = 31
+    ph = ms.cubic_inclusion(N, 9)
+    assert _digest(ph) == g["phase_sha256"]
+    s = Solver((N, N, N), precision=prec)
+    s.set_phases(ph)
+    s.set_material(TABLE)
+    rec = g["increments"][0]
+    st, F, P, Pbar, S = s.solve_increment(ms.simple_shear(1.0))
+    _check_increment("e1", prec, st, S[0], Pbar[0], rec)
+    assert rec["n_solves"] == 5
+    if prec == "fp64":
+        assert S[0]["n_solves"] == 5
+        _check_fields("e1", F, P, N ** 3, g["final"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_benchmark_cell_all_increments(torch_cuda, prec):
+    """The 128^3 two-phase cell, all five increments of the isochoric stretch,
+    in the benchmark's launch configuration."""
+    from paper_1603_08893_amd.fftnk import Solver
+    g = _golden("c2")
+    N = 128
+    ph = ms.grf_threshold(N, ell=8.0, frac=0.3, seed=1603)
+    assert _digest(ph) == g["phase_sha256"]
+    s = Solver((N, N, N), precision=prec)
+    s.set_phases(ph)
+    s.set_material(TABLE)
+    sched = ms.c2_schedule(5)
+    F = P = None
+    for t, rec in enumerate(g["increments"]):
+        assert np.allclose(rec["Fbar"], sched[t], rtol=0, atol=0)
+        st, F, P, Pbar, S = s.solve_increment(sched[t])
+        _check_increment("c2 increment %d" % t, prec, st, S[0], Pbar[0], rec)
+    if prec == "fp64" and g.get("complete"):
+        _check_fields("c2", F, P, N ** 3, g["final"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_cells_one_per_size(torch_cuda, prec):
+    """The 64-cell batch as one context; the first cell of each size class
+    (32^3, 48^3, 64^3, 96^3) against the oracle's single-cell runs."""
+    torch = torch_cuda
+    from paper_1603_08893_amd.fftnk import Solver
+    g = _golden("c3")
+    print("c3 inputs", flush=True)
+    items = ms.c3_batch()
+    dims = [(it["N"],) * 3 for it in items]
+    ph = np.concatenate([(it["phase"].reshape(-1) + 2 * r).astype(np.uint8) for r, it in enumerate(items)])
+    s = Solver(dims, precision=prec)
+    s.set_phases(ph)
+    s.set_material([row for it in items for row in it["table"]])
+    st, F, P, Pbar, stats = s.solve_increment(np.array([it["Fbar"] for it in items]), raise_on_error=False)
+    offs = np.cumsum([0] + [9 * it["N"] ** 3 for it in items])
+    for cell in g["cells"]:
+        r = cell["index"]
+        assert _digest(items[r]["phase"]) == cell["phase_sha256"], r
+        assert np.array_equal(np.asarray(cell["Fbar"]), items[r]["Fbar"])
+        rec = cell["increments"][0]
+        _check_increment("c3 cell %d (%d^3)" % (r, items[r]["N"]), prec, stats[r]["status"], stats[r], Pbar[r], rec)
+        if prec == "fp64":
+            n = items[r]["N"] ** 3
+            _check_fields("c3 cell %d" % r, F[offs[r]:offs[r + 1]], P[offs[r]:offs[r + 1]], n, cell["final"])
+    del s
+    torch.cuda.empty_cache()
+
+
+def test_j2_increments(torch_cuda):
+    """Finite-strain J2 on the 96^3 sphere cell, the stored increments (through
+    yield of both phases)."""
+    from paper_1603_08893_amd.fftnk import J2, Solver
+    g = _golden("c4")
+    N = 96
+    ph, frac = ms.rsa_spheres(N, 0.25, seed=1604)
+    assert _digest(ph) == g["phase_sha256"]
+    s = Solver((N, N, N), precision="fp64")
+    s.set_phases(ph)
+    s.set_material(g["table"], model=J2)
+    sched = ms.c4_schedule(20, 0.1)
+    F = P = None
+    for t, rec in enumerate(g["increments"]):
+        st, F, P, Pbar, S = s.solve_increment(sched[t])
+        _check_increment("c4 increment %d" % t, "fp64", st, S[0], Pbar[0], rec)
+    if g.get("complete"):
+        _check_fields("c4", F, P, N ** 3, g["final"])
+        eps = s.get_history().view(7, -1)[6]
+        import torch
+        idx = torch.as_tensor(g["final"]["sample_index"], device=eps.device)
+        e = float(np.max(np.abs(eps[idx].cpu().numpy() - np.array(g["final"]["eps_p_samples"]))))
+        print("c4 eps_p samples max abs err %.2e" % e, flush=True)
+        assert e <= 1e-8
+
+
+def test_adjoint_load_case(torch_cuda):
+    """The adjoint configuration: 8 load cases on the 192^3 log-normal modulus
+    field as one batched context; case 0's forward solve and its adjoint (the
+    oracle's cotangent 2 (P-bar - P-bar_target)) against the oracle."""
+    torch = torch_cuda
+    from paper_1603_08893_amd.fftnk import Solver
+    g = _golden("c5")
+    if "adjoint" not in g:
+        pytest.skip("oracle adjoint for the 192^3 case not finished")
+    N = 192
+    n = N ** 3
+    print("c5 inputs", flush=True)
+    mu = ms.lognormal_field(N, 0.5, 8.0, seed=1605)
+    assert _digest(mu) == g["mu_sha256"]
+    cases = np.array(ms.c5_load_cases(0.05))
+    assert np.array_equal(cases[g["load_case"]], np.asarray(g["Fbar"]))
+    s = Solver([(N,) * 3] * len(cases), precision="fp64")
+    s.set_phases(np.zeros(len(cases) * n, dtype=np.uint8))
+    s.set_material([(ms.K_SOFT, ms.MU_SOFT)])
+    s.set_modulus_field(torch.from_numpy(mu.reshape(-1)).cuda().repeat(len(cases)))
+    del mu
+    st, F, P, Pbar, stats = s.solve_increment(cases)
+    c = g["load_case"]
+    _check_increment("c5 forward", "fp64", stats[c]["status"], stats[c], Pbar[c], g["forward"])
+    _check_fields("c5 forward", F[9 * n * c:9 * n * (c + 1)], P[9 * n * c:9 * n * (c + 1)], n, g["forward"]["final"])
+    del F, P
+    gbar = np.zeros((len(cases), 9))
+    gbar[c] = g["adjoint"]["gbar"]
+    dmu, _, astats = s.adjoint(gbar)
+    d = dmu.view(len(cases), n)[c]
+    adj = g["adjoint"]
+    idx = torch.as_tensor(adj["sample_index"], device=d.device)
+    eS = float(np.max(np.abs(d[idx].cpu().numpy() - np.array(adj["dLdmu_samples"])))) / adj["dLdmu_absmax"]
+    eN = abs(d.norm().item() - adj["dLdmu_norm"]) / adj["dLdmu_norm"]
+    print("c5 adjoint: cg %d / %d, dL/dmu samples err %.2e (of max), norm err %.2e" % (
+        astats[c]["cg_iters"][0], adj["cg_iters"], eS, eN), flush=True)
+    assert abs(astats[c]["cg_iters"][0] - adj["cg_iters"]) <= 2
+    assert eS <= 1e-6 and eN <= 1e-7
+    # the other cases had a zero cotangent: no adjoint work, zero gradient
+    assert float(dmu.view(len(cases), n)[[k for k in range(len(cases)) if k != c]].abs().max()) == 0.0

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 from paper_1603_08893_amd import microstructure as ms
+from tests.fieldcheck import assert_fields_close
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +43,7 @@ def test_project_long_axes(torch_cuda, orc, shape, prec, tol):
     s.set_phases(np.zeros(shape, dtype=np.uint8))
     s.set_material([(1.0, 1.0)])
     got = s.project(torch.from_numpy(A.reshape(-1))).double().cpu().numpy()
-    assert _rel(got, orc.project(A)) <= tol
+    assert_fields_close(got, orc.project(A), tol)
 
 
 def _j2_inputs(ph):

@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 from paper_1603_08893_amd import microstructure as ms
+from tests.fieldcheck import assert_fields_close
 
 pytestmark = pytest.mark.gpu
 
@@ -84,8 +85,8 @@ def test_every_policy_matches_oracle(torch_cuda, orc, dims, prec, tol):
         G = s.project(A).double().cpu().numpy()
         Ap = s.apply_operator(A).double().cpu().numpy()
         for r in range(len(dims)):
-            assert _rel(G[offs[r]:offs[r + 1]], refG[r]) <= tol, (pol, r)
-            assert _rel(Ap[offs[r]:offs[r + 1]], refA[r]) <= tol, (pol, r)
+            assert_fields_close(G[offs[r]:offs[r + 1]], refG[r], tol, (pol, r))
+            assert_fields_close(Ap[offs[r]:offs[r + 1]], refA[r], tol, (pol, r))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
