@@ -16,9 +16,12 @@ the timed steps.  Besides that line's fields the JSON carries one CG
 iteration kernel by kernel (stream events around every launch; `roofline`
 is its slowest kernel, with the hardware-counter traffic recorded for these
 kernel sources under profiles/ when it matches), the operator alone
-(back-to-back applications) pass by pass, a plain 1 GiB device copy for
-reference, the FP32-mixed solve of the same increments, and the CPU oracle's
-rate.
+(back-to-back applications) pass by pass, the achievable streaming rate of
+the device measured with the library's own read / write / copy / triad
+kernels (every fraction is also given against it), the operator and CG
+iteration at 192^3 (spectra beyond the last-level cache), the FP32-mixed solve
+of the same increments, P-bar against the oracle's stored run of the same
+cell, and the CPU oracle's rate (one pinned core, -O3 -march=native build).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -108,6 +111,89 @@ def recorded_traffic(kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def cg_kernel_rows(ms_by_kernel, bytes_per_voxel, n, ceiling=None):
+    """Per-kernel rows of one CG iteration: ms, algorithmic bytes per voxel,
+    GB/s, fraction of the 8 TB/s peak and of the measured streaming ceiling."""
+    rows = {}
+    for k, t in ms_by_kernel.items():
+        row = {"ms": round(t, 5), "bytes_per_voxel": round(bytes_per_voxel[k], 3)}
+        if bytes_per_voxel[k] > 0:
+            gbs = bytes_per_voxel[k] * n / (t * 1e-3) / 1e9
+            row.update({"GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+            if ceiling:
+                row["frac_of_ceiling"] = round(gbs / ceiling, 4)
+        rows[k] = row
+    return rows
+
+
+def stream_ceiling(torch, dev, gib=2, reps=10):
+    """The achievable HBM streaming rate, measured with the library's own
+    stream kernels (fftnk_stream, 8-byte lanes) on arrays of `gib` GiB: read,
+    write, copy, triad, with normal and with non-temporal accesses; the
+    ceiling for kernels that read and write is the best copy or triad."""
+    from paper_1603_08893_amd.fftnk import stream
+    nb = gib << 30
+    a = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+    b = torch.ones_like(a)
+    c = torch.ones_like(a)
+    out = {"bytes_per_array": nb, "lane_bytes": 8, "kernels": "fftnk_stream (k_stream_*<double, nt>)"}
+    for nt in (False, True):
+        for kind in ("read", "write", "copy", "triad"):
+            _, gbs = stream(kind, 8, c if kind == "read" else a, b, c, reps=reps, nontemporal=nt)
+            out[kind + ("_nt" if nt else "") + "_GB_s"] = round(gbs, 1)
+    out["ceiling_GB_s"] = max(out["copy_GB_s"], out["triad_GB_s"], out["copy_nt_GB_s"], out["triad_nt_GB_s"])
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
+def oracle_pbars(name):
+    """P-bar per increment of the oracle's stored run of a configuration
+    (tests/golden/oracle_<name>.json), or [] when absent."""
+    try:
+        d = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_%s.json" % name)))
+    except (OSError, ValueError):
+        return [], {}
+    return [np.asarray(r["Pbar"]) for r in d.get("increments", []) if r.get("status") == 0], d
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
+
+
+def cpu_baseline_leg(budget=20.0):
+    """The oracle timed on one pinned host core, built -O3 -march=native on this
+    host, in a child process (python -m oracle.timing); with the time of a
+    whole increment of the benchmark cell extrapolated from the oracle's own
+    operator counts."""
+    import subprocess
+    res = subprocess.run([sys.executable, "-m", "oracle.timing", "--grid", str(N), "--budget", str(budget),
+                          "--max-reps", "5"], cwd=ROOT, capture_output=True, text=True, timeout=600)
+    lines = [l for l in res.stdout.splitlines() if l.startswith("{")]
+    if res.returncode != 0 or not lines:
+        sys.stderr.write(res.stdout[-2000:] + res.stderr[-2000:])
+        return None
+    t = json.loads(lines[-1])
+    spm = t["sec_per_matvec"]
+    out = {"value": round(1.0 / spm, 4), "unit": "matvec/s", "cores": t["threads"], "kind": "oracle",
+           "sample": "%d projected-tangent operator applications on the 128^3 two-phase cell (FP64, F = I + "
+                     "U(-0.01, 0.01)) on one pinned host core, %.1f s; oracle built %s on this host" % (
+                         t["reps"], sum(t["seconds"]), t["flags"]),
+           "cpu_model": t["cpu_model"], "host_cpus": t["host_cpus"], "pinned_core": t["core"]}
+    _, gold = oracle_pbars("c2")
+    incs = gold.get("increments", []) if gold else []
+    if incs:
+        # an increment costs its CG iterations plus one operator-sized right-hand
+        # side per linear solve (the boundary-condition one included)
+        ops = [sum(r["cg_iters"]) + r["n_solves"] for r in incs]
+        out["increment_seconds_extrapolated"] = [round(o * spm, 1) for o in ops]
+        out["extrapolation"] = ("timed operator applications x (CG iterations + right-hand sides) of the oracle's "
+                                "own run of each increment")
+        out["increment_seconds_build_host"] = [r["seconds"] for r in incs]
+        out["build_host_note"] = "the same oracle (-O2 build) measured whole on another machine's core"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +202,7 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-192", action="store_true", help="skip the 192^3 operator and CG-iteration rows")
     ap.add_argument("--operator-only", action="store_true",
                     help="profiling mode: only the operator passes at a synthetic linearisation point, plus one "
                          "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
@@ -192,13 +279,6 @@ def main():
     n = N ** 3
     cgk = s64.profile_cg(20)
     cgb = cg_bytes_per_voxel(8, N)
-    cg_rows = {}
-    for k, t in cgk.items():
-        row = {"ms": round(t, 5), "bytes_per_voxel": round(cgb[k], 3)}
-        if cgb[k] > 0:
-            gbs = cgb[k] * n / (t * 1e-3) / 1e9
-            row.update({"GB_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
-        cg_rows[k] = row
     cg_iter_ms = sum(cgk.values())
     dom = max(cgk, key=lambda k: cgk[k])
     achieved = cgb[dom] * n / (cgk[dom] * 1e-3) / 1e9
@@ -262,6 +342,7 @@ def main():
         torch.cuda.synchronize()
         sec32 = e0.elapsed_time(e1) / 1e3
         err = max(float(np.max(np.abs(a - b)) / np.max(np.abs(b))) for a, b in zip(pbars32, pbars64))
+        cgk32 = s32.profile_cg(20)
         t_mv32, passes32 = operator_bench(s32, args.matvec_reps)
         bpv32 = pass_bytes_per_voxel(4, N)
         fp32 = {
@@ -276,42 +357,78 @@ def main():
             "passes_ms": {k: round(v, 5) for k, v in passes32.items()},
             "pbar_rel_diff_vs_fp64_gpu": err,
             "speedup_vs_fp64": round((min(args.steps, 5) / sec32) / (args.steps / sec), 3),
+            "cg_iteration_kernels": cgk32,
         }
+        pbars32_all = pbars32
         del s32
 
-    # ------------------------------------------------------------ reference: a plain 1 GiB device copy
-    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
-    b = torch.empty_like(a)
-    a.fill_(1.0)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_ref = {"ms": round(e0.elapsed_time(e1), 4),
-                "GB_s": round(2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)}
-    del a, b
+    # ------------------------------------------------------------ the achievable streaming rate (own kernels)
+    ceil = stream_ceiling(torch, dev)
+    ceiling = ceil["ceiling_GB_s"]
+    print("# stream ceiling %s" % ceil, file=sys.stderr, flush=True)
+    for row in pass_rows.values():
+        row["frac_of_ceiling"] = round(row["GB_s"] / ceiling, 4)
+    if fp32 is not None:
+        cb32 = cg_bytes_per_voxel(4, N)
+        rows32 = cg_kernel_rows(fp32.pop("cg_iteration_kernels"), cb32, n, ceiling)
+        d32 = max((k for k in rows32 if cb32[k] > 0), key=lambda k: rows32[k]["ms"])
+        fp32["cg_iteration"] = {"ms": round(sum(r["ms"] for r in rows32.values()), 4),
+                                "bytes_per_voxel": round(sum(cb32.values()), 2), "kernels": rows32}
+        fp32["roofline"] = {"bound": "hbm", "kernel": KERNEL_NAMES[d32].replace("double", "float"),
+                            "achieved": rows32[d32]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": rows32[d32]["frac"], "frac_of_ceiling": rows32[d32]["frac_of_ceiling"],
+                            "traffic": recorded_traffic(KERNEL_NAMES[d32].replace("double", "float")),
+                            "algorithmic_bytes_per_launch": int(round(cb32[d32] * n)), "launch_ms": rows32[d32]["ms"]}
+
+    # ------------------------------------------------------------ 192^3: spectra beyond the last-level cache
+    big = {}
+    if not args.no_192:
+        N2 = 192
+        ph2 = ms.grf_threshold(N2, ell=8.0, frac=0.3, seed=1603)
+        for prec, pb in (("fp64", 8), ("fp32", 4)):
+            s = Solver((N2,) * 3, precision=prec)
+            s.set_phases(ph2)
+            s.set_material(TABLE)
+            s.solve_increment(sched[0], 1e-5, 1e-8, fields=False)
+            k = s.profile_cg(10)
+            cb = cg_bytes_per_voxel(pb, N2)
+            it_ms = sum(k.values())
+            s.set_linearization(s.get_state())
+            p = s.project(torch.from_numpy(ms.random_field((N2,) * 3, seed=42).reshape(-1)).to(dev))
+            out = s.field()
+            for _ in range(3):
+                s.apply_operator(p, out)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                s.apply_operator(p, out)
+            e1.record()
+            torch.cuda.synchronize()
+            t_op = e0.elapsed_time(e1) / 20
+            ob = sum(pass_bytes_per_voxel(pb, N2).values()) * N2 ** 3
+            big[prec] = {"operator_ms": round(t_op, 4), "operator_GB_s": round(ob / (t_op * 1e-3) / 1e9, 1),
+                         "operator_frac": round(ob / (t_op * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "operator_frac_of_ceiling": round(ob / (t_op * 1e-3) / 1e9 / ceiling, 4),
+                         "cg_iteration_ms": round(it_ms, 4),
+                         "cg_iteration_GB_s": round(sum(cb.values()) * N2 ** 3 / (it_ms * 1e-3) / 1e9, 1),
+                         "cg_kernels": cg_kernel_rows(k, cb, N2 ** 3, ceiling)}
+            del s, p, out
+            torch.cuda.empty_cache()
+        print("# 192^3: %s" % {k: (v["operator_ms"], v["cg_iteration_ms"]) for k, v in big.items()}, file=sys.stderr,
+              flush=True)
 
     # ------------------------------------------------------------ CPU oracle on a bounded sample
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        oracle.build()
-        K, mu = ms.phase_moduli(phase, TABLE)
-        F_np = F_lin.view(9, N, N, N).cpu().numpy()
-        p_np = ms.random_field((N, N, N), seed=42)
-        reps, t_cpu = 0, 0.0
-        while reps < 3 and t_cpu < 20.0:
-            c0 = time.perf_counter()
-            oracle.apply_operator(F_np, K, mu, p_np)
-            t_cpu += time.perf_counter() - c0
-            reps += 1
-        cpu = {"value": round(reps / t_cpu, 4), "unit": "matvec/s", "cores": 1, "kind": "oracle",
-               "sample": "%d projected-tangent operator applications at 128^3 (FP64, the benchmark cell's linearisation point) on one "
-                         "host core, %.1f s" % (reps, t_cpu)}
+    cpu = None if args.no_cpu_baseline else cpu_baseline_leg()
+
+    # ------------------------------------------------------------ P-bar against the oracle's run of the same cell
+    gold, _ = oracle_pbars("c2")
+    vs_oracle = None
+    if gold:
+        m = min(len(gold), args.steps, 5)
+        vs_oracle = {"increments_compared": m,
+                     "fp64": max(rel_err(pbars64[t], gold[t]) for t in range(m))}
+        if fp32 is not None:
+            vs_oracle["fp32_mixed"] = max(rel_err(pbars32_all[t], gold[t]) for t in range(min(m, len(pbars32_all))))
 
     line = {
         "metric": "projected-tangent matvecs/s at 128^3 (FP64 Newton-Krylov solve)",
@@ -338,6 +455,9 @@ def main():
                      "bytes_5pass_per_voxel": round(sum(bpv64.values()), 2),
                      "GB_s": round(mv_bytes64 / (t_mv64 * 1e-3) / 1e9, 1),
                      "frac_of_hbm_peak": round(mv_bytes64 / (t_mv64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "frac_of_ceiling": round(mv_bytes64 / (t_mv64 * 1e-3) / 1e9 / ceiling, 4),
+                     "cache_note": "at 128^3 the FP64 half spectrum (153 MB) fits the 256 MB last-level cache: "
+                                   "passes 2-4 are cache-assisted; grid_192 holds the HBM-bound rates",
                      # the same time over the 3-kernel lower-bound bytes
                      "bytes_3kernel_per_voxel": round(three_kernel_bytes_per_voxel(8, N), 2),
                      "effective_frac": round(three_kernel_bytes_per_voxel(8, N) * n / (t_mv64 * 1e-3) / 1e9
@@ -346,10 +466,14 @@ def main():
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(KERNEL_NAMES[dom]),
-                     "algorithmic_bytes_per_launch": int(round(cgb[dom] * n)), "launch_ms": round(cgk[dom], 5)},
+                     "algorithmic_bytes_per_launch": int(round(cgb[dom] * n)), "launch_ms": round(cgk[dom], 5),
+                     "ceiling_GB_s": ceiling, "frac_of_ceiling": round(achieved / ceiling, 4)},
         "cg_iteration": {"ms": round(cg_iter_ms, 4), "bytes_per_voxel": round(sum(cgb.values()), 2),
-                         "GB_s": round(sum(cgb.values()) * n / (cg_iter_ms * 1e-3) / 1e9, 1), "kernels": cg_rows},
-        "copy_1GiB": copy_ref,
+                         "GB_s": round(sum(cgb.values()) * n / (cg_iter_ms * 1e-3) / 1e9, 1),
+                         "kernels": cg_kernel_rows(cgk, cgb, n, ceiling)},
+        "stream_ceiling": ceil,
+        "grid_192": big,
+        "pbar_rel_err_vs_oracle": vs_oracle,
         "fp32_mixed": fp32,
         "cpu_baseline": cpu,
     }
@@ -357,7 +481,8 @@ def main():
 
 
 def operator_only(args):
-    """Operator passes alone at F = I + G(0.01 U(-1,1)) on the 128^3 two-phase cell, then a 1 GiB copy."""
+    """Operator passes alone at F = I + G(0.01 U(-1,1)) on the 128^3 two-phase cell, then the library's own
+    1 GiB copy kernel (the reference that scales memory counters)."""
     import torch
     from paper_1603_08893_amd import microstructure as ms
     from paper_1603_08893_amd.fftnk import Solver
@@ -387,18 +512,12 @@ def operator_only(args):
         e1.record()
         torch.cuda.synchronize()
         res["pass%d_ms" % k] = round(e0.elapsed_time(e1) / args.matvec_reps, 5)
-    a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+    from paper_1603_08893_amd.fftnk import stream
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
     b = torch.empty_like(a)
-    a.fill_(1.0)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    e0.record()
-    b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    res["copy_1GiB_ms"] = round(e0.elapsed_time(e1), 4)
-    res["copy_GB_s"] = round(2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    ms_copy, gbs = stream("copy", 8, b, a, reps=3)  # k_stream_copy<double>: 2^30 bytes read and written per launch
+    res["copy_1GiB_ms"] = round(ms_copy, 4)
+    res["copy_GB_s"] = round(gbs, 1)
     print(json.dumps({"operator_only": res, "precision": args.precision}), flush=True)
 
 

@@ -378,7 +378,8 @@ int fftnk_profile_cg(fftnk_ctx* ctx, int iters, double* ms_host);
  * transforms as the cost, and on this device they are bound by memory).
  * kind: FFTNK_STREAM_READ (sum of src1, one partial per work-group written to
  * the first doubles of dst), _WRITE (fill dst), _COPY (dst = src1), _TRIAD
- * (dst = src1 + 0.5 src2); lane_bytes 8 or 16 (double or double2 accesses).
+ * (dst = src1 + 0.5 src2); lane_bytes 8 or 16 (double or double2 accesses);
+ * kind | FFTNK_STREAM_NONTEMPORAL: every load and store non-temporal.
  * dst, src1, src2: caller-owned device buffers of `bytes` bytes each (src1 /
  * src2 may be NULL where the kind does not read them); bytes a multiple of
  * lane_bytes.  One untimed launch, then `reps` (1..10000) back-to-back
@@ -408,7 +409,8 @@ int fftnk_profile_cg(fftnk_ctx* ctx, int iters, double* ms_host);
  */
 int fftnk_project_noalloc(int n0, int n1, int n2, int precision, const void* a_dev, void* Ga_dev, void* hip_stream);
 
-enum { FFTNK_STREAM_READ = 0, FFTNK_STREAM_WRITE = 1, FFTNK_STREAM_COPY = 2, FFTNK_STREAM_TRIAD = 3 };
+enum { FFTNK_STREAM_READ = 0, FFTNK_STREAM_WRITE = 1, FFTNK_STREAM_COPY = 2, FFTNK_STREAM_TRIAD = 3,
+       FFTNK_STREAM_NONTEMPORAL = 16 };
 int fftnk_stream(int kind, int lane_bytes, void* dst, const void* src1, const void* src2, size_t bytes, int reps,
                  void* hip_stream, double* ms_host);
 

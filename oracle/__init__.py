@@ -45,25 +45,39 @@ class Stats(ctypes.Structure):
         }
 
 
-def build(force=False):
-    """Compile the oracle with g++ (no GPU code, no shared sources)."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["g++", "-O2", "-fcx-limited-range", "-std=c++17", "-fPIC", "-shared", "-o", tmp, _SRC])
-    os.replace(tmp, _LIB)
-    return _LIB
+FLAGS = ["-O2", "-fcx-limited-range"]
+TIMED_FLAGS = ["-O3", "-march=native", "-fcx-limited-range"]  # the build the CPU baseline is timed with
+
+
+def build(force=False, path=None, flags=None):
+    """Compile the oracle with g++ (no GPU code, no shared sources): the test
+    build in-tree, or with `flags` to `path` (e.g. the timed build)."""
+    out = path or _LIB
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(_SRC):
+        return out
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["g++"] + (flags or FLAGS) + ["-std=c++17", "-fPIC", "-shared", "-o", tmp, _SRC])
+    os.replace(tmp, out)
+    return out
 
 
 _lib = None
+_lib_path = _LIB
+
+
+def use_library(path):
+    """Load the oracle from another build of the same source (before any call)."""
+    global _lib, _lib_path
+    _lib_path = path
+    _lib = None
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if _lib_path == _LIB and not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(_lib_path)
         dp = ctypes.POINTER(ctypes.c_double)
         i = ctypes.c_int
         L.orc_fft1d.argtypes = [dp, i, i]

@@ -995,7 +995,7 @@ int newton_solve(fftnk_ctx* c, const double* Fbar, const std::vector<int>& run, 
     // are laid out by the launch tables of that mask)
     const void* dF = newton_update_source(c);  // FP64 in both precisions
     launch_newton_update(PREC_F64, c->launch(), mat, c->F(), dF, c->P(), c->F32(), it == 0);
-    e = reduce_fetch(c, {{K_VOX, {SLOT_DF, 1}}, {K_VOX, {SLOT_PBAR, 9}}});
+    e = reduce_fetch(c, {{K_VOX, {SLOT_DF, 1}}, {K_VOX, {SLOT_PBAR, 9}}, {K_VOX, {SLOT_FAIL, 1}}});
     if (e) return e;
     for (int r = 0; r < nr; ++r) {
       if (done[r]) continue;
@@ -1006,7 +1006,10 @@ int newton_solve(fftnk_ctx* c, const double* Fbar, const std::vector<int>& run, 
         pbar[9 * r + k] = red_at(c, r, SLOT_PBAR + k) / (double)c->g[r].n;
         finite = finite && std::isfinite(pbar[9 * r + k]);
       }
-      if (!finite) {
+      if (red_at(c, r, SLOT_FAIL) > 0.0) {  // the return mapping failed somewhere (e.g. det F <= 0)
+        status[r] = FFTNK_EMATERIAL;
+        done[r] = 1;
+      } else if (!finite) {
         status[r] = FFTNK_ENONFINITE;
         done[r] = 1;
       } else if (res < eta_nw && it > 0) {

@@ -102,7 +102,8 @@ enum {
   SLOT_FF = 5,    // ||F_t + dFbar||^2
   SLOT_PBAR = 6,  // 9 slots: sum of P
   SLOT_FBAR = 15, // 9 slots: sum of F
-  SLOT_AUX = 24,  // 2 spare slots
+  SLOT_AUX = 24,  // spare slot (GMRES: ||w||^2)
+  SLOT_FAIL = 25, // voxels whose constitutive update failed (Newton update)
   SLOT_DOT = 26,  // kGmDot slots: GMRES inner products <w, v_i>
   NSLOT = 42
 };

@@ -204,13 +204,16 @@ __global__ __launch_bounds__(kThreads) void k_set_F(Batch B, const double* Ft, d
 }
 
 // Stress of the voxel's material law at F; J2 also writes the history of the
-// return from the committed state (hnew may be null).  NaN on failure.
+// return from the committed state (hnew may be null).  Returns false (and NaN
+// stress) where the update is undefined (J2: det F <= 0 or a non-positive
+// trial eigenvalue).
 template <int LAW>
-__device__ __forceinline__ void stress_at(const Material& mat, long long gv, const double* f, double* Pv, bool hnew) {
+__device__ __forceinline__ bool stress_at(const Material& mat, long long gv, const double* f, double* Pv, bool hnew) {
   if constexpr (LAW == MODEL_J2) {
     double K, mu, ty0, H, h[7], hn[7];
     j2_point_data(mat, gv, K, mu, ty0, H, h);
-    if (!j2_stress(f, h, K, mu, ty0, H, Pv, hn)) {
+    const bool ok = j2_stress(f, h, K, mu, ty0, H, Pv, hn);
+    if (!ok) {
 #pragma unroll
       for (int c = 0; c < 9; ++c) Pv[c] = __builtin_nan("");
 #pragma unroll
@@ -219,16 +222,19 @@ __device__ __forceinline__ void stress_at(const Material& mat, long long gv, con
     if (hnew)
 #pragma unroll
       for (int k = 0; k < 7; ++k) mat.hist_new[k * mat.ntot + gv] = hn[k];
+    return ok;
   } else {
     double lam, mu, S[9];
     material_at(mat, gv, lam, mu);
     svk_S<double>(f, lam, mu, S);
     mat33<double>(f, S, Pv);
+    return true;
   }
 }
 
 // F += dF (+ dFbar on the first iteration), constitutive update P = P(F),
-// ||dF||^2 and the sums of P; the next linearisation point in FP32.
+// ||dF||^2, the sums of P and the count of voxels whose update failed; the
+// next linearisation point in FP32.
 template <typename T, int LAW>
 __global__ __launch_bounds__(kThreads) void k_newton_update(Batch B, Material mat, double* __restrict__ F,
                                                             const T* __restrict__ x, double* __restrict__ P,
@@ -242,9 +248,9 @@ __global__ __launch_bounds__(kThreads) void k_newton_update(Batch B, Material ma
   double u[9];
 #pragma unroll
   for (int c = 0; c < 9; ++c) u[c] = add_uni ? B.uni[9 * rv + c] : 0.0;
-  double acc[10];
+  double acc[11];
 #pragma unroll
-  for (int k = 0; k < 10; ++k) acc[k] = 0.0;
+  for (int k = 0; k < 11; ++k) acc[k] = 0.0;
   FOR_RVE_RANGE(v, n, local, nb) {
     double f[9], Pv[9];
 #pragma unroll
@@ -255,18 +261,19 @@ __global__ __launch_bounds__(kThreads) void k_newton_update(Batch B, Material ma
       acc[0] += d * d;
       if (Flin32) Flin32[off + c * n + v] = (float)f[c];
     }
-    stress_at<LAW>(mat, g.vox_off + v, f, Pv, true);
+    if (!stress_at<LAW>(mat, g.vox_off + v, f, Pv, true)) acc[10] += 1.0;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       P[off + c * n + v] = Pv[c];
       acc[1 + c] += Pv[c];
     }
   }
-  double res[10];
-  block_sums<10>(acc, res);
+  double res[11];
+  block_sums<11>(acc, res);
   if (threadIdx.x == 0) {
     pslot(B, SLOT_DF)[blockIdx.x] = res[0];
     for (int c = 0; c < 9; ++c) pslot(B, SLOT_PBAR + c)[blockIdx.x] = res[1 + c];
+    pslot(B, SLOT_FAIL)[blockIdx.x] = res[10];
   }
 }
 

@@ -160,7 +160,7 @@ STREAM_KINDS = {"read": 0, "write": 1, "copy": 2, "triad": 3}
 STREAM_MOVES = {"read": 1, "write": 1, "copy": 2, "triad": 3}  # arrays of `bytes` moved per launch
 
 
-def stream(kind, lane_bytes, dst, src1=None, src2=None, reps=20, stream=None):
+def stream(kind, lane_bytes, dst, src1=None, src2=None, reps=20, stream=None, nontemporal=False):
     """Mean ms per launch of a streaming kernel (fftnk_stream) over torch CUDA
     buffers of equal size; returns (ms, GB/s)."""
     import torch
@@ -168,7 +168,7 @@ def stream(kind, lane_bytes, dst, src1=None, src2=None, reps=20, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream(dst.device)
     ms = ctypes.c_double(0.0)
     ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
-    _check(lib().fftnk_stream(STREAM_KINDS[kind], int(lane_bytes), ptr(dst), ptr(src1), ptr(src2), nbytes, int(reps),
+    _check(lib().fftnk_stream(STREAM_KINDS[kind] | (16 if nontemporal else 0), int(lane_bytes), ptr(dst), ptr(src1), ptr(src2), nbytes, int(reps),
                               ctypes.c_void_p(st.cuda_stream), ctypes.byref(ms)), "fftnk_stream")
     return ms.value, STREAM_MOVES[kind] * nbytes / (ms.value * 1e-3) / 1e9
 
@@ -218,6 +218,9 @@ class Solver:
         aligned = (base + 255) // 256 * 256
         _check(L.fftnk_bind_workspace(ctx, ctypes.c_void_p(aligned), nbytes), "fftnk_bind_workspace")
         self.workspace_bytes = nbytes
+        # bumped by every call that changes the committed state, the phases or
+        # the moduli (what fftnk_adjoint differentiates at)
+        self.generation = 0
 
     def __del__(self):
         if getattr(self, "ctx", None) is not None and _lib is not None:
@@ -229,6 +232,7 @@ class Solver:
         return self.torch.empty(9 * self.ntot, dtype=dtype or self.vdtype, device=self.device)
 
     def set_phases(self, phase):
+        self.generation += 1
         ph = np.ascontiguousarray(phase, dtype=np.uint8).reshape(-1)
         if ph.size != self.ntot:
             raise FftnkError(EINVAL, "set_phases: %d values for %d voxels" % (ph.size, self.ntot))
@@ -240,6 +244,7 @@ class Solver:
         _check(lib().fftnk_set_phases(self.ctx, ctypes.c_void_p(t.data_ptr())), "fftnk_set_phases")
 
     def set_material(self, table, model=SVK):
+        self.generation += 1
         tab = np.ascontiguousarray(table, dtype=np.float64)
         if getattr(self, "_max_phase", None) is not None and self._max_phase >= tab.shape[0]:
             raise FftnkError(EINVAL, "set_material: fewer phases than the phase map uses")
@@ -247,6 +252,7 @@ class Solver:
         _check(lib().fftnk_set_material(self.ctx, model, tab.shape[0], _dptr(tab)), "fftnk_set_material")
 
     def set_modulus_field(self, mu):
+        self.generation += 1
         if mu is None:
             _check(lib().fftnk_set_modulus_field(self.ctx, None), "fftnk_set_modulus_field")
             return
@@ -291,12 +297,14 @@ class Solver:
                "fftnk_set_krylov")
 
     def reset_state(self):
+        self.generation += 1
         _check(lib().fftnk_reset_state(self.ctx), "fftnk_reset_state")
 
     # ------------------------------------------------------------ solve
     def solve_increment(self, Fbar, eta_nw=1e-5, eta_cg=1e-8, max_newton=50, max_cg=10000, fields=True,
                         raise_on_error=True):
         """One load increment.  Returns (status, F, P, Pbar[nrve, 9], stats list)."""
+        self.generation += 1
         Fb = np.ascontiguousarray(np.asarray(Fbar, dtype=np.float64).reshape(self.nrve, 9))
         Pbar = np.zeros((self.nrve, 9))
         stats = (Stats * self.nrve)()
@@ -317,6 +325,7 @@ class Solver:
         Ptarget, Fbar: [9] or [nrve, 9].
 
         Returns (status, F, P, Pbar[nrve, 9], Fbar[nrve, 9], stats list, outer[nrve])."""
+        self.generation += 1
         Fb = np.array(np.broadcast_to(np.asarray(Fbar, dtype=np.float64).reshape(-1, 9), (self.nrve, 9)),
                       dtype=np.float64, order="C")
         Pt = np.ascontiguousarray(np.broadcast_to(np.asarray(Ptarget, dtype=np.float64).reshape(-1, 9),
@@ -420,6 +429,7 @@ class Solver:
         return h
 
     def set_history(self, h):
+        self.generation += 1
         h = h.to(self.device, self.torch.float64).contiguous()
         _check(lib().fftnk_set_history(self.ctx, ctypes.c_void_p(h.data_ptr())), "fftnk_set_history")
 
@@ -429,6 +439,7 @@ class Solver:
         return F
 
     def set_state(self, F):
+        self.generation += 1
         F = F.to(self.device, self.torch.float64).contiguous()
         _check(lib().fftnk_set_state(self.ctx, ctypes.c_void_p(F.data_ptr())), "fftnk_set_state")
 
@@ -443,7 +454,8 @@ def _autograd_function():
         forward(mu [N0, N1, N2] float64 cuda, solver, Fbars [nrve, 9]) -> Pbar [nrve, 9]
         The solver's RVEs share the modulus field (one load case per RVE, same
         grid).  backward runs fftnk_adjoint (one CG per load case at the
-        converged states) and sums the per-case gradients.
+        converged states) and sums the per-case gradients; it raises if the
+        solver's state changed after this forward (Solver.generation).
         """
 
         @staticmethod
@@ -453,6 +465,7 @@ def _autograd_function():
             solver.reset_state()
             _, _, _, Pbar, stats = solver.solve_increment(Fbars, eta_nw, eta_cg, fields=False)
             ctx.solver = solver
+            ctx.generation = solver.generation
             ctx.eta_cg = eta_cg
             ctx.shape = mu.shape
             ctx.forward_stats = stats
@@ -461,6 +474,10 @@ def _autograd_function():
         @staticmethod
         def backward(ctx, grad_Pbar):
             s = ctx.solver
+            if s.generation != ctx.generation:
+                raise RuntimeError("HomogenizedStress.backward: the solver's state changed after this forward "
+                                   "(another solve, reset or set_* call); the adjoint would be taken at the "
+                                   "wrong equilibrium -- run forward again before backward")
             dmu, _, _ = s.adjoint(grad_Pbar.detach().cpu().numpy(), eta_cg=ctx.eta_cg)
             g = dmu.view(s.nrve, -1).sum(dim=0).reshape(ctx.shape)
             return g, None, None, None, None

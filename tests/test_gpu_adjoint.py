@@ -103,3 +103,22 @@ def test_adjoint_fp32_mixed_close_to_fp64(torch_cuda, mu24):
         s.solve_increment(cases, 1e-10, 1e-10)
         out[prec] = s.adjoint(g, eta_cg=1e-10)[0].cpu().numpy()
     assert np.linalg.norm(out["fp32"] - out["fp64"]) <= 1e-4 * np.linalg.norm(out["fp64"])
+
+
+def test_backward_refuses_a_changed_state(torch_cuda, mu24):
+    """A solve on the same Solver between forward and backward would move the
+    equilibrium the adjoint is taken at: backward raises instead of returning
+    a gradient of another state; a fresh forward works again."""
+    torch = torch_cuda
+    from paper_1603_08893_amd.fftnk import homogenized_stress
+    shape = mu24.shape
+    cases = np.array(ms.c5_load_cases()[:2])
+    s = _solver(shape, len(cases))
+    mu = torch.from_numpy(mu24).cuda().requires_grad_(True)
+    L = homogenized_stress(mu, s, cases).sum()
+    s.solve_increment(cases * 1.0 + 0.01 * np.eye(3).reshape(9), fields=False)  # another solve in between
+    with pytest.raises(RuntimeError, match="state changed"):
+        L.backward()
+    L2 = homogenized_stress(mu, s, cases).sum()
+    L2.backward()
+    assert torch.isfinite(mu.grad).all()

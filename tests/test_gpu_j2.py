@@ -104,3 +104,26 @@ def test_j2_failed_increment_keeps_history(torch_cuda):
     st, *_ = s.solve_increment(ms.simple_shear(0.012), max_cg=1, raise_on_error=False)
     assert st == ECG_MAXIT
     assert torch.equal(s.get_history(), h0) and torch.equal(s.get_state(), F0)
+
+
+def test_j2_inverted_deformation_is_a_material_failure(torch_cuda, orc):
+    """det F <= 0 after the boundary-condition solve: the oracle's return
+    mapping fails (status 6) and the GPU reports FFTNK_EMATERIAL after the same
+    single solve, leaving the committed state and history untouched."""
+    torch = torch_cuda
+    from paper_1603_08893_amd.fftnk import EMATERIAL
+    shape = (5, 5, 5)
+    ph = ms.laminate(shape, 0, 0.4)
+    tab = [(ms.K_SOFT, ms.MU_SOFT, 0.003, 0.01), (ms.K_SOFT, ms.MU_SOFT, 0.006, 0.01)]
+    t = np.asarray(tab)
+    K, mu, ty0, H = (t[ph, k].copy() for k in range(4))
+    Fb = np.diag([-0.5, 1.0, 1.0]).reshape(9)
+    sto, *_, So = orc.solve_increment_j2(K, mu, ty0, H, orc.virgin_history(shape), orc.identity_field(shape), Fb)
+    assert sto == 6
+    s = _solver(shape, ph)
+    h0 = s.get_history().clone()
+    F0 = s.get_state().clone()
+    st, _, _, _, S = s.solve_increment(Fb, raise_on_error=False)
+    assert st == EMATERIAL and S[0]["status"] == EMATERIAL
+    assert S[0]["n_solves"] == So["n_solves"] == 1
+    assert torch.equal(s.get_history(), h0) and torch.equal(s.get_state(), F0)

@@ -57,3 +57,18 @@ def test_homogeneous_increment_closed_form(orc, tmp_path):
     lam = ms.K_SOFT - 2.0 * ms.MU_SOFT / 3.0
     P = Fm @ (lam * np.trace(E) * np.eye(3) + 2.0 * ms.MU_SOFT * E)
     assert np.max(np.abs(np.array(rec["pbar"]) - P.reshape(-1))) <= 1e-14
+
+
+def test_timing_front_end_small_grid():
+    """python -m oracle.timing: pinned, built on the host with the timed flags,
+    one JSON line with the per-application times and the host description."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-m", "oracle.timing", "--grid", "12", "--budget", "0.05", "--max-reps", "2"],
+                       cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    d = json.loads([l for l in r.stdout.splitlines() if l.startswith("{")][-1])
+    assert d["grid"] == 12 and 1 <= d["reps"] <= 2 and d["threads"] == 1
+    assert d["sec_per_matvec"] > 0 and "-O3" in d["flags"] and d["cpu_model"]

@@ -204,3 +204,16 @@ def test_j2_homogeneous_increments(orc):
         assert st == 0 and S["cg_iters"] == [0, 0]
         st, Pp, hp = orc.j2_stress(_one(Fb), K0, MU0, 0.003, 0.01, hp)
         assert np.max(np.abs(Pbar - Pp.ravel())) < 1e-15
+
+
+def test_j2_inverted_deformation_fails(orc):
+    """det F <= 0 has no logarithmic strain: the return mapping, and with it
+    the increment, fails (status 6) instead of producing a stress."""
+    shape = (5, 5, 5)
+    ph = ms.laminate(shape, 0, 0.4)
+    tab = np.array([(K0, MU0, 0.003, 0.01), (K0, MU0, 0.006, 0.01)])
+    K, mu, ty0, H = (tab[ph, k].copy() for k in range(4))
+    Fb = np.diag([-0.5, 1.0, 1.0]).reshape(9)
+    st, F, P, Pbar, hist, S = orc.solve_increment_j2(K, mu, ty0, H, orc.virgin_history(shape),
+                                                     orc.identity_field(shape), Fb)
+    assert st == 6 and S["n_solves"] == 1
