@@ -208,7 +208,7 @@ def main():
                          "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--extra", default="",
-                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d,tune,cpu_baseline,slab: instead of the headline line, one JSON "
+                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d,passes2d,oddeven,tune,cpu_baseline,slab: instead of the headline line, one JSON "
                          "line per extra measurement (operator at 96^3..256^3; 64 batched cells; J2 at 96^3; adjoint "
                          "8 x 192^3; the two Nyquist choices at 128^3; mixed control at 128^3; CG / Chebyshev / "
                          "Richardson / GMRES at 128^3; the 2-D plane-strain example at 451^2; the plan autotuner on "
@@ -593,6 +593,37 @@ def extra(args):
                       "matvecs_per_s": round(1e3 / t, 1), "bytes_per_voxel": round(bpv, 2), "GB_s": round(gbs, 1),
                       "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
                 del s, fl, p, out
+                torch.cuda.empty_cache()
+
+    if "passes2d" in which:
+        # the operator's passes one by one on the 2-D example's cell size and
+        # its neighbours: 448 = 2^6 7, 450 = 2 3^2 5^2, 451 = 11 41 (prime
+        # radices 11 and 41), 452 = 2^2 113; 20 back-to-back launches of each
+        for n_ in (448, 450, 451, 452):
+            shape = (n_, n_, 2)
+            for prec in ("fp64", "fp32"):
+                s = Solver(shape, precision=prec)
+                s.set_phases(np.zeros(shape, dtype=np.uint8))
+                s.set_material(TABLE)
+                s.set_linearization(torch.from_numpy(ms.near_identity_field(shape, seed=12, scale=0.01).reshape(-1)))
+                p = s.project(torch.from_numpy(ms.random_field(shape, seed=13).reshape(-1)).to(dev))
+                out = s.field()
+                s.apply_operator(p, out)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                us = {}
+                for k in range(1, 6):
+                    s.launch_pass(k)
+                    e0.record()
+                    for _ in range(20):
+                        s.launch_pass(k)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    us[k] = round(e0.elapsed_time(e1) / 20 * 1e3, 2)
+                pb = pass_bytes_per_voxel(8 if prec == "fp64" else 4, 2)
+                emit({"extra": "passes2d", "grid": list(shape), "precision": prec, "pass_us": us,
+                      "pass_GB_s": {k: round(pb[k] * n_ * n_ * 2 / (us[k] * 1e-6) / 1e9, 1) for k in us}})
+                del s, p, out
                 torch.cuda.empty_cache()
 
     if "cpu_baseline" in which:

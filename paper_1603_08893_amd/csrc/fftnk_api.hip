@@ -31,12 +31,28 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-// Radix plan: the power-of-two part in as few stages of 8 / 4 / 2 as possible
-// (bits spread evenly), then 3, 5, 7 and any remaining prime (direct sum).
+// Radix plan: primes of 11 and above first, largest first (the first stage
+// has no stage twiddles, and a prime stage would otherwise apply them once per
+// group of output pairs), then the power-of-two part in as few stages of
+// 8 / 4 / 2 as possible (bits spread evenly), then 3, 5, 7.
 bool make_plan(int n, AxisPlan& pl, bool allow12) {
   pl.n = n;
   pl.nstages = 0;
   int m = n, e2 = 0;
+  {
+    int big[kMaxStages], nb = 0, r = n;
+    for (int p = 2; p * p <= r; ++p)
+      while (r % p == 0) {
+        if (p >= 11) big[nb++] = p;
+        r /= p;
+      }
+    if (r >= 11) big[nb++] = r;
+    for (int i = nb - 1; i >= 0; --i) {  // ascending factorisation: largest last
+      if (pl.nstages >= kMaxStages) return false;
+      pl.radix[pl.nstages++] = big[i];
+      m /= big[i];
+    }
+  }
   while (m % 2 == 0) {
     m /= 2;
     ++e2;
@@ -50,13 +66,14 @@ bool make_plan(int n, AxisPlan& pl, bool allow12) {
       pl.radix[pl.nstages++] = 1 << b[s];
     }
   }
-  for (int p = 3; m > 1; p += 2) {
+  for (int p = 3; m > 1 && p <= 7; p += 2) {
     while (m % p == 0) {
       if (pl.nstages >= kMaxStages) return false;
       pl.radix[pl.nstages++] = p;
       m /= p;
     }
   }
+  if (m != 1) return false;
   if ((1 << e2) == n && e2 >= 3 && n <= kMaxRegLen)
     pl.reg = 8;
   else if (allow12 && n == 3 * (1 << e2) && e2 >= 2 && n <= 192)

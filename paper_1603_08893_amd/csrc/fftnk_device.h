@@ -272,51 +272,88 @@ __device__ __forceinline__ void stage_lds(const cx<T>* __restrict__ src, cx<T>* 
   }
 }
 
-// Stage for a prime radix R > 8: one output per thread, direct sum.
-// Output q of butterfly j: sum_r x[j + r n/R] W_n^{r (k n/(Ns R) + q n/R)}.
+// Stage for a prime radix R >= 11.  The outputs of a butterfly come in pairs
+// (q, R - q) that share their terms: with the stage-twiddled inputs
+// y_r = x[j + r n/R] W_n^{k r n/(Ns R)} and, for r = 1 .. (R-1)/2,
+// a_r = y_r + y_{R-r}, b_r = y_r - y_{R-r} and theta = 2 pi r q / R,
+//   X_0     = y_0 + sum_r a_r
+//   X_q     = y_0 + sum_r a_r cos(theta) -/+ i sum_r b_r sin(theta)
+//   X_{R-q} = y_0 + sum_r a_r cos(theta) +/- i sum_r b_r sin(theta)
+// (upper signs forward, W = exp(-2 pi i / R)): half the multiply-adds of the
+// direct sum, and each input is read once per group of kPrimePairs output
+// pairs instead of once per output.  A work item is (butterfly, group of
+// pairs); consecutive items walk the butterflies, so the lanes of a wave read
+// the same cos / sin entries (LDS broadcasts).  The cos / sin of theta are
+// W_R^m = W_n^{m n/R} from the stage's twiddle table.
+constexpr int kPrimePairs = 5;
 template <typename T>
-__device__ __forceinline__ void stage_lds_prime(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n, int Ns, int R,
-                                int npen, int sp, int se, const cx<T>* tw, bool inv, bool pen_fast) {
-  const int nbf = n / R;
-  const int total = n * npen;
+__device__ __forceinline__ void stage_lds_prime(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n, int Ns,
+                                                int R, int npen, int sp, int se, const cx<T>* tw, bool inv,
+                                                bool pen_fast) {
+  constexpr int C = kPrimePairs;
+  const int nbf = n / R, half = (R - 1) / 2;
+  const int ngrp = (half + C - 1) / C;
+  const int nb = nbf * npen;
+  const int total = nb * ngrp;
   const int tws = n / (Ns * R);
-  for (int b = threadIdx.x; b < total; b += kThreads) {
-    int m, idx;
+  const T sg = inv ? (T)1 : (T)-1;  // X_q = U + sg i V
+  for (int it = threadIdx.x; it < total; it += kThreads) {
+    const int grp = it / nb, bb = it - grp * nb;
+    int m, j;
     if (pen_fast) {
-      idx = b / npen;
-      m = b - idx * npen;
+      j = bb / npen;
+      m = bb - j * npen;
     } else {
-      m = b / n;
-      idx = b - m * n;
+      m = bb / nbf;
+      j = bb - m * nbf;
     }
-    const int q = idx / nbf, j = idx - q * nbf;
     const int k = j % Ns;
-    const int e = k * tws + q * nbf;  // < n
+    const int ek = k * tws;  // stage twiddle of input r: W_n^{ek r}
     const cx<T>* s = src + m * sp;
-    // four partial sums, so that the reads of four terms are in flight together
-    cx<T> acc0 = s[j * se], acc1{(T)0, (T)0}, acc2{(T)0, (T)0}, acc3{(T)0, (T)0};
-    int er = e;  // (r e) mod n of the next term r
-    int r = 1;
-    for (; r + 3 < R; r += 4) {
-      int e2 = er + e;
-      if (e2 >= n) e2 -= n;
-      int e3 = e2 + e;
-      if (e3 >= n) e3 -= n;
-      int e4 = e3 + e;
-      if (e4 >= n) e4 -= n;
-      acc0 = acc0 + cmul(s[(j + r * nbf) * se], twid(tw, er, inv));
-      acc1 = acc1 + cmul(s[(j + (r + 1) * nbf) * se], twid(tw, e2, inv));
-      acc2 = acc2 + cmul(s[(j + (r + 2) * nbf) * se], twid(tw, e3, inv));
-      acc3 = acc3 + cmul(s[(j + (r + 3) * nbf) * se], twid(tw, e4, inv));
-      er = e4 + e;
-      if (er >= n) er -= n;
+    const cx<T> y0 = s[j * se];
+    const int q0 = 1 + grp * C;
+    cx<T> U[C], V[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      U[c] = y0;
+      V[c] = cx<T>{(T)0, (T)0};
     }
-    for (; r < R; ++r) {
-      acc0 = acc0 + cmul(s[(j + r * nbf) * se], twid(tw, er, inv));
-      er += e;
-      if (er >= n) er -= n;
+    cx<T> sum_a = y0;
+    int ep = ek;                                      // (ek r) mod n
+    int em = (int)(((long long)ek * (R - 1)) % n);  // (ek (R - r)) mod n
+    for (int r = 1; r <= half; ++r) {
+      cx<T> yp = s[(j + r * nbf) * se], ym = s[(j + (R - r) * nbf) * se];
+      if (k != 0) {
+        yp = cmul(yp, twid(tw, ep, inv));
+        ym = cmul(ym, twid(tw, em, inv));
+      }
+      ep += ek;
+      if (ep >= n) ep -= n;
+      em -= ek;
+      if (em < 0) em += n;
+      const cx<T> a = yp + ym, d = yp - ym;
+      sum_a = sum_a + a;
+      int e = (r * q0) % R;  // r q mod R for q = q0 + c
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const cx<T> w = tw[lpad(e * nbf)];  // (cos theta, -sin theta)
+        U[c] = U[c] + cscale(a, w.x);
+        V[c] = V[c] - cscale(d, w.y);
+        e += r;
+        if (e >= R) e -= R;
+      }
     }
-    dst[m * sp + ((j - k) * R + k + q * Ns) * se] = (acc0 + acc1) + (acc2 + acc3);
+    cx<T>* dd = dst + m * sp;
+    const int base = (j - k) * R + k;
+    if (grp == 0) dd[base * se] = sum_a;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int q = q0 + c;
+      if (q > half) break;
+      const cx<T> iv{-sg * V[c].y, sg * V[c].x};  // sg i V
+      dd[(base + q * Ns) * se] = U[c] + iv;
+      dd[(base + (R - q) * Ns) * se] = U[c] - iv;
+    }
   }
 }
 
