@@ -208,7 +208,7 @@ def main():
                          "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--extra", default="",
-                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d,passes2d,oddeven,tune,cpu_baseline,slab: instead of the headline line, one JSON "
+                    help="comma list of sizes,c3,c4,c5,nyq,mixed,krylov,c2d,passes2d,j2tangent,oddeven,tune,cpu_baseline,slab: instead of the headline line, one JSON "
                          "line per extra measurement (operator at 96^3..256^3; 64 batched cells; J2 at 96^3; adjoint "
                          "8 x 192^3; the two Nyquist choices at 128^3; mixed control at 128^3; CG / Chebyshev / "
                          "Richardson / GMRES at 128^3; the 2-D plane-strain example at 451^2; the plan autotuner on "
@@ -626,6 +626,103 @@ def extra(args):
                 del s, p, out
                 torch.cuda.empty_cache()
 
+    if "j2tangent" in which:
+        # J2 at 96^3 (the J2 workload's sphere cell), the first four simple-shear
+        # increments, with the tangent recomputed per operator application and
+        # with the compact tangent stored per linearisation point; St.V-K on
+        # the same phase map for reference; CG kernels by profile_cg
+        ph, frac = ms.rsa_spheres(96, 0.25, seed=1604)
+        sched = ms.c4_schedule(20, 0.1)
+        res = {"extra": "j2_tangent", "grid": 96, "sphere_fraction": round(frac, 4), "increments": 4}
+        for name in ("svk", "j2_recomputed", "j2_stored"):
+            s = Solver((96,) * 3, precision="fp64", j2_stored_tangent=(name == "j2_stored"))
+            s.set_phases(ph)
+            if name == "svk":
+                s.set_material([(ms.K_SOFT, ms.MU_SOFT), (2 * ms.K_SOFT, 2 * ms.MU_SOFT)])
+            else:
+                s.set_material([(ms.K_SOFT, ms.MU_SOFT, 0.003, 0.01), (ms.K_SOFT, ms.MU_SOFT, 0.006, 0.01)], model=J2)
+            s.solve_increment(sched[0], fields=False)  # warm-up
+            s.reset_state()
+
+            def run():
+                out = []
+                for Fb in sched[:4]:
+                    out.append(s.solve_increment(Fb, fields=False))
+                return out
+            outs, sec = timed(run)
+            cg = int(sum(sum(o[4][0]["cg_iters"]) for o in outs))
+            k = s.profile_cg(20)
+            res[name] = {"seconds": round(sec, 4), "cg_iterations": cg, "ms_per_cg_in_solve": round(sec * 1e3 / cg, 4),
+                         "cg_kernels_ms": {kk: round(v, 4) for kk, v in k.items()},
+                         "cg_iteration_ms": round(sum(k.values()), 4), "pbar_last": [float(v) for v in outs[-1][3][0]]}
+            del s
+            torch.cuda.empty_cache()
+        a, b = res["j2_recomputed"]["pbar_last"], res["j2_stored"]["pbar_last"]
+        res["pbar_rel_diff_stored_vs_recomputed"] = float(max(abs(x - y) for x, y in zip(a, b)) / max(abs(v) for v in a))
+        emit(res)
+
+    if "oddeven" in which:
+        # App. C closes with odd against even grids ("one pixel more"): the
+        # paper's cubic inclusion on 31^3 and 32^3 (same 9^3 cube) under simple
+        # shear 0.05, the paper's shear 1 and a tensile load, G-hat zero at
+        # Nyquist frequencies on both grids and identity there on the even one;
+        # then the 2-D example (J2, chi = 2, pure shear to 1.2 in 250
+        # increments) on the 451 x 451 stand-in micrograph and its 452 x 452
+        # extension, P-bar along the load path
+        from paper_1603_08893_amd.fftnk import OPT_NYQUIST
+        loads = {"shear_0.05": ms.simple_shear(0.05), "shear_1": ms.simple_shear(1.0),
+                 "tension": np.array([[1.03, 0.004, 0.0], [0.002, 1.02, 0.003], [0.0, -0.002, 1.025]]).reshape(9)}
+        for lname, Fb in loads.items():
+            res = {"extra": "odd_even_cubic_inclusion", "load": lname, "inclusion": 9}
+            pb = {}
+            for n_, nyq in ((31, 0), (32, 0), (32, 1)):
+                s = Solver((n_,) * 3, precision="fp64")
+                s.set_phases(ms.cubic_inclusion(n_, 9))
+                s.set_material(TABLE)
+                s.set_option(OPT_NYQUIST, nyq)
+                st, _, _, Pb, S = s.solve_increment(Fb, fields=False, raise_on_error=False)
+                key = "%d_%s" % (n_, "identity" if nyq else "zero")
+                res[key] = {"status": int(st), "newton_solves": S[0]["n_solves"], "cg_iterations": S[0]["cg_iters"],
+                            "pbar": [float(v) for v in Pb[0]]}
+                if st == 0:
+                    pb[key] = Pb[0]
+                del s
+            for a, b in (("32_zero", "31_zero"), ("32_identity", "31_zero"), ("32_identity", "32_zero")):
+                if a in pb and b in pb:
+                    res["pbar_rel_diff_%s_vs_%s" % (a, b)] = float(np.max(np.abs(pb[a] - pb[b])) / np.max(np.abs(pb[b])))
+            emit(res)
+        odd = ms.micrograph_2d(N=451)
+        sched = ms.pure_shear_schedule(250, 1.2)
+        traj = {}
+        res = {"extra": "odd_even_2d_example", "chi": 2.0, "increments": len(sched)}
+        for ph in (odd, ms.extend_by_one_pixel(odd, axes=(0, 1))):
+            s = Solver(ph.shape, precision="fp64", j2_stored_tangent=True)
+            s.set_phases(ph)
+            s.set_material(ms.plane_strain_j2_table(2.0), model=J2)
+            t0 = time.perf_counter()
+            pbs, newton, status = [], [], 0
+            for Fb in sched:
+                st, _, _, Pb, S = s.solve_increment(Fb, fields=False, raise_on_error=False)
+                if st:
+                    status = st
+                    break
+                pbs.append(Pb[0].copy())
+                newton.append(S[0]["n_solves"])
+            torch.cuda.synchronize()
+            traj[ph.shape[0]] = np.array(pbs)
+            res["%d" % ph.shape[0]] = {"status": int(status), "increments_done": len(pbs),
+                                       "seconds": round(time.perf_counter() - t0, 2),
+                                       "newton_per_increment_mean": round(float(np.mean(newton)), 3),
+                                       "pbar_01_every_25": [float(p[1]) for p in pbs[24::25]]}
+            print("# oddeven 2-D %d done" % ph.shape[0], file=sys.stderr, flush=True)
+            del s
+            torch.cuda.empty_cache()
+        m = min(len(traj[451]), len(traj[452]))
+        if m:
+            d = [float(np.max(np.abs(traj[452][k] - traj[451][k])) / np.max(np.abs(traj[451][k]))) for k in range(m)]
+            res["pbar_rel_diff_452_vs_451"] = {"max": max(d), "last": d[-1], "every_25": d[24::25]}
+        emit(res)
+
     if "cpu_baseline" in which:
         # the oracle timed on the host beside the GPU path: operator
         # applications at several sizes on one core (GPU operator time of the
@@ -900,7 +997,7 @@ def extra(args):
         ph = ms.micrograph_2d(N=n_)
         sched = ms.pure_shear_schedule(nincr, 1.2)
         for chi in (np.sqrt(2.0), 2.0, 4.0, 8.0):
-            s = Solver(ph.shape, precision="fp64")
+            s = Solver(ph.shape, precision="fp64", j2_stored_tangent=True)
             s.set_phases(ph)
             s.set_material(ms.plane_strain_j2_table(chi), model=J2)
             s.solve_increment(sched[0], fields=False)  # warm-up (graphs), then start over
@@ -1013,7 +1110,7 @@ def extra(args):
     if "c4" in which:
         # finite-strain J2 at 96^3: spheres at 25 %, simple shear to 0.1 in 20 increments
         ph, frac = ms.rsa_spheres(96, 0.25, seed=1604)
-        s = Solver((96,) * 3, precision="fp64")
+        s = Solver((96,) * 3, precision="fp64", j2_stored_tangent=True)
         s.set_phases(ph)
         s.set_material([(ms.K_SOFT, ms.MU_SOFT, 0.003, 0.01), (ms.K_SOFT, ms.MU_SOFT, 0.006, 0.01)], model=J2)
         sched = ms.c4_schedule(20, 0.1)

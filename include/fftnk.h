@@ -186,8 +186,17 @@ int fftnk_set_modulus_field(fftnk_ctx* ctx, const double* mu_dev);
  * GMRES (m + 1 vector fields of the context precision) in the workspace: set
  * it after creation and before fftnk_workspace_bytes / fftnk_bind_workspace
  * (afterwards FFTNK_ESTATE); it enables FFTNK_KRYLOV_GMRES.
+ * FFTNK_OPT_J2_TANGENT (0 default, 1): for the J2 law (Sec. 5) in FP64, 1
+ * stores the parts of the consistent tangent that do not depend on the
+ * direction (eigenbasis of the trial elastic left Cauchy-Green tensor, the
+ * principal algorithmic moduli, the principal Kirchhoff stresses; 24 doubles
+ * per voxel, reserved in the workspace) once per linearisation point, instead
+ * of redoing the return mapping and eigen-decomposition at every operator
+ * application.  Same results up to rounding order.  Set it before
+ * fftnk_workspace_bytes / fftnk_bind_workspace (afterwards FFTNK_ESTATE).
  */
-enum { FFTNK_OPT_GRAPHS = 1, FFTNK_OPT_CHECK_EVERY = 2, FFTNK_OPT_NYQUIST = 3, FFTNK_OPT_GMRES_RESTART = 4 };
+enum { FFTNK_OPT_GRAPHS = 1, FFTNK_OPT_CHECK_EVERY = 2, FFTNK_OPT_NYQUIST = 3, FFTNK_OPT_GMRES_RESTART = 4,
+       FFTNK_OPT_J2_TANGENT = 5 };
 int fftnk_set_option(fftnk_ctx* ctx, int option, int value);
 
 /* F_t := I (and virgin history): the start state of Algorithm 1. */

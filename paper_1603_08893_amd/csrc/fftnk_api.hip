@@ -228,6 +228,9 @@ struct fftnk_ctx {
   int krylov = KRYLOV_CG;  // fftnk_set_krylov
   double k_lo = 0.0, k_hi = 0.0;
   int gm = 0;              // GMRES restart length (FFTNK_OPT_GMRES_RESTART), basis of gm + 1 vectors
+  int jt = 0;              // FFTNK_OPT_J2_TANGENT: 1 = compact J2 tangent stored per linearisation point
+  bool jt_ready = false;   // the stored compact tangent was computed (for the last linearisation point)
+  size_t o_jt = 0;         // its workspace offset, [kJ2Tan][ntot] doubles after the GMRES basis
   size_t total_base = 0;   // workspace bytes without the GMRES basis
   // workspace layout (byte offsets)
   size_t o_hist, o_hnew;  // J2 history: committed and of the current iterate, [7][ntot] each
@@ -300,11 +303,13 @@ struct fftnk_ctx {
     m.table = at<double>(o_mtab);
     m.hist = at<double>(o_hist);
     m.hist_new = at<double>(o_hnew);
+    m.j2t = (jt_active() && jt_ready) ? at<double>(o_jt) : nullptr;
     m.ntot = ntot;
     m.model = model;
     m.nphase = nphase;
     return m;
   }
+  bool jt_active() const { return jt && model == MODEL_J2 && prec == PREC_F64; }
   const CgState* host_cg() const { return reinterpret_cast<const CgState*>(pinned); }
   const double* host_red() const { return reinterpret_cast<const double*>(pinned); }
 };
@@ -339,6 +344,23 @@ int upload_active(fftnk_ctx* c) {
   HIP_TRY(hipStreamSynchronize(c->stream));  // the host tables may change again at once
   return FFTNK_OK;
 }
+// workspace bytes: the base layout, the GMRES basis, the compact J2 tangent
+void size_workspace(fftnk_ctx* c) {
+  size_t o = c->total_base;
+  if (c->gm) o = align_up(o + (size_t)(c->gm + 1) * gm_vstride(c->ntot) * (c->prec == PREC_F64 ? 8 : 4));
+  c->o_jt = o;
+  if (c->jt) o = align_up(o + (size_t)kJ2Tan * c->ntot * sizeof(double));
+  c->total = o;
+}
+
+// J2 with the stored tangent: the compact tangent at the linearisation point
+// Flin (committed history), before a run of operator applications there
+void refresh_j2_tangent(fftnk_ctx* c, const void* flin) {
+  if (!c->jt_active()) return;
+  launch_j2_tangent_data(c->launch(), c->material(), static_cast<const double*>(flin), c->at<double>(c->o_jt));
+  c->jt_ready = true;
+}
+
 int upload_uni(fftnk_ctx* c) {
   HIP_TRY(hipMemcpyAsync(c->ws + c->o_uni, c->uni.data(), 9 * c->nrve * sizeof(double), hipMemcpyHostToDevice,
                          c->stream));
@@ -508,6 +530,7 @@ void middle_passes(int prec, const Launch& L, void* spec, const CgState* cg) {
 // partials: ||Y||^2 in SLOT_YY, ||b||^2 in SLOT_BB.  Y is produced by pass 1
 // in `mode` (the field in, or the tangent at Flin applied to Batch::uni).
 void rhs_pipeline(fftnk_ctx* c, int mode, const double* Y, const double* Flin, double sign) {
+  if (mode != FWD_COPY) refresh_j2_tangent(c, Flin);
   const Launch L = c->launch();
   launch_fwd_a2(PREC_F64, mode, L, c->material(), Y, nullptr, nullptr, nullptr, Flin, 1.0, c->spec(), nullptr);
   middle_passes(PREC_F64, L, c->spec(), nullptr);
@@ -585,6 +608,7 @@ int launch_iterations(fftnk_ctx* c, int k, bool eager = false) {
 int run_gmres(fftnk_ctx* c, double eta, int max_it);
 
 int run_cg(fftnk_ctx* c, double eta, int max_cg) {
+  refresh_j2_tangent(c, c->flin());
   if (c->krylov == KRYLOV_GMRES) return run_gmres(c, eta, max_cg);
   if (c->graph_active != c->active) {  // the graphs hold the launch sizes of another mask
     drop_graphs(c);
@@ -1208,6 +1232,7 @@ std::map<std::string, unsigned> g_tuned;  // process-wide: tuning key -> policy
 // milliseconds per operator application (x -> w, tangent at the committed
 // state F_t), the best of three rounds of `reps` back-to-back applications
 int time_operator(fftnk_ctx* c, int reps, const void* flin, double* ms) {
+  refresh_j2_tangent(c, flin);
   const Launch L = c->launch();
   const Material mat = c->material();
   auto apply = [&]() {
@@ -1406,10 +1431,15 @@ int fftnk_set_option(fftnk_ctx* c, int option, int value) {
       if (value < 1 || value > 256) return FFTNK_EINVAL;
       if (c->ws) return FFTNK_ESTATE;  // sizes the workspace: set before binding it
       c->gm = value;
-      const size_t fv = (size_t)gm_vstride(c->ntot) * (c->prec == PREC_F64 ? 8 : 4);
-      c->total = align_up(c->total_base + (size_t)(value + 1) * fv);
+      size_workspace(c);
       return FFTNK_OK;
     }
+    case FFTNK_OPT_J2_TANGENT:
+      if (value != 0 && value != 1) return FFTNK_EINVAL;
+      if (c->ws) return FFTNK_ESTATE;  // sizes the workspace: set before binding it
+      c->jt = value;
+      size_workspace(c);
+      return FFTNK_OK;
     case FFTNK_OPT_NYQUIST:
       if (value != 0 && value != 1) return FFTNK_EINVAL;
       if (value == c->nyq_id) return FFTNK_OK;
@@ -1737,6 +1767,7 @@ int fftnk_set_linearization(fftnk_ctx* c, const double* F_dev) {
 int fftnk_apply_operator(fftnk_ctx* c, const void* p_dev, void* Ap_dev) {
   if (!c || !p_dev || !Ap_dev || p_dev == Ap_dev) return FFTNK_EINVAL;
   if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
+  refresh_j2_tangent(c, c->flin());
   const Launch L = c->launch();
   launch_fwd_a2(c->prec, FWD_TANGENT, L, c->material(), p_dev, nullptr, nullptr, nullptr, c->flin(), 1.0, c->spec(),
                 nullptr);
@@ -1814,6 +1845,7 @@ int fftnk_launch_pass(fftnk_ctx* c, int pass) {
 int fftnk_profile_cg(fftnk_ctx* c, int iters, double* ms) {
   if (!c || !ms || iters < 1 || iters > 10000) return FFTNK_EINVAL;
   if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
+  refresh_j2_tangent(c, c->flin());
   const Launch L = c->launch();
   CgState* cg = c->cg();
   rhs_pipeline(c, FWD_COPY, c->P(), nullptr, -1.0);

@@ -61,7 +61,14 @@ __device__ __forceinline__ void tangent_at(const Material& mat, long long gv, co
   if constexpr (LAW == MODEL_J2) {
     double K, mu, ty0, H, h[7];
     j2_point_data(mat, gv, K, mu, ty0, H, h);
-    j2_tangent(F, h, K, mu, ty0, H, p, d);
+    if (mat.j2t) {  // the compact tangent stored for this linearisation point
+      double t[kJ2Tan];
+#pragma unroll
+      for (int k = 0; k < kJ2Tan; ++k) t[k] = __builtin_nontemporal_load(mat.j2t + k * mat.ntot + gv);
+      j2_tangent_compact(F, h, t, p, d);
+    } else {
+      j2_tangent(F, h, K, mu, ty0, H, p, d);
+    }
   } else {
     double lam, mu;
     material_at(mat, gv, lam, mu);

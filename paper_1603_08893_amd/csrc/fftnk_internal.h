@@ -86,10 +86,17 @@ struct Material {
   const double* table;     // [nphase][4] device table: K, mu, tau_y0, H
   const double* hist;      // J2: committed history [7][ntot] (Cp^-1 xx yy zz xy yz xz, eps_p)
   double* hist_new;        // J2: history of the current iterate [7][ntot]
+  const double* j2t;       // J2: compact tangent at the linearisation point [kJ2Tan][ntot], or null (recomputed)
   long long ntot;
   int model;
   int nphase;
 };
+
+// Compact J2 tangent per voxel at a linearisation point (frozen history):
+// eigenvectors Q of the trial be (9, Q[3 i + a]), the off-diagonal principal
+// moduli (3: pairs 01, 12, 02), the diagonal principal block (9, D[3 a + b]),
+// the principal Kirchhoff stresses (3).
+constexpr int kJ2Tan = 24;
 
 // Slots of block partial sums (FP64); each slot holds one value per work-group
 // of the launch that fills it.
@@ -213,6 +220,8 @@ void launch_set_F(const Launch& L, const double* Ft, double* F, float* Flin32);
 void launch_newton_update(int prec, const Launch& L, const Material& mat, double* F, const void* x_T, double* P,
                           float* Flin32, bool add_uni);
 void launch_constitutive(const Launch& L, const Material& mat, const double* F, double* P);
+// J2: the compact tangent at the linearisation point F into out [kJ2Tan][ntot]
+void launch_j2_tangent_data(const Launch& L, const Material& mat, const double* F, double* out);
 void launch_field_sum(const Launch& L, const double* X, int slot0);
 // out[r * NSLOT + slot0 + s] = sum over RVE r's work-groups of slot slot0 + s, for s < nslots
 void launch_reduce(const Launch& L, int kind, int slot0, int nslots, double* out);

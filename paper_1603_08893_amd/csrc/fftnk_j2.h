@@ -256,6 +256,102 @@ __device__ __forceinline__ void j2_tangent(const double* F, const double* h, dou
       out[3 * i + j] = t1[3 * i] * s.Fi[3 * j] + t1[3 * i + 1] * s.Fi[3 * j + 1] + t1[3 * i + 2] * s.Fi[3 * j + 2];
 }
 
+// The compact tangent at F (frozen history): everything of the tangent action
+// that does not depend on dF, computed once per linearisation point (see
+// kJ2Tan).  With f_ab the divided differences of ln in the eigenvalues of the
+// trial be, the principal increments are dt_ab = G_ab dq_ab (a != b) and
+// dt_aa = sum_b D_ab dq_bb for dq = Q^T dbe Q.  false (and NaN data) where the
+// return mapping fails.
+__device__ __forceinline__ bool j2_tangent_data(const double* F, const double* h, double K, double mu, double ty0,
+                                                double H, double* t) {
+  J2Point s;
+  if (!j2_return(F, h, K, mu, ty0, H, s)) {
+#pragma unroll
+    for (int k = 0; k < kJ2Tan; ++k) t[k] = __builtin_nan("");
+    return false;
+  }
+  const double c1 = s.plastic ? 1.0 - 3.0 * mu * s.dgam / s.q : 1.0;
+  const double c2 = s.plastic ? 2.0 * mu * (1.0 / (3.0 * mu + H) - s.dgam / s.q) : 0.0;
+  const double nsum = s.np[0] + s.np[1] + s.np[2];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) t[k] = s.Q[k];
+  t[9] = c1 * mu * log_divdiff(s.be[0], s.be[1]);
+  t[10] = c1 * mu * log_divdiff(s.be[1], s.be[2]);
+  t[11] = c1 * mu * log_divdiff(s.be[0], s.be[2]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double m = (a == b ? c1 * 2.0 * mu : 0.0) + K - c1 * 2.0 * mu / 3.0 -
+                       c2 * 2.0 * mu * s.np[a] * (s.np[b] - nsum / 3.0);
+      t[12 + 3 * a + b] = m * 0.5 * log_divdiff(s.be[b], s.be[b]);
+    }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) t[21 + k] = s.tp[k];
+  return true;
+}
+
+// Tangent action dP = (dP/dF at frozen history)[dF] from the compact tangent t
+// at F (same steps as j2_tangent after its return mapping).
+__device__ __forceinline__ void j2_tangent_compact(const double* F, const double* h, const double* t, const double* dF,
+                                                   double* out) {
+  double Fi[9], det;
+  inv33(F, Fi, det);
+  const double* Q = t;
+  const double C[9] = {h[0], h[3], h[5], h[3], h[1], h[4], h[5], h[4], h[2]};
+  double dFC[9], M[9];
+  mat33<double>(dF, C, dFC);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) M[3 * i + j] = dFC[3 * i] * F[3 * j] + dFC[3 * i + 1] * F[3 * j + 1] + dFC[3 * i + 2] * F[3 * j + 2];
+  double db[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) db[3 * i + j] = M[3 * i + j] + M[3 * j + i];
+  double t1[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) t1[3 * a + j] = Q[a] * db[j] + Q[3 + a] * db[3 + j] + Q[6 + a] * db[6 + j];
+  auto dq = [&](int a, int b) { return t1[3 * a] * Q[b] + t1[3 * a + 1] * Q[3 + b] + t1[3 * a + 2] * Q[6 + b]; };
+  const double q00 = dq(0, 0), q11 = dq(1, 1), q22 = dq(2, 2);
+  double dt[9];
+  dt[0] = t[12] * q00 + t[13] * q11 + t[14] * q22;
+  dt[4] = t[15] * q00 + t[16] * q11 + t[17] * q22;
+  dt[8] = t[18] * q00 + t[19] * q11 + t[20] * q22;
+  dt[1] = dt[3] = t[9] * dq(0, 1);
+  dt[5] = dt[7] = t[10] * dq(1, 2);
+  dt[2] = dt[6] = t[11] * dq(0, 2);
+  // dtau = Q dt Q^T, tau = Q diag(tp) Q^T
+  double dtau[9], tau[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) t1[3 * i + b] = Q[3 * i] * dt[b] + Q[3 * i + 1] * dt[3 + b] + Q[3 * i + 2] * dt[6 + b];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dtau[3 * i + j] = t1[3 * i] * Q[3 * j] + t1[3 * i + 1] * Q[3 * j + 1] + t1[3 * i + 2] * Q[3 * j + 2];
+  from_principal(Q, t + 21, tau);
+  double A[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) A[3 * i + j] = tau[3 * i] * Fi[3 * j] + tau[3 * i + 1] * Fi[3 * j + 1] + tau[3 * i + 2] * Fi[3 * j + 2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      t1[3 * i + j] = dtau[3 * i + j] - (A[3 * i] * dF[3 * j] + A[3 * i + 1] * dF[3 * j + 1] + A[3 * i + 2] * dF[3 * j + 2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      out[3 * i + j] = t1[3 * i] * Fi[3 * j] + t1[3 * i + 1] * Fi[3 * j + 1] + t1[3 * i + 2] * Fi[3 * j + 2];
+}
+
 }  // namespace fftnk
 
 namespace fftnk {

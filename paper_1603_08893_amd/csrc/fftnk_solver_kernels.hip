@@ -685,6 +685,31 @@ void launch_constitutive(const Launch& L, const Material& mat, const double* F, 
     hipLaunchKernelGGL((k_constitutive<MODEL_SVK>), dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, mat, F, P);
 }
 
+// The compact J2 tangent at the linearisation point F (committed history).
+__global__ __launch_bounds__(kThreads) void k_j2_tangent_data(Batch B, Material mat, const double* __restrict__ F,
+                                                             double* __restrict__ out) {
+  int local;
+  const int rv = find_rve(B, K_VOX, blockIdx.x, local);
+  if (skip_rve(B, nullptr, rv)) return;
+  const Grid& g = B.grids[rv];
+  const int nb = rve_blocks(B, K_VOX, rv);
+  const long long n = g.n, off = 9 * g.vox_off;
+  FOR_RVE_RANGE(v, n, local, nb) {
+    double f[9], t[kJ2Tan], K, mu, ty0, H, h[7];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) f[c] = F[off + c * n + v];
+    const long long gv = g.vox_off + v;
+    j2_point_data(mat, gv, K, mu, ty0, H, h);
+    j2_tangent_data(f, h, K, mu, ty0, H, t);
+#pragma unroll
+    for (int k = 0; k < kJ2Tan; ++k) out[k * mat.ntot + gv] = t[k];
+  }
+}
+
+void launch_j2_tangent_data(const Launch& L, const Material& mat, const double* F, double* out) {
+  hipLaunchKernelGGL(k_j2_tangent_data, dim3(L.nblk[K_VOX]), dim3(kThreads), 0, L.s, L.b, mat, F, out);
+}
+
 // J2 virgin state: Cp^-1 = I, eps_p = 0 ([7][ntot])
 __global__ __launch_bounds__(kThreads) void k_virgin_history(double* __restrict__ h, long long ntot) {
   for (long long v = blockIdx.x * (long long)kThreads + threadIdx.x; v < ntot; v += (long long)gridDim.x * kThreads)

@@ -16,7 +16,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "li
 OK, EINVAL, ESTATE, ENOMEM, EHIP, ECG_MAXIT, ECG_BREAKDOWN, ENEWTON_MAXIT, ENONFINITE, EMATERIAL, EUNSUPPORTED = range(11)
 FP64, FP32_MIXED = 0, 1
 SVK, J2 = 0, 1
-OPT_GRAPHS, OPT_CHECK_EVERY, OPT_NYQUIST, OPT_GMRES_RESTART = 1, 2, 3, 4
+OPT_GRAPHS, OPT_CHECK_EVERY, OPT_NYQUIST, OPT_GMRES_RESTART, OPT_J2_TANGENT = 1, 2, 3, 4, 5
 KRYLOV = {"cg": 0, "chebyshev": 1, "richardson": 2, "gmres": 3}
 MAX_SOLVES = 64
 
@@ -188,9 +188,12 @@ class Solver:
     dims: (n0, n1, n2) or a list of them (batched).  precision: "fp64" or
     "fp32" (FP32 Krylov solve, FP64 Newton residual).  gmres_restart: reserve
     the basis of restarted GMRES with this restart length (0: none).
+    j2_stored_tangent: reserve and use the compact J2 tangent stored per
+    linearisation point (FFTNK_OPT_J2_TANGENT; J2 law, FP64).
     """
 
-    def __init__(self, dims, precision="fp64", device="cuda", stream=None, gmres_restart=0):
+    def __init__(self, dims, precision="fp64", device="cuda", stream=None, gmres_restart=0,
+                 j2_stored_tangent=False):
         import torch
         self.torch = torch
         if isinstance(dims[0], (int, np.integer)):
@@ -212,6 +215,8 @@ class Solver:
         self.ctx = ctx
         if gmres_restart:
             _check(L.fftnk_set_option(ctx, OPT_GMRES_RESTART, int(gmres_restart)), "fftnk_set_option")
+        if j2_stored_tangent:
+            _check(L.fftnk_set_option(ctx, OPT_J2_TANGENT, 1), "fftnk_set_option")
         nbytes = L.fftnk_workspace_bytes(ctx)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()

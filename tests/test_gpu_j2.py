@@ -6,6 +6,8 @@
   addition, 25 %), tau_y0 = 0.003 / 0.006, H = 0.01, same elastic K, mu in both
   phases, simple shear in increments: equal Newton counts, CG counts within
   +-2, P-bar within 1e-10, histories within 1e-9, committed state transactional.
+* Both with the tangent recomputed at every operator application and with the
+  compact tangent stored per linearisation point (FFTNK_OPT_J2_TANGENT).
 """
 import numpy as np
 import pytest
@@ -26,9 +28,9 @@ def torch_cuda():
     return torch
 
 
-def _solver(shape, ph):
+def _solver(shape, ph, stored=False):
     from paper_1603_08893_amd.fftnk import J2, Solver
-    s = Solver(shape, precision="fp64")
+    s = Solver(shape, precision="fp64", j2_stored_tangent=stored)
     s.set_phases(ph)
     s.set_material(MATS, model=J2)
     return s
@@ -43,7 +45,8 @@ def _rel(a, b):
     return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
 
 
-def test_j2_constitutive_and_operator_parity(torch_cuda, orc):
+@pytest.mark.parametrize("stored", [False, True])
+def test_j2_constitutive_and_operator_parity(torch_cuda, orc, stored):
     torch = torch_cuda
     shape = (8, 9, 10)
     rng = np.random.default_rng(11)
@@ -53,7 +56,7 @@ def test_j2_constitutive_and_operator_parity(torch_cuda, orc):
     st, _, hist = orc.j2_stress(F0, K, mu, ty0, H, orc.virgin_history(shape))
     assert st == 0 and hist[6].max() > 0
     F = F0 + ms.random_field(shape, seed=13, scale=0.01)
-    s = _solver(shape, ph)
+    s = _solver(shape, ph, stored)
     for h in [orc.virgin_history(shape), hist]:
         s.set_history(torch.from_numpy(h.reshape(-1)))
         st, Pref, _ = orc.j2_stress(F, K, mu, ty0, H, h)
@@ -67,13 +70,14 @@ def test_j2_constitutive_and_operator_parity(torch_cuda, orc):
         assert_fields_close(got, ref, 1e-12)
 
 
+@pytest.mark.parametrize("stored", [False, True])
 @pytest.mark.parametrize("N", [15, 16])
-def test_j2_increments_vs_oracle(torch_cuda, orc, N):
+def test_j2_increments_vs_oracle(torch_cuda, orc, N, stored):
     torch = torch_cuda
     shape = (N, N, N)
     ph, frac = ms.rsa_spheres(N, 0.25, seed=1604, rmin=2, rmax=4)
     K, mu, ty0, H = _fields(ph)
-    s = _solver(shape, ph)
+    s = _solver(shape, ph, stored)
     F = orc.identity_field(shape)
     hist = orc.virgin_history(shape)
     for t in range(1, 9):

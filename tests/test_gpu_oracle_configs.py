@@ -162,15 +162,17 @@ def test_batched_cells_one_per_size(torch_cuda, prec):
     torch.cuda.empty_cache()
 
 
-def test_j2_increments(torch_cuda):
+@pytest.mark.parametrize("stored", [False, True])
+def test_j2_increments(torch_cuda, stored):
     """Finite-strain J2 on the 96^3 sphere cell, the stored increments (through
-    yield of both phases)."""
+    yield of both phases), with the tangent recomputed per operator
+    application and with the compact tangent stored per linearisation point."""
     from paper_1603_08893_amd.fftnk import J2, Solver
     g = _golden("c4")
     N = 96
     ph, frac = ms.rsa_spheres(N, 0.25, seed=1604)
     assert _digest(ph) == g["phase_sha256"]
-    s = Solver((N, N, N), precision="fp64")
+    s = Solver((N, N, N), precision="fp64", j2_stored_tangent=stored)
     s.set_phases(ph)
     s.set_material(g["table"], model=J2)
     sched = ms.c4_schedule(20, 0.1)
