@@ -29,16 +29,25 @@ def hipcc():
     return "hipcc"
 
 
-def build(force=True, verbose=False):
+# host code instrumented with AddressSanitizer and UndefinedBehaviorSanitizer
+# (each -fsanitize= right after -Xarch_host: the device code is built as usual)
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
+
+
+def build(force=True, verbose=False, out=None, sanitize=False):
     """Compile every source to an object in parallel (one hipcc per file), then
-    link the shared library."""
-    os.makedirs(LIBDIR, exist_ok=True)
+    link the shared library (to `out`, default the in-tree library).  With
+    sanitize, the host code is built with ASan and UBSan (for the CPU tests of
+    the host logic; load it with the compiler's ASan runtime preloaded)."""
+    lib_path = out or LIB
+    os.makedirs(os.path.dirname(lib_path), exist_ok=True)
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     deps = srcs + [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(ROOT, "include", "fftnk.h")]
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= max(os.path.getmtime(d) for d in deps):
-        return LIB
-    objs = [os.path.join(LIBDIR, os.path.basename(s) + ".%d.o" % os.getpid()) for s in srcs]
-    compile_flags = [f for f in HIPFLAGS if f != "-shared"]
+    if not force and os.path.exists(lib_path) and os.path.getmtime(lib_path) >= max(os.path.getmtime(d) for d in deps):
+        return lib_path
+    objs = [os.path.join(os.path.dirname(lib_path), os.path.basename(s) + ".%d.o" % os.getpid()) for s in srcs]
+    compile_flags = [f for f in HIPFLAGS if f != "-shared"] + (SANITIZE_FLAGS if sanitize else [])
     procs = []
     for src, obj in zip(srcs, objs):
         cmd = [hipcc()] + compile_flags + ["-c", "-o", obj, src]
@@ -54,20 +63,21 @@ def build(force=True, verbose=False):
     try:
         if failed:
             raise RuntimeError("hipcc failed building libfftnk")
-        tmp = LIB + ".tmp%d" % os.getpid()
-        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        tmp = lib_path + ".tmp%d" % os.getpid()
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + (
+            ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"] if sanitize else [])
         if verbose:
             print(" ".join(cmd), flush=True)
         res = subprocess.run(cmd, capture_output=True, text=True)
         if res.returncode != 0:
             sys.stderr.write(res.stdout + res.stderr)
             raise RuntimeError("hipcc failed linking libfftnk")
-        os.replace(tmp, LIB)
+        os.replace(tmp, lib_path)
     finally:
         for o in objs:
             if os.path.exists(o):
                 os.remove(o)
-    return LIB
+    return lib_path
 
 
 if __name__ == "__main__":
