@@ -33,9 +33,10 @@ __device__ __forceinline__ const T* byte_off(const T* p, unsigned b) {
   return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + b);
 }
 
-// Streaming accesses of the CG passes.  Fields that one pass reads or writes
-// once and that are not touched again before the data would be evicted anyway
-// (the Krylov vectors r, p, x in pass 1, the residual in pass 5) use
+// Streaming accesses of the operator passes.  Fields that one pass reads or
+// writes once and that are not touched again before the data would be evicted
+// anyway (the Krylov vectors r, p, x in pass 1, the residual in pass 5, the
+// direction and the result of a single operator application) use
 // non-temporal loads and stores.  With the 36 read and 27 write streams of
 // pass 1 in flight per voxel, the normal replacement policy held the HBM rate
 // about 10 % below the non-temporal one (128^3 FP64 and FP32, 192^3, 256^3).
@@ -44,10 +45,10 @@ __device__ __forceinline__ const T* byte_off(const T* p, unsigned b) {
 // fields fit the last-level cache, where pass 1 of the next iteration finds r.
 // Bit k of the policy switches the accesses of class k (per element size).
 #ifndef FFTNK_NT_POLICY64
-#define FFTNK_NT_POLICY64 (1 | 4 | 16 | 32)
+#define FFTNK_NT_POLICY64 (1 | 4 | 16 | 32 | 64 | 128)
 #endif
 #ifndef FFTNK_NT_POLICY32
-#define FFTNK_NT_POLICY32 (1 | 4)
+#define FFTNK_NT_POLICY32 (1 | 4 | 64 | 128)
 #endif
 enum {
   NT_P1_LOAD_VEC = 1,   // pass 1: loads of r, the previous p, x
@@ -55,7 +56,9 @@ enum {
   NT_P1_STORE_VEC = 4,  // pass 1: stores of x and p
   NT_P1_STORE_SPEC = 8, // pass 1: stores of the half spectrum
   NT_P5_LOAD_R = 16,    // pass 5 (CG): loads of r
-  NT_P5_STORE_R = 32    // pass 5 (CG): stores of r
+  NT_P5_STORE_R = 32,   // pass 5 (CG): stores of r
+  NT_OP_LOAD_P = 64,    // pass 1 (operator): loads of the direction
+  NT_OP_STORE_OUT = 128 // pass 5 (operator, projection): stores of the result
 };
 template <typename T>
 __host__ __device__ constexpr int nt_policy() {

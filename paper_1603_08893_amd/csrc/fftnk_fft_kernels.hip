@@ -163,7 +163,7 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
           for (int c = 0; c < 9; ++c) F[c] = *byte_off(Flin + off + c * n, vb);
         } else if (MODE == FWD_TANGENT) {
 #pragma unroll
-          for (int c = 0; c < 9; ++c) p[c] = *byte_off(in + off + c * n, vb);
+          for (int c = 0; c < 9; ++c) p[c] = ld_stream<NT_OP_LOAD_P>(byte_off(in + off + c * n, vb));
 #pragma unroll
           for (int c = 0; c < 9; ++c) F[c] = *byte_off(Flin + off + c * n, vb);
         } else {  // FWD_CG
@@ -825,7 +825,7 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
           const T w = h == 0 ? v[q].x : v[q].y;
           if (MODE == INV_OUT) {
             const T o = (T)scale * w;
-            out[idx] = (TO)o;
+            st_stream<NT_OP_STORE_OUT>(out + idx, (TO)o);
             acc[0] += (double)o * (double)o;
           } else if (MODE == INV_CGR) {
             const TO rn = (TO)((T)rin[q][h] - alpha * w);
