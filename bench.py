@@ -450,6 +450,7 @@ def main():
         "linear_solves": solves64,
         "cg_iterations": cg64,
         "cg_per_increment": [s["cg_iters"] for s in stats64],
+        "inputs_sha256": {"phase": __import__("hashlib").sha256(np.ascontiguousarray(phase).tobytes()).hexdigest()},
         "pbar_last": [float(v) for v in pbars64[-1]],
         "operator": {"ms": round(t_mv64, 4), "matvecs_per_s": round(1e3 / t_mv64, 1),
                      "bytes_5pass_per_voxel": round(sum(bpv64.values()), 2),

@@ -11,6 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libfftnk.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 SOURCES = ["fftnk_fft_kernels.hip", "fftnk_solver_kernels.hip", "fftnk_api.hip", "fftnk_stream.hip"]
 HEADERS = ["fftnk_internal.h", "fftnk_device.h", "fftnk_j2.h"]
 
@@ -64,7 +65,8 @@ def build(force=True, verbose=False, out=None, sanitize=False):
         if failed:
             raise RuntimeError("hipcc failed building libfftnk")
         tmp = lib_path + ".tmp%d" % os.getpid()
-        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + (
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
+            "-L" + os.path.join(ROCM, "lib"), "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + os.path.join(ROCM, "lib")] + (
             ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"] if sanitize else [])
         if verbose:
             print(" ".join(cmd), flush=True)

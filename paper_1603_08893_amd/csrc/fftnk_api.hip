@@ -13,6 +13,8 @@
 #include "fftnk.h"
 #include "fftnk_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -316,6 +318,15 @@ struct fftnk_ctx {
 
 namespace {
 
+// A named range on the host timeline (rocprofv3 --marker-trace) for the scope
+// of one host-driver step; free when no profiler is attached.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
 #define HIP_TRY(expr)                            \
   do {                                           \
     if ((expr) != hipSuccess) return FFTNK_EHIP; \
@@ -530,6 +541,7 @@ void middle_passes(int prec, const Launch& L, void* spec, const CgState* cg) {
 // partials: ||Y||^2 in SLOT_YY, ||b||^2 in SLOT_BB.  Y is produced by pass 1
 // in `mode` (the field in, or the tangent at Flin applied to Batch::uni).
 void rhs_pipeline(fftnk_ctx* c, int mode, const double* Y, const double* Flin, double sign) {
+  const Range range_("fftnk right-hand side");
   if (mode != FWD_COPY) refresh_j2_tangent(c, Flin);
   const Launch L = c->launch();
   launch_fwd_a2(PREC_F64, mode, L, c->material(), Y, nullptr, nullptr, nullptr, Flin, 1.0, c->spec(), nullptr);
@@ -608,6 +620,7 @@ int launch_iterations(fftnk_ctx* c, int k, bool eager = false) {
 int run_gmres(fftnk_ctx* c, double eta, int max_it);
 
 int run_cg(fftnk_ctx* c, double eta, int max_cg) {
+  const Range range_("fftnk linear solve");
   refresh_j2_tangent(c, c->flin());
   if (c->krylov == KRYLOV_GMRES) return run_gmres(c, eta, max_cg);
   if (c->graph_active != c->active) {  // the graphs hold the launch sizes of another mask
@@ -971,6 +984,7 @@ int run_gmres(fftnk_ctx* c, double eta, int max_it) {
 int newton_solve(fftnk_ctx* c, const double* Fbar, const std::vector<int>& run, bool warm, double eta_nw,
                  double eta_cg, int max_newton, int max_cg, std::vector<fftnk_stats>& st, std::vector<int>& status,
                  std::vector<double>& pbar) {
+  const Range range_("fftnk Newton iterations");
   const int nr = c->nrve;
   std::vector<int> done(nr, 0);
   std::vector<double> Fn(nr, 0.0);
@@ -1073,6 +1087,7 @@ int newton_solve(fftnk_ctx* c, const double* Fbar, const std::vector<int>& run, 
 // Commit the RVEs with status OK (transactional per RVE: F_t, J2 history),
 // copy their F and P out, restore the all-active mask.  *worst: first failure.
 int commit_rves(fftnk_ctx* c, const std::vector<int>& status, double* F_dev, double* P_dev, int* worst) {
+  const Range range_("fftnk commit");
   *worst = FFTNK_OK;
   for (int r = 0; r < c->nrve; ++r) {
     if (status[r]) {
@@ -1462,6 +1477,7 @@ int fftnk_set_plan(fftnk_ctx* c, unsigned policy) {
 }
 
 int fftnk_autotune(fftnk_ctx* c, int reps, int use_cache, unsigned* policy, double* ms) {
+  const Range range_("fftnk_autotune");
   if (!c || reps < 1 || reps > 1000) return FFTNK_EINVAL;
   if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
   const std::string key = tune_key(c);
@@ -1546,6 +1562,7 @@ int fftnk_reset_state(fftnk_ctx* c) {
 
 int fftnk_solve_increment(fftnk_ctx* c, const double* Fbar, double eta_nw, double eta_cg, int max_newton, int max_cg,
                           double* F_dev, double* P_dev, double* Pbar, fftnk_stats* stats) {
+  const Range range_("fftnk_solve_increment");
   if (!c || !Fbar || !Pbar) return FFTNK_EINVAL;
   if (!(eta_nw > 0) || !(eta_cg > 0) || max_newton < 2 || max_newton > FFTNK_MAX_SOLVES || max_cg < 1)
     return FFTNK_EINVAL;
@@ -1578,6 +1595,7 @@ int fftnk_solve_increment_mixed(fftnk_ctx* c, double* Fbar, const int* mask, con
                                 double tol_stress, int max_outer, double eta_nw, double eta_cg, int max_newton,
                                 int max_cg, double* F_dev, double* P_dev, double* Pbar, fftnk_stats* stats,
                                 int* outer) {
+  const Range range_("fftnk_solve_increment_mixed");
   if (!c || !Fbar || !mask || !Ptarget || !Pbar) return FFTNK_EINVAL;
   if (!(tol_stress > 0) || max_outer < 1 || !(eta_nw > 0) || !(eta_cg > 0) || max_newton < 2 ||
       max_newton > FFTNK_MAX_SOLVES || max_cg < 1)
@@ -1689,6 +1707,7 @@ int fftnk_solve_increment_mixed(fftnk_ctx* c, double* Fbar, const int* mask, con
 
 int fftnk_macro_tangent(fftnk_ctx* c, const int* want, double eta_cg, int max_cg, double* C_host,
                         fftnk_stats* stats) {
+  const Range range_("fftnk_macro_tangent");
   if (!c || !C_host || !(eta_cg > 0) || max_cg < 1) return FFTNK_EINVAL;
   if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
   const int nr = c->nrve;
@@ -1716,6 +1735,7 @@ int fftnk_macro_tangent(fftnk_ctx* c, const int* want, double eta_cg, int max_cg
 
 int fftnk_adjoint(fftnk_ctx* c, const double* gbar, double eta_cg, int max_cg, double* dLdmu, double* dLdK,
                   fftnk_stats* stats) {
+  const Range range_("fftnk_adjoint");
   if (!c || !gbar || !dLdmu || !(eta_cg > 0) || max_cg < 1) return FFTNK_EINVAL;
   if (!c->ws || !c->have_phase || !c->have_mat) return FFTNK_ESTATE;
   if (c->model != MODEL_SVK) return FFTNK_EUNSUPPORTED;  // the gradient formula is St. Venant-Kirchhoff's
