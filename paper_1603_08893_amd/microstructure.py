@@ -231,26 +231,26 @@ def c5_load_cases(mag=0.05):
     return out
 
 
+def c3_cell(r, seed0=1603000, sizes=(32, 48, 64, 96), per_size=16):
+    """Cell r of the 64-cell batch (see c3_batch)."""
+    N = sizes[r // per_size]
+    rng = np.random.default_rng(seed0 + r)
+    target = rng.uniform(0.20, 0.40)
+    chi = rng.uniform(5.0, 20.0)
+    H = rng.uniform(-0.05, 0.05, size=(3, 3))
+    ph, frac = rsa_spheres(N, target, seed=seed0 + r + 500000)
+    return {
+        "N": N,
+        "phase": ph,
+        "frac": frac,
+        "table": [(K_SOFT, MU_SOFT), (chi * K_SOFT, chi * MU_SOFT)],
+        "Fbar": (np.eye(3) + H).reshape(9),
+    }
+
+
 def c3_batch(seed0=1603000, sizes=(32, 48, 64, 96), per_size=16):
     """64 RVEs: sphere microstructures, per-RVE contrast and load.
 
     Returns a list of dicts with keys N, phase, frac, table, Fbar.
     """
-    out = []
-    r = 0
-    for N in sizes:
-        for _ in range(per_size):
-            rng = np.random.default_rng(seed0 + r)
-            target = rng.uniform(0.20, 0.40)
-            chi = rng.uniform(5.0, 20.0)
-            H = rng.uniform(-0.05, 0.05, size=(3, 3))
-            ph, frac = rsa_spheres(N, target, seed=seed0 + r + 500000)
-            out.append({
-                "N": N,
-                "phase": ph,
-                "frac": frac,
-                "table": [(K_SOFT, MU_SOFT), (chi * K_SOFT, chi * MU_SOFT)],
-                "Fbar": (np.eye(3) + H).reshape(9),
-            })
-            r += 1
-    return out
+    return [c3_cell(r, seed0, sizes, per_size) for r in range(len(sizes) * per_size)]
