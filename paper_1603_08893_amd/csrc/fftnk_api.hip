@@ -193,7 +193,10 @@ int make_geo(const std::vector<Grid>& cells, unsigned pol, Geo& o) {
   for (const Grid& g : o.g) {
     o.lds[0] = std::max(o.lds[0], row_lds(g, g.rt, g.ax[2].reg, 16));
     o.lds[1] = std::max(o.lds[1], row_lds(g, g.rt, g.ax[2].reg, 8));
-    for (int d = 0; d < 3; ++d) o.eng[d] |= g.ax[d].reg == 8 ? 2 : (g.ax[d].reg == 12 ? 4 : 1);
+    for (int d = 0; d < 3; ++d) {
+      const bool pairs = d < 2 && col_engine(g.ax[d].reg, g.ax[d].n, g.h, g.spec_off, 4) == 16;
+      o.eng[d] |= pairs ? 8 : g.ax[d].reg == 8 ? 2 : (g.ax[d].reg == 12 ? 4 : 1);
+    }
     o.lds[6] = std::max(o.lds[6], row_lds(g, g.rt1, pass1_engine(g.ax[2].reg), 16));
     o.lds[7] = std::max(o.lds[7], row_lds(g, g.rt1, pass1_engine(g.ax[2].reg), 8));
     o.lds[2] = std::max(o.lds[2], col_lds(g, 1, 16));
@@ -224,7 +227,8 @@ struct fftnk_ctx {
   int nblk[NKIND] = {};
   std::vector<int> graph_active;  // the mask the CG graphs were captured under
   size_t lds[8] = {};  // row64, row32, col1_64, col1_32, col0_64, col0_32, row1_64, row1_32
-  int eng[3] = {};     // per axis: bit 0 some cell on the LDS engine, bit 1 on the 8-point, bit 2 on the 12-point one
+  int eng[3] = {};     // per axis: bit 0 some cell on the LDS engine, bit 1 on the 8-point, bit 2 on the 12-point one,
+                       // bit 3 on the 8-point one with FP32 pencil pairs
   int nyq_id = 0;      // FFTNK_OPT_NYQUIST
   unsigned policy = 0;  // fftnk_set_plan
   int krylov = KRYLOV_CG;  // fftnk_set_krylov

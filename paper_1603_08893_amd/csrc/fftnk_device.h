@@ -90,6 +90,12 @@ struct alignas(2 * sizeof(T)) cx {
   T x, y;
 };
 
+// two complex values adjacent in memory (one 4 sizeof(T)-byte access)
+template <typename T>
+struct alignas(4 * sizeof(T)) cx2 {
+  cx<T> a, b;
+};
+
 template <typename T>
 __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) {
   return {a.x + b.x, a.y + b.y};

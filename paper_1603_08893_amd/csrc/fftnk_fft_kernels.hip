@@ -31,7 +31,8 @@ static int reg_pencils(const AxisPlan& pl) { return kThreads / (pl.n / pl.reg); 
 
 int col1_blocks(const Grid& g, int prec) {
   if (g.ax[1].reg) {
-    const long long np = 9LL * g.n0 * g.h, mb = reg_pencils(g.ax[1]);
+    long long np = 9LL * g.n0 * g.h, mb = reg_pencils(g.ax[1]);
+    if (prec == PREC_F32 && col_engine(g.ax[1].reg, g.n1, g.h, g.spec_off, 4) == 16) mb *= 2;
     return (int)((np + mb - 1) / mb);
   }
   const int M = prec == PREC_F64 ? g.m64 : g.m32;
@@ -40,7 +41,8 @@ int col1_blocks(const Grid& g, int prec) {
 
 int col0_blocks(const Grid& g, int prec) {
   if (g.ax[0].reg) {
-    const long long np = 3LL * g.n1 * g.h, mb = reg_pencils(g.ax[0]);
+    long long np = 3LL * g.n1 * g.h, mb = reg_pencils(g.ax[0]);
+    if (prec == PREC_F32 && col_engine(g.ax[0].reg, g.n0, g.h, g.spec_off, 4) == 16) mb *= 2;
     return (int)((np + mb - 1) / mb);
   }
   const int M = prec == PREC_F64 ? g.m64 : g.m32;
@@ -310,7 +312,7 @@ __device__ __forceinline__ void tile_col_a1(const Batch& B, cx<T>* __restrict__ 
   const int rv = find_rve(B, sizeof(T) == 8 ? K_COL1_64 : K_COL1_32, b, local);
   if (skip_rve(B, cg, rv)) return;
   const auto& g = grid_of(B, rv);
-  if (g.ax[1].reg != ENG) return;  // another engine's launch owns this cell
+  if (col_engine(g.ax[1].reg, g.n1, g.h, g.spec_off, sizeof(T)) != ENG) return;  // another launch owns this cell
   extern __shared__ unsigned char smem_raw[];
   const int N1 = g.n1, H = g.h;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
@@ -318,11 +320,34 @@ __device__ __forceinline__ void tile_col_a1(const Batch& B, cx<T>* __restrict__ 
   cx<T>* S0 = spec + g.spec_off;
 
   if constexpr (ENG != 0) {
-    constexpr int P = ENG;  // points per thread of the register engine
+    constexpr int P = ENG == 16 ? 8 : ENG;  // points per thread of the register engine
     cx<T>* xl = tw + padded_len(N1);
     const int Tp = N1 / P, Mb = kThreads / Tp;
     const int m = threadIdx.x % Mb, t = threadIdx.x / Mb;
     const long long npen = 9LL * g.n0 * H;
+    if constexpr (ENG == 16) {
+      // pencils pen, pen + 1 (same k2 line): one 16-byte access per element
+      long long pen = 2 * ((long long)local * Mb + m);
+      const bool valid = pen < npen;  // npen is even here
+      if (!valid) pen = 0;
+      const long long plane = pen / H;
+      cx2<T>* base = reinterpret_cast<cx2<T>*>(S0 + plane * N1 * H + (pen - plane * H));
+      const long long hs = H / 2;  // a row of the spectrum in pairs
+      cx<T> va[P], vb[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const cx2<T> w = valid ? base[(long long)(t + Tp * q) * hs] : cx2<T>{};
+        va[q] = w.a;
+        vb[q] = w.b;
+      }
+      reg_fft<T, false, P>(va, N1, t, tw, INV, xl + m);
+      reg_fft<T, false, P>(vb, N1, t, tw, INV, xl + m);
+      if (valid) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) base[(long long)(t + Tp * q) * hs] = cx2<T>{va[q], vb[q]};
+      }
+      return;
+    }
     long long pen = (long long)local * Mb + m;
     const bool valid = pen < npen;
     if (!valid) pen = 0;
@@ -409,6 +434,90 @@ __device__ __forceinline__ void project_point(cx<T>& a0, cx<T>& a1, cx<T>& a2, i
   a2 = cscale(s, xi2 * coef);
 }
 
+// One pencil (tensor row i, k1, k2) of pass 3 on the register engine, held as
+// v[component][point]: transform, project, transform back, in place.  Two
+// forward and two inverse transforms (the scheme of the single-pencil path of
+// tile_col_a0_project), or three of each with the identity choice at Nyquist
+// frequencies (ID).
+template <typename T, int P, bool ID, typename G>
+__device__ __forceinline__ void reg_pencil_project(cx<T> (&v)[3][P], const G& g, int k1, int k2, int t,
+                                                   const cx<T>* tw, cx<T>* xl, T rn0, T rn1, T rn2) {
+  const int N0 = g.n0, Tp = N0 / P;
+  if constexpr (ID) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) reg_fft<T, false, P>(v[c], N0, t, tw, false, xl);
+#pragma unroll
+    for (int q = 0; q < P; ++q) project_point(v[0][q], v[1][q], v[2][q], t + Tp * q, k1, k2, g, rn0, rn1, rn2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) reg_fft<T, false, P>(v[c], N0, t, tw, true, xl);
+  } else {
+    const int f1 = signed_freq(k1, g.n1);
+    const T xi1 = (T)f1 * rn1, xi2 = (T)k2 * rn2;
+    const bool pen_zero = (g.n1 % 2 == 0) && (2 * k1 == g.n1);
+#pragma unroll
+    for (int q = 0; q < P; ++q) v[1][q] = cscale(v[1][q], xi1) + cscale(v[2][q], xi2);
+    reg_fft<T, false, P>(v[1], N0, t, tw, false, xl);
+    reg_fft<T, false, P>(v[0], N0, t, tw, false, xl);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const int k0 = t + Tp * q;
+      const int f0 = signed_freq(k0, N0);
+      const T xi0 = (T)f0 * rn0;
+      const bool zero = pen_zero || (f0 == 0 && f1 == 0 && k2 == 0) || ((N0 % 2 == 0) && (2 * k0 == N0));
+      const T c = zero ? (T)0 : (T)g.inv_n / (xi0 * xi0 + xi1 * xi1 + xi2 * xi2);
+      const cx<T> sc = cscale(cscale(v[0][q], xi0) + v[1][q], c);
+      v[0][q] = cscale(sc, xi0);
+      v[1][q] = sc;
+    }
+    reg_fft<T, false, P>(v[0], N0, t, tw, true, xl);
+    reg_fft<T, false, P>(v[1], N0, t, tw, true, xl);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      v[2][q] = cscale(v[1][q], xi2);
+      v[1][q] = cscale(v[1][q], xi1);
+    }
+  }
+}
+
+// Pass 3 on the register engine for FP32 pencils taken in k2-adjacent pairs
+// (col_engine 16): every load and store is one 16-byte access covering both
+// pencils of the pair, each pencil transformed and projected on its own.
+template <typename T, int P, bool ID, typename G>
+__device__ __forceinline__ void col_a0_project_pairs(const G& g, cx<T>* __restrict__ S0, const cx<T>* tw, cx<T>* xl,
+                                                     int local, int Mb, int m, int t, T rn0, T rn1, T rn2) {
+  const int N0 = g.n0, N1 = g.n1, H = g.h;
+  const int Tp = N0 / P;
+  const long long S2 = (long long)N1 * H / 2;  // element stride along a0, in pairs
+  const long long cstride2 = g.rows * H / 2;
+  const long long npen = 3LL * N1 * H;
+  long long pen = 2 * ((long long)local * Mb + m);
+  const bool valid = pen < npen;  // npen is even here
+  if (!valid) pen = 0;
+  const long long qq = pen / H;
+  const int k2 = (int)(pen - qq * H);
+  const int i = (int)(qq / N1), k1 = (int)(qq - (long long)i * N1);
+  cx2<T>* base = reinterpret_cast<cx2<T>*>(S0) + (long long)(3 * i) * cstride2 + ((long long)k1 * H + k2) / 2 +
+                 (long long)t * S2;
+  auto at = [&](int c, int q) { return base + (long long)c * cstride2 + (long long)q * Tp * S2; };
+  cx<T> va[3][P], vb[3][P];  // the two pencils of the pair, [component][point]
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const cx2<T> v = valid ? *at(c, q) : cx2<T>{};
+      va[c][q] = v.a;
+      vb[c][q] = v.b;
+    }
+  reg_pencil_project<T, P, ID>(va, g, k1, k2, t, tw, xl, rn0, rn1, rn2);
+  reg_pencil_project<T, P, ID>(vb, g, k1, k2 + 1, t, tw, xl, rn0, rn1, rn2);
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int q = 0; q < P; ++q) *at(c, q) = cx2<T>{va[c][q], vb[c][q]};
+  }
+}
+
 template <typename T, int ENG>
 __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __restrict__ spec,
                                                              const CgState* __restrict__ cg, const int b) {
@@ -416,7 +525,7 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
   const int rv = find_rve(B, sizeof(T) == 8 ? K_COL0_64 : K_COL0_32, b, local);
   if (skip_rve(B, cg, rv)) return;
   const auto& g = grid_of(B, rv);
-  if (g.ax[0].reg != ENG) return;  // another engine's launch owns this cell
+  if (col_engine(g.ax[0].reg, g.n0, g.h, g.spec_off, sizeof(T)) != ENG) return;  // another launch owns this cell
   extern __shared__ unsigned char smem_raw[];
   const int N0 = g.n0, N1 = g.n1, H = g.h;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
@@ -427,11 +536,15 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
   const T rn0 = (T)1 / (T)N0, rn1 = (T)1 / (T)N1, rn2 = (T)1 / (T)g.n2;
 
   if constexpr (ENG != 0) {
-    constexpr int P = ENG;  // points per thread of the register engine
+    constexpr int P = ENG == 16 ? 8 : ENG;  // points per thread of the register engine
     cx<T>* xl = tw + padded_len(N0);
     const int Tp = N0 / P, Mb = kThreads / Tp;
     const int m = threadIdx.x % Mb, t = threadIdx.x / Mb;
     const long long npen = 3LL * N1 * H;
+    if constexpr (ENG == 16) {
+      col_a0_project_pairs<T, P, false>(g, S0, tw, xl + m, local, Mb, m, t, rn0, rn1, rn2);
+      return;
+    }
     long long pen = (long long)local * Mb + m;
     const bool valid = pen < npen;
     if (!valid) pen = 0;
@@ -592,7 +705,7 @@ __device__ __forceinline__ void tile_col_a0_project_id(const Batch& B, cx<T>* __
   const int rv = find_rve(B, sizeof(T) == 8 ? K_COL0_64 : K_COL0_32, b, local);
   if (skip_rve(B, cg, rv)) return;
   const auto& g = grid_of(B, rv);
-  if (g.ax[0].reg != ENG) return;  // another engine's launch owns this cell
+  if (col_engine(g.ax[0].reg, g.n0, g.h, g.spec_off, sizeof(T)) != ENG) return;  // another launch owns this cell
   extern __shared__ unsigned char smem_raw[];
   const int N0 = g.n0, N1 = g.n1, H = g.h;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
@@ -603,11 +716,15 @@ __device__ __forceinline__ void tile_col_a0_project_id(const Batch& B, cx<T>* __
   const T rn0 = (T)1 / (T)N0, rn1 = (T)1 / (T)N1, rn2 = (T)1 / (T)g.n2;
 
   if constexpr (ENG != 0) {
-    constexpr int P = ENG;
+    constexpr int P = ENG == 16 ? 8 : ENG;
     cx<T>* xl = tw + padded_len(N0);
     const int Tp = N0 / P, Mb = kThreads / Tp;
     const int m = threadIdx.x % Mb, t = threadIdx.x / Mb;
     const long long npen = 3LL * N1 * H;
+    if constexpr (ENG == 16) {
+      col_a0_project_pairs<T, P, true>(g, S0, tw, xl + m, local, Mb, m, t, rn0, rn1, rn2);
+      return;
+    }
     long long pen = (long long)local * Mb + m;
     const bool valid = pen < npen;
     if (!valid) pen = 0;
@@ -696,11 +813,13 @@ __device__ __forceinline__ void tile_col_a0_project_id(const Batch& B, cx<T>* __
 }
 
 // Three work-groups per CU, but two (256 VGPRs) where the registers of a
-// pencil's transforms do not fit otherwise: FP64 12-point pencils and the
-// identity choice's three transforms; one (accumulation registers too) for
-// the identity choice's three FP64 12-point transforms.
+// pencil's transforms do not fit otherwise: FP64 12-point pencils, the
+// identity choice's three transforms and FP32 pencil pairs under it; one
+// (accumulation registers too) for the identity choice's three FP64 12-point
+// transforms.
 template <typename T, int ENG, bool NYQ_ID>
 constexpr int a0_groups_per_cu() {
+  if (ENG == 16) return NYQ_ID ? 2 : 3;
   if (sizeof(T) == 8 && NYQ_ID && ENG == 12) return 1;
   return (sizeof(T) == 8 && (ENG == 12 || (NYQ_ID && ENG != 0))) || (NYQ_ID && ENG == 12) ? 2 : 3;
 }
@@ -990,7 +1109,10 @@ static void col_a1_t(const Launch& L, void* spec, const CgState* cg) {
   const int ntiles = L.nblk[sizeof(T) == 8 ? K_COL1_64 : K_COL1_32];
   const size_t lds = sizeof(T) == 8 ? L.lds_col1_64 : L.lds_col1_32;
   cx<T>* sp = static_cast<cx<T>*>(spec);
-  if (L.eng[1] & 2) launch_tiles(&k_col_a1<T, INV, 8>, ntiles, lds, L.s, L.b, sp, cg);
+  // cells with FP32 pencil pairs (bit 3) run on the 8-point kernel in FP64
+  if (L.eng[1] & (sizeof(T) == 8 ? 10 : 2)) launch_tiles(&k_col_a1<T, INV, 8>, ntiles, lds, L.s, L.b, sp, cg);
+  if constexpr (sizeof(T) == 4)
+    if (L.eng[1] & 8) launch_tiles(&k_col_a1<T, INV, 16>, ntiles, lds, L.s, L.b, sp, cg);
   if (L.eng[1] & 4) launch_tiles(&k_col_a1<T, INV, 12>, ntiles, lds, L.s, L.b, sp, cg);
   if (L.eng[1] & 1) launch_tiles(&k_col_a1<T, INV, 0>, ntiles, lds, L.s, L.b, sp, cg);
 }
@@ -1014,13 +1136,18 @@ static void col_a0_t(const Launch& L, void* spec, const CgState* cg) {
   const int ntiles = L.nblk[sizeof(T) == 8 ? K_COL0_64 : K_COL0_32];
   const size_t lds = sizeof(T) == 8 ? L.lds_col0_64 : L.lds_col0_32;
   cx<T>* sp = static_cast<cx<T>*>(spec);
+  const int eng8 = sizeof(T) == 8 ? 10 : 2;  // cells with FP32 pencil pairs (bit 3) run on the 8-point kernel in FP64
   if (L.nyq) {
-    if (L.eng[0] & 2) launch_tiles(&k_col_a0_project<T, 8, true>, ntiles, lds, L.s, L.b, sp, cg);
+    if (L.eng[0] & eng8) launch_tiles(&k_col_a0_project<T, 8, true>, ntiles, lds, L.s, L.b, sp, cg);
+    if constexpr (sizeof(T) == 4)
+      if (L.eng[0] & 8) launch_tiles(&k_col_a0_project<T, 16, true>, ntiles, lds, L.s, L.b, sp, cg);
     if (L.eng[0] & 4) launch_tiles(&k_col_a0_project<T, 12, true>, ntiles, lds, L.s, L.b, sp, cg);
     if (L.eng[0] & 1) launch_tiles(&k_col_a0_project<T, 0, true>, ntiles, lds, L.s, L.b, sp, cg);
     return;
   }
-  if (L.eng[0] & 2) launch_tiles(&k_col_a0_project<T, 8, false>, ntiles, lds, L.s, L.b, sp, cg);
+  if (L.eng[0] & eng8) launch_tiles(&k_col_a0_project<T, 8, false>, ntiles, lds, L.s, L.b, sp, cg);
+  if constexpr (sizeof(T) == 4)
+    if (L.eng[0] & 8) launch_tiles(&k_col_a0_project<T, 16, false>, ntiles, lds, L.s, L.b, sp, cg);
   if (L.eng[0] & 4) launch_tiles(&k_col_a0_project<T, 12, false>, ntiles, lds, L.s, L.b, sp, cg);
   if (L.eng[0] & 1) launch_tiles(&k_col_a0_project<T, 0, false>, ntiles, lds, L.s, L.b, sp, cg);
 }

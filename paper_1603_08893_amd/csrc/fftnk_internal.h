@@ -62,6 +62,23 @@ struct Grid {
   AxisPlan ax[3];
 };
 
+// FP32 register-engine column passes take their pencils in k2-adjacent pairs
+// (one 16-byte access per element for the two) where a work-group's pencils
+// would otherwise span fewer than 128 bytes of a spectrum row: register plans
+// that leave fewer than 16 pencils per work-group (n = 256), when the half
+// line h is even (so that no pair straddles two k2 lines) and the cell's
+// spectrum starts on a pair boundary (16-byte aligned).
+__host__ __device__ constexpr bool col_pairs32(int pencils_per_group, int h, long long spec_off) {
+  return pencils_per_group < 16 && h % 2 == 0 && spec_off % 2 == 0;
+}
+
+// Engine of a cell's column pass over an axis (a1 or a0) for elements of esz
+// bytes: the axis' register engine (8, 12) or LDS engine (0), or 16 for the
+// 8-point register engine on FP32 pencil pairs.
+__host__ __device__ constexpr int col_engine(int reg, int n, int h, long long spec_off, int esz) {
+  return esz == 4 && reg == 8 && col_pairs32(kThreads / (n / 8), h, spec_off) ? 16 : reg;
+}
+
 // Launch kinds: every kernel launch covers all RVEs of a context; work-group b
 // belongs to RVE r when starts[kind][r] <= b < starts[kind][r + 1].
 enum {
@@ -199,7 +216,8 @@ struct Launch {
   Batch b;
   int nblk[NKIND];
   size_t lds_row64, lds_row32, lds_col1_64, lds_col1_32, lds_col0_64, lds_col0_32, lds_row1_64, lds_row1_32;
-  int eng[3];  // per grid axis: bit 0 some cell transforms it with the LDS engine, bit 1 / 2 with the 8- / 12-point register engine
+  int eng[3];  // per grid axis: bit 0 some cell transforms it with the LDS engine, bit 1 / 2 with the 8- / 12-point
+               // register engine, bit 3 with the 8-point one on a cell where FP32 takes pencil pairs (col_engine)
   int nyq;     // 1: the cells use the identity choice at Nyquist frequencies (pass 3 variant)
   hipStream_t s;
 };

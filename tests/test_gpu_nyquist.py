@@ -47,7 +47,9 @@ def _rel(a, b):
 
 
 SHAPES = [(8, 8, 8), (64, 64, 64), (24, 24, 24), (12, 10, 16), (7, 6, 9), (6, 7, 9), (5, 5, 8), (48, 40, 36),
-          (3, 64, 4), (10, 48, 12), (6, 12, 96), (4, 6, 192), (2, 2, 2), (96, 6, 8), (12, 7, 6)]
+          (3, 64, 4), (10, 48, 12), (6, 12, 96), (4, 6, 192), (2, 2, 2), (96, 6, 8), (12, 7, 6),
+          # 256-long a0 / a1 with even h: FP32 pencil pairs
+          (256, 5, 8), (6, 256, 4)]
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])

@@ -49,7 +49,9 @@ def _rel(a, b):
 SHAPES = [(5, 5, 5), (8, 8, 8), (7, 6, 9), (24, 24, 24), (31, 31, 31), (32, 32, 32), (12, 10, 17), (48, 40, 36),
           (3, 64, 4),
           # lengths 3 * 2^k (12-point register engine: radix 12, then 4 / 2) on a1 / a2, and on a0
-          (10, 48, 12), (6, 12, 96), (3, 192, 24), (4, 6, 192), (96, 8, 10), (192, 4, 6), (12, 6, 8), (24, 5, 4)]
+          (10, 48, 12), (6, 12, 96), (3, 192, 24), (4, 6, 192), (96, 8, 10), (192, 4, 6), (12, 6, 8), (24, 5, 4),
+          # a 256-long a0 / a1 axis: FP32 column passes take k2-adjacent pencil pairs where h is even
+          (256, 5, 8), (6, 256, 4), (256, 256, 6), (5, 256, 9)]
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])
@@ -80,6 +82,27 @@ def test_apply_operator_parity(torch_cuda, orc, shape, prec, tol):
     s.set_linearization(torch.from_numpy(F.reshape(-1)))
     got = s.apply_operator(torch.from_numpy(p.reshape(-1))).double().cpu().numpy()
     assert_fields_close(got, ref, tol)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 5e-6)])
+def test_project_parity_batched_pairs(torch_cuda, orc, prec, tol):
+    """A batch whose 256-long cells start on even and on odd spectrum offsets
+    (FP32 pencil pairs only where the offset is even), each cell against the
+    oracle's projection."""
+    torch = torch_cuda
+    from paper_1603_08893_amd.fftnk import Solver
+    dims = [(6, 256, 4), (256, 4, 8), (3, 5, 5), (6, 256, 4), (256, 4, 8)]  # offsets even, even, -, odd, odd
+    print("project batched pairs", prec, flush=True)
+    fields = [ms.random_field(d, seed=31 + r) for r, d in enumerate(dims)]
+    s = Solver(dims, precision=prec)
+    s.set_phases(np.zeros(sum(int(np.prod(d)) for d in dims), dtype=np.uint8))
+    s.set_material([(1.0, 1.0)])
+    got = s.project(torch.from_numpy(np.concatenate([f.reshape(-1) for f in fields]))).double().cpu().numpy()
+    off = 0
+    for d, f in zip(dims, fields):
+        m = 9 * int(np.prod(d))
+        assert_fields_close(got[off:off + m], orc.project(f), tol, d)
+        off += m
 
 
 def test_constitutive_parity(torch_cuda, orc):

@@ -40,6 +40,18 @@ def _reg_engine(n):
     return 0
 
 
+def _pairs32(c, axis):
+    """FP32 column passes over a 256-long axis take k2-adjacent pencil pairs
+    (one 16-byte access per element) where h and the spectrum offset are even."""
+    ax = c["axes"][axis]
+    return axis < 2 and ax["reg"] == 8 and THREADS // (ax["n"] // 8) < 16 and c["h"] % 2 == 0 and \
+        c["spec_off"] % 2 == 0
+
+
+def _eng_bit(c, axis):
+    return 8 if _pairs32(c, axis) else {8: 2, 12: 4, 0: 1}[c["axes"][axis]["reg"]]
+
+
 def _check_cell(c, prec, policy=0):
     n0, n1, n2 = c["n"]
     h = n2 // 2 if n2 % 2 == 0 else (n2 + 1) // 2
@@ -58,6 +70,8 @@ def _check_cell(c, prec, policy=0):
         for key, M in ((k64, c["m64"]), (k32, c["m32"])):
             if ax["reg"]:
                 per = THREADS // (ax["n"] // ax["reg"])
+                if key.endswith("_32") and _pairs32(c, axis):
+                    per *= 2
                 assert b[key] * per >= npen > (b[key] - 1) * per, (key, c)
             else:
                 # M consecutive pencils in k2-fastest order (across k2 lines where h < M)
@@ -86,8 +100,7 @@ def test_single_cell_geometry(prec):
         assert d["nblk"] == [b["row"], b["row1"], b["col1_64"], b["col1_32"], b["col0_64"], b["col0_32"],
                              b["elem9"], b["vox"]]
         for axis in range(3):
-            bit = {8: 2, 12: 4, 0: 1}[c["axes"][axis]["reg"]]
-            assert d["eng"][axis] == bit, (shape, d["eng"])
+            assert d["eng"][axis] == _eng_bit(c, axis), (shape, d["eng"])
         esz = 8 if prec == "fp64" else 4
         assert d["workspace_bytes"] >= 9 * math.prod(shape) * (3 * 8 + 4 * esz)
 
@@ -109,7 +122,7 @@ def test_batched_geometry():
         b = c["blocks"]
         sums += [b["row"], b["row1"], b["col1_64"], b["col1_32"], b["col0_64"], b["col0_32"], b["elem9"], b["vox"]]
         for axis in range(3):
-            eng[axis] |= {8: 2, 12: 4, 0: 1}[c["axes"][axis]["reg"]]
+            eng[axis] |= _eng_bit(c, axis)
     assert d["nblk"] == sums.tolist() and d["eng"] == eng
     assert max(d["lds"]) <= LDS_LIMIT
     # one twiddle table per distinct length
