@@ -203,6 +203,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-192", action="store_true", help="skip the 192^3 operator and CG-iteration rows")
+    ap.add_argument("--no-256", action="store_true", help="skip the 256^3 operator rows")
     ap.add_argument("--operator-only", action="store_true",
                     help="profiling mode: only the operator passes at a synthetic linearisation point, plus one "
                          "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
@@ -417,6 +418,38 @@ def main():
         print("# 192^3: %s" % {k: (v["operator_ms"], v["cg_iteration_ms"]) for k, v in big.items()}, file=sys.stderr,
               flush=True)
 
+    # ------------------------------------------------------------ 256^3: operator alone (no solve)
+    big256 = {}
+    if not args.no_256:
+        N3 = 256
+        ph3 = ms.grf_threshold(N3, ell=8.0, frac=0.3, seed=1603)
+        Flin = torch.from_numpy(ms.near_identity_field((N3,) * 3, seed=43, scale=0.01).reshape(-1)).to(dev)
+        for prec, pb in (("fp64", 8), ("fp32", 4)):
+            s = Solver((N3,) * 3, precision=prec)
+            s.set_phases(ph3)
+            s.set_material(TABLE)
+            s.set_linearization(Flin)
+            p = s.project(torch.from_numpy(ms.random_field((N3,) * 3, seed=42).reshape(-1)).to(dev))
+            out = s.field()
+            for _ in range(3):
+                s.apply_operator(p, out)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(20):
+                s.apply_operator(p, out)
+            e1.record()
+            torch.cuda.synchronize()
+            t_op = e0.elapsed_time(e1) / 20
+            ob = sum(pass_bytes_per_voxel(pb, N3).values()) * N3 ** 3
+            big256[prec] = {"operator_ms": round(t_op, 4), "operator_GB_s": round(ob / (t_op * 1e-3) / 1e9, 1),
+                            "operator_frac": round(ob / (t_op * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "operator_frac_of_ceiling": round(ob / (t_op * 1e-3) / 1e9 / ceiling, 4)}
+            del s, p, out
+            torch.cuda.empty_cache()
+        del Flin
+        torch.cuda.empty_cache()
+        print("# 256^3 operator: %s" % {k: v["operator_ms"] for k, v in big256.items()}, file=sys.stderr, flush=True)
+
     # ------------------------------------------------------------ CPU oracle on a bounded sample
     cpu = None if args.no_cpu_baseline else cpu_baseline_leg()
 
@@ -474,6 +507,7 @@ def main():
                          "kernels": cg_kernel_rows(cgk, cgb, n, ceiling)},
         "stream_ceiling": ceil,
         "grid_192": big,
+        "grid_256": big256,
         "pbar_rel_err_vs_oracle": vs_oracle,
         "fp32_mixed": fp32,
         "cpu_baseline": cpu,
