@@ -56,17 +56,29 @@ def pass_bytes_per_voxel(prec_bytes, n2):
     return {1: 2 * field + 1 + spec, 2: 2 * spec, 3: 2 * spec, 4: 2 * spec, 5: spec + field}
 
 
-def cg_bytes_per_voxel(prec_bytes, n2):
+def cg_bytes_per_voxel(prec_bytes, n2, x_window=8):
     """Algorithmic HBM bytes per voxel of each kernel of one CG iteration (after
-    the first): pass 1 reads r, the previous p, x and the linearisation point F
-    (and one phase byte), writes x (deferred update), p and the spectrum; passes
-    2-4 read and write the spectrum; pass 5 reads the spectrum and r, writes r;
-    alpha and beta touch only per-cell scalars and block partial sums."""
+    the first), averaged over a window of W = x_window iterations: pass 1 reads
+    r, the previous p and the linearisation point F (and one phase byte), writes
+    p and the spectrum, and once per window reads x and the W - 1 older
+    directions and writes x (the deferred x updates; W = 1: every iteration);
+    passes 2-4 read and write the spectrum; pass 5 reads the spectrum and r,
+    writes r; alpha and beta touch only per-cell scalars and block partial sums."""
     op = pass_bytes_per_voxel(prec_bytes, n2)
     field = 9 * prec_bytes
     spec = op[2] / 2
-    return {"pass1": 4 * field + 1 + 2 * field + spec, "alpha": 0.0, "pass2": op[2], "pass3": op[3],
-            "pass4": op[4], "pass5": spec + 2 * field, "beta": 0.0}
+    W = x_window
+    return {"pass1": 3 * field + 1 + field + spec + (W + 1) * field / W, "alpha": 0.0, "pass2": op[2],
+            "pass3": op[3], "pass4": op[4], "pass5": spec + 2 * field, "beta": 0.0}
+
+
+def pass1_variant_bytes(prec_bytes, n2, x_window):
+    """Pass 1 of the CG inside a window (no x update) and at its start (x
+    updated with the window's W directions), bytes per voxel."""
+    field = 9 * prec_bytes
+    plain = 3 * field + 1 + field + pass_bytes_per_voxel(prec_bytes, n2)[2] / 2
+    return {"pass1_within_window": plain if x_window > 1 else plain + 2 * field,
+            "pass1_xupdate": plain + (x_window + 1) * field}
 
 
 def three_kernel_bytes_per_voxel(prec_bytes, n2):
@@ -204,6 +216,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-192", action="store_true", help="skip the 192^3 operator and CG-iteration rows")
     ap.add_argument("--no-256", action="store_true", help="skip the 256^3 operator rows")
+    ap.add_argument("--x-window", type=int, default=None,
+                    help="CG directions kept for the windowed x update (1..8; default: the library's)")
     ap.add_argument("--operator-only", action="store_true",
                     help="profiling mode: only the operator passes at a synthetic linearisation point, plus one "
                          "1 GiB device copy (the reference for scaling memory counters); prints per-pass times")
@@ -239,7 +253,7 @@ def main():
           flush=True)
 
     def make(prec):
-        s = Solver((N, N, N), precision=prec)
+        s = Solver((N, N, N), precision=prec, x_window=args.x_window)
         s.set_phases(phase)
         s.set_material(TABLE)
         return s
@@ -278,8 +292,12 @@ def main():
     # state of the last timed increment)
     F_lin = s64.get_state()
     n = N ** 3
-    cgk = s64.profile_cg(20)
-    cgb = cg_bytes_per_voxel(8, N)
+    cgk, p1var = s64.profile_cg(20, detail=True)
+    cgb = cg_bytes_per_voxel(8, N, s64.x_window)
+    p1b = pass1_variant_bytes(8, N, s64.x_window)
+    for key in ("pass1_within_window", "pass1_xupdate"):
+        p1var[key] = {"ms": round(p1var[key], 5), "bytes_per_voxel": p1b[key],
+                      "GB_s": round(p1b[key] * n / (p1var[key] * 1e-3) / 1e9, 1)}
     cg_iter_ms = sum(cgk.values())
     dom = max(cgk, key=lambda k: cgk[k])
     achieved = cgb[dom] * n / (cgk[dom] * 1e-3) / 1e9
@@ -343,7 +361,12 @@ def main():
         torch.cuda.synchronize()
         sec32 = e0.elapsed_time(e1) / 1e3
         err = max(float(np.max(np.abs(a - b)) / np.max(np.abs(b))) for a, b in zip(pbars32, pbars64))
-        cgk32 = s32.profile_cg(20)
+        cgk32, p1var32 = s32.profile_cg(20, detail=True)
+        x_window32 = s32.x_window
+        p1b32 = pass1_variant_bytes(4, N, x_window32)
+        for key in ("pass1_within_window", "pass1_xupdate"):
+            p1var32[key] = {"ms": round(p1var32[key], 5), "bytes_per_voxel": p1b32[key],
+                            "GB_s": round(p1b32[key] * n / (p1var32[key] * 1e-3) / 1e9, 1)}
         t_mv32, passes32 = operator_bench(s32, args.matvec_reps)
         bpv32 = pass_bytes_per_voxel(4, N)
         fp32 = {
@@ -370,11 +393,12 @@ def main():
     for row in pass_rows.values():
         row["frac_of_ceiling"] = round(row["GB_s"] / ceiling, 4)
     if fp32 is not None:
-        cb32 = cg_bytes_per_voxel(4, N)
+        cb32 = cg_bytes_per_voxel(4, N, x_window32)
         rows32 = cg_kernel_rows(fp32.pop("cg_iteration_kernels"), cb32, n, ceiling)
         d32 = max((k for k in rows32 if cb32[k] > 0), key=lambda k: rows32[k]["ms"])
         fp32["cg_iteration"] = {"ms": round(sum(r["ms"] for r in rows32.values()), 4),
-                                "bytes_per_voxel": round(sum(cb32.values()), 2), "kernels": rows32}
+                                "bytes_per_voxel": round(sum(cb32.values()), 2), "kernels": rows32,
+                                "x_window": x_window32, "pass1_variants": p1var32}
         fp32["roofline"] = {"bound": "hbm", "kernel": KERNEL_NAMES[d32].replace("double", "float"),
                             "achieved": rows32[d32]["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                             "frac": rows32[d32]["frac"], "frac_of_ceiling": rows32[d32]["frac_of_ceiling"],
@@ -392,7 +416,7 @@ def main():
             s.set_material(TABLE)
             s.solve_increment(sched[0], 1e-5, 1e-8, fields=False)
             k = s.profile_cg(10)
-            cb = cg_bytes_per_voxel(pb, N2)
+            cb = cg_bytes_per_voxel(pb, N2, s.x_window)
             it_ms = sum(k.values())
             s.set_linearization(s.get_state())
             p = s.project(torch.from_numpy(ms.random_field((N2,) * 3, seed=42).reshape(-1)).to(dev))
@@ -504,7 +528,8 @@ def main():
                      "ceiling_GB_s": ceiling, "frac_of_ceiling": round(achieved / ceiling, 4)},
         "cg_iteration": {"ms": round(cg_iter_ms, 4), "bytes_per_voxel": round(sum(cgb.values()), 2),
                          "GB_s": round(sum(cgb.values()) * n / (cg_iter_ms * 1e-3) / 1e9, 1),
-                         "kernels": cg_kernel_rows(cgk, cgb, n, ceiling)},
+                         "kernels": cg_kernel_rows(cgk, cgb, n, ceiling),
+                         "x_window": s64.x_window, "pass1_variants": p1var},
         "stream_ceiling": ceil,
         "grid_192": big,
         "grid_256": big256,

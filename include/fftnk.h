@@ -194,9 +194,17 @@ int fftnk_set_modulus_field(fftnk_ctx* ctx, const double* mu_dev);
  * of redoing the return mapping and eigen-decomposition at every operator
  * application.  Same results up to rounding order.  Set it before
  * fftnk_workspace_bytes / fftnk_bind_workspace (afterwards FFTNK_ESTATE).
+ * FFTNK_OPT_X_WINDOW (1..8, default 8): the CG of Sec. 2.6 keeps the search
+ * directions of this many iterations (W vector fields of the context
+ * precision in the workspace) and adds their steps alpha_j p_j to the iterate
+ * x once every W iterations, in the order of j, instead of reading and
+ * writing x at every iteration; the same roundings, so the same results for
+ * every W.  1 keeps one direction and updates x at every iteration.  Set it
+ * before fftnk_workspace_bytes / fftnk_bind_workspace (afterwards
+ * FFTNK_ESTATE).
  */
 enum { FFTNK_OPT_GRAPHS = 1, FFTNK_OPT_CHECK_EVERY = 2, FFTNK_OPT_NYQUIST = 3, FFTNK_OPT_GMRES_RESTART = 4,
-       FFTNK_OPT_J2_TANGENT = 5 };
+       FFTNK_OPT_J2_TANGENT = 5, FFTNK_OPT_X_WINDOW = 6 };
 int fftnk_set_option(fftnk_ctx* ctx, int option, int value);
 
 /* F_t := I (and virgin history): the start state of Algorithm 1. */
@@ -369,14 +377,17 @@ int fftnk_launch_pass(fftnk_ctx* ctx, int pass);
  * Instrumentation: time each kernel of a CG iteration (Sec. 2.6) at the
  * current iterate.  The right-hand side is -G(P) of the current iterate's
  * stress (so call it after a solve); the CG runs with tolerance 0 and no
- * iteration cap, two whole iterations untimed, then every kernel `iters` times
- * back to back between two stream events (the repeated launches keep the
- * work of an iteration, not its values: the context's Krylov vectors x, r, p
- * are clobbered, the committed state is not).  ms_host[7] (host) receives the
- * mean time of one launch of: 0 pass 1 (p update, deferred x update, tangent
- * action, a2 forward), 1 alpha, 2 pass 2, 3 pass 3, 4 pass 4, 5 pass 5 (a2
- * inverse, residual update), 6 beta.  1 <= iters <= 10000.  FFTNK_ESTATE if a
- * cell's right-hand side is zero (nothing to iterate on); synchronises.
+ * iteration cap: W whole iterations untimed (W = FFTNK_OPT_X_WINDOW), pass 1
+ * of iteration W (which applies the window of x updates) `iters` times, one
+ * more whole iteration, then every kernel `iters` times back to back between
+ * two stream events (the repeated launches keep the work of an iteration, not
+ * its values: the context's Krylov vectors are clobbered, the committed state
+ * is not).  ms_host[8] (host) receives the mean time of one launch of: 0 pass
+ * 1 (p update, tangent action, a2 forward; for W > 1 at an iteration without
+ * the x update), 1 alpha, 2 pass 2, 3 pass 3, 4 pass 4, 5 pass 5 (a2 inverse,
+ * residual update), 6 beta, 7 pass 1 at an iteration that applies the window
+ * of x updates.  1 <= iters <= 10000.  FFTNK_ESTATE if a cell's right-hand
+ * side is zero (nothing to iterate on); synchronises.
  */
 int fftnk_profile_cg(fftnk_ctx* ctx, int iters, double* ms_host);
 

@@ -237,6 +237,8 @@ struct fftnk_ctx {
   int jt = 0;              // FFTNK_OPT_J2_TANGENT: 1 = compact J2 tangent stored per linearisation point
   bool jt_ready = false;   // the stored compact tangent was computed (for the last linearisation point)
   size_t o_jt = 0;         // its workspace offset, [kJ2Tan][ntot] doubles after the GMRES basis
+  int xwin = kMaxXWin;     // FFTNK_OPT_X_WINDOW: CG directions kept for the windowed x update
+  size_t o_pwin = 0;       // their slots after the compact tangent (xwin > 1; else the p vector)
   size_t total_base = 0;   // workspace bytes without the GMRES basis
   // workspace layout (byte offsets)
   size_t o_hist, o_hnew;  // J2 history: committed and of the current iterate, [7][ntot] each
@@ -266,6 +268,9 @@ struct fftnk_ctx {
   void* x() const { return ws + o_x; }
   void* r() const { return ws + o_r; }
   void* p() const { return ws + o_p; }
+  // slot 0 of the CG directions (the others follow, pslot_bytes apart)
+  void* pw() const { return ws + (xwin > 1 ? o_pwin : o_p); }
+  size_t pslot_bytes() const { return align_up(9 * (size_t)ntot * (prec == PREC_F64 ? 8 : 4)); }
   void* w() const { return ws + o_w; }
   float* F32() const { return prec == PREC_F32 ? at<float>(o_F32) : nullptr; }
   double* d64() const { return at<double>(o_d64); }  // FP64 copy of the FP32 solution (FP32 mode)
@@ -287,6 +292,8 @@ struct fftnk_ctx {
     L.b.pstride = pstride;
     L.b.nyq = ws + o_nyq;
     L.b.nrve = nrve;
+    L.b.xwin = xwin;
+    L.b.vstride = (long long)(pslot_bytes() / (prec == PREC_F64 ? 8 : 4));
     for (int k = 0; k < NKIND; ++k) L.nblk[k] = nblk[k];
     L.lds_row64 = lds[0];
     L.lds_row32 = lds[1];
@@ -365,6 +372,8 @@ void size_workspace(fftnk_ctx* c) {
   if (c->gm) o = align_up(o + (size_t)(c->gm + 1) * gm_vstride(c->ntot) * (c->prec == PREC_F64 ? 8 : 4));
   c->o_jt = o;
   if (c->jt) o = align_up(o + (size_t)kJ2Tan * c->ntot * sizeof(double));
+  c->o_pwin = o;
+  if (c->xwin > 1) o = align_up(o + (size_t)c->xwin * c->pslot_bytes());
   c->total = o;
 }
 
@@ -511,7 +520,7 @@ int init_ctx(fftnk_ctx* c, int nrve, const int* dims, int precision, void* strea
   c->o_coef = take((size_t)nrve * kGmCoef * sizeof(double));
   c->o_gm = o;
   c->total_base = o;
-  c->total = o;
+  size_workspace(c);
   c->active.assign(nrve, 1);
   c->uni.assign(9 * (size_t)nrve, 0.0);
   c->pinned_bytes = std::max((size_t)nrve * NSLOT * 8, (size_t)nrve * sizeof(CgState)) + 256;
@@ -572,7 +581,7 @@ const void* newton_update_source(fftnk_ctx* c) {
 // one CG iteration on every RVE whose CG is still running
 void cg_iteration(fftnk_ctx* c, const Launch& L) {
   CgState* cg = c->cg();
-  launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->p(), c->x(), c->flin(), 1.0, c->spec(), cg);
+  launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->pw(), c->x(), c->flin(), 1.0, c->spec(), cg);
   launch_cg_alpha(L, cg);
   middle_passes(c->prec, L, c->spec(), cg);
   launch_inv_a2(c->prec, INV_CGR, L, c->spec(), c->r(), c->prec, nullptr, 1.0, cg);
@@ -670,7 +679,7 @@ int run_cg(fftnk_ctx* c, double eta, int max_cg) {
     if (all) {
       if (most > 0) c->cg_estimate = most;
       if ((e = nar.restore())) return e;
-      launch_cg_finish(c->prec, c->launch(), c->x(), c->p(), c->cg());  // the last iteration's deferred x update
+      launch_cg_finish(c->prec, c->launch(), c->x(), c->pw(), c->cg());  // the deferred x updates still due
       return check_launch();
     }
     if (launched > max_cg + 64) return FFTNK_ECG_MAXIT;  // unreachable: k_cg_beta stops at max_cg
@@ -1317,8 +1326,8 @@ int fftnk_describe(const fftnk_ctx* c, char* buf, size_t len, size_t* needed) {
     j += t;
   };
   add("{\"nrve\": %d, \"precision\": %d, \"workspace_bytes\": %zu, \"workspace_base_bytes\": %zu, \"gmres_restart\": %d, "
-      "\"policy\": %u, \"pstride\": %lld, ",
-      c->nrve, c->prec, c->total, c->total_base, c->gm, c->policy, c->pstride);
+      "\"x_window\": %d, \"policy\": %u, \"pstride\": %lld, ",
+      c->nrve, c->prec, c->total, c->total_base, c->gm, c->xwin, c->policy, c->pstride);
   j += "\"nblk\": [";
   for (int k = 0; k < NKIND; ++k) add(k ? ", %d" : "%d", c->nblk[k]);
   j += "], \"lds\": [";
@@ -1457,6 +1466,12 @@ int fftnk_set_option(fftnk_ctx* c, int option, int value) {
       if (value != 0 && value != 1) return FFTNK_EINVAL;
       if (c->ws) return FFTNK_ESTATE;  // sizes the workspace: set before binding it
       c->jt = value;
+      size_workspace(c);
+      return FFTNK_OK;
+    case FFTNK_OPT_X_WINDOW:
+      if (value < 1 || value > kMaxXWin) return FFTNK_EINVAL;
+      if (c->ws) return FFTNK_ESTATE;  // sizes the workspace: set before binding it
+      c->xwin = value;
       size_workspace(c);
       return FFTNK_OK;
     case FFTNK_OPT_NYQUIST:
@@ -1879,12 +1894,10 @@ int fftnk_profile_cg(fftnk_ctx* c, int iters, double* ms) {
   if (e) return e;
   for (int r = 0; r < c->nrve; ++r)
     if (c->host_cg()[r].done) return FFTNK_ESTATE;
-  // two whole iterations: afterwards every kernel sees a previous direction
-  for (int i = 0; i < 2; ++i) cg_iteration(c, L);
   auto kernel = [&](int k) {
     switch (k) {
       case 0:
-        launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->p(), c->x(), c->flin(), 1.0, c->spec(),
+        launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->pw(), c->x(), c->flin(), 1.0, c->spec(),
                       cg);
         break;
       case 1: launch_cg_alpha(L, cg); break;
@@ -1902,9 +1915,7 @@ int fftnk_profile_cg(fftnk_ctx* c, int iters, double* ms) {
     return FFTNK_EHIP;
   }
   int err = check_launch();
-  // each kernel `iters` times back to back between two events (beta last: it
-  // advances the iteration counter)
-  for (int k = 0; k < 7 && !err; ++k) {
+  auto timed = [&](int k, double* out) {
     (void)hipEventRecord(e0, c->stream);
     for (int i = 0; i < iters; ++i) kernel(k);
     (void)hipEventRecord(e1, c->stream);
@@ -1912,8 +1923,18 @@ int fftnk_profile_cg(fftnk_ctx* c, int iters, double* ms) {
     float t = 0.f;
     if (!err && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))
       err = FFTNK_EHIP;
-    ms[k] = (double)t / iters;
-  }
+    *out = (double)t / iters;
+  };
+  // W whole iterations: the first pass of iteration W applies the window of
+  // x updates (timed as ms[7]); one more iteration, then every kernel `iters`
+  // times back to back between two events (beta last: it advances the
+  // iteration counter), the first pass at an iteration inside a window (for
+  // W > 1) where every kernel sees a previous direction
+  for (int i = 0; i < c->xwin && !err; ++i) cg_iteration(c, L);
+  if (!err) err = check_launch();
+  if (!err) timed(0, &ms[7]);
+  if (!err) cg_iteration(c, L);
+  for (int k = 0; k < 7 && !err; ++k) timed(k, &ms[k]);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return err;

@@ -168,32 +168,51 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
           for (int c = 0; c < 9; ++c) p[c] = ld_stream<NT_OP_LOAD_P>(byte_off(in + off + c * n, vb));
 #pragma unroll
           for (int c = 0; c < 9; ++c) F[c] = *byte_off(Flin + off + c * n, vb);
-        } else {  // FWD_CG
-          const bool first = cptr(cg)[rv].iter == 0;
-          if (first) {  // p_0 = r_0, x_0 = 0
+        } else {  // FWD_CG, iteration k: p_k goes to slot k mod W
+          const int k = cptr(cg)[rv].iter, W = B.xwin;
+          T* pnew = pvec + (long long)(k % W) * B.vstride;
+          if (k == 0) {  // p_0 = r_0, x_0 = 0
 #pragma unroll
             for (int c = 0; c < 9; ++c) p[c] = ld_stream<NT_P1_LOAD_VEC>(byte_off(rvec + off + c * n, vb));
 #pragma unroll
             for (int c = 0; c < 9; ++c) F[c] = ld_stream<NT_P1_LOAD_F>(byte_off(Flin + off + c * n, vb));
-          } else {  // x += alpha p_old (previous iteration), p = r + beta p_old
-            const T alpha = (T)cptr(cg)[rv].alpha, beta = (T)cptr(cg)[rv].beta;
-            T po[9], xo[9];
+          } else {  // p_k = r + beta p_{k-1}
+            const T beta = (T)cptr(cg)[rv].beta;
+            const T* pold = pvec + (long long)((k - 1) % W) * B.vstride;
+            T po[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
               p[c] = ld_stream<NT_P1_LOAD_VEC>(byte_off(rvec + off + c * n, vb));
-              po[c] = ld_stream<NT_P1_LOAD_VEC>(byte_off(pvec + off + c * n, vb));
-              xo[c] = ld_stream<NT_P1_LOAD_VEC>(byte_off(xvec + off + c * n, vb));
+              po[c] = ld_stream<NT_P1_LOAD_VEC>(byte_off(pold + off + c * n, vb));
             }
 #pragma unroll
             for (int c = 0; c < 9; ++c) F[c] = ld_stream<NT_P1_LOAD_F>(byte_off(Flin + off + c * n, vb));
+            if (k % W == 0) {
+              // start of a window: slots 0 .. W-1 hold p_{k-W} .. p_{k-1} (the last
+              // one is p_old); x += alpha_j p_j in the order of j, as the updates of
+              // the single iterations would (the same roundings)
+              T xo[9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) {
-              st_stream<NT_P1_STORE_VEC>(byte_off(xvec + off + c * n, vb), xo[c] + alpha * po[c]);
-              p[c] = p[c] + beta * po[c];
+              for (int c = 0; c < 9; ++c) xo[c] = ld_stream<NT_P1_LOAD_VEC>(byte_off(xvec + off + c * n, vb));
+#pragma unroll 1
+              for (int i = 0; i < W - 1; ++i) {
+                const T a = (T)cptr(cg)[rv].ahist[i];
+                const T* pi = pvec + (long long)i * B.vstride;
+                T q[9];
+#pragma unroll
+                for (int c = 0; c < 9; ++c) q[c] = ld_stream<NT_P1_LOAD_VEC>(byte_off(pi + off + c * n, vb));
+#pragma unroll
+                for (int c = 0; c < 9; ++c) xo[c] = xo[c] + a * q[c];
+              }
+              const T a = (T)cptr(cg)[rv].ahist[W - 1];
+#pragma unroll
+              for (int c = 0; c < 9; ++c) st_stream<NT_P1_STORE_VEC>(byte_off(xvec + off + c * n, vb), xo[c] + a * po[c]);
             }
+#pragma unroll
+            for (int c = 0; c < 9; ++c) p[c] = p[c] + beta * po[c];
           }
 #pragma unroll
-          for (int c = 0; c < 9; ++c) st_stream<NT_P1_STORE_VEC>(byte_off(pvec + off + c * n, vb), p[c]);
+          for (int c = 0; c < 9; ++c) st_stream<NT_P1_STORE_VEC>(byte_off(pnew + off + c * n, vb), p[c]);
         }
         tangent_at<T, LAW>(mat, g.vox_off + v, F, p, d);
         if (MODE == FWD_CG) {

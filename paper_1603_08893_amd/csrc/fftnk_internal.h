@@ -19,6 +19,7 @@ constexpr int kMaxRve = 256;       // RVEs of one batched context
 constexpr int kRedBlocks = 8192;   // most work-groups of an element-wise kernel per RVE
 constexpr int kRegP = 8;           // points per thread of the register-resident FFT engine
 constexpr int kMaxPpt = 4;         // points per thread of an LDS-engine column tile (n * m <= kMaxPpt * kThreads)
+constexpr int kMaxXWin = 8;        // CG directions kept for the windowed update of x (FFTNK_OPT_X_WINDOW)
 
 // LDS padding: entry e of a twiddle table or of a contiguous (unit-stride)
 // exchange line sits at e + e / 8, so that eight lanes touching entries 8
@@ -152,8 +153,10 @@ struct CgState {
   int stall_limit; // 0: off; else stop when <r, r> has not dropped below 0.75 rr_min for this many iterations
   int since_min;
   int zero_rhs;    // 1: ||b|| at the round-off floor of the projected field, dF = 0
-  int x_due;       // 1: x still lacks alpha p of the last iteration (applied by the next
-                   //    iteration's first pass, or by the finishing kernel)
+  int x_lo, x_hi;  // the terms alpha_j p_j, x_lo <= j < x_hi, that x still lacks (applied by
+                   //    the first pass of an iteration that starts a new window, or by the
+                   //    finishing kernel)
+  double ahist[kMaxXWin];  // alpha_j at slot j mod W
   int method;      // KRYLOV_*: how alpha and beta are chosen
   double lo, hi;   // spectral bounds of A on range(G) (Chebyshev, Richardson)
   double rho, gam; // Chebyshev recurrence: rho_k and the step gamma_k of the current direction
@@ -181,6 +184,10 @@ struct Batch {
   // cell block at 9 row_off, component c of line l at c rows + l.
   void* nyq;
   int nrve;
+  // CG directions: W = xwin slots of vstride elements from the p vector, p_j
+  // in slot j mod W; x is brought up to date once every W iterations
+  int xwin;
+  long long vstride;
 };
 
 // Modes of the first (a2, forward) pass.
@@ -188,9 +195,10 @@ enum {
   FWD_COPY = 0,        // transform the input field itself (scaled)
   FWD_TANGENT = 1,     // transform K(F) : p
   FWD_TANGENT_UNI = 2, // transform K(F) : U with the RVE's uniform tensor U (Batch::uni)
-  FWD_CG = 3           // CG: x += alpha p (deferred update of the previous iteration),
-                       // p <- r + beta p (or r on the first iteration), then K(F) : p and
-                       // the partial <p, K(F) : p> (= <p, A p>, see k_cg_alpha)
+  FWD_CG = 3           // CG iteration k: at the start of a window (k >= W, k mod W = 0)
+                       // x += sum of alpha_j p_j over the W previous iterations; then
+                       // p_k <- r + beta p_{k-1} (or r when k = 0) in slot k mod W, K(F) : p
+                       // and the partial <p, K(F) : p> (= <p, A p>, see k_cg_alpha)
 };
 // Modes of the last (a2, inverse) pass.
 enum {

@@ -22,20 +22,26 @@ enum { ST_OK = 0, ST_CG_MAXIT = 5, ST_CG_BREAKDOWN = 6, ST_NONFINITE = 8 };
 #define FOR_RVE_RANGE(i, m, local, nb) \
   for (long long i = (long long)(local) * kThreads + threadIdx.x; i < (m); i += (long long)(nb) * kThreads)
 
-// Iteration k's update x += alpha_k p_k is deferred: the first pass of
-// iteration k + 1 applies it while it reads p_k anyway.  After the last
-// iteration of a solve this kernel applies the one still due (x_due).
+// The updates x += alpha_j p_j are deferred: the directions of W iterations
+// stay in their slots (p_j in slot j mod W, W = Batch::xwin) and the first
+// pass of every iteration k with k mod W = 0 applies the W of them, in the
+// order of j.  After the last iteration of a solve this kernel applies the
+// ones still due, j in [x_lo, x_hi), in the same order.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_cg_finish(Batch B, T* __restrict__ x, const T* __restrict__ p,
                                                         const CgState* __restrict__ cg) {
   int local;
   const int rv = find_rve(B, K_ELEM9, blockIdx.x, local);
-  if (!cptr(cg)[rv].x_due) return;
+  const int lo = cptr(cg)[rv].x_lo, hi = cptr(cg)[rv].x_hi, W = B.xwin;
+  if (hi <= lo) return;
   const auto& g = grid_of(B, rv);
   const int nb = rve_blocks(B, K_ELEM9, rv);
   const long long m = 9 * g.n, off = 9 * g.vox_off;
-  const T alpha = (T)cptr(cg)[rv].alpha;
-  FOR_RVE_RANGE(i, m, local, nb) x[off + i] += alpha * p[off + i];
+  FOR_RVE_RANGE(i, m, local, nb) {
+    T v = x[off + i];
+    for (int j = lo; j < hi; ++j) v = v + (T)cptr(cg)[rv].ahist[j % W] * p[(long long)(j % W) * B.vstride + off + i];
+    x[off + i] = v;
+  }
 }
 
 __device__ __forceinline__ int kstart(const Batch& B, int kind, int r) { return B.starts[kind * (B.nrve + 1) + r]; }
@@ -62,7 +68,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(Batch B, CgState* cg, doub
       s.iter = 0;
       s.status = ST_OK;
       s.zero_rhs = 1;
-      s.x_due = 0;
+      s.x_lo = s.x_hi = 0;
     }
     return;
   }
@@ -82,7 +88,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(Batch B, CgState* cg, doub
     s.stall_limit = stall;
     s.status = isfinite(bb) ? ST_OK : ST_NONFINITE;
     s.zero_rhs = (bb == 0.0 || sqrt(bb) <= 1e-14 * sqrt(yy)) ? 1 : 0;
-    s.x_due = 0;
+    s.x_lo = s.x_hi = 0;
     s.done = (s.zero_rhs || !isfinite(bb) || bb <= s.stop2) ? 1 : 0;
   }
 }
@@ -91,14 +97,21 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(Batch B, CgState* cg, doub
 // G the orthogonal projection (symmetric, p in its range as every Krylov
 // direction is), <p, A p> = <G p, K p> = <p, K p>: the first pass sums it from
 // p and K p in registers, so the last pass never reads p again.
+//
+// Bookkeeping of the deferred x updates: iteration k's first pass applied
+// the window of directions before k when k mod W = 0 (x_lo = k); alpha_k goes
+// to its slot of the history and term k becomes due (x_hi = k + 1) unless the
+// iteration breaks down.
 __global__ __launch_bounds__(kThreads) void k_cg_alpha(Batch B, CgState* cg) {
   const int rv = blockIdx.x;
   CgState& s = cg[rv];
   if (s.done) return;
+  if (threadIdx.x == 0 && s.iter > 0 && s.iter % B.xwin == 0) s.x_lo = s.iter;
   if (s.method != KRYLOV_CG) {  // fixed coefficients: the step of the recurrence
     if (threadIdx.x == 0) {
       s.alpha = s.method == KRYLOV_CHEBYSHEV ? s.gam : 2.0 / (s.lo + s.hi);
-      s.x_due = 1;
+      s.ahist[s.iter % B.xwin] = s.alpha;
+      s.x_hi = s.iter + 1;
     }
     return;
   }
@@ -116,10 +129,11 @@ __global__ __launch_bounds__(kThreads) void k_cg_alpha(Batch B, CgState* cg) {
                                                                                          : ST_CG_BREAKDOWN;
       s.done = 1;
       s.alpha = 0.0;
-      s.x_due = 0;  // this iteration's first pass applied the previous update
+      s.x_hi = s.iter;  // this iteration's direction is not applied
     } else {
       s.alpha = s.rr / pw;
-      s.x_due = 1;
+      s.ahist[s.iter % B.xwin] = s.alpha;
+      s.x_hi = s.iter + 1;
     }
   }
 }

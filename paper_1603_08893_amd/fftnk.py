@@ -16,7 +16,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "li
 OK, EINVAL, ESTATE, ENOMEM, EHIP, ECG_MAXIT, ECG_BREAKDOWN, ENEWTON_MAXIT, ENONFINITE, EMATERIAL, EUNSUPPORTED = range(11)
 FP64, FP32_MIXED = 0, 1
 SVK, J2 = 0, 1
-OPT_GRAPHS, OPT_CHECK_EVERY, OPT_NYQUIST, OPT_GMRES_RESTART, OPT_J2_TANGENT = 1, 2, 3, 4, 5
+OPT_GRAPHS, OPT_CHECK_EVERY, OPT_NYQUIST, OPT_GMRES_RESTART, OPT_J2_TANGENT, OPT_X_WINDOW = 1, 2, 3, 4, 5, 6
 KRYLOV = {"cg": 0, "chebyshev": 1, "richardson": 2, "gmres": 3}
 MAX_SOLVES = 64
 
@@ -134,13 +134,19 @@ def describe(dims, precision="fp64", gmres_restart=0, policy=0):
             _check(L.fftnk_set_option(ctx, OPT_GMRES_RESTART, int(gmres_restart)), "fftnk_set_option")
         if policy:
             _check(L.fftnk_set_plan(ctx, int(policy)), "fftnk_set_plan")
-        need = ctypes.c_size_t(0)
-        L.fftnk_describe(ctx, None, 0, ctypes.byref(need))
-        buf = ctypes.create_string_buffer(need.value)
-        _check(L.fftnk_describe(ctx, buf, need.value, None), "fftnk_describe")
-        return json.loads(buf.value.decode())
+        return _describe_ctx(ctx)
     finally:
         L.fftnk_destroy(ctx)
+
+
+def _describe_ctx(ctx):
+    import json
+    L = lib()
+    need = ctypes.c_size_t(0)
+    L.fftnk_describe(ctx, None, 0, ctypes.byref(need))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(L.fftnk_describe(ctx, buf, need.value, None), "fftnk_describe")
+    return json.loads(buf.value.decode())
 
 
 def project_noalloc(a, dims, out=None, stream=None):
@@ -189,11 +195,13 @@ class Solver:
     "fp32" (FP32 Krylov solve, FP64 Newton residual).  gmres_restart: reserve
     the basis of restarted GMRES with this restart length (0: none).
     j2_stored_tangent: reserve and use the compact J2 tangent stored per
-    linearisation point (FFTNK_OPT_J2_TANGENT; J2 law, FP64).
+    linearisation point (FFTNK_OPT_J2_TANGENT; J2 law, FP64).  x_window: CG
+    directions kept for the windowed update of the iterate (FFTNK_OPT_X_WINDOW,
+    1..8; None: the library's default).
     """
 
     def __init__(self, dims, precision="fp64", device="cuda", stream=None, gmres_restart=0,
-                 j2_stored_tangent=False):
+                 j2_stored_tangent=False, x_window=None):
         import torch
         self.torch = torch
         if isinstance(dims[0], (int, np.integer)):
@@ -217,6 +225,9 @@ class Solver:
             _check(L.fftnk_set_option(ctx, OPT_GMRES_RESTART, int(gmres_restart)), "fftnk_set_option")
         if j2_stored_tangent:
             _check(L.fftnk_set_option(ctx, OPT_J2_TANGENT, 1), "fftnk_set_option")
+        if x_window is not None:
+            _check(L.fftnk_set_option(ctx, OPT_X_WINDOW, int(x_window)), "fftnk_set_option")
+        self.x_window = int(_describe_ctx(ctx)["x_window"])
         nbytes = L.fftnk_workspace_bytes(ctx)
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
@@ -420,12 +431,20 @@ class Solver:
 
     CG_KERNELS = ("pass1", "alpha", "pass2", "pass3", "pass4", "pass5", "beta")
 
-    def profile_cg(self, iters=20):
+    def profile_cg(self, iters=20, detail=False):
         """Mean ms per launch of each kernel of a CG iteration at the current iterate
-        (timing instrumentation; call after a solve, clobbers the Krylov vectors)."""
-        ms = np.zeros(7, dtype=np.float64)
+        (timing instrumentation; call after a solve, clobbers the Krylov vectors).
+        pass1 is its mean over a window of x_window iterations (one of which
+        applies the window's x updates); detail=True also returns both times."""
+        ms = np.zeros(8, dtype=np.float64)
         _check(lib().fftnk_profile_cg(self.ctx, int(iters), ms.ctypes.data), "fftnk_profile_cg")
-        return dict(zip(self.CG_KERNELS, ms.tolist()))
+        W = self.x_window
+        k = dict(zip(self.CG_KERNELS, ms[:7].tolist()))
+        if W > 1:
+            k["pass1"] = ((W - 1) * ms[0] + ms[7]) / W
+        if detail:
+            return k, {"x_window": W, "pass1_within_window": float(ms[0]), "pass1_xupdate": float(ms[7])}
+        return k
 
     def get_history(self):
         """J2 history, [7 * ntot] device doubles (C_p^-1 xx yy zz xy yz xz, eps_p)."""

@@ -138,7 +138,11 @@ def test_gmres_basis_and_refused_lengths():
         extra = d["workspace_bytes"] - d["workspace_base_bytes"]
         stride = -(-9 * math.prod(shape) // 64) * 64  # basis vectors start on even element counts
         need = 13 * stride * esz
-        assert need <= extra < need + 256
+        # and the CG directions of the windowed x update (slots of 256-byte aligned fields)
+        W = d["x_window"]
+        assert 1 <= W <= 8
+        need += W * (-(-9 * math.prod(shape) * esz // 256) * 256) if W > 1 else 0
+        assert need <= extra < need + 512
     for bad in ((513, 4, 4), (4, 600, 4), (4, 4, 257), (1, 4, 4)):
         with pytest.raises(fftnk.FftnkError):
             fftnk.describe(bad)
@@ -179,3 +183,28 @@ def test_every_policy_geometry(prec):
                 assert c["rt"] == max(1, b0["rt"] // 2)
     with pytest.raises(fftnk.FftnkError):
         fftnk.describe((8, 8, 8), prec, policy=64)
+
+
+def test_x_window_option():
+    """FFTNK_OPT_X_WINDOW: 1..8 (default 8) CG directions in the workspace,
+    refused outside that range and once the workspace is bound."""
+    import ctypes
+    fftnk = _lib_or_skip()
+    L = fftnk.lib()
+    shape = (24, 20, 16)
+    for prec, esz in ((fftnk.FP64, 8), (fftnk.FP32_MIXED, 4)):
+        ctx = ctypes.c_void_p()
+        assert L.fftnk_create(ctypes.byref(ctx), *shape, prec, None) == fftnk.OK
+        try:
+            assert fftnk._describe_ctx(ctx)["x_window"] == 8
+            slot = -(-9 * math.prod(shape) * esz // 256) * 256
+            base = L.fftnk_workspace_bytes(ctx)
+            for bad in (0, 9, -1):
+                assert L.fftnk_set_option(ctx, fftnk.OPT_X_WINDOW, bad) == fftnk.EINVAL
+            assert L.fftnk_set_option(ctx, fftnk.OPT_X_WINDOW, 1) == fftnk.OK
+            assert base - L.fftnk_workspace_bytes(ctx) == 8 * slot  # W = 1 uses the p vector itself
+            assert L.fftnk_set_option(ctx, fftnk.OPT_X_WINDOW, 3) == fftnk.OK
+            assert base - L.fftnk_workspace_bytes(ctx) == 5 * slot
+            assert fftnk._describe_ctx(ctx)["x_window"] == 3
+        finally:
+            L.fftnk_destroy(ctx)

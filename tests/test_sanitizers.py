@@ -86,7 +86,7 @@ HOST_SCRIPT = textwrap.dedent('''
     assert L.fftnk_create(ctypes.byref(ctx), 513, 8, 8, 0, None) == fftnk.EUNSUPPORTED
     assert L.fftnk_create(ctypes.byref(ctx), 24, 20, 16, 0, None) == fftnk.OK
     for opt, val in ((fftnk.OPT_GMRES_RESTART, 12), (fftnk.OPT_J2_TANGENT, 1), (fftnk.OPT_NYQUIST, 1),
-                     (fftnk.OPT_CHECK_EVERY, 8), (fftnk.OPT_GRAPHS, 0)):
+                     (fftnk.OPT_CHECK_EVERY, 8), (fftnk.OPT_GRAPHS, 0), (fftnk.OPT_X_WINDOW, 5)):
         assert L.fftnk_set_option(ctx, opt, val) == fftnk.OK
     assert L.fftnk_set_option(ctx, fftnk.OPT_J2_TANGENT, 2) == fftnk.EINVAL
     assert L.fftnk_workspace_bytes(ctx) > 0
