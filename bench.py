@@ -92,7 +92,7 @@ def three_kernel_bytes_per_voxel(prec_bytes, n2):
 
 
 KERNEL_NAMES = {"pass1": "k_fwd_a2<double,FWD_CG>", "pass2": "k_col_a1<double,fwd>", "pass3": "k_col_a0_project<double>",
-                "pass4": "k_col_a1<double,inv>", "pass5": "k_inv_a2<double,INV_CGR>", "alpha": "k_cg_alpha",
+                "pass4": "k_col_a1<double,inv>", "pass5": "k_inv_a2<double,INV_CGR>", "alpha": "k_col_a1 (step-length groups)",
                 "beta": "k_cg_beta"}
 
 

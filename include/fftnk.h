@@ -384,7 +384,8 @@ int fftnk_launch_pass(fftnk_ctx* ctx, int pass);
  * its values: the context's Krylov vectors are clobbered, the committed state
  * is not).  ms_host[8] (host) receives the mean time of one launch of: 0 pass
  * 1 (p update, tangent action, a2 forward; for W > 1 at an iteration without
- * the x update), 1 alpha, 2 pass 2, 3 pass 3, 4 pass 4, 5 pass 5 (a2 inverse,
+ * the x update), 1 alpha (0: its work-groups run in pass 2's launch and are
+ * timed with it), 2 pass 2, 3 pass 3, 4 pass 4, 5 pass 5 (a2 inverse,
  * residual update), 6 beta, 7 pass 1 at an iteration that applies the window
  * of x updates.  1 <= iters <= 10000.  FFTNK_ESTATE if a cell's right-hand
  * side is zero (nothing to iterate on); synchronises.

@@ -544,8 +544,8 @@ int reset_state(fftnk_ctx* c) {
 // ---------------------------------------------------------------------------
 // pipelines
 // ---------------------------------------------------------------------------
-void middle_passes(int prec, const Launch& L, void* spec, const CgState* cg) {
-  launch_col_a1(prec, false, L, spec, cg);
+void middle_passes(int prec, const Launch& L, void* spec, const CgState* cg, CgState* alpha_cg = nullptr) {
+  launch_col_a1(prec, false, L, spec, cg, alpha_cg);
   launch_col_a0_project(prec, L, spec, cg);
   launch_col_a1(prec, true, L, spec, cg);
 }
@@ -582,8 +582,7 @@ const void* newton_update_source(fftnk_ctx* c) {
 void cg_iteration(fftnk_ctx* c, const Launch& L) {
   CgState* cg = c->cg();
   launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->pw(), c->x(), c->flin(), 1.0, c->spec(), cg);
-  launch_cg_alpha(L, cg);
-  middle_passes(c->prec, L, c->spec(), cg);
+  middle_passes(c->prec, L, c->spec(), cg, cg);  // alpha in extra work-groups of the a1 pass
   launch_inv_a2(c->prec, INV_CGR, L, c->spec(), c->r(), c->prec, nullptr, 1.0, cg);
   launch_cg_beta(L, cg);
 }
@@ -1900,8 +1899,8 @@ int fftnk_profile_cg(fftnk_ctx* c, int iters, double* ms) {
         launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->pw(), c->x(), c->flin(), 1.0, c->spec(),
                       cg);
         break;
-      case 1: launch_cg_alpha(L, cg); break;
-      case 2: launch_col_a1(c->prec, false, L, c->spec(), cg); break;
+      case 1: break;  // alpha: work-groups of the a1 pass's launch (timed with it)
+      case 2: launch_col_a1(c->prec, false, L, c->spec(), cg, cg); break;
       case 3: launch_col_a0_project(c->prec, L, c->spec(), cg); break;
       case 4: launch_col_a1(c->prec, true, L, c->spec(), cg); break;
       case 5: launch_inv_a2(c->prec, INV_CGR, L, c->spec(), c->r(), c->prec, nullptr, 1.0, cg); break;

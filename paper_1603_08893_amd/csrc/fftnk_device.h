@@ -597,6 +597,55 @@ __device__ __forceinline__ double reduce_range(const double* part, int lo, int h
   return bc;
 }
 
+// The CG step length of RVE rv by one work-group (its whole block), right
+// after the first pass: alpha = <r, r> / <p, A p>.  It runs as extra work-
+// groups of the second pass's launch (the middle passes do not use alpha;
+// the last pass does).  With A = G K and
+// G the orthogonal projection (symmetric, p in its range as every Krylov
+// direction is), <p, A p> = <G p, K p> = <p, K p>: the first pass sums it from
+// p and K p in registers, so the last pass never reads p again.
+//
+// Bookkeeping of the deferred x updates: iteration k's first pass applied
+// the window of directions before k when k mod W = 0 (x_lo = k); alpha_k goes
+// to its slot of the history and term k becomes due (x_hi = k + 1) unless the
+// iteration breaks down.
+__device__ __forceinline__ int kstart(const Batch& B, int kind, int r) { return B.starts[kind * (B.nrve + 1) + r]; }
+
+__device__ __forceinline__ void cg_alpha_group(const Batch& B, CgState* cg, int rv) {
+  CgState& s = cg[rv];
+  if (s.done) return;
+  if (threadIdx.x == 0 && s.iter > 0 && s.iter % B.xwin == 0) s.x_lo = s.iter;
+  if (s.method != KRYLOV_CG) {  // fixed coefficients: the step of the recurrence
+    if (threadIdx.x == 0) {
+      s.alpha = s.method == KRYLOV_CHEBYSHEV ? s.gam : 2.0 / (s.lo + s.hi);
+      s.ahist[s.iter % B.xwin] = s.alpha;
+      s.x_hi = s.iter + 1;
+    }
+    return;
+  }
+  const double pw = reduce_range(pslot(B, SLOT_PW), kstart(B, K_ROW1, rv), kstart(B, K_ROW1, rv + 1));
+  if (threadIdx.x == 0) {
+    s.pw = pw;
+    if (!(pw > 0.0) || !isfinite(pw)) {
+      // With the stagnation guard on (FP32 Krylov vectors), a non-positive
+      // curvature once the residual is near the FP32 rounding floor (relative
+      // residual <= 1e-5, after the first iteration) means the direction is
+      // round-off noise: stop and keep the last iterate, as for stagnation; the
+      // FP64 Newton residual corrects the inexact update.  Otherwise it is a
+      // breakdown (indefinite tangent), as in FP64.
+      s.status = (s.stall_limit > 0 && s.iter > 0 && isfinite(pw) && s.rr <= 1e-10 * s.bb) ? ST_OK
+                                                                                         : ST_CG_BREAKDOWN;
+      s.done = 1;
+      s.alpha = 0.0;
+      s.x_hi = s.iter;  // this iteration's direction is not applied
+    } else {
+      s.alpha = s.rr / pw;
+      s.ahist[s.iter % B.xwin] = s.alpha;
+      s.x_hi = s.iter + 1;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // St. Venant-Kirchhoff (Sec. 4.2) and its tangent action (Sec. 4.3), per voxel.
 //   S = lam tr(E) I + 2 mu E, E = (F^T F - I)/2, P = F S

@@ -123,7 +123,7 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
   if (skip_rve(B, MODE == FWD_CG ? cg : nullptr, rv)) return;
   const auto& g = grid_of(B, rv);
   if (pass1_engine(g.ax[2].reg) != ENG) return;  // another engine's launch owns this cell
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int N2 = g.n2, RT = g.rt1, H = g.h;
   const int npen = 5 * RT;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
@@ -325,14 +325,14 @@ __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, cons
 // order (several planes where a plane has fewer k2).
 // ---------------------------------------------------------------------------
 template <typename T, bool INV, int ENG>
-__device__ __forceinline__ void tile_col_a1(const Batch& B, cx<T>* __restrict__ spec,
-                                                     const CgState* __restrict__ cg, const int b) {
+__device__ __forceinline__ void tile_col_a1(const Batch& B, cx<T>* __restrict__ spec, const CgState* cg,
+                                            const int b) {
   int local;
   const int rv = find_rve(B, sizeof(T) == 8 ? K_COL1_64 : K_COL1_32, b, local);
   if (skip_rve(B, cg, rv)) return;
   const auto& g = grid_of(B, rv);
   if (col_engine(g.ax[1].reg, g.n1, g.h, g.spec_off, sizeof(T)) != ENG) return;  // another launch owns this cell
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int N1 = g.n1, H = g.h;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   load_twiddles<T>(tw, B, g.ax[1].tw, N1);
@@ -411,8 +411,18 @@ __device__ __forceinline__ void tile_col_a1(const Batch& B, cx<T>* __restrict__ 
 }
 
 template <typename T, bool INV, int ENG>
-__global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict__ spec, const CgState* __restrict__ cg) {
-  tile_col_a1<T, INV, ENG>(B, spec, cg, blockIdx.x);
+__global__ __launch_bounds__(kThreads) void k_col_a1(Batch B, cx<T>* __restrict__ spec, const CgState* cg,
+                                                     CgState* alpha_cg) {
+  // the first nrve work-groups of a CG iteration's forward launch compute the
+  // step lengths from the first pass's partial sums (alpha_cg == cg); a
+  // breakdown found there marks its RVE done while this launch runs, which
+  // may skip part of that RVE's tiles: harmless, its CG is over
+  const int na = alpha_cg ? B.nrve : 0;
+  if ((int)blockIdx.x < na) {
+    cg_alpha_group(B, alpha_cg, blockIdx.x);
+    return;
+  }
+  tile_col_a1<T, INV, ENG>(B, spec, cg, (int)blockIdx.x - na);
 }
 
 // ---------------------------------------------------------------------------
@@ -545,7 +555,7 @@ __device__ __forceinline__ void tile_col_a0_project(const Batch& B, cx<T>* __res
   if (skip_rve(B, cg, rv)) return;
   const auto& g = grid_of(B, rv);
   if (col_engine(g.ax[0].reg, g.n0, g.h, g.spec_off, sizeof(T)) != ENG) return;  // another launch owns this cell
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int N0 = g.n0, N1 = g.n1, H = g.h;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   load_twiddles<T>(tw, B, g.ax[0].tw, N0);
@@ -725,7 +735,7 @@ __device__ __forceinline__ void tile_col_a0_project_id(const Batch& B, cx<T>* __
   if (skip_rve(B, cg, rv)) return;
   const auto& g = grid_of(B, rv);
   if (col_engine(g.ax[0].reg, g.n0, g.h, g.spec_off, sizeof(T)) != ENG) return;  // another launch owns this cell
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int N0 = g.n0, N1 = g.n1, H = g.h;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
   load_twiddles<T>(tw, B, g.ax[0].tw, N0);
@@ -874,7 +884,7 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
   if (skip_rve(B, MODE == INV_CGR ? cg : nullptr, rv)) return;
   const auto& g = grid_of(B, rv);
   if (g.ax[2].reg != ENG) return;  // another engine's launch owns this cell
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
   const int N2 = g.n2, RT = g.rt, H = g.h;
   const int npen = 5 * RT;
   cx<T>* tw = reinterpret_cast<cx<T>*>(smem_raw);
@@ -1124,29 +1134,35 @@ void launch_fwd_a2(int prec, int mode, const Launch& L, const Material& mat, con
 }
 
 template <typename T, bool INV>
-static void col_a1_t(const Launch& L, void* spec, const CgState* cg) {
+static void col_a1_t(const Launch& L, void* spec, const CgState* cg, CgState* alpha_cg) {
   const int ntiles = L.nblk[sizeof(T) == 8 ? K_COL1_64 : K_COL1_32];
   const size_t lds = sizeof(T) == 8 ? L.lds_col1_64 : L.lds_col1_32;
   cx<T>* sp = static_cast<cx<T>*>(spec);
+  // the first engine variant launched carries the step-length work-groups
+  CgState* a = alpha_cg;
+  auto go = [&](auto kernel) {
+    launch_tiles(kernel, ntiles + (a ? L.b.nrve : 0), lds, L.s, L.b, sp, cg, a);
+    a = nullptr;
+  };
   // cells with FP32 pencil pairs (bit 3) run on the 8-point kernel in FP64
-  if (L.eng[1] & (sizeof(T) == 8 ? 10 : 2)) launch_tiles(&k_col_a1<T, INV, 8>, ntiles, lds, L.s, L.b, sp, cg);
+  if (L.eng[1] & (sizeof(T) == 8 ? 10 : 2)) go(&k_col_a1<T, INV, 8>);
   if constexpr (sizeof(T) == 4)
-    if (L.eng[1] & 8) launch_tiles(&k_col_a1<T, INV, 16>, ntiles, lds, L.s, L.b, sp, cg);
-  if (L.eng[1] & 4) launch_tiles(&k_col_a1<T, INV, 12>, ntiles, lds, L.s, L.b, sp, cg);
-  if (L.eng[1] & 1) launch_tiles(&k_col_a1<T, INV, 0>, ntiles, lds, L.s, L.b, sp, cg);
+    if (L.eng[1] & 8) go(&k_col_a1<T, INV, 16>);
+  if (L.eng[1] & 4) go(&k_col_a1<T, INV, 12>);
+  if (L.eng[1] & 1) go(&k_col_a1<T, INV, 0>);
 }
 
-void launch_col_a1(int prec, bool inverse, const Launch& L, void* spec, const CgState* cg) {
+void launch_col_a1(int prec, bool inverse, const Launch& L, void* spec, const CgState* cg, CgState* alpha_cg) {
   if (prec == PREC_F64) {
     if (inverse)
-      col_a1_t<double, true>(L, spec, cg);
+      col_a1_t<double, true>(L, spec, cg, alpha_cg);
     else
-      col_a1_t<double, false>(L, spec, cg);
+      col_a1_t<double, false>(L, spec, cg, alpha_cg);
   } else {
     if (inverse)
-      col_a1_t<float, true>(L, spec, cg);
+      col_a1_t<float, true>(L, spec, cg, alpha_cg);
     else
-      col_a1_t<float, false>(L, spec, cg);
+      col_a1_t<float, false>(L, spec, cg, alpha_cg);
   }
 }
 

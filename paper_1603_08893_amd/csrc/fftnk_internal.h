@@ -167,6 +167,8 @@ struct CgState {
 // Chebyshev and Richardson (fixed coefficients from [lo, hi]); and GMRES,
 // driven from the host over the operator passes and the kernels below.
 enum { KRYLOV_CG = 0, KRYLOV_CHEBYSHEV = 1, KRYLOV_RICHARDSON = 2, KRYLOV_GMRES = 3 };
+// per-RVE outcome codes of the device Krylov and Newton kernels (CgState::status)
+enum { ST_OK = 0, ST_CG_MAXIT = 5, ST_CG_BREAKDOWN = 6, ST_NONFINITE = 8 };
 
 // Everything a launch needs to find its RVE, tables and partial-sum slots.
 struct Batch {
@@ -198,7 +200,7 @@ enum {
   FWD_CG = 3           // CG iteration k: at the start of a window (k >= W, k mod W = 0)
                        // x += sum of alpha_j p_j over the W previous iterations; then
                        // p_k <- r + beta p_{k-1} (or r when k = 0) in slot k mod W, K(F) : p
-                       // and the partial <p, K(F) : p> (= <p, A p>, see k_cg_alpha)
+                       // and the partial <p, K(F) : p> (= <p, A p>, see cg_alpha_group)
 };
 // Modes of the last (a2, inverse) pass.
 enum {
@@ -231,14 +233,15 @@ struct Launch {
 };
 void launch_fwd_a2(int prec, int mode, const Launch& L, const Material& mat, const void* in_T, const void* r_T,
                    void* p_T, void* x_T, const void* Flin, double scale, void* spec, const CgState* cg);
-void launch_col_a1(int prec, bool inverse, const Launch& L, void* spec, const CgState* cg);
+// alpha_cg: the launch also computes the CG step lengths (cg_alpha_group) in
+// nrve extra work-groups (the forward pass of a CG iteration)
+void launch_col_a1(int prec, bool inverse, const Launch& L, void* spec, const CgState* cg, CgState* alpha_cg = nullptr);
 void launch_col_a0_project(int prec, const Launch& L, void* spec, const CgState* cg);
 void launch_inv_a2(int prec, int mode, const Launch& L, const void* spec, void* out_T, int out_prec, void* x_T,
                    double scale, const CgState* cg);
 
 // ---- launchers (fftnk_solver_kernels.hip) ---------------------------------
 void launch_cg_finish(int prec, const Launch& L, void* x_T, const void* p_T, const CgState* cg);
-void launch_cg_alpha(const Launch& L, CgState* cg);
 void launch_cg_beta(const Launch& L, CgState* cg);
 void launch_cg_init(const Launch& L, CgState* cg, double eta, int max_cg, int stall, int method = KRYLOV_CG,
                     double lo = 0.0, double hi = 0.0);

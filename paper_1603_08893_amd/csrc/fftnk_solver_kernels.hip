@@ -16,7 +16,6 @@
 
 namespace fftnk {
 
-enum { ST_OK = 0, ST_CG_MAXIT = 5, ST_CG_BREAKDOWN = 6, ST_NONFINITE = 8 };
 
 // loop over this work-group's share of the RVE's index range [0, m)
 #define FOR_RVE_RANGE(i, m, local, nb) \
@@ -44,7 +43,6 @@ __global__ __launch_bounds__(kThreads) void k_cg_finish(Batch B, T* __restrict__
   }
 }
 
-__device__ __forceinline__ int kstart(const Batch& B, int kind, int r) { return B.starts[kind * (B.nrve + 1) + r]; }
 
 // One work-group per RVE.  A finished RVE (Newton mask) gets done = 1 at once.
 // If ||b|| is at the round-off floor of the projected field Y
@@ -90,51 +88,6 @@ __global__ __launch_bounds__(kThreads) void k_cg_init(Batch B, CgState* cg, doub
     s.zero_rhs = (bb == 0.0 || sqrt(bb) <= 1e-14 * sqrt(yy)) ? 1 : 0;
     s.x_lo = s.x_hi = 0;
     s.done = (s.zero_rhs || !isfinite(bb) || bb <= s.stop2) ? 1 : 0;
-  }
-}
-
-// alpha = <r, r> / <p, A p>, run right after the first pass.  With A = G K and
-// G the orthogonal projection (symmetric, p in its range as every Krylov
-// direction is), <p, A p> = <G p, K p> = <p, K p>: the first pass sums it from
-// p and K p in registers, so the last pass never reads p again.
-//
-// Bookkeeping of the deferred x updates: iteration k's first pass applied
-// the window of directions before k when k mod W = 0 (x_lo = k); alpha_k goes
-// to its slot of the history and term k becomes due (x_hi = k + 1) unless the
-// iteration breaks down.
-__global__ __launch_bounds__(kThreads) void k_cg_alpha(Batch B, CgState* cg) {
-  const int rv = blockIdx.x;
-  CgState& s = cg[rv];
-  if (s.done) return;
-  if (threadIdx.x == 0 && s.iter > 0 && s.iter % B.xwin == 0) s.x_lo = s.iter;
-  if (s.method != KRYLOV_CG) {  // fixed coefficients: the step of the recurrence
-    if (threadIdx.x == 0) {
-      s.alpha = s.method == KRYLOV_CHEBYSHEV ? s.gam : 2.0 / (s.lo + s.hi);
-      s.ahist[s.iter % B.xwin] = s.alpha;
-      s.x_hi = s.iter + 1;
-    }
-    return;
-  }
-  const double pw = reduce_range(pslot(B, SLOT_PW), kstart(B, K_ROW1, rv), kstart(B, K_ROW1, rv + 1));
-  if (threadIdx.x == 0) {
-    s.pw = pw;
-    if (!(pw > 0.0) || !isfinite(pw)) {
-      // With the stagnation guard on (FP32 Krylov vectors), a non-positive
-      // curvature once the residual is near the FP32 rounding floor (relative
-      // residual <= 1e-5, after the first iteration) means the direction is
-      // round-off noise: stop and keep the last iterate, as for stagnation; the
-      // FP64 Newton residual corrects the inexact update.  Otherwise it is a
-      // breakdown (indefinite tangent), as in FP64.
-      s.status = (s.stall_limit > 0 && s.iter > 0 && isfinite(pw) && s.rr <= 1e-10 * s.bb) ? ST_OK
-                                                                                         : ST_CG_BREAKDOWN;
-      s.done = 1;
-      s.alpha = 0.0;
-      s.x_hi = s.iter;  // this iteration's direction is not applied
-    } else {
-      s.alpha = s.rr / pw;
-      s.ahist[s.iter % B.xwin] = s.alpha;
-      s.x_hi = s.iter + 1;
-    }
   }
 }
 
@@ -659,10 +612,6 @@ void launch_cg_finish(int prec, const Launch& L, void* x, const void* p, const C
   else
     hipLaunchKernelGGL((k_cg_finish<float>), grid, block, 0, L.s, L.b, static_cast<float*>(x),
                        static_cast<const float*>(p), cg);
-}
-
-void launch_cg_alpha(const Launch& L, CgState* cg) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(L.b.nrve), dim3(kThreads), 0, L.s, L.b, cg);
 }
 
 void launch_cg_beta(const Launch& L, CgState* cg) {
