@@ -15,6 +15,7 @@ context plans (fftnk_describe), checked against what the kernels assume.
   unsupported lengths are refused.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -208,3 +209,18 @@ def test_x_window_option():
             assert fftnk._describe_ctx(ctx)["x_window"] == 3
         finally:
             L.fftnk_destroy(ctx)
+
+
+def test_dynamic_lds_declared_aligned():
+    """Kernels that also hold static LDS (block reductions) start their dynamic
+    LDS right after it: every dynamic LDS declaration is 16-byte aligned so
+    that the 16-byte complex accesses of the transforms stay aligned."""
+    import glob
+    import re
+    csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1603_08893_amd", "csrc")
+    decls = []
+    for f in glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h")):
+        decls += [(f, l) for l in open(f) if re.search(r"extern\s+__shared__", l)]
+    assert decls
+    for f, l in decls:
+        assert "aligned(16)" in l, (f, l)
