@@ -305,6 +305,7 @@ struct fftnk_ctx {
     L.lds_row1_32 = lds[7];
     for (int d = 0; d < 3; ++d) L.eng[d] = eng[d];
     L.nyq = nyq_id;
+    L.ntop = op_nontemporal(ntot, prec == PREC_F64 ? 8 : 4);
     L.s = s;
     return L;
   }

@@ -81,6 +81,18 @@ __device__ __forceinline__ void st_stream(T* p, T v) {
     *p = v;
   }
 }
+// the same where a launch decides: NT false keeps ordinary accesses (operator
+// applications on cells whose fields fit the last-level cache, Launch::ntop)
+template <bool NT, int CLASS, typename T>
+__device__ __forceinline__ T ld_stream_if(const T* p) {
+  if constexpr (NT) return ld_stream<CLASS>(p);
+  else return *p;
+}
+template <bool NT, int CLASS, typename T>
+__device__ __forceinline__ void st_stream_if(T* p, T v) {
+  if constexpr (NT) st_stream<CLASS>(p, v);
+  else *p = v;
+}
 
 // ---------------------------------------------------------------------------
 // complex arithmetic

@@ -113,7 +113,7 @@ __device__ __forceinline__ void st_spec(cx<T>* p, cx<T> v) {
   }
 }
 
-template <typename T, int MODE, int LAW, int ENG>
+template <typename T, int MODE, int LAW, int ENG, bool NTOP>
 __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat, const T* __restrict__ in,
                                             const T* __restrict__ rvec, T* __restrict__ pvec, T* __restrict__ xvec,
                                             const T* __restrict__ Flin, double scale, cx<T>* __restrict__ spec,
@@ -165,7 +165,7 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
           for (int c = 0; c < 9; ++c) F[c] = *byte_off(Flin + off + c * n, vb);
         } else if (MODE == FWD_TANGENT) {
 #pragma unroll
-          for (int c = 0; c < 9; ++c) p[c] = ld_stream<NT_OP_LOAD_P>(byte_off(in + off + c * n, vb));
+          for (int c = 0; c < 9; ++c) p[c] = ld_stream_if<NTOP, NT_OP_LOAD_P>(byte_off(in + off + c * n, vb));
 #pragma unroll
           for (int c = 0; c < 9; ++c) F[c] = *byte_off(Flin + off + c * n, vb);
         } else {  // FWD_CG, iteration k: p_k goes to slot k mod W
@@ -307,14 +307,14 @@ __device__ __forceinline__ void tile_fwd_a2(const Batch& B, const Material& mat,
   if (threadIdx.x == 0) pslot(B, MODE == FWD_CG ? SLOT_PW : SLOT_YY)[b] = res[0];
 }
 
-template <typename T, int MODE, int LAW, int ENG>
+template <typename T, int MODE, int LAW, int ENG, bool NTOP = true>
 __global__ __launch_bounds__(kThreads) void k_fwd_a2(Batch B, Material mat, const T* __restrict__ in,
                                                      const T* __restrict__ rvec, T* __restrict__ pvec,
                                                      T* __restrict__ xvec, const T* __restrict__ Flin, double scale,
                                                      cx<T>* __restrict__ spec, const CgState* __restrict__ cg) {
   // tiles in reverse order: pass 1 starts on the grid lines that the previous
   // pass 5 wrote last (still in the last-level cache); see k_col_a0_project
-  tile_fwd_a2<T, MODE, LAW, ENG>(B, mat, in, rvec, pvec, xvec, Flin, scale, spec, cg, gridDim.x - 1 - blockIdx.x);
+  tile_fwd_a2<T, MODE, LAW, ENG, NTOP>(B, mat, in, rvec, pvec, xvec, Flin, scale, spec, cg, gridDim.x - 1 - blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -875,7 +875,7 @@ __global__ __launch_bounds__(kThreads, (a0_groups_per_cu<T, ENG, NYQ_ID>())) voi
 // the identity choice at Nyquist frequencies), transformed back, and
 // Re / Im give the two real components.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE, typename TO, int ENG>
+template <typename T, int MODE, typename TO, int ENG, bool NTOP>
 __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restrict__ spec, TO* __restrict__ out,
                                             TO* __restrict__ x, double scale,
                                                      const CgState* __restrict__ cg, const int b) {
@@ -973,7 +973,7 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
           const T w = h == 0 ? v[q].x : v[q].y;
           if (MODE == INV_OUT) {
             const T o = (T)scale * w;
-            st_stream<NT_OP_STORE_OUT>(out + idx, (TO)o);
+            st_stream_if<NTOP, NT_OP_STORE_OUT>(out + idx, (TO)o);
             acc[0] += (double)o * (double)o;
           } else if (MODE == INV_CGR) {
             const TO rn = (TO)((T)rin[q][h] - alpha * w);
@@ -1068,11 +1068,11 @@ __device__ __forceinline__ void tile_inv_a2(const Batch& B, const cx<T>* __restr
   if (threadIdx.x == 0) pslot(B, MODE == INV_CGR ? SLOT_RR : SLOT_BB)[b] = res[0];
 }
 
-template <typename T, int MODE, typename TO, int ENG>
+template <typename T, int MODE, typename TO, int ENG, bool NTOP = true>
 __global__ __launch_bounds__(kThreads) void k_inv_a2(Batch B, const cx<T>* __restrict__ spec, TO* __restrict__ out,
                                                      TO* __restrict__ x, double scale,
                                                      const CgState* __restrict__ cg) {
-  tile_inv_a2<T, MODE, TO, ENG>(B, spec, out, x, scale, cg, blockIdx.x);
+  tile_inv_a2<T, MODE, TO, ENG, NTOP>(B, spec, out, x, scale, cg, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1092,16 +1092,16 @@ static void launch_tiles(void (*kernel)(KArgs...), int ntiles, size_t lds, hipSt
 // the batch needs (Launch::eng, per axis: bit 0 some cell on the LDS engine,
 // bit 1 on the 8-point register engine, bit 2 on the 12-point one) and each
 // skips the others' cells.
-template <typename T, int MODE, int LAW>
+template <typename T, int MODE, int LAW, bool NTOP = true>
 static void fwd_a2_mode(const Launch& L, const Material& mat, const T* in, const T* r, T* p, T* x, const T* Flin,
                         double scale, cx<T>* spec, const CgState* cg) {
   const int ntiles = L.nblk[K_ROW1];
   const size_t lds = sizeof(T) == 8 ? L.lds_row1_64 : L.lds_row1_32;
   // pass 1 runs 12-point axes on the LDS engine (pass1_engine)
   if (L.eng[2] & 2)
-    launch_tiles(&k_fwd_a2<T, MODE, LAW, 8>, ntiles, lds, L.s, L.b, mat, in, r, p, x, Flin, scale, spec, cg);
+    launch_tiles(&k_fwd_a2<T, MODE, LAW, 8, NTOP>, ntiles, lds, L.s, L.b, mat, in, r, p, x, Flin, scale, spec, cg);
   if (L.eng[2] & 5)
-    launch_tiles(&k_fwd_a2<T, MODE, LAW, 0>, ntiles, lds, L.s, L.b, mat, in, r, p, x, Flin, scale, spec, cg);
+    launch_tiles(&k_fwd_a2<T, MODE, LAW, 0, NTOP>, ntiles, lds, L.s, L.b, mat, in, r, p, x, Flin, scale, spec, cg);
 }
 
 template <typename T, int LAW>
@@ -1115,7 +1115,12 @@ static void fwd_a2_t(int mode, const Launch& L, const Material& mat, const void*
   cx<T>* sp = static_cast<cx<T>*>(spec);
   switch (mode) {
     case FWD_COPY: fwd_a2_mode<T, FWD_COPY, MODEL_SVK>(L, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
-    case FWD_TANGENT: fwd_a2_mode<T, FWD_TANGENT, LAW>(L, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
+    case FWD_TANGENT:
+      if (L.ntop)
+        fwd_a2_mode<T, FWD_TANGENT, LAW, true>(L, mat, ti, tr, tp, tx, tf, scale, sp, cg);
+      else
+        fwd_a2_mode<T, FWD_TANGENT, LAW, false>(L, mat, ti, tr, tp, tx, tf, scale, sp, cg);
+      break;
     case FWD_TANGENT_UNI: fwd_a2_mode<T, FWD_TANGENT_UNI, LAW>(L, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
     default: fwd_a2_mode<T, FWD_CG, LAW>(L, mat, ti, tr, tp, tx, tf, scale, sp, cg); break;
   }
@@ -1194,13 +1199,13 @@ void launch_col_a0_project(int prec, const Launch& L, void* spec, const CgState*
     col_a0_t<float>(L, spec, cg);
 }
 
-template <typename T, int MODE, typename TO>
+template <typename T, int MODE, typename TO, bool NTOP = true>
 static void inv_a2_mode(const Launch& L, const cx<T>* spec, TO* out, TO* x, double scale, const CgState* cg) {
   const int ntiles = L.nblk[K_ROW];
   const size_t lds = sizeof(T) == 8 ? L.lds_row64 : L.lds_row32;
-  if (L.eng[2] & 2) launch_tiles(&k_inv_a2<T, MODE, TO, 8>, ntiles, lds, L.s, L.b, spec, out, x, scale, cg);
-  if (L.eng[2] & 4) launch_tiles(&k_inv_a2<T, MODE, TO, 12>, ntiles, lds, L.s, L.b, spec, out, x, scale, cg);
-  if (L.eng[2] & 1) launch_tiles(&k_inv_a2<T, MODE, TO, 0>, ntiles, lds, L.s, L.b, spec, out, x, scale, cg);
+  if (L.eng[2] & 2) launch_tiles(&k_inv_a2<T, MODE, TO, 8, NTOP>, ntiles, lds, L.s, L.b, spec, out, x, scale, cg);
+  if (L.eng[2] & 4) launch_tiles(&k_inv_a2<T, MODE, TO, 12, NTOP>, ntiles, lds, L.s, L.b, spec, out, x, scale, cg);
+  if (L.eng[2] & 1) launch_tiles(&k_inv_a2<T, MODE, TO, 0, NTOP>, ntiles, lds, L.s, L.b, spec, out, x, scale, cg);
 }
 
 template <typename T, typename TO>
@@ -1210,7 +1215,12 @@ static void inv_a2_t(int mode, const Launch& L, const void* spec, void* out, voi
   TO* to = static_cast<TO*>(out);
   TO* tx = static_cast<TO*>(x);
   switch (mode) {
-    case INV_OUT: inv_a2_mode<T, INV_OUT, TO>(L, sp, to, tx, scale, cg); break;
+    case INV_OUT:
+      if (L.ntop)
+        inv_a2_mode<T, INV_OUT, TO, true>(L, sp, to, tx, scale, cg);
+      else
+        inv_a2_mode<T, INV_OUT, TO, false>(L, sp, to, tx, scale, cg);
+      break;
     case INV_CGR: inv_a2_mode<T, INV_CGR, TO>(L, sp, to, tx, scale, cg); break;
     default: inv_a2_mode<T, INV_RHS, TO>(L, sp, to, tx, scale, cg); break;
   }

@@ -19,6 +19,7 @@ constexpr int kMaxRve = 256;       // RVEs of one batched context
 constexpr int kRedBlocks = 8192;   // most work-groups of an element-wise kernel per RVE
 constexpr int kRegP = 8;           // points per thread of the register-resident FFT engine
 constexpr int kMaxPpt = 4;         // points per thread of an LDS-engine column tile (n * m <= kMaxPpt * kThreads)
+constexpr double kLlcBytes = 256.0 * 1024 * 1024;  // last-level (Infinity) cache of the device
 constexpr int kMaxXWin = 8;        // CG directions kept for the windowed update of x (FFTNK_OPT_X_WINDOW)
 
 // LDS padding: entry e of a twiddle table or of a contiguous (unit-stride)
@@ -79,6 +80,12 @@ __host__ __device__ constexpr bool col_pairs32(int pencils_per_group, int h, lon
 __host__ __device__ constexpr int col_engine(int reg, int n, int h, long long spec_off, int esz) {
   return esz == 4 && reg == 8 && col_pairs32(kThreads / (n / 8), h, spec_off) ? 16 : reg;
 }
+
+// Non-temporal streams in single operator applications pay off only where the
+// operator's fields (direction, linearisation point, spectrum, result: about
+// 36 element sizes per voxel) exceed the last-level cache; on smaller cells
+// they cost (96^3: FP32 0.100 -> 0.110 ms, FP64 0.162 -> 0.166 ms).
+inline bool op_nontemporal(long long ntot, int esz) { return 36.0 * (double)ntot * esz > kLlcBytes; }
 
 // Launch kinds: every kernel launch covers all RVEs of a context; work-group b
 // belongs to RVE r when starts[kind][r] <= b < starts[kind][r + 1].
@@ -229,6 +236,8 @@ struct Launch {
   int eng[3];  // per grid axis: bit 0 some cell transforms it with the LDS engine, bit 1 / 2 with the 8- / 12-point
                // register engine, bit 3 with the 8-point one on a cell where FP32 takes pencil pairs (col_engine)
   int nyq;     // 1: the cells use the identity choice at Nyquist frequencies (pass 3 variant)
+  int ntop;    // 1: single operator applications load the direction and store the result
+               //    non-temporally (their fields exceed the last-level cache: op_nontemporal)
   hipStream_t s;
 };
 void launch_fwd_a2(int prec, int mode, const Launch& L, const Material& mat, const void* in_T, const void* r_T,
