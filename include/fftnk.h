@@ -377,18 +377,18 @@ int fftnk_launch_pass(fftnk_ctx* ctx, int pass);
  * Instrumentation: time each kernel of a CG iteration (Sec. 2.6) at the
  * current iterate.  The right-hand side is -G(P) of the current iterate's
  * stress (so call it after a solve); the CG runs with tolerance 0 and no
- * iteration cap: W whole iterations untimed (W = FFTNK_OPT_X_WINDOW), pass 1
- * of iteration W (which applies the window of x updates) `iters` times, one
- * more whole iteration, then every kernel `iters` times back to back between
- * two stream events (the repeated launches keep the work of an iteration, not
- * its values: the context's Krylov vectors are clobbered, the committed state
- * is not).  ms_host[8] (host) receives the mean time of one launch of: 0 pass
- * 1 (p update, tangent action, a2 forward; for W > 1 at an iteration without
- * the x update), 1 alpha (0: its work-groups run in pass 2's launch and are
- * timed with it), 2 pass 2, 3 pass 3, 4 pass 4, 5 pass 5 (a2 inverse,
- * residual update), 6 beta, 7 pass 1 at an iteration that applies the window
- * of x updates.  1 <= iters <= 10000.  FFTNK_ESTATE if a cell's right-hand
- * side is zero (nothing to iterate on); synchronises.
+ * iteration cap: W + 1 whole iterations untimed (W = FFTNK_OPT_X_WINDOW), then
+ * max(iters, W) whole iterations with pass 1 between two stream events, in
+ * place (it reads what the iteration before wrote), then every other kernel
+ * `iters` times back to back between two events (the context's Krylov vectors
+ * are clobbered, the committed state is not).  ms_host[8] (host) receives the mean time of
+ * one launch of: 0 pass 1 (p update, tangent action, a2 forward) at an
+ * iteration inside a window, 1 alpha (0: its work-groups run in pass 2's
+ * launch and are timed with it), 2 pass 2, 3 pass 3, 4 pass 4, 5 pass 5 (a2
+ * inverse, residual update), 6 beta, 7 pass 1 at an iteration that applies the
+ * window of x updates (W = 1: every iteration; then 0 and 7 agree).
+ * 1 <= iters <= 10000.  FFTNK_ESTATE if a cell's right-hand side is zero
+ * (nothing to iterate on); synchronises.
  */
 int fftnk_profile_cg(fftnk_ctx* ctx, int iters, double* ms_host);
 

@@ -1894,13 +1894,45 @@ int fftnk_profile_cg(fftnk_ctx* c, int iters, double* ms) {
   if (e) return e;
   for (int r = 0; r < c->nrve; ++r)
     if (c->host_cg()[r].done) return FFTNK_ESTATE;
-  auto kernel = [&](int k) {
-    switch (k) {
-      case 0:
-        launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->pw(), c->x(), c->flin(), 1.0, c->spec(),
-                      cg);
-        break;
-      case 1: break;  // alpha: work-groups of the a1 pass's launch (timed with it)
+  // W + 1 whole iterations untimed (every kernel then sees a previous
+  // direction, a window start has passed).  Pass 1, which reads what pass 5
+  // of the iteration before wrote, in place: whole iterations with pass 1
+  // between two events on the stream, apart at window starts (iteration k
+  // with k mod W = 0; every cell runs in step: tolerance 0, no cap).  The
+  // other kernels `iters` times back to back between two events (beta last:
+  // it advances the iteration counter).
+  int err = FFTNK_OK;
+  for (int i = 0; i <= c->xwin && !err; ++i) cg_iteration(c, L);
+  err = check_launch();
+  if (err) return err;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) err = FFTNK_EHIP;
+  double s_in = 0, s_start = 0, n_in = 0, n_start = 0;
+  const int runs = std::max(iters, c->xwin);
+  for (int it = 0, k = c->xwin + 1; it < runs && !err; ++it, ++k) {
+    (void)hipEventRecord(e0, c->stream);
+    launch_fwd_a2(c->prec, FWD_CG, L, c->material(), nullptr, c->r(), c->pw(), c->x(), c->flin(), 1.0, c->spec(), cg);
+    (void)hipEventRecord(e1, c->stream);
+    launch_col_a1(c->prec, false, L, c->spec(), cg, cg);  // and alpha
+    launch_col_a0_project(c->prec, L, c->spec(), cg);
+    launch_col_a1(c->prec, true, L, c->spec(), cg);
+    launch_inv_a2(c->prec, INV_CGR, L, c->spec(), c->r(), c->prec, nullptr, 1.0, cg);
+    launch_cg_beta(L, cg);
+    err = check_launch();
+    float t = 0.f;
+    if (!err && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+      err = FFTNK_EHIP;
+    if (err) break;
+    if (k % c->xwin == 0) {
+      s_start += t;
+      n_start += 1;
+    } else {
+      s_in += t;
+      n_in += 1;
+    }
+  }
+  auto kernel = [&](int q) {
+    switch (q) {
       case 2: launch_col_a1(c->prec, false, L, c->spec(), cg, cg); break;
       case 3: launch_col_a0_project(c->prec, L, c->spec(), cg); break;
       case 4: launch_col_a1(c->prec, true, L, c->spec(), cg); break;
@@ -1908,36 +1940,23 @@ int fftnk_profile_cg(fftnk_ctx* c, int iters, double* ms) {
       default: launch_cg_beta(L, cg); break;
     }
   };
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return FFTNK_EHIP;
-  }
-  int err = check_launch();
-  auto timed = [&](int k, double* out) {
+  for (int q = 2; q <= 6 && !err; ++q) {
     (void)hipEventRecord(e0, c->stream);
-    for (int i = 0; i < iters; ++i) kernel(k);
+    for (int i = 0; i < iters; ++i) kernel(q);
     (void)hipEventRecord(e1, c->stream);
     err = check_launch();
     float t = 0.f;
     if (!err && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))
       err = FFTNK_EHIP;
-    *out = (double)t / iters;
-  };
-  // W whole iterations: the first pass of iteration W applies the window of
-  // x updates (timed as ms[7]); one more iteration, then every kernel `iters`
-  // times back to back between two events (beta last: it advances the
-  // iteration counter), the first pass at an iteration inside a window (for
-  // W > 1) where every kernel sees a previous direction
-  for (int i = 0; i < c->xwin && !err; ++i) cg_iteration(c, L);
-  if (!err) err = check_launch();
-  if (!err) timed(0, &ms[7]);
-  if (!err) cg_iteration(c, L);
-  for (int k = 0; k < 7 && !err; ++k) timed(k, &ms[k]);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return err;
+    ms[q] = (double)t / iters;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (err) return err;
+  ms[7] = s_start / std::max(1.0, n_start);
+  ms[0] = n_in > 0 ? s_in / n_in : ms[7];  // W = 1: every iteration updates x
+  ms[1] = 0.0;                          // alpha: work-groups of pass 2's launch
+  return FFTNK_OK;
 }
 
 int fftnk_get_history(fftnk_ctx* c, double* hist_dev) {
