@@ -38,7 +38,12 @@ __global__ __launch_bounds__(kThreads) void k_cg_finish(Batch B, T* __restrict__
   const long long m = 9 * g.n, off = 9 * g.vox_off;
   FOR_RVE_RANGE(i, m, local, nb) {
     T v = x[off + i];
-    for (int j = lo; j < hi; ++j) v = v + (T)cptr(cg)[rv].ahist[j % W] * p[(long long)(j % W) * B.vstride + off + i];
+    // at most W <= kMaxXWin terms: a fixed unrolled loop keeps their loads in flight together
+#pragma unroll
+    for (int jj = 0; jj < kMaxXWin; ++jj) {
+      const int j = lo + jj;
+      if (j < hi) v = v + (T)cptr(cg)[rv].ahist[j % W] * p[(long long)(j % W) * B.vstride + off + i];
+    }
     x[off + i] = v;
   }
 }
@@ -219,13 +224,17 @@ __global__ __launch_bounds__(kThreads) void k_newton_update(Batch B, Material ma
 #pragma unroll
   for (int k = 0; k < 11; ++k) acc[k] = 0.0;
   FOR_RVE_RANGE(v, n, local, nb) {
-    double f[9], Pv[9];
+    double f[9], Pv[9], d[9];
+    // all loads before the first store (F is read and written)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) d[c] = (double)x[off + c * n + v];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) f[c] = F[off + c * n + v];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
-      const double d = (double)x[off + c * n + v];
-      f[c] = F[off + c * n + v] + u[c] + d;
+      f[c] = f[c] + u[c] + d[c];
       F[off + c * n + v] = f[c];
-      acc[0] += d * d;
+      acc[0] += d[c] * d[c];
       if (Flin32) Flin32[off + c * n + v] = (float)f[c];
     }
     if (!stress_at<LAW>(mat, g.vox_off + v, f, Pv, true)) acc[10] += 1.0;
